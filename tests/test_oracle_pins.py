@@ -1,0 +1,391 @@
+"""Pins for the CPU oracle: checks against what the paper and the mathematics
+fix, independent of the oracle's own formulas.
+
+Each test names the passage or the mathematical fact it relies on.  A
+plausible slip anywhere in the oracle (normalisation, recurrence coefficient,
+sign of the derivative, index order, periodic image handling, h^3 placement)
+fails at least one of them.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import special
+
+import oracle
+from paper_1905_00480_amd import workloads as wl
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ------------------------------------------------------------- counting ----
+
+def test_nsho_matches_paper_printed_sizes():
+    """Appendix A and table 1 print the basis sizes for nu_max 0..5."""
+    rows = np.loadtxt(os.path.join(GOLDEN, "nsho_sizes.txt"), dtype=int)
+    for nu, size in rows:
+        assert oracle.nsho(nu) == size
+
+
+def test_nsho_closed_form_and_shell_degeneracy():
+    """Sec. 2.5 eq. SHO_basis_size and the (nu+1)(nu+2)/2 shell degeneracy of
+    sec. 2.4: count the triples directly."""
+    for nu in range(0, 14):
+        triples = [(x, y, z) for z in range(nu + 1) for y in range(nu + 1)
+                   for x in range(nu + 1) if x + y + z <= nu]
+        assert oracle.nsho(nu) == len(triples)
+        shell = [t for t in triples if sum(t) == nu]
+        assert len(shell) == (nu + 1) * (nu + 2) // 2
+
+
+def test_coeff_index_order_explicit():
+    """nz outermost, then ny, nx fastest (written out for nu = 2)."""
+    order = [(0, 0, 0), (1, 0, 0), (2, 0, 0), (0, 1, 0), (1, 1, 0), (0, 2, 0),
+             (0, 0, 1), (1, 0, 1), (0, 1, 1), (0, 0, 2)]
+    for k, (x, y, z) in enumerate(order):
+        assert oracle.coeff_index(2, x, y, z) == k
+    assert oracle.coeff_index(2, 1, 1, 1) == -1
+
+
+# --------------------------------------------------------- 1D functions ----
+
+def _phi_scipy(n, sigma, u):
+    """Normalised Hermite function from scipy's physicists' polynomials."""
+    t = u / sigma
+    norm = 1.0 / math.sqrt(2.0 ** n * math.factorial(n) * math.sqrt(math.pi) * sigma)
+    return norm * special.eval_hermite(n, t) * np.exp(-0.5 * t * t)
+
+
+@pytest.mark.parametrize("sigma", [0.4, 0.6, 1.2])
+def test_phi_matches_library_hermite(sigma):
+    """Sec. 2.2 eq. 1HO-eigenstate with the paper's monic recurrence (sec. 3.7)
+    equals the textbook normalised Hermite function built from scipy's H_n."""
+    nu = 12
+    u = np.linspace(-7 * sigma, 7 * sigma, 301)
+    got = oracle.phi(nu, sigma, u)
+    for n in range(nu + 1):
+        ref = _phi_scipy(n, sigma, u)
+        scale = np.max(np.abs(ref))
+        assert np.max(np.abs(got[n] - ref)) <= 2e-14 * scale, n
+
+
+def test_phi_closed_values_at_origin():
+    """phi_{2k}(0) = (-1)^k sqrt((2k)!)/(2^k k!) pi^{-1/4} sigma^{-1/2}; odd
+    orders vanish (parity of H_n)."""
+    for sigma in (0.5, 0.9):
+        v = oracle.phi(14, sigma, np.array([0.0]))[:, 0]
+        for n in range(15):
+            if n % 2:
+                assert v[n] == 0.0
+            else:
+                k = n // 2
+                ref = ((-1) ** k * math.sqrt(math.factorial(2 * k))
+                       / (2 ** k * math.factorial(k)) * math.pi ** -0.25
+                       / math.sqrt(sigma))
+                assert abs(v[n] - ref) <= 1e-15 * abs(ref) * 4
+
+
+def test_phi_orthonormal_gauss_hermite():
+    """int phi_n phi_m du = delta_nm, evaluated exactly by Gauss-Hermite
+    quadrature (numpy's hermgauss) of the polynomial part."""
+    sigma = 0.7
+    nu = 14
+    t, wts = np.polynomial.hermite.hermgauss(40)
+    f = oracle.phi(nu, sigma, sigma * t) * np.exp(0.5 * t * t)[None, :]
+    gram = sigma * (f * wts[None, :]) @ f.T
+    assert np.max(np.abs(gram - np.eye(nu + 1))) < 5e-14
+
+
+def test_phi_orthonormal_fine_grid():
+    """Riemann sums on a grid with sigma/h = 3 reproduce the continuum
+    orthonormality (the functions are band-limited, sec. 3.6)."""
+    sigma, h = 0.6, 0.2
+    u = np.arange(-80, 81) * h + 0.037  # off-grid centre
+    f = oracle.phi(10, sigma, u)
+    gram = h * f @ f.T
+    assert np.max(np.abs(gram - np.eye(11))) < 1e-13
+
+
+def test_dphi_ladder_identity_and_fd():
+    """phi_n' = (1/sigma)[sqrt(n/2) phi_{n-1} - sqrt((n+1)/2) phi_{n+1}]
+    (harmonic-oscillator ladder), and central differences."""
+    sigma = 0.55
+    nu = 11
+    u = np.linspace(-5 * sigma, 5 * sigma, 97)
+    d = oracle.dphi(nu, sigma, u)
+    f = oracle.phi(nu + 1, sigma, u)
+    for n in range(nu + 1):
+        lad = -math.sqrt((n + 1) / 2) * f[n + 1]
+        if n:
+            lad = lad + math.sqrt(n / 2) * f[n - 1]
+        lad /= sigma
+        assert np.max(np.abs(d[n] - lad)) < 1e-13 * max(1.0, np.max(np.abs(lad)))
+    eps = 1e-6
+    fd = (oracle.phi(nu, sigma, u + eps) - oracle.phi(nu, sigma, u - eps)) / (2 * eps)
+    assert np.max(np.abs(fd - d)) < 1e-7
+
+
+# --------------------------------------------------------------- support ---
+
+def test_support_is_sphere_with_wrap_and_clip():
+    """Sphere of radius R around the centre (sec. 6 'projection sphere');
+    periodic axes wrap modulo N, isolated axes drop outside points."""
+    n, h = (12, 10, 9), 0.3
+    centre = np.array([0.2, 1.45, 2.6])
+    R = 1.7
+    for periodic in [(True, True, True), (False, True, False)]:
+        idx, mem = oracle.support(n, h, periodic, centre, R)
+        lo = np.floor((centre - R) / h).astype(int) - 3
+        hi = np.ceil((centre + R) / h).astype(int) + 3
+        pts = np.stack(np.meshgrid(*[np.arange(l, u + 1) for l, u in zip(lo, hi)],
+                                   indexing="ij"), -1).reshape(-1, 3)
+        d = pts * h - centre
+        inside = np.sqrt((d ** 2).sum(1)) <= R * (1 - 1e-12)
+        border = np.abs(np.sqrt((d ** 2).sum(1)) - R) <= 1e-12 * R
+        for ax in range(3):
+            if not periodic[ax]:
+                ok = (pts[:, ax] >= 0) & (pts[:, ax] < n[ax])
+                inside &= ok
+                border &= ok
+        got = {tuple(p) for p in idx}
+        want = {tuple(p) for p in pts[inside]}
+        assert want <= got
+        assert got <= want | {tuple(p) for p in pts[border]}
+        wrapped = np.stack([idx[:, k] % n[k] for k in range(3)], 1)
+        assert np.array_equal(mem, (wrapped[:, 2] * n[1] + wrapped[:, 1]) * n[0]
+                              + wrapped[:, 0])
+
+
+def test_box_radius_rule():
+    """sigma*sqrt(2 nu + 3) is the classical turning radius of shell nu
+    (E sigma^2 = 2nu+3, sec. 2.2; potential r^2 sigma^-4), plus 2h."""
+    assert oracle.box_radius(0.6, 5, 0.2) == pytest.approx(0.6 * math.sqrt(13) + 0.4,
+                                                          rel=1e-15)
+
+
+def test_workloads_respect_sampling_bound():
+    """Every workload satisfies h <= pi sigma / sqrt(2 nu_max + 1)
+    (sec. 3.6 eq. max_grid_spacing)."""
+    for s in (wl.tiny(), wl.small_periodic(), wl.diff()):
+        hmax = np.pi * s.sigma / np.sqrt(2 * s.numax + 1)
+        assert np.all(s.h <= hmax)
+    # the batching and serving draws at their worst corner
+    assert 0.18 <= np.pi * 0.4 / np.sqrt(19)
+    assert 0.2 <= np.pi * 0.4 / np.sqrt(19)
+
+
+# ---------------------------------------------------------- projection -----
+
+def _isolated_grid(npts, h):
+    return (npts, npts, npts), h, (False, False, False)
+
+
+def test_project_gaussian_closed_form():
+    """psi = exp(-|r-R|^2 / 2 sigma^2) is proportional to the (0,0,0) function:
+    c_000 = pi^{3/4} sigma^{3/2}, all other coefficients vanish
+    (orthonormality of the Cartesian basis, sec. 2.2 / 2.5)."""
+    sigma, h = 0.5, 0.5 / 3.0
+    n, h, per = _isolated_grid(72, h)
+    R = np.array([[5.93, 6.07, 6.011]])
+    x = np.arange(72) * h
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    r2 = (X - R[0, 0]) ** 2 + (Y - R[0, 1]) ** 2 + (Z - R[0, 2]) ** 2
+    psi = np.exp(-r2 / (2 * sigma ** 2))[..., None]
+    c = oracle.project(n, h, per, R, [sigma], [5], psi, rbox=[10 * sigma])
+    ref = np.zeros(56)
+    ref[0] = math.pi ** 0.75 * sigma ** 1.5
+    assert np.max(np.abs(c - ref)) < 1e-12 * ref[0]
+
+
+def test_project_plane_waves_fourier_eigenfunctions():
+    """Hermite functions are Fourier eigenfunctions (sec. 3.6):
+    int phi_n(u) e^{iku} du = sigma^{1/2} sqrt(2 pi) i^n phi_n(k sigma; 1).
+    Project cos(k.r) and sin(k.r) and compare with the closed form."""
+    sigma, h = 0.5, 0.125
+    nu = 5
+    npts = 96
+    n, h, per = _isolated_grid(npts, h)
+    R = np.array([6.013, 5.981, 6.04])
+    ks = np.array([[0.9, -1.3, 0.4], [2.1, 0.3, -1.7], [-0.5, 3.0, 1.1]])
+    x = np.arange(npts) * h
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    bands = []
+    for k in ks:
+        ph = k[0] * X + k[1] * Y + k[2] * Z
+        bands += [np.cos(ph), np.sin(ph)]
+    psi = np.stack(bands, -1)
+    c = oracle.project(n, h, per, R[None], [sigma], [nu], psi,
+                       rbox=[10 * sigma]).reshape(oracle.nsho(nu), len(bands))
+    trip = [(x_, y_, z_) for z_ in range(nu + 1) for y_ in range(nu + 1 - z_)
+            for x_ in range(nu + 1 - z_ - y_)]
+    for j, k in enumerate(ks):
+        f1 = [np.sqrt(sigma) * np.sqrt(2 * np.pi) * (1j) ** np.arange(nu + 1)
+              * oracle.phi(nu, 1.0, [k[d] * sigma])[:, 0] for d in range(3)]
+        pre = np.exp(1j * np.dot(k, R))
+        ref = np.array([pre * f1[0][a] * f1[1][b] * f1[2][cc] for a, b, cc in trip])
+        assert np.max(np.abs(c[:, 2 * j] - ref.real)) < 1e-12
+        assert np.max(np.abs(c[:, 2 * j + 1] - ref.imag)) < 1e-12
+
+
+def test_recovery_project_expand_enlarged_box():
+    """Completeness within the truncated basis (sec. 2.5): on a box that holds
+    the functions entirely, project(expand(c)) = c."""
+    sigma, h = 0.7, 0.2
+    nu = 4
+    n, h, per = _isolated_grid(80, h)
+    pos = np.array([[7.93, 8.11, 7.87], [8.6, 7.4, 8.3]])
+    rng = np.random.default_rng(5)
+    B = 3
+    c = rng.standard_normal(2 * oracle.nsho(nu) * B)
+    rb = [10 * sigma] * 2
+    psi = oracle.expand(n, h, per, pos[:1], [sigma], [nu], c[:oracle.nsho(nu) * B],
+                        np.zeros((80, 80, 80, B)), rbox=rb[:1])
+    back = oracle.project(n, h, per, pos[:1], [sigma], [nu], psi, rbox=rb[:1])
+    assert np.max(np.abs(back - c[:oracle.nsho(nu) * B])) < 1e-12
+
+
+def test_adjoint_identity_periodic_overlapping():
+    """<project psi, w> = h^3 <psi, expand w> for overlapping atoms whose boxes
+    wrap across a small periodic cell (h^3 sits in the projection only)."""
+    s = wl.make_system("adj", (14, 12, 10), 0.25, (True, True, True), 3, None,
+                       None, 4, 21, sigma_range=(0.4, 0.9), numax_range=(1, 6))
+    psi = wl.psi_for(s)
+    w = wl.coeffs_for(s)
+    c = oracle.project(*s.geometry(), psi)
+    e = oracle.expand(*s.geometry(), w, np.zeros(s.psi_shape))
+    lhs = float(np.dot(c, w))
+    rhs = s.h ** 3 * float(np.sum(psi * e))
+    assert abs(lhs - rhs) < 1e-13 * (np.abs(c).sum() + 1)
+
+
+def test_expand_at_agrees_with_full_expand():
+    s = wl.make_system("ea", (10, 11, 9), 0.3, (True, False, True), 4, None, None,
+                       3, 22, sigma_range=(0.5, 1.0), numax_range=(0, 5))
+    c = wl.coeffs_for(s)
+    psi_in = wl.psi_for(s)
+    full = oracle.expand(*s.geometry(), c, psi_in)
+    pts = np.array([0, 7, 99, 500, 989])
+    at = oracle.expand_at(*s.geometry(), c, pts,
+                          psi_in.reshape(-1, 3)[pts])
+    assert np.max(np.abs(at - full.reshape(-1, 3)[pts])) < 1e-14 * np.max(np.abs(full))
+
+
+# ------------------------------------------------------------- invariants --
+
+def test_translation_by_grid_vector_and_cell():
+    """Moving the atom by k grid points and rolling psi by k points leaves c
+    unchanged; moving it by one cell length changes nothing at all."""
+    s = wl.small_periodic(natoms=2, nbands=3, n=20)
+    psi = wl.psi_for(s)
+    c0 = oracle.project(*s.geometry(), psi)
+    k = np.array([3, -2, 5])
+    pos = s.pos + k * s.h
+    psi_r = np.roll(psi, shift=(k[2], k[1], k[0]), axis=(0, 1, 2))
+    c1 = oracle.project(s.n, s.h, s.periodic, pos, s.sigma, s.numax, psi_r)
+    assert np.max(np.abs(c1 - c0)) < 1e-13 * np.max(np.abs(c0))
+    pos_l = s.pos + np.array(s.n) * s.h
+    c2 = oracle.project(s.n, s.h, s.periodic, pos_l, s.sigma, s.numax, psi)
+    assert np.max(np.abs(c2 - c0)) < 1e-13 * np.max(np.abs(c0))
+
+
+def test_mirror_parity():
+    """Mirroring psi through an atom that sits on a grid point multiplies each
+    coefficient by (-1)^nx (parity of H_n)."""
+    n = (24, 24, 24)
+    h = 0.2
+    nu = 5
+    X = np.array([[12 * h, 11 * h + 0.071, 12 * h - 0.033]])
+    rng = np.random.default_rng(9)
+    psi = rng.standard_normal((24, 24, 24, 2))
+    # mirror x -> 24 - x (index), i.e. x - X -> X - x around ix = 12
+    psi_m = psi[:, :, (24 - np.arange(24)) % 24, :]
+    per = (True, True, True)
+    c = oracle.project(n, h, per, X, [0.6], [nu], psi).reshape(-1, 2)
+    cm = oracle.project(n, h, per, X, [0.6], [nu], psi_m).reshape(-1, 2)
+    sign = np.array([(-1) ** x for z in range(nu + 1) for y in range(nu + 1 - z)
+                     for x in range(nu + 1 - z - y)])
+    assert np.max(np.abs(cm - sign[:, None] * c)) < 1e-13 * np.max(np.abs(c))
+
+
+# ------------------------------------------------------------- derivative --
+
+def test_force_central_differences_frozen_support():
+    """g = dL/dR with L = sum w c, support frozen: compare with central
+    differences, delta = 1e-5 Bohr."""
+    s = wl.make_system("fd", (18, 17, 16), 0.2, (False, True, False), 3, 0.6, 4,
+                       5, 31)
+    psi = wl.psi_for(s)
+    w = wl.coeffs_for(s)
+    g = oracle.force(*s.geometry(), psi, w)
+    delta = 1e-5
+    for a in range(s.natoms):
+        for d in range(3):
+            pp = s.pos.copy()
+            pm = s.pos.copy()
+            pp[a, d] += delta
+            pm[a, d] -= delta
+            cp = oracle.project(s.n, s.h, s.periodic, pp, s.sigma, s.numax, psi,
+                                spos=s.pos)
+            cm = oracle.project(s.n, s.h, s.periodic, pm, s.sigma, s.numax, psi,
+                                spos=s.pos)
+            fd = (np.dot(w, cp) - np.dot(w, cm)) / (2 * delta)
+            assert abs(fd - g[a, d]) < 1e-7 * max(1.0, abs(g[a, d]))
+
+
+def test_force_ladder_identity_on_frozen_box():
+    """dc_n/dX = -(1/sigma)[sqrt(nx/2) c~(nx-1) - sqrt((nx+1)/2) c~(nx+1)] where
+    c~ is the nu+1 projection on the same (nu) support."""
+    s = wl.make_system("lad", (16, 16, 16), 0.2, (True,) * 3, 2, 0.6, 3, 2, 33)
+    psi = wl.psi_for(s)
+    w = wl.coeffs_for(s)
+    _, dc = oracle.force(*s.geometry(), psi, w, with_dc=True)
+    nu, B = 3, 2
+    N = oracle.nsho(nu)
+    N1 = oracle.nsho(nu + 1)
+    rb = [oracle.box_radius(0.6, nu, s.h)] * s.natoms
+    ct = oracle.project(s.n, s.h, s.periodic, s.pos, s.sigma, s.numax + 1, psi,
+                        rbox=rb)
+    for a in range(s.natoms):
+        cta = ct[a * N1 * B:(a + 1) * N1 * B].reshape(N1, B)
+        dca = dc[3 * a * N * B:3 * (a + 1) * N * B].reshape(3, N, B)
+        for z in range(nu + 1):
+            for y in range(nu + 1 - z):
+                for x in range(nu + 1 - z - y):
+                    n = (x, y, z)
+                    k = oracle.coeff_index(nu, x, y, z)
+                    for d in range(3):
+                        up = list(n)
+                        up[d] += 1
+                        ref = math.sqrt((n[d] + 1) / 2) * cta[oracle.coeff_index(nu + 1, *up)]
+                        if n[d]:
+                            dn = list(n)
+                            dn[d] -= 1
+                            ref = ref - math.sqrt(n[d] / 2) * cta[oracle.coeff_index(nu + 1, *dn)]
+                        ref = ref / 0.6
+                        assert np.max(np.abs(dca[d, k] - ref)) < 1e-13 * (1 + np.max(np.abs(ref)))
+
+
+def test_force_plane_wave_sign():
+    """Continuum check of the sign: for psi = e^{i k.r}, c(R) = e^{i k.R} const,
+    so dc/dX = i k_x c; with cos/sin bands dc_cos/dX = -k_x c_sin and
+    dc_sin/dX = k_x c_cos."""
+    sigma, h = 0.5, 0.125
+    nu = 3
+    npts = 96
+    n, h, per = _isolated_grid(npts, h)
+    R = np.array([[6.013, 5.981, 6.04]])
+    k = np.array([1.1, -0.7, 0.5])
+    x = np.arange(npts) * h
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    ph = k[0] * X + k[1] * Y + k[2] * Z
+    psi = np.stack([np.cos(ph), np.sin(ph)], -1)
+    N = oracle.nsho(nu)
+    c = oracle.project(n, h, per, R, [sigma], [nu], psi, rbox=[10 * sigma]).reshape(N, 2)
+    w = np.zeros(2 * N)
+    _, dc = oracle.force(n, h, per, R, [sigma], [nu], psi, w, rbox=[10 * sigma],
+                         with_dc=True)
+    dc = dc.reshape(3, N, 2)
+    for d in range(3):
+        assert np.max(np.abs(dc[d, :, 0] + k[d] * c[:, 1])) < 1e-11
+        assert np.max(np.abs(dc[d, :, 1] - k[d] * c[:, 0])) < 1e-11
