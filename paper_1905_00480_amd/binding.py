@@ -1,0 +1,305 @@
+"""ctypes binding of libsho.so (argument marshalling only).
+
+Every operation runs in the library's gfx950 kernels on the caller's current
+torch stream; PyTorch only provides device memory and streams.  There is no
+fallback: if the library is missing or no GPU is present the calls raise.
+
+Layouts (see include/sho.h):
+  psi   float64 tensor (nz, ny, nx, B) on the GPU, band index fastest
+  c, w  float64 tensor with coeff_doubles entries, per-atom blocks
+        [N_SHO(nu_a)][B] in atom order (n: nz outer, ny, nx fastest)
+  grad  float64 tensor (natoms, 3)
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libsho.so")
+
+SHO_OK = 0
+SHO_E_INVALID = -1
+SHO_E_UNDERSAMPLED = -2
+SHO_E_NU_RANGE = -3
+SHO_E_BOX = -4
+SHO_E_NOMEM = -5
+SHO_E_DEVICE = -6
+SHO_E_BUDGET = -7
+SHO_NU_MAX = 10
+FLAG_STORED = 0x1
+FLAG_ALLOW_UNDERSAMPLED = 0x2
+FLAG_HOST_ONLY = 0x4
+
+# every symbol include/sho.h declares
+EXPORTS = (
+    "sho_nsho", "sho_last_error", "sho_plan_create", "sho_plan_destroy",
+    "sho_plan_get_info", "sho_plan_coeff_offsets", "sho_plan_support_counts",
+    "sho_plan_set_centres", "sho_plan_project", "sho_plan_expand",
+    "sho_plan_force", "sho_project", "sho_expand", "sho_force",
+    "sho_cache_clear",
+)
+
+
+class ShoError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("libsho error %d: %s" % (code, msg))
+        self.code = code
+
+
+class sho_grid(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32 * 3), ("h", ctypes.c_double),
+                ("periodic", ctypes.c_int32 * 3)]
+
+
+class sho_plan_info(ctypes.Structure):
+    _fields_ = [("natoms", ctypes.c_int32), ("nbands", ctypes.c_int32),
+                ("nu_max", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("coeff_rows", ctypes.c_int64), ("coeff_doubles", ctypes.c_int64),
+                ("support_points", ctypes.c_int64), ("lines", ctypes.c_int64),
+                ("planes", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
+                ("stored_bytes", ctypes.c_int64)]
+
+
+_lib = None
+_dp = ctypes.POINTER(ctypes.c_double)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_vp = ctypes.c_void_p
+
+
+def load_library(path=None):
+    """Load libsho.so (after torch, so that both share one HIP runtime)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    import torch  # noqa: F401  -- torch's HIP runtime must be the one in use
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(
+            "libsho.so not built: run `python -m paper_1905_00480_amd.build` "
+            "(or __graft_entry__.build()) first")
+    lib = ctypes.CDLL(p)
+    G = ctypes.POINTER(sho_grid)
+    P = _vp
+    lib.sho_nsho.argtypes = [ctypes.c_int32]
+    lib.sho_nsho.restype = ctypes.c_int32
+    lib.sho_last_error.argtypes = []
+    lib.sho_last_error.restype = ctypes.c_char_p
+    lib.sho_plan_create.argtypes = [G, ctypes.c_int32, _dp, _dp, _i32p, _dp,
+                                    ctypes.c_int32, ctypes.c_uint32,
+                                    ctypes.POINTER(_vp)]
+    lib.sho_plan_destroy.argtypes = [P]
+    lib.sho_plan_get_info.argtypes = [P, ctypes.POINTER(sho_plan_info)]
+    lib.sho_plan_coeff_offsets.argtypes = [P, _i64p]
+    lib.sho_plan_support_counts.argtypes = [P, _i64p]
+    lib.sho_plan_set_centres.argtypes = [P, _dp, _vp]
+    lib.sho_plan_project.argtypes = [P, _vp, _vp, _vp]
+    lib.sho_plan_expand.argtypes = [P, _vp, _vp, _vp]
+    lib.sho_plan_force.argtypes = [P, _vp, _vp, _vp, _vp]
+    geo = [G, ctypes.c_int32, _dp, _dp, _i32p, ctypes.c_int32]
+    lib.sho_project.argtypes = geo + [_vp, _vp, ctypes.c_uint32, _vp]
+    lib.sho_expand.argtypes = geo + [_vp, _vp, ctypes.c_uint32, _vp]
+    lib.sho_force.argtypes = geo + [_vp, _vp, _vp, ctypes.c_uint32, _vp]
+    lib.sho_cache_clear.argtypes = []
+    for name in EXPORTS:
+        if name not in ("sho_nsho", "sho_last_error"):
+            getattr(lib, name).restype = ctypes.c_int32
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _check(code):
+    if code != SHO_OK:
+        msg = load_library().sho_last_error().decode(errors="replace")
+        raise ShoError(code, msg)
+
+
+def make_grid(n, h, periodic):
+    g = sho_grid()
+    for d in range(3):
+        g.n[d] = int(n[d])
+        g.periodic[d] = 1 if periodic[d] else 0
+    g.h = float(h)
+    return g
+
+
+def _host_f64(a, shape):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(shape))
+
+
+def _host_i32(a, shape):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.int32).reshape(shape))
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev(t, numel, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a GPU tensor" % name)
+    if t.dtype != torch.float64:
+        raise TypeError("%s must be float64" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if t.numel() != numel:
+        raise ValueError("%s has %d elements, expected %d" % (name, t.numel(), numel))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """Reusable geometry plan: supports, line tables, device buffers."""
+
+    def __init__(self, n, h, periodic, pos, sigma, numax, nbands, rbox=None,
+                 flags=0):
+        lib = load_library()
+        self._lib = lib
+        self.n = tuple(int(v) for v in n)
+        self.h = float(h)
+        self.periodic = tuple(bool(v) for v in periodic)
+        pos = _host_f64(pos, (-1, 3))
+        self.natoms = pos.shape[0]
+        self._pos = pos
+        self._sigma = _host_f64(sigma, (self.natoms,))
+        self._numax = _host_i32(numax, (self.natoms,))
+        self._rbox = None if rbox is None else _host_f64(rbox, (self.natoms,))
+        self.nbands = int(nbands)
+        self._grid = make_grid(self.n, self.h, self.periodic)
+        handle = ctypes.c_void_p()
+        _check(lib.sho_plan_create(
+            ctypes.byref(self._grid), self.natoms,
+            self._pos.ctypes.data_as(_dp), self._sigma.ctypes.data_as(_dp),
+            self._numax.ctypes.data_as(_i32p),
+            None if self._rbox is None else self._rbox.ctypes.data_as(_dp),
+            self.nbands, int(flags), ctypes.byref(handle)))
+        self._h = handle
+        info = sho_plan_info()
+        _check(lib.sho_plan_get_info(self._h, ctypes.byref(info)))
+        self.info = {k: getattr(info, k) for k, _ in sho_plan_info._fields_}
+        self.coeff_doubles = int(info.coeff_doubles)
+        self.support_points = int(info.support_points)
+
+    @classmethod
+    def from_system(cls, s, flags=0, rbox=None):
+        return cls(s.n, s.h, s.periodic, s.pos, s.sigma, s.numax, s.nbands,
+                   rbox=rbox if rbox is not None else s.rbox, flags=flags)
+
+    @property
+    def psi_numel(self):
+        return self.n[0] * self.n[1] * self.n[2] * self.nbands
+
+    def coeff_offsets(self):
+        off = np.empty(self.natoms + 1, dtype=np.int64)
+        _check(self._lib.sho_plan_coeff_offsets(self._h, off.ctypes.data_as(_i64p)))
+        return off
+
+    def support_counts(self):
+        cnt = np.empty(max(self.natoms, 1), dtype=np.int64)
+        _check(self._lib.sho_plan_support_counts(self._h, cnt.ctypes.data_as(_i64p)))
+        return cnt[:self.natoms]
+
+    def set_centres(self, pos, stream=None):
+        pos = _host_f64(pos, (self.natoms, 3))
+        _check(self._lib.sho_plan_set_centres(self._h, pos.ctypes.data_as(_dp),
+                                              _stream(stream)))
+
+    def project(self, psi, c=None, stream=None):
+        import torch
+        if c is None:
+            c = torch.empty(self.coeff_doubles, dtype=torch.float64, device=psi.device)
+        _check(self._lib.sho_plan_project(
+            self._h, _dev(psi, self.psi_numel, "psi"),
+            _dev(c, self.coeff_doubles, "c"), _stream(stream)))
+        return c
+
+    def expand(self, c, psi, stream=None):
+        _check(self._lib.sho_plan_expand(
+            self._h, _dev(c, self.coeff_doubles, "c"),
+            _dev(psi, self.psi_numel, "psi"), _stream(stream)))
+        return psi
+
+    def force(self, psi, w, grad=None, stream=None):
+        import torch
+        if grad is None:
+            grad = torch.empty((self.natoms, 3), dtype=torch.float64, device=psi.device)
+        _check(self._lib.sho_plan_force(
+            self._h, _dev(psi, self.psi_numel, "psi"),
+            _dev(w, self.coeff_doubles, "w"), _dev(grad, 3 * self.natoms, "grad"),
+            _stream(stream)))
+        return grad
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(self._lib.sho_plan_destroy(self._h))
+        self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _geo(n, h, periodic, pos, sigma, numax):
+    pos = _host_f64(pos, (-1, 3))
+    na = pos.shape[0]
+    return (make_grid(n, h, periodic), na, pos, _host_f64(sigma, (na,)),
+            _host_i32(numax, (na,)))
+
+
+def _ncoeff(numax, nbands):
+    nu = np.asarray(numax, dtype=np.int64)
+    return int(((nu + 1) * (nu + 2) * (nu + 3) // 6).sum()) * int(nbands)
+
+
+def project(n, h, periodic, pos, sigma, numax, psi, c=None, flags=0, stream=None):
+    """Stateless projection (plan built or reused from the library's cache)."""
+    import torch
+    lib = load_library()
+    g, na, pos, sigma, numax = _geo(n, h, periodic, pos, sigma, numax)
+    B = psi.shape[-1]
+    if c is None:
+        c = torch.empty(_ncoeff(numax, B), dtype=torch.float64, device=psi.device)
+    _check(lib.sho_project(ctypes.byref(g), na, pos.ctypes.data_as(_dp),
+                           sigma.ctypes.data_as(_dp), numax.ctypes.data_as(_i32p), B,
+                           _dev(psi, psi.numel(), "psi"),
+                           _dev(c, _ncoeff(numax, B), "c"), int(flags), _stream(stream)))
+    return c
+
+
+def expand(n, h, periodic, pos, sigma, numax, c, psi, flags=0, stream=None):
+    lib = load_library()
+    g, na, pos, sigma, numax = _geo(n, h, periodic, pos, sigma, numax)
+    B = psi.shape[-1]
+    _check(lib.sho_expand(ctypes.byref(g), na, pos.ctypes.data_as(_dp),
+                          sigma.ctypes.data_as(_dp), numax.ctypes.data_as(_i32p), B,
+                          _dev(c, _ncoeff(numax, B), "c"),
+                          _dev(psi, psi.numel(), "psi"), int(flags), _stream(stream)))
+    return psi
+
+
+def force(n, h, periodic, pos, sigma, numax, psi, w, grad=None, flags=0, stream=None):
+    import torch
+    lib = load_library()
+    g, na, pos, sigma, numax = _geo(n, h, periodic, pos, sigma, numax)
+    B = psi.shape[-1]
+    if grad is None:
+        grad = torch.empty((na, 3), dtype=torch.float64, device=psi.device)
+    _check(lib.sho_force(ctypes.byref(g), na, pos.ctypes.data_as(_dp),
+                         sigma.ctypes.data_as(_dp), numax.ctypes.data_as(_i32p), B,
+                         _dev(psi, psi.numel(), "psi"), _dev(w, _ncoeff(numax, B), "w"),
+                         _dev(grad, 3 * na, "grad"), int(flags), _stream(stream)))
+    return grad
+
+
+def nsho(nu):
+    return load_library().sho_nsho(int(nu))
+
+
+def cache_clear():
+    _check(load_library().sho_cache_clear())

@@ -1,0 +1,68 @@
+"""Build libsho.so in-tree for gfx950 (hipcc cross-compiles without a GPU).
+
+Objects:
+  sho_plan.cpp     host geometry, g++ -ffp-contract=off (the support membership
+                   test must be evaluated in the documented operation order)
+  sho_api.cpp      C ABI layer (host HIP runtime calls)
+  sho_kernels.hip  gfx950 kernels
+"""
+import os
+import shutil
+import subprocess
+import sys
+import time
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+INCLUDE = os.path.join(ROOT, "include")
+BUILD = os.path.join(ROOT, "_build")
+LIB = os.path.join(PKG, "libsho.so")
+ARCH = os.environ.get("SHO_OFFLOAD_ARCH", "gfx950")
+
+HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             "-Wall", "-Wno-unused-result", "-I", INCLUDE, "-I", CSRC]
+HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-ffp-contract=off",
+              "-fno-fast-math", "-Wall", "-Wextra", "-I", INCLUDE, "-I", CSRC]
+
+
+def _run(cmd, verbose):
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+
+
+def build(verbose: bool = False, jobs: int = 3) -> str:
+    """Compile every source and link libsho.so (always rebuilds)."""
+    os.makedirs(BUILD, exist_ok=True)
+    t0 = time.time()
+    objs = []
+    procs = []
+    plan_o = os.path.join(BUILD, "sho_plan.o")
+    cmd = ["g++"] + HOST_FLAGS + ["-c", os.path.join(CSRC, "sho_plan.cpp"), "-o", plan_o]
+    procs.append((cmd, subprocess.Popen(cmd)))
+    objs.append(plan_o)
+    for src in ("sho_api.cpp", "sho_kernels.hip"):
+        o = os.path.join(BUILD, src.rsplit(".", 1)[0] + ".o")
+        lang = ["-x", "hip"] if src.endswith(".hip") else []
+        cmd = [HIPCC] + HIP_FLAGS + lang + ["-c", os.path.join(CSRC, src), "-o", o]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((cmd, subprocess.Popen(cmd)))
+        objs.append(o)
+    bad = [c for c, p in procs if p.wait() != 0]
+    if bad:
+        raise RuntimeError("compile failed: " + " ".join(bad[0]))
+    tmp = LIB + ".tmp"
+    _run([HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs
+         + ["-Wl,-rpath,/opt/rocm/lib"], verbose)
+    os.replace(tmp, LIB)
+    if verbose:
+        print("built %s in %.1fs" % (LIB, time.time() - t0), flush=True)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose="-v" in sys.argv)

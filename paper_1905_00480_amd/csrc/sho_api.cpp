@@ -1,0 +1,462 @@
+// sho_api.cpp -- C ABI of libsho.so: plans, uploads, launch orchestration,
+// error reporting and the small plan cache behind the stateless calls.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <list>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "sho_launch.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+sho_status fail(sho_status code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+
+sho_status hip_fail(hipError_t e, const char *what) {
+  return fail(SHO_E_DEVICE,
+              std::string(what) + ": " + hipGetErrorString(e));
+}
+
+struct Group {
+  int32_t nu;
+  int32_t list_begin;  // into the device atom-list array
+  int32_t count;
+  int32_t mstride;     // largest table extent among these atoms
+  int32_t mstride_f;   // same, used by the derivative (same support)
+};
+
+}  // namespace
+
+struct sho_plan_s {
+  sho::HostPlan hp;
+  int device = 0;
+  size_t lds_limit = 0;
+  std::vector<Group> groups;
+  sho::AtomRec *d_atoms = nullptr;
+  sho::PlaneRec *d_planes = nullptr;
+  sho::LineRec *d_lines = nullptr;
+  int32_t *d_list = nullptr;
+  int64_t device_bytes = 0;
+  int64_t stored_bytes = 0;
+};
+
+namespace {
+
+template <typename T>
+hipError_t upload(T **dst, const std::vector<T> &src, int64_t *bytes) {
+  const size_t n = std::max<size_t>(src.size(), 1) * sizeof(T);
+  hipError_t e = hipMalloc((void **)dst, n);
+  if (e != hipSuccess) return e;
+  *bytes += (int64_t)n;
+  if (!src.empty()) e = hipMemcpy(*dst, src.data(), src.size() * sizeof(T),
+                                  hipMemcpyHostToDevice);
+  return e;
+}
+
+void free_plan_device(sho_plan_s *p) {
+  if (p->d_atoms) (void)hipFree(p->d_atoms);
+  if (p->d_planes) (void)hipFree(p->d_planes);
+  if (p->d_lines) (void)hipFree(p->d_lines);
+  if (p->d_list) (void)hipFree(p->d_list);
+  p->d_atoms = nullptr;
+  p->d_planes = nullptr;
+  p->d_lines = nullptr;
+  p->d_list = nullptr;
+}
+
+// Bands per line slot: a power of two <= 64 covering nbands when possible,
+// reduced until a workgroup's LDS fits.
+int choose_tb_shift(int nbands, int nf, int mstride, size_t lds_limit) {
+  int shift = 0;
+  while ((1 << shift) < nbands && shift < 6) ++shift;
+  while (shift > 0 && sho::lds_bytes(nf, mstride, 1 << shift) > lds_limit) --shift;
+  if (sho::lds_bytes(nf, mstride, 1 << shift) > lds_limit) return -1;
+  return shift;
+}
+
+sho::KArgs make_args(const sho_plan_s *p, const Group &g, int nf,
+                     int tb_shift) {
+  sho::KArgs K;
+  K.atoms = p->d_atoms;
+  K.planes = p->d_planes;
+  K.lines = p->d_lines;
+  K.atom_list = p->d_list + g.list_begin;
+  K.nlist = g.count;
+  K.nx = p->hp.grid.n[0];
+  K.B = p->hp.nbands;
+  K.tb_shift = tb_shift;
+  K.ntiles = (p->hp.nbands + (1 << tb_shift) - 1) >> tb_shift;
+  K.mstride = std::max(g.mstride, 1);
+  K.h = p->hp.grid.h;
+  K.h3 = K.h * K.h * K.h;
+  (void)nf;
+  return K;
+}
+
+// A device buffer of at least `bytes` bytes must start at ptr: checked
+// against the runtime's allocation record so that a wrong size or a host
+// pointer is refused before any kernel touches it.
+bool device_range_ok(const void *ptr, int64_t bytes) {
+  if (!ptr) return false;
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, ptr) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  if (attr.type != hipMemoryTypeDevice && !attr.isManaged) return false;
+  hipDeviceptr_t base = nullptr;
+  size_t size = 0;
+  if (hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)ptr) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  const char *b = static_cast<const char *>(base);
+  const char *q = static_cast<const char *>(ptr);
+  return q >= b && (int64_t)(q - b) + bytes <= (int64_t)size;
+}
+
+int64_t psi_bytes(const sho_plan_s *p) {
+  return (int64_t)p->hp.grid.n[0] * p->hp.grid.n[1] * p->hp.grid.n[2] *
+         p->hp.nbands * (int64_t)sizeof(double);
+}
+
+int64_t coeff_bytes(const sho_plan_s *p) {
+  return p->hp.coeff_rows * p->hp.nbands * (int64_t)sizeof(double);
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------- C ABI --
+
+extern "C" {
+
+int32_t sho_nsho(int32_t nu) { return nu < 0 ? -1 : sho::nsho(nu); }
+
+const char *sho_last_error(void) { return g_err.c_str(); }
+
+sho_status sho_plan_create(const sho_grid *grid, int32_t natoms,
+                           const double *pos, const double *sigma,
+                           const int32_t *numax, const double *rbox,
+                           int32_t nbands, uint32_t flags, sho_plan_t *out) {
+  if (!out) return fail(SHO_E_INVALID, "out must not be NULL");
+  *out = nullptr;
+  if (flags & SHO_FLAG_STORED)
+    return fail(SHO_E_INVALID, "stored-projector plans are not available yet");
+  sho_plan_s *p = new (std::nothrow) sho_plan_s();
+  if (!p) return fail(SHO_E_NOMEM, "host allocation failed");
+  std::string msg;
+  sho_status st = sho::build_host_plan(grid, natoms, pos, sigma, numax, rbox,
+                                       nbands, flags, &p->hp, &msg);
+  if (st != SHO_OK) {
+    delete p;
+    return fail(st, msg);
+  }
+  if (flags & SHO_FLAG_HOST_ONLY) {
+    *out = p;
+    return SHO_OK;
+  }
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) {
+    delete p;
+    return hip_fail(e, "hipGetDevice");
+  }
+  int shm = 0;
+  e = hipDeviceGetAttribute(&shm, hipDeviceAttributeMaxSharedMemoryPerBlock,
+                            p->device);
+  if (e != hipSuccess) {
+    delete p;
+    return hip_fail(e, "hipDeviceGetAttribute");
+  }
+  p->lds_limit = (size_t)std::max(shm - 1024, 0);  // static LDS of the kernels
+
+  // group atoms by nu (one launch per group)
+  std::vector<int32_t> list;
+  for (int nu = 0; nu <= SHO_NU_MAX; ++nu) {
+    Group g{nu, (int32_t)list.size(), 0, 0, 0};
+    for (int32_t a = 0; a < p->hp.natoms; ++a) {
+      const sho::AtomRec &A = p->hp.atoms[a];
+      if (A.nu != nu || A.npoints == 0) continue;
+      list.push_back(a);
+      g.count++;
+      g.mstride = std::max(g.mstride, std::max(A.mx, std::max(A.my, A.mz)));
+    }
+    g.mstride_f = g.mstride;
+    if (g.count) {
+      if (choose_tb_shift(1, nu + 2, g.mstride, p->lds_limit) < 0) {
+        delete p;
+        return fail(SHO_E_BOX, "support box too wide for the on-chip tables");
+      }
+      p->groups.push_back(g);
+    }
+  }
+  if ((e = upload(&p->d_atoms, p->hp.atoms, &p->device_bytes)) != hipSuccess ||
+      (e = upload(&p->d_planes, p->hp.planes, &p->device_bytes)) != hipSuccess ||
+      (e = upload(&p->d_lines, p->hp.lines, &p->device_bytes)) != hipSuccess ||
+      (e = upload(&p->d_list, list, &p->device_bytes)) != hipSuccess) {
+    free_plan_device(p);
+    delete p;
+    (void)hipGetLastError();
+    return e == hipErrorOutOfMemory ? fail(SHO_E_NOMEM, "device allocation failed")
+                                    : hip_fail(e, "plan upload");
+  }
+  *out = p;
+  return SHO_OK;
+}
+
+sho_status sho_plan_destroy(sho_plan_t p) {
+  if (!p) return SHO_OK;
+  if (p->hp.flags & SHO_FLAG_HOST_ONLY) {
+    delete p;
+    return SHO_OK;
+  }
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  if (cur != p->device) (void)hipSetDevice(p->device);
+  hipError_t e = hipDeviceSynchronize();
+  free_plan_device(p);
+  if (cur != p->device) (void)hipSetDevice(cur);
+  delete p;
+  if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+  return SHO_OK;
+}
+
+sho_status sho_plan_get_info(sho_plan_t p, sho_plan_info *info) {
+  if (!p || !info) return fail(SHO_E_INVALID, "NULL plan or info");
+  info->natoms = p->hp.natoms;
+  info->nbands = p->hp.nbands;
+  info->nu_max = p->hp.nu_max;
+  info->flags = (int32_t)p->hp.flags;
+  info->coeff_rows = p->hp.coeff_rows;
+  info->coeff_doubles = p->hp.coeff_rows * p->hp.nbands;
+  info->support_points = p->hp.support_points;
+  info->lines = (int64_t)p->hp.lines.size();
+  info->planes = (int64_t)p->hp.planes.size();
+  info->device_bytes = p->device_bytes;
+  info->stored_bytes = p->stored_bytes;
+  return SHO_OK;
+}
+
+sho_status sho_plan_coeff_offsets(sho_plan_t p, int64_t *off) {
+  if (!p || !off) return fail(SHO_E_INVALID, "NULL plan or output");
+  std::memcpy(off, p->hp.coeff_off.data(),
+              p->hp.coeff_off.size() * sizeof(int64_t));
+  return SHO_OK;
+}
+
+sho_status sho_plan_support_counts(sho_plan_t p, int64_t *counts) {
+  if (!p || !counts) return fail(SHO_E_INVALID, "NULL plan or output");
+  for (int32_t a = 0; a < p->hp.natoms; ++a) counts[a] = p->hp.atoms[a].npoints;
+  return SHO_OK;
+}
+
+sho_status sho_plan_set_centres(sho_plan_t p, const double *pos, void *stream) {
+  if (!p || (!pos && p->hp.natoms)) return fail(SHO_E_INVALID, "NULL plan or pos");
+  if (p->hp.flags & SHO_FLAG_HOST_ONLY)
+    return fail(SHO_E_INVALID, "host-only plan has no device tables");
+  for (int32_t a = 0; a < p->hp.natoms; ++a)
+    for (int d = 0; d < 3; ++d)
+      if (!std::isfinite(pos[3 * a + d]))
+        return fail(SHO_E_INVALID, "non-finite position");
+  for (int32_t a = 0; a < p->hp.natoms; ++a) {
+    p->hp.atoms[a].cx = pos[3 * a];
+    p->hp.atoms[a].cy = pos[3 * a + 1];
+    p->hp.atoms[a].cz = pos[3 * a + 2];
+  }
+  if (!p->hp.natoms) return SHO_OK;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(p->d_atoms, p->hp.atoms.data(),
+                                p->hp.atoms.size() * sizeof(sho::AtomRec),
+                                hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "centre upload");
+  return SHO_OK;
+}
+
+sho_status sho_plan_project(sho_plan_t p, const double *psi, double *c,
+                            void *stream) {
+  if (!p) return fail(SHO_E_INVALID, "NULL plan");
+  if (p->hp.flags & SHO_FLAG_HOST_ONLY)
+    return fail(SHO_E_INVALID, "host-only plan cannot run kernels");
+  if (p->hp.coeff_rows == 0) return SHO_OK;
+  if (!device_range_ok(psi, psi_bytes(p)) || !device_range_ok(c, coeff_bytes(p)))
+    return fail(SHO_E_INVALID, "psi and c must be device buffers of the plan's sizes");
+  if ((const char *)c < (const char *)psi + psi_bytes(p) &&
+      (const char *)psi < (const char *)c + coeff_bytes(p))
+    return fail(SHO_E_INVALID, "psi and c overlap");
+  hipStream_t s = (hipStream_t)stream;
+  // atoms whose support missed the grid entirely keep zero coefficients
+  bool empty = false;
+  for (const auto &A : p->hp.atoms) empty |= (A.npoints == 0);
+  if (empty) {
+    hipError_t e = sho::launch_fill(c, p->hp.coeff_rows * p->hp.nbands, 0.0, s);
+    if (e != hipSuccess) return hip_fail(e, "fill");
+  }
+  for (const Group &g : p->groups) {
+    const int tbs = choose_tb_shift(p->hp.nbands, g.nu + 1, g.mstride, p->lds_limit);
+    sho::KArgs K = make_args(p, g, g.nu + 1, tbs);
+    hipError_t e = sho::launch_project(g.nu, K, psi, c, s);
+    if (e != hipSuccess) return hip_fail(e, "project launch");
+  }
+  return SHO_OK;
+}
+
+sho_status sho_plan_expand(sho_plan_t p, const double *c, double *psi,
+                           void *stream) {
+  if (!p) return fail(SHO_E_INVALID, "NULL plan");
+  if (p->hp.flags & SHO_FLAG_HOST_ONLY)
+    return fail(SHO_E_INVALID, "host-only plan cannot run kernels");
+  if (p->hp.coeff_rows == 0) return SHO_OK;
+  if (!device_range_ok(psi, psi_bytes(p)) || !device_range_ok(c, coeff_bytes(p)))
+    return fail(SHO_E_INVALID, "psi and c must be device buffers of the plan's sizes");
+  if ((const char *)c < (const char *)psi + psi_bytes(p) &&
+      (const char *)psi < (const char *)c + coeff_bytes(p))
+    return fail(SHO_E_INVALID, "psi and c overlap");
+  hipStream_t s = (hipStream_t)stream;
+  for (const Group &g : p->groups) {
+    const int tbs = choose_tb_shift(p->hp.nbands, g.nu + 1, g.mstride, p->lds_limit);
+    sho::KArgs K = make_args(p, g, g.nu + 1, tbs);
+    hipError_t e = sho::launch_expand(g.nu, K, c, psi, s);
+    if (e != hipSuccess) return hip_fail(e, "expand launch");
+  }
+  return SHO_OK;
+}
+
+sho_status sho_plan_force(sho_plan_t p, const double *psi, const double *w,
+                          double *grad, void *stream) {
+  if (!p) return fail(SHO_E_INVALID, "NULL plan");
+  if (p->hp.flags & SHO_FLAG_HOST_ONLY)
+    return fail(SHO_E_INVALID, "host-only plan cannot run kernels");
+  if (p->hp.natoms == 0) return SHO_OK;
+  if (!device_range_ok(psi, psi_bytes(p)) || !device_range_ok(w, coeff_bytes(p)) ||
+      !device_range_ok(grad, 3 * (int64_t)p->hp.natoms * (int64_t)sizeof(double)))
+    return fail(SHO_E_INVALID, "psi, w and grad must be device buffers of the plan's sizes");
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = sho::launch_fill(grad, 3 * (int64_t)p->hp.natoms, 0.0, s);
+  if (e != hipSuccess) return hip_fail(e, "fill");
+  for (const Group &g : p->groups) {
+    const int tbs = choose_tb_shift(p->hp.nbands, g.nu + 2, g.mstride, p->lds_limit);
+    sho::KArgs K = make_args(p, g, g.nu + 2, tbs);
+    e = sho::launch_force(g.nu, K, psi, w, grad, s);
+    if (e != hipSuccess) return hip_fail(e, "force launch");
+  }
+  return SHO_OK;
+}
+
+}  // extern "C"
+
+// ----------------------------------------------------- stateless + cache --
+
+namespace {
+
+std::mutex g_cache_mu;
+std::list<std::pair<std::string, sho_plan_t>> g_cache;  // most recent first
+constexpr size_t kCacheSize = 8;
+
+std::string cache_key(const sho_grid *grid, int32_t natoms, const double *pos,
+                      const double *sigma, const int32_t *numax,
+                      int32_t nbands, uint32_t flags, int device) {
+  std::string k;
+  auto put = [&k](const void *p, size_t n) {
+    k.append(reinterpret_cast<const char *>(p), n);
+  };
+  put(grid, sizeof(sho_grid));
+  put(&natoms, sizeof natoms);
+  put(&nbands, sizeof nbands);
+  put(&flags, sizeof flags);
+  put(&device, sizeof device);
+  if (natoms > 0) {
+    put(pos, 3 * sizeof(double) * (size_t)natoms);
+    put(sigma, sizeof(double) * (size_t)natoms);
+    put(numax, sizeof(int32_t) * (size_t)natoms);
+  }
+  return k;
+}
+
+sho_status cached_plan(const sho_grid *grid, int32_t natoms, const double *pos,
+                       const double *sigma, const int32_t *numax,
+                       int32_t nbands, uint32_t flags, sho_plan_t *out) {
+  if (!grid || natoms < 0 || (natoms > 0 && (!pos || !sigma || !numax)))
+    return fail(SHO_E_INVALID, "NULL geometry arguments");
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::string key = cache_key(grid, natoms, pos, sigma, numax, nbands, flags, dev);
+  std::lock_guard<std::mutex> lock(g_cache_mu);
+  for (auto it = g_cache.begin(); it != g_cache.end(); ++it) {
+    if (it->first == key) {
+      g_cache.splice(g_cache.begin(), g_cache, it);
+      *out = g_cache.front().second;
+      return SHO_OK;
+    }
+  }
+  sho_plan_t p = nullptr;
+  sho_status st = sho_plan_create(grid, natoms, pos, sigma, numax, nullptr,
+                                  nbands, flags, &p);
+  if (st != SHO_OK) return st;
+  g_cache.emplace_front(std::move(key), p);
+  while (g_cache.size() > kCacheSize) {
+    sho_plan_destroy(g_cache.back().second);
+    g_cache.pop_back();
+  }
+  *out = p;
+  return SHO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sho_status sho_project(const sho_grid *grid, int32_t natoms, const double *pos,
+                       const double *sigma, const int32_t *numax,
+                       int32_t nbands, const double *psi, double *c,
+                       uint32_t flags, void *stream) {
+  sho_plan_t p = nullptr;
+  sho_status st = cached_plan(grid, natoms, pos, sigma, numax, nbands, flags, &p);
+  if (st != SHO_OK) return st;
+  return sho_plan_project(p, psi, c, stream);
+}
+
+sho_status sho_expand(const sho_grid *grid, int32_t natoms, const double *pos,
+                      const double *sigma, const int32_t *numax,
+                      int32_t nbands, const double *c, double *psi,
+                      uint32_t flags, void *stream) {
+  sho_plan_t p = nullptr;
+  sho_status st = cached_plan(grid, natoms, pos, sigma, numax, nbands, flags, &p);
+  if (st != SHO_OK) return st;
+  return sho_plan_expand(p, c, psi, stream);
+}
+
+sho_status sho_force(const sho_grid *grid, int32_t natoms, const double *pos,
+                     const double *sigma, const int32_t *numax, int32_t nbands,
+                     const double *psi, const double *w, double *grad,
+                     uint32_t flags, void *stream) {
+  sho_plan_t p = nullptr;
+  sho_status st = cached_plan(grid, natoms, pos, sigma, numax, nbands, flags, &p);
+  if (st != SHO_OK) return st;
+  return sho_plan_force(p, psi, w, grad, stream);
+}
+
+sho_status sho_cache_clear(void) {
+  std::lock_guard<std::mutex> lock(g_cache_mu);
+  sho_status st = SHO_OK;
+  for (auto &kv : g_cache) {
+    sho_status s2 = sho_plan_destroy(kv.second);
+    if (s2 != SHO_OK) st = s2;
+  }
+  g_cache.clear();
+  return st;
+}
+
+}  // extern "C"

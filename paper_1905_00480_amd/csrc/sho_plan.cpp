@@ -1,0 +1,226 @@
+// sho_plan.cpp -- host-side geometry: validation and support tables.
+//
+// Compiled without floating-point contraction (-ffp-contract=off) so that the
+// support membership test below is evaluated in exactly the IEEE double
+// operation order the interface documents:
+//     d = i*h - centre  (per axis),  r2 = (dx*dx + dy*dy) + dz*dz,
+//     member  <=>  r2 <= R*R.
+// The support is the projection sphere of sec. 6 of the paper; its default
+// radius sigma*sqrt(2 nu + 3) + 2h is the classical turning radius of the
+// highest shell nu (E sigma^2 = 2 nu + 3, sec. 2.2) plus two spacings.
+#include <cmath>
+#include <cstdio>
+#include <limits>
+
+#include "sho_internal.hpp"
+
+namespace sho {
+namespace {
+
+int32_t wrap_index(int64_t i, int32_t n) {
+  int64_t m = i % n;
+  return (int32_t)(m < 0 ? m + n : m);
+}
+
+bool finite3(const double *p) {
+  return std::isfinite(p[0]) && std::isfinite(p[1]) && std::isfinite(p[2]);
+}
+
+}  // namespace
+
+sho_status build_host_plan(const sho_grid *grid, int32_t natoms,
+                           const double *pos, const double *sigma,
+                           const int32_t *numax, const double *rbox,
+                           int32_t nbands, uint32_t flags, HostPlan *out,
+                           std::string *msg) {
+  char buf[256];
+  if (!grid || !out) {
+    *msg = "grid and output pointers must not be NULL";
+    return SHO_E_INVALID;
+  }
+  if (natoms < 0 || (natoms > 0 && (!pos || !sigma || !numax))) {
+    *msg = "natoms < 0 or NULL atom arrays";
+    return SHO_E_INVALID;
+  }
+  if (nbands <= 0) {
+    *msg = "nbands must be positive";
+    return SHO_E_INVALID;
+  }
+  const double h = grid->h;
+  if (!(h > 0) || !std::isfinite(h)) {
+    *msg = "grid spacing h must be positive and finite";
+    return SHO_E_INVALID;
+  }
+  int64_t npts = 1;
+  for (int d = 0; d < 3; ++d) {
+    if (grid->n[d] <= 0) {
+      *msg = "grid point counts must be positive";
+      return SHO_E_INVALID;
+    }
+    npts *= grid->n[d];
+  }
+  if ((int64_t)grid->n[2] * grid->n[1] > std::numeric_limits<int32_t>::max() ||
+      npts > std::numeric_limits<int64_t>::max() / 8 / nbands) {
+    *msg = "grid too large";
+    return SHO_E_INVALID;
+  }
+  const uint32_t known =
+      SHO_FLAG_STORED | SHO_FLAG_ALLOW_UNDERSAMPLED | SHO_FLAG_HOST_ONLY;
+  if (flags & ~known) {
+    *msg = "unknown flag bits";
+    return SHO_E_INVALID;
+  }
+
+  HostPlan &P = *out;
+  P = HostPlan();
+  P.grid = *grid;
+  P.natoms = natoms;
+  P.nbands = nbands;
+  P.flags = flags;
+  P.atoms.resize(natoms);
+  P.support_centre.assign(pos, pos + 3 * (size_t)natoms);
+  P.coeff_off.resize(natoms + 1);
+  P.coeff_off[0] = 0;
+
+  for (int32_t a = 0; a < natoms; ++a) {
+    const double *c = pos + 3 * a;
+    const double s = sigma[a];
+    const int32_t nu = numax[a];
+    if (!finite3(c) || !(s > 0) || !std::isfinite(s)) {
+      snprintf(buf, sizeof buf, "atom %d: non-finite position or sigma <= 0", a);
+      *msg = buf;
+      return SHO_E_INVALID;
+    }
+    if (nu < 0 || nu > SHO_NU_MAX) {
+      snprintf(buf, sizeof buf, "atom %d: nu_max %d outside 0..%d", a, nu,
+               SHO_NU_MAX);
+      *msg = buf;
+      return SHO_E_NU_RANGE;
+    }
+    // sampling bound, sec. 3.6 eq. max_grid_spacing
+    const double hmax = M_PI * s / std::sqrt(2.0 * nu + 1.0);
+    if (!(flags & SHO_FLAG_ALLOW_UNDERSAMPLED) && h > hmax) {
+      snprintf(buf, sizeof buf,
+               "atom %d: h = %g exceeds pi*sigma/sqrt(2nu+1) = %g", a, h, hmax);
+      *msg = buf;
+      return SHO_E_UNDERSAMPLED;
+    }
+    double R = s * std::sqrt(2.0 * nu + 3.0) + 2.0 * h;
+    if (rbox) {
+      R = rbox[a];
+      if (!(R > 0) || !std::isfinite(R)) {
+        snprintf(buf, sizeof buf, "atom %d: rbox must be positive", a);
+        *msg = buf;
+        return SHO_E_INVALID;
+      }
+    }
+    const double R2 = R * R;
+    // scan ranges that surely contain every member
+    int64_t lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = (int64_t)std::floor((c[d] - R) / h) - 1;
+      hi[d] = (int64_t)std::ceil((c[d] + R) / h) + 1;
+      if (!grid->periodic[d]) {
+        if (lo[d] < 0) lo[d] = 0;
+        if (hi[d] > grid->n[d] - 1) hi[d] = grid->n[d] - 1;
+      }
+      if (hi[d] - lo[d] + 1 > 4 * kMaxTable) {
+        snprintf(buf, sizeof buf, "atom %d: support box too wide", a);
+        *msg = buf;
+        return SHO_E_BOX;
+      }
+    }
+    AtomRec &A = P.atoms[a];
+    A = AtomRec();
+    A.cx = c[0];
+    A.cy = c[1];
+    A.cz = c[2];
+    A.sigma = s;
+    A.nu = nu;
+    A.plane_begin = (int32_t)P.planes.size();
+    A.line_begin = (int32_t)P.lines.size();
+    A.point_begin = P.support_points;
+    int64_t xmin = INT64_MAX, xmax = INT64_MIN, ymin = INT64_MAX,
+            ymax = INT64_MIN, zmin = INT64_MAX, zmax = INT64_MIN;
+    struct RawLine { int64_t z, y, x0, len; };
+    std::vector<RawLine> raw;
+    for (int64_t iz = lo[2]; iz <= hi[2]; ++iz) {
+      const double dz = (double)iz * h - c[2];
+      for (int64_t iy = lo[1]; iy <= hi[1]; ++iy) {
+        const double dy = (double)iy * h - c[1];
+        int64_t x0 = 0, len = 0;
+        for (int64_t ix = lo[0]; ix <= hi[0]; ++ix) {
+          const double dx = (double)ix * h - c[0];
+          double r2 = dx * dx + dy * dy;
+          r2 = r2 + dz * dz;
+          if (r2 <= R2) {
+            if (len == 0) x0 = ix;
+            ++len;
+          } else if (len) {
+            break;  // the members of a line are contiguous (sphere)
+          }
+        }
+        if (!len) continue;
+        raw.push_back({iz, iy, x0, len});
+        xmin = std::min(xmin, x0);
+        xmax = std::max(xmax, x0 + len - 1);
+        ymin = std::min(ymin, iy);
+        ymax = std::max(ymax, iy);
+        zmin = std::min(zmin, iz);
+        zmax = std::max(zmax, iz);
+      }
+    }
+    if (!raw.empty()) {
+      A.ix0 = (int32_t)xmin;
+      A.iy0 = (int32_t)ymin;
+      A.iz0 = (int32_t)zmin;
+      A.mx = (int32_t)(xmax - xmin + 1);
+      A.my = (int32_t)(ymax - ymin + 1);
+      A.mz = (int32_t)(zmax - zmin + 1);
+      if (A.mx > kMaxTable || A.my > kMaxTable || A.mz > kMaxTable) {
+        snprintf(buf, sizeof buf,
+                 "atom %d: support box spans more than %d points per axis", a,
+                 kMaxTable);
+        *msg = buf;
+        return SHO_E_BOX;
+      }
+      P.m_max = std::max(P.m_max, std::max(A.mx, std::max(A.my, A.mz)));
+    }
+    int64_t cur_z = INT64_MIN;
+    for (const RawLine &r : raw) {
+      if (r.z != cur_z) {
+        PlaneRec pl;
+        pl.jz = (int32_t)(r.z - zmin);
+        pl.line_begin = (int32_t)P.lines.size();
+        pl.nlines = 0;
+        pl.npoints = 0;
+        P.planes.push_back(pl);
+        cur_z = r.z;
+      }
+      LineRec L;
+      L.row = wrap_index(r.z, grid->n[2]) * grid->n[1] + wrap_index(r.y, grid->n[1]);
+      L.x0m = wrap_index(r.x0, grid->n[0]);
+      L.jx0 = (int16_t)(r.x0 - xmin);
+      L.jy = (int16_t)(r.y - ymin);
+      L.len = (int32_t)r.len;
+      P.lines.push_back(L);
+      P.planes.back().nlines++;
+      P.planes.back().npoints += (int32_t)r.len;
+      A.npoints += r.len;
+    }
+    if (P.lines.size() > (size_t)std::numeric_limits<int32_t>::max()) {
+      *msg = "too many support lines";
+      return SHO_E_INVALID;
+    }
+    A.nplanes = (int32_t)P.planes.size() - A.plane_begin;
+    A.nlines = (int32_t)P.lines.size() - A.line_begin;
+    A.coeff_row = P.coeff_rows;
+    P.coeff_rows += nsho(nu);
+    P.coeff_off[a + 1] = P.coeff_rows * nbands;
+    P.support_points += A.npoints;
+    P.nu_max = std::max(P.nu_max, nu);
+  }
+  return SHO_OK;
+}
+
+}  // namespace sho
