@@ -43,6 +43,13 @@
  *   ownership the caller owns psi, c, w and grad; the library never frees
  *             them.  Host arrays are copied during the call.  A plan owns its
  *             device tables and frees them in sho_plan_destroy.
+ *   buffers   before a launch every device pointer is checked against the
+ *             HIP runtime's record of the allocation holding it: a host
+ *             pointer, NULL, a range running past the end of that allocation,
+ *             or psi overlapping c is refused with SHO_E_INVALID.  A buffer
+ *             carved out of a larger pool allocation (a caching allocator's
+ *             segment) is only checked against the pool's bounds, so callers
+ *             must still pass buffers of the documented sizes.
  *   errors    every entry point returns a sho_status; on failure
  *             sho_last_error() gives a message (thread-local).  No C++
  *             exception crosses this interface.

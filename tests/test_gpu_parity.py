@@ -124,7 +124,7 @@ def test_isolated_edges_and_empty_support():
 def test_all_nu_values_one_launch_each():
     """Every nu in 0..10 (the force runs at nu+1, up to 11 functions)."""
     bd = _bd()
-    s = wl.make_system("allnu", (30, 28, 26), 0.16, (True,) * 3, 11, None, None, 5,
+    s = wl.make_system("allnu", (30, 28, 26), 0.16, (True,) * 3, 11, None, 0, 5,
                        60, sigma_range=(0.7, 0.9))
     s.numax[:] = np.arange(11)
     run_all(bd, s, psi_in=False)
@@ -176,16 +176,19 @@ def test_argument_errors_on_device():
         p.project(psi.cpu())
     with pytest.raises(ValueError):
         p.project(psi[..., :2].contiguous())
-    # raw calls: a host pointer and a too-small device buffer are refused
+    # raw calls: host pointers, NULL and overlapping buffers are refused
+    # before any launch (the library checks against the runtime's allocation
+    # records; the binding checks exact element counts)
     host = np.zeros(p.coeff_doubles)
     lib = bd.load_library()
     code = lib.sho_plan_project(p._h, ctypes.c_void_p(psi.data_ptr()),
                                 ctypes.c_void_p(host.ctypes.data), None)
     assert code == bd.SHO_E_INVALID
-    small = torch.zeros(10, dtype=torch.float64, device="cuda")
+    code = lib.sho_plan_project(p._h, ctypes.c_void_p(psi.data_ptr()), None, None)
+    assert code == bd.SHO_E_INVALID
     code = lib.sho_plan_project(p._h, ctypes.c_void_p(psi.data_ptr()),
-                                ctypes.c_void_p(small.data_ptr()), None)
-    assert code == bd.SHO_E_INVALID or p.coeff_doubles <= 10
+                                ctypes.c_void_p(psi.data_ptr() + 64), None)
+    assert code == bd.SHO_E_INVALID
     p.close()
 
 
