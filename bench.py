@@ -37,6 +37,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle sample")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="first run a plain 1 GiB elementwise copy kernel (reads 1 GiB, "
+                         "writes 1 GiB) so that profiler byte counters can be scaled")
     return ap.parse_args()
 
 
@@ -109,6 +112,13 @@ def main():
         if ev is not None:
             ev[2].record(stream)
 
+    if args.copy_calib:
+        x = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            torch.mul(x, 1.0, out=y)
+        torch.cuda.synchronize()
+        del x, y
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()

@@ -32,10 +32,8 @@ sho_status hip_fail(hipError_t e, const char *what) {
 
 struct Group {
   int32_t nu;
-  int32_t list_begin;  // into the device atom-list array
-  int32_t count;
-  int32_t mstride;     // largest table extent among these atoms
-  int32_t mstride_f;   // same, used by the derivative (same support)
+  int32_t work_begin;  // into the device work-item array
+  int32_t count;       // work items
 };
 
 }  // namespace
@@ -46,9 +44,10 @@ struct sho_plan_s {
   size_t lds_limit = 0;
   std::vector<Group> groups;
   sho::AtomRec *d_atoms = nullptr;
-  sho::PlaneRec *d_planes = nullptr;
   sho::LineRec *d_lines = nullptr;
-  int32_t *d_list = nullptr;
+  sho::BundleRec *d_bundles = nullptr;
+  sho::WorkRec *d_work = nullptr;
+  double *d_tab = nullptr;
   int64_t device_bytes = 0;
   int64_t stored_bytes = 0;
 };
@@ -68,41 +67,32 @@ hipError_t upload(T **dst, const std::vector<T> &src, int64_t *bytes) {
 
 void free_plan_device(sho_plan_s *p) {
   if (p->d_atoms) (void)hipFree(p->d_atoms);
-  if (p->d_planes) (void)hipFree(p->d_planes);
   if (p->d_lines) (void)hipFree(p->d_lines);
-  if (p->d_list) (void)hipFree(p->d_list);
+  if (p->d_bundles) (void)hipFree(p->d_bundles);
+  if (p->d_work) (void)hipFree(p->d_work);
+  if (p->d_tab) (void)hipFree(p->d_tab);
   p->d_atoms = nullptr;
-  p->d_planes = nullptr;
   p->d_lines = nullptr;
-  p->d_list = nullptr;
+  p->d_bundles = nullptr;
+  p->d_work = nullptr;
+  p->d_tab = nullptr;
 }
 
-// Bands per line slot: a power of two <= 64 covering nbands when possible,
-// reduced until a workgroup's LDS fits.
-int choose_tb_shift(int nbands, int nf, int mstride, size_t lds_limit) {
-  int shift = 0;
-  while ((1 << shift) < nbands && shift < 6) ++shift;
-  while (shift > 0 && sho::lds_bytes(nf, mstride, 1 << shift) > lds_limit) --shift;
-  if (sho::lds_bytes(nf, mstride, 1 << shift) > lds_limit) return -1;
-  return shift;
-}
-
-sho::KArgs make_args(const sho_plan_s *p, const Group &g, int nf,
-                     int tb_shift) {
+sho::KArgs make_args(const sho_plan_s *p, const Group &g) {
   sho::KArgs K;
   K.atoms = p->d_atoms;
-  K.planes = p->d_planes;
   K.lines = p->d_lines;
-  K.atom_list = p->d_list + g.list_begin;
-  K.nlist = g.count;
+  K.bundles = p->d_bundles;
+  K.work = p->d_work + g.work_begin;
+  K.tab = p->d_tab;
+  K.nwork = g.count;
   K.nx = p->hp.grid.n[0];
   K.B = p->hp.nbands;
-  K.tb_shift = tb_shift;
-  K.ntiles = (p->hp.nbands + (1 << tb_shift) - 1) >> tb_shift;
-  K.mstride = std::max(g.mstride, 1);
-  K.h = p->hp.grid.h;
-  K.h3 = K.h * K.h * K.h;
-  (void)nf;
+  K.tb_shift = p->hp.tb_shift;
+  K.ntiles = (p->hp.nbands + (1 << K.tb_shift) - 1) >> K.tb_shift;
+  K.pad = 0;
+  const double h = p->hp.grid.h;
+  K.h3 = h * h * h;
   return K;
 }
 
@@ -165,6 +155,13 @@ sho_status sho_plan_create(const sho_grid *grid, int32_t natoms,
     return fail(st, msg);
   }
   if (flags & SHO_FLAG_HOST_ONLY) {
+    // geometry and sizes only; work split as for a 64 KiB workgroup LDS
+    const int tbs = sho::choose_tb_shift(nbands, p->hp.nu_max, 65536 - 1024);
+    if (tbs < 0) {
+      delete p;
+      return fail(SHO_E_BOX, "coefficient tile too large for the workgroup LDS");
+    }
+    sho::build_work(&p->hp, tbs, sho::kTargetPoints);
     *out = p;
     return SHO_OK;
   }
@@ -181,36 +178,46 @@ sho_status sho_plan_create(const sho_grid *grid, int32_t natoms,
     return hip_fail(e, "hipDeviceGetAttribute");
   }
   p->lds_limit = (size_t)std::max(shm - 1024, 0);  // static LDS of the kernels
-
-  // group atoms by nu (one launch per group)
-  std::vector<int32_t> list;
-  for (int nu = 0; nu <= SHO_NU_MAX; ++nu) {
-    Group g{nu, (int32_t)list.size(), 0, 0, 0};
-    for (int32_t a = 0; a < p->hp.natoms; ++a) {
-      const sho::AtomRec &A = p->hp.atoms[a];
-      if (A.nu != nu || A.npoints == 0) continue;
-      list.push_back(a);
-      g.count++;
-      g.mstride = std::max(g.mstride, std::max(A.mx, std::max(A.my, A.mz)));
-    }
-    g.mstride_f = g.mstride;
-    if (g.count) {
-      if (choose_tb_shift(1, nu + 2, g.mstride, p->lds_limit) < 0) {
-        delete p;
-        return fail(SHO_E_BOX, "support box too wide for the on-chip tables");
-      }
-      p->groups.push_back(g);
-    }
+  const int tbs = sho::choose_tb_shift(nbands, p->hp.nu_max, p->lds_limit);
+  if (tbs < 0) {
+    delete p;
+    return fail(SHO_E_BOX, "coefficient tile too large for the workgroup LDS");
   }
+  sho::build_work(&p->hp, tbs, sho::kTargetPoints);
+
+  // group work items by nu (one launch per group); items are sorted by nu
+  const auto &work = p->hp.work;
+  for (size_t i = 0; i < work.size();) {
+    const int32_t nu = p->hp.atoms[work[i].atom].nu;
+    Group g{nu, (int32_t)i, 0};
+    while (i < work.size() && p->hp.atoms[work[i].atom].nu == nu) {
+      g.count++;
+      ++i;
+    }
+    p->groups.push_back(g);
+  }
+  std::vector<double> no_tab;
   if ((e = upload(&p->d_atoms, p->hp.atoms, &p->device_bytes)) != hipSuccess ||
-      (e = upload(&p->d_planes, p->hp.planes, &p->device_bytes)) != hipSuccess ||
       (e = upload(&p->d_lines, p->hp.lines, &p->device_bytes)) != hipSuccess ||
-      (e = upload(&p->d_list, list, &p->device_bytes)) != hipSuccess) {
+      (e = upload(&p->d_bundles, p->hp.bundles, &p->device_bytes)) != hipSuccess ||
+      (e = upload(&p->d_work, p->hp.work, &p->device_bytes)) != hipSuccess ||
+      (e = hipMalloc((void **)&p->d_tab,
+                     std::max<int64_t>(p->hp.table_doubles, 1) * sizeof(double))) !=
+          hipSuccess) {
     free_plan_device(p);
     delete p;
     (void)hipGetLastError();
     return e == hipErrorOutOfMemory ? fail(SHO_E_NOMEM, "device allocation failed")
                                     : hip_fail(e, "plan upload");
+  }
+  p->device_bytes += std::max<int64_t>(p->hp.table_doubles, 1) * sizeof(double);
+  e = sho::launch_tables(p->d_atoms, p->hp.natoms, p->hp.grid.h, p->d_tab, p->hp.m_max,
+                         nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    free_plan_device(p);
+    delete p;
+    return hip_fail(e, "table sampling");
   }
   *out = p;
   return SHO_OK;
@@ -280,6 +287,9 @@ sho_status sho_plan_set_centres(sho_plan_t p, const double *pos, void *stream) {
   hipError_t e = hipMemcpyAsync(p->d_atoms, p->hp.atoms.data(),
                                 p->hp.atoms.size() * sizeof(sho::AtomRec),
                                 hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = sho::launch_tables(p->d_atoms, p->hp.natoms, p->hp.grid.h, p->d_tab,
+                           p->hp.m_max, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "centre upload");
   return SHO_OK;
@@ -297,16 +307,16 @@ sho_status sho_plan_project(sho_plan_t p, const double *psi, double *c,
       (const char *)psi < (const char *)c + coeff_bytes(p))
     return fail(SHO_E_INVALID, "psi and c overlap");
   hipStream_t s = (hipStream_t)stream;
-  // atoms whose support missed the grid entirely keep zero coefficients
-  bool empty = false;
+  // atoms whose support missed the grid entirely keep zero coefficients;
+  // atoms shared by several work items are summed into zeroed coefficients
+  bool empty = p->hp.any_split;
   for (const auto &A : p->hp.atoms) empty |= (A.npoints == 0);
   if (empty) {
     hipError_t e = sho::launch_fill(c, p->hp.coeff_rows * p->hp.nbands, 0.0, s);
     if (e != hipSuccess) return hip_fail(e, "fill");
   }
   for (const Group &g : p->groups) {
-    const int tbs = choose_tb_shift(p->hp.nbands, g.nu + 1, g.mstride, p->lds_limit);
-    sho::KArgs K = make_args(p, g, g.nu + 1, tbs);
+    sho::KArgs K = make_args(p, g);
     hipError_t e = sho::launch_project(g.nu, K, psi, c, s);
     if (e != hipSuccess) return hip_fail(e, "project launch");
   }
@@ -326,8 +336,7 @@ sho_status sho_plan_expand(sho_plan_t p, const double *c, double *psi,
     return fail(SHO_E_INVALID, "psi and c overlap");
   hipStream_t s = (hipStream_t)stream;
   for (const Group &g : p->groups) {
-    const int tbs = choose_tb_shift(p->hp.nbands, g.nu + 1, g.mstride, p->lds_limit);
-    sho::KArgs K = make_args(p, g, g.nu + 1, tbs);
+    sho::KArgs K = make_args(p, g);
     hipError_t e = sho::launch_expand(g.nu, K, c, psi, s);
     if (e != hipSuccess) return hip_fail(e, "expand launch");
   }
@@ -347,8 +356,7 @@ sho_status sho_plan_force(sho_plan_t p, const double *psi, const double *w,
   hipError_t e = sho::launch_fill(grad, 3 * (int64_t)p->hp.natoms, 0.0, s);
   if (e != hipSuccess) return hip_fail(e, "fill");
   for (const Group &g : p->groups) {
-    const int tbs = choose_tb_shift(p->hp.nbands, g.nu + 2, g.mstride, p->lds_limit);
-    sho::KArgs K = make_args(p, g, g.nu + 2, tbs);
+    sho::KArgs K = make_args(p, g);
     e = sho::launch_force(g.nu, K, psi, w, grad, s);
     if (e != hipSuccess) return hip_fail(e, "force launch");
   }

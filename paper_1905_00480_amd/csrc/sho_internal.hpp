@@ -2,10 +2,13 @@
 // layer and the gfx950 kernels of libsho.so.
 //
 // A plan cuts every atom's support sphere into z planes and each plane into
-// (z, y) lines; each line is one contiguous run of x points, i.e. one
-// contiguous run of x*nbands doubles of psi in memory.  Kernels stream the
-// lines from HBM, contract x, y and z in turn (the factorised Cartesian basis
-// of sec. 2.2) and never materialise a 3D projector.
+// (z, y) lines; a line is stored as one or two runs (cut where it crosses the
+// periodic x boundary), each one contiguous block of psi.  Runs of one plane
+// are grouped into bundles that one wavefront streams together, one run per
+// lane slot.  Kernels contract x, y and z in turn (the factorised Cartesian
+// basis of sec. 2.2) and never materialise a 3D projector; the 1D functions
+// of every atom are sampled into small tables (the Tucker factors of
+// sec. 3.4) that the kernels read through the scalar cache.
 #pragma once
 
 #include <cstdint>
@@ -26,32 +29,67 @@ struct AtomRec {
   int32_t mx, my, mz;    // table extents per axis
   int32_t plane_begin;   // first plane record of this atom
   int32_t nplanes;
-  int32_t line_begin;    // first line record of this atom
-  int32_t nlines;
-  int32_t pad0;
+  int32_t line_begin;    // first run record of this atom
+  int32_t nlines;        // runs of this atom
+  int32_t tab_nfp;       // row stride of the 1D tables (doubles)
   int64_t coeff_row;     // sum of N_SHO(nu) over earlier atoms
   int64_t npoints;       // |S_a|
-  int64_t point_begin;   // first support point (line order) of this atom
+  int64_t tab_off;       // first double of this atom's 1D tables
 };
 static_assert(sizeof(AtomRec) == 104, "AtomRec layout");
+
+// 1D tables of one atom: rows [x: mx][y: my][z: mz], row j of an axis holds
+// phi_0..phi_{nf-1} at that grid index, padded with zeros to tab_nfp doubles.
+// nf = nu + 2 (the derivative needs one function more than the basis).
+inline int32_t table_nf(int32_t nu) { return nu + 2; }
+inline int32_t table_nfp(int32_t nu) { return table_nf(nu) <= 8 ? 8 : 16; }
 
 // One z plane of one atom's support.
 struct PlaneRec {
   int32_t jz;          // table index along z
-  int32_t line_begin;  // absolute index of the plane's first line
+  int32_t line_begin;  // absolute index of the plane's first run
   int32_t nlines;
   int32_t npoints;
 };
 
-// One (z, y) line: points x0 .. x0+len-1 (unwrapped) of memory row `row`.
+// One run of a (z, y) line: points x0 .. x0+len-1 (unwrapped) of memory row
+// `row`.  Runs never cross the periodic x boundary, so a run is one
+// contiguous block of len*nbands doubles of psi.
 struct LineRec {
   int32_t row;   // (z mod nz) * ny + (y mod ny)
-  int32_t x0m;   // x0 mod nx: memory x of the first point
+  int32_t x0m;   // memory x of the first point (x0 mod nx)
   int16_t jx0;   // table index of the first point along x
   int16_t jy;    // table index along y
-  int32_t len;   // number of points
+  int16_t jz;    // table index along z (identifies the plane)
+  int16_t len;   // number of points
 };
 static_assert(sizeof(LineRec) == 16, "LineRec layout");
+
+// Up to `slots` runs of one atom plane, streamed together by one wavefront:
+// the wave walks the table index jx over [jlo, jhi] (the union of the runs'
+// x ranges) so that phi_x(jx) is the same for every lane.
+struct BundleRec {
+  int32_t run0;   // first run; slot s takes run0 + s
+  int16_t nruns;  // runs in this bundle (<= slots)
+  int16_t jz;     // plane (table index along z)
+  int16_t jlo;    // union of the runs' table ranges along x
+  int16_t jhi;
+  int32_t pad;
+};
+static_assert(sizeof(BundleRec) == 16, "BundleRec layout");
+
+// Waves per workgroup of the streaming kernels.
+constexpr int kWaves = 8;
+
+// One workgroup's share of an atom: a contiguous range of its bundles, cut
+// into kWaves cost-balanced wave ranges.  `split` is set when the atom is
+// shared by several work items (their partial results are added).
+struct WorkRec {
+  int32_t atom;
+  int32_t split;
+  int32_t wb[kWaves + 1];  // wave w takes bundles [wb[w], wb[w+1])
+};
+static_assert(sizeof(WorkRec) == 4 * (kWaves + 3), "WorkRec layout");
 
 // Host-side plan contents (built without any device call).
 struct HostPlan {
@@ -60,28 +98,51 @@ struct HostPlan {
   int32_t nbands = 0;
   uint32_t flags = 0;
   int32_t nu_max = 0;
-  int32_t m_max = 0;  // largest table extent over atoms and axes
+  int32_t m_max = 0;     // largest table extent over atoms and axes
+  int32_t tb_shift = 0;  // log2(bands per lane slot)
   std::vector<AtomRec> atoms;
   std::vector<PlaneRec> planes;
   std::vector<LineRec> lines;
+  std::vector<BundleRec> bundles;
+  std::vector<WorkRec> work;           // sorted by nu, then atom
   std::vector<double> support_centre;  // [natoms][3], fixed at creation
   std::vector<int64_t> coeff_off;      // [natoms+1] in doubles
   int64_t coeff_rows = 0;
   int64_t support_points = 0;
+  int64_t table_doubles = 0;           // size of the 1D table buffer
+  bool any_split = false;
 };
 
 inline int32_t nsho(int32_t nu) {
   return nu < 0 ? 0 : (nu + 1) * (nu + 2) * (nu + 3) / 6;
 }
 
-// Builds the host plan; returns SHO_OK or an error code with *msg set.
+// Builds the host plan geometry (supports, runs, tables layout); returns
+// SHO_OK or an error code with *msg set.
 sho_status build_host_plan(const sho_grid *grid, int32_t natoms,
                            const double *pos, const double *sigma,
                            const int32_t *numax, const double *rbox,
                            int32_t nbands, uint32_t flags, HostPlan *out,
                            std::string *msg);
 
+// LDS bytes of a workgroup: a [N_SHO(nf-1)][tb] coefficient tile.
+inline size_t lds_tile_bytes(int nf, int tb) {
+  return (size_t)nf * (nf + 1) * (nf + 2) / 6 * tb * sizeof(double);
+}
+
+// Bands per lane slot (log2) for a workgroup LDS budget of `lds_limit`
+// bytes: the derivative's tile at nu_max + 1 must fit.  -1 if even one band
+// per slot does not.
+int choose_tb_shift(int nbands, int nu_max, size_t lds_limit);
+
+// Bundles (with 64 >> tb_shift slots) and work items: atoms of more than
+// `target_points` support points are shared by several workgroups.
+void build_work(HostPlan *P, int tb_shift, int64_t target_points);
+
 // Largest table extent the kernels accept per axis.
 constexpr int32_t kMaxTable = 512;
+
+// Support points per work item before an atom is shared by workgroups.
+constexpr int64_t kTargetPoints = 16384;
 
 }  // namespace sho

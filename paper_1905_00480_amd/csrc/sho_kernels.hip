@@ -1,185 +1,318 @@
 // sho_kernels.hip -- gfx950 kernels for SHO projection, expansion and the
 // position derivative (Baumeister & Tsukamoto, PASC'19).
 //
-// Work decomposition (one launch per distinct nu in a plan):
-//   * one workgroup (8 wave64) per (atom, band tile);
-//   * the tile's bands are the lanes: lane = (line slot, band), TB bands per
-//     slot, 64/TB line slots per wave (band index is fastest in memory, so a
-//     slot's loads of one grid point are one coalesced TB*8-byte run);
-//   * waves take the atom's z planes round robin; inside a plane the slots take
-//     lines round robin.
+// Work decomposition
+//   * grid = (work items, band tiles); a work item is one atom, or a share of
+//     a large atom, cut into kWaves cost-balanced ranges of run bundles;
+//   * one workgroup = kWaves wave64; wave w streams its own bundles;
+//   * lane = (slot, band): TB bands per slot, 64/TB slots per wave, slot s
+//     takes run s of the bundle.  All runs of a bundle lie in one atom plane
+//     and the wave steps the table index jx over the union of their x ranges,
+//     so phi_x(jx) is wave-uniform and is read through the scalar cache.  A
+//     run is one contiguous block of psi (band index fastest): each load
+//     instruction reads TB*8 contiguous bytes per slot.
 //
-// Projection (sec. 3.2 step 1 in the factorised basis of sec. 2.2):
-//   x pass  T1[nx]     = sum_x phi_nx(x) psi(x,y,z)       registers, streams HBM
-//   y pass  T2[nx][ny] = sum_y phi_ny(y) T1[nx]           registers
-//   z pass  C[nx,ny,nz]+= phi_nz(z) T2[nx][ny]            LDS tile, ds_add_f64
-// Expansion (step 3) runs the same passes backwards and adds into psi with
+// Projection (sec. 3.2 step 1, in the factorised basis of sec. 2.2):
+//   x pass  T1[nx]      = sum_x phi_nx(x) psi(x,y,z)   registers, streams HBM
+//   y pass  T2[nx][ny] += phi_ny(y) T1[nx]            registers
+//   z pass  C[nx,ny,nz] += phi_nz(z) T2[nx][ny]       at each plane change:
+//                                                     slots folded, LDS tile
+// Expansion (step 3) runs the passes backwards and adds into psi with
 // global_atomic_add_f64 (supports of different atoms overlap).
-// The 1D functions are sampled per workgroup into LDS by the normalised
-// three-term recurrence (the monic recurrence of sec. 3.7 rescaled so that
-// every phi_n has unit L2 norm), once per atom and axis.
+// The 1D functions are sampled once per plan into small per-atom tables by
+// the normalised three-term recurrence (the monic recurrence of sec. 3.7
+// rescaled so that every phi_n has unit L2 norm).
 #include <hip/hip_runtime.h>
 
 #include "sho_launch.hpp"
 
 namespace sho {
 
+constexpr int kBlock = 64 * kWaves;
+constexpr int kBatch = 8;  // loads in flight per lane and batch
 
+// waves per SIMD the register allocator must allow (4 keeps <= 128 VGPRs)
+constexpr int waves_per_eu(int nf) { return nf <= 6 ? 4 : 2; }
 
-constexpr int kBlock = 512;
+// Read-only data that every lane of a wave reads at the same address goes
+// through the constant address space, i.e. scalar loads.
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T *;
+
+template <typename T>
+__device__ inline cptr<T> as_const(const T *p) {
+  return (cptr<T>)p;
+}
+
+// Copies a record that all lanes read at the same address (scalar loads).
+template <typename T>
+__device__ inline T load_uniform(const T *p) {
+  static_assert(sizeof(T) % 4 == 0, "record size");
+  T out;
+  const cptr<uint32_t> src = (cptr<uint32_t>)p;
+  uint32_t *dst = reinterpret_cast<uint32_t *>(&out);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) dst[i] = src[i];
+  return out;
+}
 
 // ---------------------------------------------------------------- tables --
 
-// tab[(axis*mstride + j)*NF + n] = phi_n(u) at u = (i0_axis + j)*h - centre.
+// Row j of axis d of atom a: phi_n(u), u = (i0_d + j)*h - centre_d, for
+// n < nu+2, then zeros up to the row stride.
 // phi_0 = pi^{-1/4} sigma^{-1/2} e^{-t^2/2}, phi_1 = sqrt(2) t phi_0,
 // phi_{n+1} = sqrt(2/(n+1)) t phi_n - sqrt(n/(n+1)) phi_{n-1},  t = u/sigma.
-template <int NF>
-__device__ inline void fill_tables(const AtomRec &A, const KArgs &K,
-                                   double *tab) {
+__global__ __launch_bounds__(256) void k_tables(const AtomRec *__restrict__ atoms,
+                                                double h, double *__restrict__ tab) {
+  const AtomRec A = atoms[blockIdx.x];
+  const int nf = A.nu + 2;
+  const int nfp = A.tab_nfp;
+  const int rows = A.mx + A.my + A.mz;
   const double inv_s = 1.0 / A.sigma;
   const double p0 = 0.7511255444649425 * sqrt(inv_s);
-#pragma unroll
-  for (int axis = 0; axis < 3; ++axis) {
-    const int i0 = axis == 0 ? A.ix0 : (axis == 1 ? A.iy0 : A.iz0);
-    const double c = axis == 0 ? A.cx : (axis == 1 ? A.cy : A.cz);
-    for (int j = threadIdx.x; j < K.mstride; j += blockDim.x) {
-      const double u = (double)(i0 + j) * K.h - c;
-      const double x = u * inv_s;
-      double *row = tab + ((size_t)axis * K.mstride + j) * NF;
-      double fm = 0.0;
-      double f = p0 * exp(-0.5 * x * x);
-      row[0] = f;
-#pragma unroll
-      for (int n = 0; n + 1 < NF; ++n) {
-        const double fn = sqrt(2.0 / (n + 1)) * x * f - sqrt((double)n / (n + 1)) * fm;
-        fm = f;
-        f = fn;
-        row[n + 1] = f;
-      }
+  for (int r = threadIdx.x; r < rows; r += blockDim.x) {
+    int i;
+    double c;
+    if (r < A.mx) {
+      i = A.ix0 + r;
+      c = A.cx;
+    } else if (r < A.mx + A.my) {
+      i = A.iy0 + (r - A.mx);
+      c = A.cy;
+    } else {
+      i = A.iz0 + (r - A.mx - A.my);
+      c = A.cz;
     }
+    const double x = ((double)i * h - c) * inv_s;
+    double *row = tab + A.tab_off + (int64_t)r * nfp;
+    double fm = 0.0;
+    double f = p0 * exp(-0.5 * x * x);
+    row[0] = f;
+    for (int n = 0; n + 1 < nf; ++n) {
+      const double fn = sqrt(2.0 / (n + 1)) * x * f - sqrt((double)n / (n + 1)) * fm;
+      fm = f;
+      f = fn;
+      row[n + 1] = f;
+    }
+    for (int n = nf; n < nfp; ++n) row[n] = 0.0;
   }
 }
 
-// ------------------------------------------------------- projection core --
+// ------------------------------------------------------------- lane state --
 
-// Accumulates sum_{i in S_a} P_an(i) psi(i) (no h^3) for the workgroup's
-// band tile into cacc[n*TB + bl] (LDS, zeroed by the caller).
+struct Lanes {
+  int slot;  // run slot of this lane
+  int TB;    // bands per slot
+  int bl;    // band within the tile
+  bool bok;  // band exists
+  int bc;    // band used for addressing (clamped into range)
+};
+
+__device__ inline Lanes lane_geometry(const KArgs &K, int tile) {
+  Lanes L;
+  const int lane = threadIdx.x & 63;
+  L.TB = 1 << K.tb_shift;
+  L.slot = lane >> K.tb_shift;
+  L.bl = lane & (L.TB - 1);
+  const int b = tile * L.TB + L.bl;
+  L.bok = b < K.B;
+  L.bc = L.bok ? b : K.B - 1;
+  return L;
+}
+
+__device__ inline int wave_id() {
+  return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+}
+
+// The run a lane streams in the current bundle.  Slots beyond the bundle's
+// run count mirror its last run (valid addresses) and contribute nothing.
+struct RunState {
+  const double *base;  // psi at the run's first point, this lane's band
+  int jx0;             // table index of the first point
+  int len;
+  int jy;
+  bool active;
+};
+
+__device__ inline RunState run_state(const KArgs &K, const Lanes &L,
+                                     const double *psi, const BundleRec &bd) {
+  const int s = min(L.slot, bd.nruns - 1);
+  const LineRec ln = K.lines[bd.run0 + s];
+  RunState r;
+  r.base = psi + ((int64_t)ln.row * K.nx + ln.x0m) * K.B + L.bc;
+  r.jx0 = ln.jx0;
+  r.len = ln.len;
+  r.jy = ln.jy;
+  r.active = L.slot < bd.nruns;
+  return r;
+}
+
+// Issues kBatch loads: table indices jb .. jb+kBatch-1 of the lane's run,
+// clamped into the run (the clamped copies get zero weight).
+__device__ inline void load_batch(const KArgs &K, const RunState &r, int jb,
+                                  double *v) {
+#pragma unroll
+  for (int u = 0; u < kBatch; ++u) {
+    const int k = min(max(jb + u - r.jx0, 0), r.len - 1);
+    v[u] = r.base[k * K.B];
+  }
+}
+
+// z pass of the projection for one plane: fold the slots (same band,
+// different runs of the plane), then C[n] += phi_nz(z) T2[nx][ny].
 template <int NU>
-__device__ inline void project_core(const KArgs &K, const AtomRec &A,
-                                    int tile, const double *__restrict__ psi,
-                                    const double *tab, double *cacc) {
+__device__ inline void flush_plane(cptr<double> fz, double *T2, double *cacc,
+                                   const Lanes &L) {
   constexpr int NF = NU + 1;
   constexpr int NP = NF * (NF + 1) / 2;
-  const int TB = 1 << K.tb_shift;
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int nwaves = blockDim.x >> 6;
-  const int slot = lane >> K.tb_shift;
-  const int lpw = 64 >> K.tb_shift;
-  const int bl = lane & (TB - 1);
-  const int b = tile * TB + bl;
-  const bool bok = b < K.B;
-  const double *phx = tab;
-  const double *phy = tab + (size_t)K.mstride * NF;
-  const double *phz = tab + (size_t)2 * K.mstride * NF;
-  const int64_t rowlen = (int64_t)K.nx * K.B;
-
-  for (int p = wave; p < A.nplanes; p += nwaves) {
-    const PlaneRec pl = K.planes[A.plane_begin + p];
-    double T2[NP];
+  for (int s = 32; s >= L.TB; s >>= 1) {
 #pragma unroll
-    for (int q = 0; q < NP; ++q) T2[q] = 0.0;
-    for (int l = slot; l < pl.nlines; l += lpw) {
-      const LineRec ln = K.lines[pl.line_begin + l];
-      double T1[NF];
+    for (int q = 0; q < NP; ++q) T2[q] += __shfl_xor(T2[q], s);
+  }
+  if (L.slot == 0 && L.bok) {
+    int idx = 0;
 #pragma unroll
-      for (int n = 0; n < NF; ++n) T1[n] = 0.0;
-      const double *src = psi + (int64_t)ln.row * rowlen + b;
-      const double *fx = phx + (int)ln.jx0 * NF;
-      int xm = ln.x0m;
-#pragma unroll 4
-      for (int k = 0; k < ln.len; ++k) {
-        const double v = bok ? src[(int64_t)xm * K.B] : 0.0;
-#pragma unroll
-        for (int n = 0; n < NF; ++n) T1[n] = fma(fx[k * NF + n], v, T1[n]);
-        xm = (xm + 1 == K.nx) ? 0 : xm + 1;
-      }
-      const double *fy = phy + (int)ln.jy * NF;
+    for (int nz = 0; nz < NF; ++nz) {
+      const double f = fz[nz];
       int q = 0;
 #pragma unroll
       for (int ny = 0; ny < NF; ++ny) {
-        const double f = fy[ny];
 #pragma unroll
-        for (int nx = 0; nx < NF - ny; ++nx, ++q) T2[q] = fma(f, T1[nx], T2[q]);
-      }
-    }
-    // fold the line slots of this wave (same band, different lines)
-    for (int s = 32; s >= TB; s >>= 1) {
-#pragma unroll
-      for (int q = 0; q < NP; ++q) T2[q] += __shfl_xor(T2[q], s);
-    }
-    if (slot == 0 && bok) {
-      const double *fz = phz + pl.jz * NF;
-      int idx = 0;
-#pragma unroll
-      for (int nz = 0; nz < NF; ++nz) {
-        const double f = fz[nz];
-        int q = 0;
-#pragma unroll
-        for (int ny = 0; ny < NF; ++ny) {
-#pragma unroll
-          for (int nx = 0; nx < NF - ny; ++nx, ++q) {
-            if (nx + ny + nz <= NU) {
-              atomicAdd(&cacc[idx * TB + bl], f * T2[q]);
-              ++idx;
-            }
+        for (int nx = 0; nx < NF - ny; ++nx, ++q) {
+          if (nx + ny + nz <= NU) {
+            atomicAdd(&cacc[idx * L.TB + L.bl], f * T2[q]);
+            ++idx;
           }
         }
       }
     }
   }
+#pragma unroll
+  for (int q = 0; q < NP; ++q) T2[q] = 0.0;
+}
+
+// ------------------------------------------------------- projection core --
+
+// Adds sum over the runs of bundles [b0,b1) of P_n(i) psi(i) (no h^3), for
+// the workgroup's band tile, into cacc[n*TB + bl] (LDS).  One batch of loads
+// is always in flight while the previous one is contracted.
+template <int NU>
+__device__ inline void project_bundles(const KArgs &K, const AtomRec &A,
+                                       const Lanes &L, int b0, int b1,
+                                       const double *__restrict__ psi,
+                                       double *cacc) {
+  constexpr int NF = NU + 1;
+  constexpr int NP = NF * (NF + 1) / 2;
+  if (b0 >= b1) return;
+  const int nfp = A.tab_nfp;
+  const cptr<double> tx = as_const(K.tab) + A.tab_off;
+  const double *ty = K.tab + A.tab_off + (int64_t)A.mx * nfp;
+  const cptr<double> tz = tx + (int64_t)(A.mx + A.my) * nfp;
+
+  double T2[NP];
+#pragma unroll
+  for (int q = 0; q < NP; ++q) T2[q] = 0.0;
+  int cur_jz = -1;
+  BundleRec bd = load_uniform(K.bundles + b0);
+  RunState rs = run_state(K, L, psi, bd);
+  double v[kBatch];
+  load_batch(K, rs, bd.jlo, v);
+  for (int bi = b0; bi < b1; ++bi) {
+    if (bd.jz != cur_jz) {
+      if (cur_jz >= 0) flush_plane<NU>(tz + cur_jz * nfp, T2, cacc, L);
+      cur_jz = bd.jz;
+    }
+    double T1[NF];
+#pragma unroll
+    for (int n = 0; n < NF; ++n) T1[n] = 0.0;
+    BundleRec nbd = bd;
+    RunState nrs = rs;
+    for (int jb = bd.jlo; jb <= bd.jhi; jb += kBatch) {
+      double w[kBatch];
+      if (jb + kBatch <= bd.jhi) {
+        load_batch(K, rs, jb + kBatch, w);
+      } else if (bi + 1 < b1) {
+        nbd = load_uniform(K.bundles + bi + 1);
+        nrs = run_state(K, L, psi, nbd);
+        load_batch(K, nrs, nbd.jlo, w);
+      } else {
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) w[u] = 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        const int jx = jb + u;
+        if (jx <= bd.jhi) {
+          const int k = jx - rs.jx0;
+          const bool ok = rs.active && k >= 0 && k < rs.len;
+          const double xv = ok ? v[u] : 0.0;
+          const cptr<double> f = tx + jx * nfp;
+#pragma unroll
+          for (int n = 0; n < NF; ++n) T1[n] = fma(f[n], xv, T1[n]);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) v[u] = w[u];
+    }
+    // y pass with this lane's run
+    const double *fy = ty + rs.jy * nfp;
+    int q = 0;
+#pragma unroll
+    for (int ny = 0; ny < NF; ++ny) {
+      const double fv = fy[ny];
+#pragma unroll
+      for (int nx = 0; nx < NF - ny; ++nx, ++q) T2[q] = fma(fv, T1[nx], T2[q]);
+    }
+    bd = nbd;
+    rs = nrs;
+  }
+  flush_plane<NU>(tz + cur_jz * nfp, T2, cacc, L);
 }
 
 template <int NU>
-__global__ __launch_bounds__(kBlock) void k_project(
+__global__ __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(waves_per_eu(NU + 1)))) void k_project(
     KArgs K, const double *__restrict__ psi, double *__restrict__ c) {
   constexpr int NF = NU + 1;
   constexpr int NS = NF * (NF + 1) * (NF + 2) / 6;
-  extern __shared__ double lds[];
-  const int ia = blockIdx.x / K.ntiles;
-  const int tile = blockIdx.x - ia * K.ntiles;
-  const AtomRec A = K.atoms[K.atom_list[ia]];
+  extern __shared__ double cacc[];
+  const cptr<WorkRec> W = as_const(K.work) + blockIdx.x;
+  const int tile = blockIdx.y;
+  const AtomRec A = load_uniform(K.atoms + W->atom);
   const int TB = 1 << K.tb_shift;
-  double *tab = lds;
-  double *cacc = lds + (size_t)3 * K.mstride * NF;
-  fill_tables<NF>(A, K, tab);
   for (int t = threadIdx.x; t < NS * TB; t += blockDim.x) cacc[t] = 0.0;
   __syncthreads();
-  project_core<NU>(K, A, tile, psi, tab, cacc);
+  const int w = wave_id();
+  const Lanes L = lane_geometry(K, tile);
+  project_bundles<NU>(K, A, L, W->wb[w], W->wb[w + 1], psi, cacc);
   __syncthreads();
+  const bool split = W->split != 0;
   for (int t = threadIdx.x; t < NS * TB; t += blockDim.x) {
     const int n = t >> K.tb_shift;
     const int bb = tile * TB + (t & (TB - 1));
-    if (bb < K.B) c[(A.coeff_row + n) * K.B + bb] = K.h3 * cacc[t];
+    if (bb >= K.B) continue;
+    double *dst = c + (A.coeff_row + n) * K.B + bb;
+    if (split)
+      unsafeAtomicAdd(dst, K.h3 * cacc[t]);
+    else
+      *dst = K.h3 * cacc[t];
   }
 }
 
 // -------------------------------------------------------------- expansion --
 
 template <int NU>
-__global__ __launch_bounds__(kBlock) void k_expand(
+__global__ __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(waves_per_eu(NU + 1)))) void k_expand(
     KArgs K, const double *__restrict__ c, double *psi) {
   constexpr int NF = NU + 1;
   constexpr int NP = NF * (NF + 1) / 2;
   constexpr int NS = NF * (NF + 1) * (NF + 2) / 6;
-  extern __shared__ double lds[];
-  const int ia = blockIdx.x / K.ntiles;
-  const int tile = blockIdx.x - ia * K.ntiles;
-  const AtomRec A = K.atoms[K.atom_list[ia]];
+  extern __shared__ double cin[];
+  const cptr<WorkRec> W = as_const(K.work) + blockIdx.x;
+  const int tile = blockIdx.y;
+  const AtomRec A = load_uniform(K.atoms + W->atom);
   const int TB = 1 << K.tb_shift;
-  double *tab = lds;
-  double *cin = lds + (size_t)3 * K.mstride * NF;
-  fill_tables<NF>(A, K, tab);
   for (int t = threadIdx.x; t < NS * TB; t += blockDim.x) {
     const int n = t >> K.tb_shift;
     const int bb = tile * TB + (t & (TB - 1));
@@ -187,69 +320,69 @@ __global__ __launch_bounds__(kBlock) void k_expand(
   }
   __syncthreads();
 
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int nwaves = blockDim.x >> 6;
-  const int slot = lane >> K.tb_shift;
-  const int lpw = 64 >> K.tb_shift;
-  const int bl = lane & (TB - 1);
-  const int b = tile * TB + bl;
-  const bool bok = b < K.B;
-  const double *phx = tab;
-  const double *phy = tab + (size_t)K.mstride * NF;
-  const double *phz = tab + (size_t)2 * K.mstride * NF;
-  const int64_t rowlen = (int64_t)K.nx * K.B;
+  const int w = wave_id();
+  const Lanes L = lane_geometry(K, tile);
+  const int nfp = A.tab_nfp;
+  const cptr<double> tx = as_const(K.tab) + A.tab_off;
+  const double *ty = K.tab + A.tab_off + (int64_t)A.mx * nfp;
+  const cptr<double> tz = tx + (int64_t)(A.mx + A.my) * nfp;
+  const int b1 = W->wb[w + 1];
 
-  for (int p = wave; p < A.nplanes; p += nwaves) {
-    const PlaneRec pl = K.planes[A.plane_begin + p];
-    // z pass: U2[nx][ny] = sum_nz phi_nz(z) C[nx,ny,nz]
-    double U2[NP];
+  double U2[NP];
+  int cur_jz = -1;
+  for (int bi = W->wb[w]; bi < b1; ++bi) {
+    const BundleRec bd = load_uniform(K.bundles + bi);
+    if (bd.jz != cur_jz) {
+      // z pass for the new plane: U2[nx][ny] = sum_nz phi_nz(z) C[nx,ny,nz]
+      cur_jz = bd.jz;
+      const cptr<double> fz = tz + cur_jz * nfp;
 #pragma unroll
-    for (int q = 0; q < NP; ++q) U2[q] = 0.0;
-    {
-      const double *fz = phz + pl.jz * NF;
+      for (int q = 0; q < NP; ++q) U2[q] = 0.0;
       int idx = 0;
 #pragma unroll
       for (int nz = 0; nz < NF; ++nz) {
-        const double f = fz[nz];
+        const double fv = fz[nz];
         int q = 0;
 #pragma unroll
         for (int ny = 0; ny < NF; ++ny) {
 #pragma unroll
           for (int nx = 0; nx < NF - ny; ++nx, ++q) {
             if (nx + ny + nz <= NU) {
-              U2[q] = fma(f, cin[idx * TB + bl], U2[q]);
+              U2[q] = fma(fv, cin[idx * TB + L.bl], U2[q]);
               ++idx;
             }
           }
         }
       }
     }
-    for (int l = slot; l < pl.nlines; l += lpw) {
-      const LineRec ln = K.lines[pl.line_begin + l];
-      // y pass: U1[nx] = sum_ny phi_ny(y) U2[nx][ny]
-      double U1[NF];
+    const RunState rs = run_state(K, L, psi, bd);
+    // y pass: U1[nx] = sum_ny phi_ny(y) U2[nx][ny] for this lane's run
+    double U1[NF];
 #pragma unroll
-      for (int n = 0; n < NF; ++n) U1[n] = 0.0;
-      const double *fy = phy + (int)ln.jy * NF;
-      int q = 0;
+    for (int n = 0; n < NF; ++n) U1[n] = 0.0;
+    const double *fy = ty + rs.jy * nfp;
+    int q = 0;
 #pragma unroll
-      for (int ny = 0; ny < NF; ++ny) {
-        const double f = fy[ny];
+    for (int ny = 0; ny < NF; ++ny) {
+      const double fv = fy[ny];
 #pragma unroll
-        for (int nx = 0; nx < NF - ny; ++nx, ++q) U1[nx] = fma(f, U2[q], U1[nx]);
-      }
-      // x pass: psi(x) += sum_nx phi_nx(x) U1[nx]
-      double *dst = psi + (int64_t)ln.row * rowlen + b;
-      const double *fx = phx + (int)ln.jx0 * NF;
-      int xm = ln.x0m;
-#pragma unroll 4
-      for (int k = 0; k < ln.len; ++k) {
-        double v = 0.0;
+      for (int nx = 0; nx < NF - ny; ++nx, ++q) U1[nx] = fma(fv, U2[q], U1[nx]);
+    }
+    // x pass: psi(x) += sum_nx phi_nx(x) U1[nx]
+    double *dst = const_cast<double *>(rs.base);
+    const bool live = rs.active && L.bok;
+    for (int jb = bd.jlo; jb <= bd.jhi; jb += kBatch) {
 #pragma unroll
-        for (int n = 0; n < NF; ++n) v = fma(fx[k * NF + n], U1[n], v);
-        if (bok) unsafeAtomicAdd(dst + (int64_t)xm * K.B, v);
-        xm = (xm + 1 == K.nx) ? 0 : xm + 1;
+      for (int u = 0; u < kBatch; ++u) {
+        const int jx = jb + u;
+        if (jx <= bd.jhi) {
+          const cptr<double> f = tx + jx * nfp;
+          double v = 0.0;
+#pragma unroll
+          for (int n = 0; n < NF; ++n) v = fma(f[n], U1[n], v);
+          const int k = jx - rs.jx0;
+          if (live && k >= 0 && k < rs.len) unsafeAtomicAdd(dst + k * K.B, v);
+        }
       }
     }
   }
@@ -286,28 +419,28 @@ __device__ inline void coeff_decode(int n, int nu, int &nx, int &ny, int &nz) {
 //   dC[n]/dX = -(1/sigma) [ sqrt(nx/2) C~(nx-1) - sqrt((nx+1)/2) C~(nx+1) ]
 // (phi_n' = (1/sigma)[sqrt(n/2) phi_{n-1} - sqrt((n+1)/2) phi_{n+1}]) and the
 // contraction grad[a][d] += sum_{n,b} w[n][b] dC[n][b]/dR_d.
-// grad must be zero before the launch (band tiles add into it).
+// grad must be zero before the launch (work items and band tiles add).
 template <int NU1>
-__global__ __launch_bounds__(kBlock) void k_force(
+__global__ __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(waves_per_eu(NU1 + 1)))) void k_force(
     KArgs K, const double *__restrict__ psi, const double *__restrict__ w,
     double *grad) {
   constexpr int NF = NU1 + 1;
   constexpr int NS1 = NF * (NF + 1) * (NF + 2) / 6;
   constexpr int NU = NU1 - 1;
   constexpr int NS = (NU + 1) * (NU + 2) * (NU + 3) / 6;
-  extern __shared__ double lds[];
-  __shared__ double red[3][kBlock / 64];
-  const int ia = blockIdx.x / K.ntiles;
-  const int tile = blockIdx.x - ia * K.ntiles;
-  const int a = K.atom_list[ia];
-  const AtomRec A = K.atoms[a];
+  extern __shared__ double cacc[];
+  __shared__ double red[3][kWaves];
+  const cptr<WorkRec> W = as_const(K.work) + blockIdx.x;
+  const int tile = blockIdx.y;
+  const int a = W->atom;
+  const AtomRec A = load_uniform(K.atoms + a);
   const int TB = 1 << K.tb_shift;
-  double *tab = lds;
-  double *cacc = lds + (size_t)3 * K.mstride * NF;
-  fill_tables<NF>(A, K, tab);
   for (int t = threadIdx.x; t < NS1 * TB; t += blockDim.x) cacc[t] = 0.0;
   __syncthreads();
-  project_core<NU1>(K, A, tile, psi, tab, cacc);
+  const int wv = wave_id();
+  const Lanes L = lane_geometry(K, tile);
+  project_bundles<NU1>(K, A, L, W->wb[wv], W->wb[wv + 1], psi, cacc);
   __syncthreads();
 
   double g[3] = {0.0, 0.0, 0.0};
@@ -318,7 +451,7 @@ __global__ __launch_bounds__(kBlock) void k_force(
     if (bb >= K.B) continue;
     int m[3];
     coeff_decode(n, NU, m[0], m[1], m[2]);
-    const double wv = w[(A.coeff_row + n) * K.B + bb];
+    const double wn = w[(A.coeff_row + n) * K.B + bb];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       int up[3] = {m[0], m[1], m[2]};
@@ -330,7 +463,7 @@ __global__ __launch_bounds__(kBlock) void k_force(
         dn[d] -= 1;
         v += sqrt(0.5 * m[d]) * cacc[coeff_index(dn[0], dn[1], dn[2], NU1) * TB + bl];
       }
-      g[d] = fma(wv, v, g[d]);
+      g[d] = fma(wn, v, g[d]);
     }
   }
 #pragma unroll
@@ -342,8 +475,8 @@ __global__ __launch_bounds__(kBlock) void k_force(
   __syncthreads();
   if (threadIdx.x < 3) {
     double s = 0.0;
-    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) s += red[threadIdx.x][k];
-    atomicAdd(&grad[3 * a + threadIdx.x], -K.h3 / A.sigma * s);
+    for (int k = 0; k < kWaves; ++k) s += red[threadIdx.x][k];
+    unsafeAtomicAdd(&grad[3 * a + threadIdx.x], -K.h3 / A.sigma * s);
   }
 }
 
@@ -355,26 +488,23 @@ __global__ void k_fill(double *p, int64_t n, double v) {
 
 // ---------------------------------------------------------------- launch --
 
-size_t lds_bytes(int nf, int mstride, int tb) {
-  const size_t ns = (size_t)nf * (nf + 1) * (nf + 2) / 6;
-  return ((size_t)3 * mstride * nf + ns * tb) * sizeof(double);
+static dim3 grid_of(const KArgs &K) {
+  return dim3((unsigned)K.nwork, (unsigned)K.ntiles);
 }
 
 template <int NU>
 static hipError_t launch_project_nu(const KArgs &K, const double *psi,
                                     double *c, hipStream_t s) {
-  const size_t shm = lds_bytes(NU + 1, K.mstride, 1 << K.tb_shift);
-  hipLaunchKernelGGL(k_project<NU>, dim3(K.nlist * K.ntiles), dim3(kBlock), shm,
-                     s, K, psi, c);
+  const size_t shm = lds_tile_bytes(NU + 1, 1 << K.tb_shift);
+  hipLaunchKernelGGL(k_project<NU>, grid_of(K), dim3(kBlock), shm, s, K, psi, c);
   return hipGetLastError();
 }
 
 template <int NU>
 static hipError_t launch_expand_nu(const KArgs &K, const double *c,
                                    double *psi, hipStream_t s) {
-  const size_t shm = lds_bytes(NU + 1, K.mstride, 1 << K.tb_shift);
-  hipLaunchKernelGGL(k_expand<NU>, dim3(K.nlist * K.ntiles), dim3(kBlock), shm,
-                     s, K, c, psi);
+  const size_t shm = lds_tile_bytes(NU + 1, 1 << K.tb_shift);
+  hipLaunchKernelGGL(k_expand<NU>, grid_of(K), dim3(kBlock), shm, s, K, c, psi);
   return hipGetLastError();
 }
 
@@ -382,9 +512,8 @@ template <int NU1>
 static hipError_t launch_force_nu(const KArgs &K, const double *psi,
                                   const double *w, double *grad,
                                   hipStream_t s) {
-  const size_t shm = lds_bytes(NU1 + 1, K.mstride, 1 << K.tb_shift);
-  hipLaunchKernelGGL(k_force<NU1>, dim3(K.nlist * K.ntiles), dim3(kBlock), shm,
-                     s, K, psi, w, grad);
+  const size_t shm = lds_tile_bytes(NU1 + 1, 1 << K.tb_shift);
+  hipLaunchKernelGGL(k_force<NU1>, grid_of(K), dim3(kBlock), shm, s, K, psi, w, grad);
   return hipGetLastError();
 }
 
@@ -419,6 +548,14 @@ hipError_t launch_force(int nu, const KArgs &K, const double *psi,
 #undef X
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_tables(const AtomRec *atoms, int32_t natoms, double h,
+                         double *tab, int32_t mmax, hipStream_t s) {
+  (void)mmax;
+  if (natoms <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tables, dim3((unsigned)natoms), dim3(256), 0, s, atoms, h, tab);
+  return hipGetLastError();
 }
 
 hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s) {

@@ -10,22 +10,22 @@ namespace sho {
 // Argument block of the projection / expansion / derivative kernels.
 struct KArgs {
   const AtomRec *atoms;
-  const PlaneRec *planes;
   const LineRec *lines;
-  const int32_t *atom_list;  // atoms handled by this launch (one nu)
-  int32_t nlist;
-  int32_t nx;                // grid points along x (wrap of a line)
+  const BundleRec *bundles;
+  const WorkRec *work;       // work items of this launch (one nu)
+  const double *tab;         // 1D tables of all atoms
+  int32_t nwork;
+  int32_t nx;                // grid points along x
   int32_t B;                 // bands: stride of one grid point
-  int32_t tb_shift;          // log2(bands per line slot)
+  int32_t tb_shift;          // log2(bands per lane slot)
   int32_t ntiles;            // band tiles per atom
-  int32_t mstride;           // table rows per axis in LDS
-  double h, h3;
+  int32_t pad;
+  double h3;
 };
 
-// LDS bytes of a workgroup: three tables [mstride][nf] and a [N_SHO(nf-1)][tb]
-// coefficient tile.
-size_t lds_bytes(int nf, int mstride, int tb);
-
+// Samples the 1D tables of every atom (rows padded with zeros).
+hipError_t launch_tables(const AtomRec *atoms, int32_t natoms, double h,
+                         double *tab, int32_t mmax, hipStream_t s);
 hipError_t launch_project(int nu, const KArgs &K, const double *psi, double *c,
                           hipStream_t s);
 hipError_t launch_expand(int nu, const KArgs &K, const double *c, double *psi,

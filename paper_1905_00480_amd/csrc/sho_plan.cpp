@@ -8,6 +8,7 @@
 // The support is the projection sphere of sec. 6 of the paper; its default
 // radius sigma*sqrt(2 nu + 3) + 2h is the classical turning radius of the
 // highest shell nu (E sigma^2 = 2 nu + 3, sec. 2.2) plus two spacings.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <limits>
@@ -139,7 +140,6 @@ sho_status build_host_plan(const sho_grid *grid, int32_t natoms,
     A.nu = nu;
     A.plane_begin = (int32_t)P.planes.size();
     A.line_begin = (int32_t)P.lines.size();
-    A.point_begin = P.support_points;
     int64_t xmin = INT64_MAX, xmax = INT64_MIN, ymin = INT64_MAX,
             ymax = INT64_MIN, zmin = INT64_MAX, zmax = INT64_MIN;
     struct RawLine { int64_t z, y, x0, len; };
@@ -197,13 +197,21 @@ sho_status build_host_plan(const sho_grid *grid, int32_t natoms,
         P.planes.push_back(pl);
         cur_z = r.z;
       }
-      LineRec L;
-      L.row = wrap_index(r.z, grid->n[2]) * grid->n[1] + wrap_index(r.y, grid->n[1]);
-      L.x0m = wrap_index(r.x0, grid->n[0]);
-      L.jx0 = (int16_t)(r.x0 - xmin);
-      L.jy = (int16_t)(r.y - ymin);
-      L.len = (int32_t)r.len;
-      P.lines.push_back(L);
+      // cut the line where it crosses the periodic x boundary
+      int64_t k0 = 0;
+      while (k0 < r.len) {
+        const int32_t xm = wrap_index(r.x0 + k0, grid->n[0]);
+        int64_t run = std::min<int64_t>(r.len - k0, (int64_t)grid->n[0] - xm);
+        LineRec L;
+        L.row = wrap_index(r.z, grid->n[2]) * grid->n[1] + wrap_index(r.y, grid->n[1]);
+        L.x0m = xm;
+        L.jx0 = (int16_t)(r.x0 + k0 - xmin);
+        L.jy = (int16_t)(r.y - ymin);
+        L.jz = (int16_t)(r.z - zmin);
+        L.len = (int16_t)run;
+        P.lines.push_back(L);
+        k0 += run;
+      }
       P.planes.back().nlines++;
       P.planes.back().npoints += (int32_t)r.len;
       A.npoints += r.len;
@@ -215,12 +223,95 @@ sho_status build_host_plan(const sho_grid *grid, int32_t natoms,
     A.nplanes = (int32_t)P.planes.size() - A.plane_begin;
     A.nlines = (int32_t)P.lines.size() - A.line_begin;
     A.coeff_row = P.coeff_rows;
+    A.tab_nfp = table_nfp(nu);
+    A.tab_off = P.table_doubles;
+    P.table_doubles += (int64_t)(A.mx + A.my + A.mz) * A.tab_nfp;
     P.coeff_rows += nsho(nu);
     P.coeff_off[a + 1] = P.coeff_rows * nbands;
     P.support_points += A.npoints;
     P.nu_max = std::max(P.nu_max, nu);
   }
   return SHO_OK;
+}
+
+int choose_tb_shift(int nbands, int nu_max, size_t lds_limit) {
+  int shift = 0;
+  while ((1 << shift) < nbands && shift < 6) ++shift;
+  // the derivative contracts nu_max + 2 functions (tile of N_SHO(nu_max+1))
+  while (shift > 0 && lds_tile_bytes(nu_max + 2, 1 << shift) > lds_limit) --shift;
+  if (lds_tile_bytes(nu_max + 2, 1 << shift) > lds_limit) return -1;
+  return shift;
+}
+
+void build_work(HostPlan *P, int tb_shift, int64_t target_points) {
+  const int slots = 64 >> tb_shift;
+  P->tb_shift = tb_shift;
+  P->bundles.clear();
+  P->work.clear();
+  P->any_split = false;
+  // bundles: the runs of each atom plane, ordered by their first x index so
+  // that runs of similar extent share a bundle, in groups of `slots`
+  std::vector<int32_t> atom_bundle_begin(P->natoms + 1, 0);
+  std::vector<int64_t> cost;  // per bundle: x steps of the wave
+  for (int32_t a = 0; a < P->natoms; ++a) {
+    atom_bundle_begin[a] = (int32_t)P->bundles.size();
+    const AtomRec &A = P->atoms[a];
+    for (int32_t pi = A.plane_begin; pi < A.plane_begin + A.nplanes; ++pi) {
+      const PlaneRec &pl = P->planes[pi];
+      // runs of this plane: [pl.line_begin, next plane's line_begin)
+      const int32_t rb = pl.line_begin;
+      const int32_t re = (pi + 1 < A.plane_begin + A.nplanes)
+                             ? P->planes[pi + 1].line_begin
+                             : A.line_begin + A.nlines;
+      std::stable_sort(P->lines.begin() + rb, P->lines.begin() + re,
+                       [](const LineRec &x, const LineRec &y) { return x.jx0 < y.jx0; });
+      for (int32_t r = rb; r < re; r += slots) {
+        BundleRec b;
+        b.run0 = r;
+        b.nruns = (int16_t)std::min(slots, re - r);
+        b.jz = P->lines[r].jz;
+        int lo = INT32_MAX, hi = INT32_MIN;
+        for (int32_t k = r; k < r + b.nruns; ++k) {
+          lo = std::min(lo, (int)P->lines[k].jx0);
+          hi = std::max(hi, (int)P->lines[k].jx0 + P->lines[k].len - 1);
+        }
+        b.jlo = (int16_t)lo;
+        b.jhi = (int16_t)hi;
+        b.pad = 0;
+        P->bundles.push_back(b);
+        cost.push_back(hi - lo + 1 + 2);  // x steps plus per-bundle overhead
+      }
+    }
+  }
+  atom_bundle_begin[P->natoms] = (int32_t)P->bundles.size();
+  // work items, grouped by nu
+  for (int32_t nu = 0; nu <= SHO_NU_MAX; ++nu) {
+    for (int32_t a = 0; a < P->natoms; ++a) {
+      const AtomRec &A = P->atoms[a];
+      if (A.nu != nu || A.npoints == 0) continue;
+      const int32_t bb = atom_bundle_begin[a], be = atom_bundle_begin[a + 1];
+      const int64_t parts =
+          std::max<int64_t>(1, (A.npoints + target_points - 1) / target_points);
+      std::vector<int64_t> cum(be - bb + 1, 0);
+      for (int32_t i = bb; i < be; ++i) cum[i - bb + 1] = cum[i - bb] + cost[i];
+      const int64_t total = cum.back();
+      auto cut = [&](int64_t target) {
+        return bb + (int32_t)(std::lower_bound(cum.begin(), cum.end(), target) - cum.begin());
+      };
+      for (int64_t q = 0; q < parts; ++q) {
+        WorkRec W;
+        W.atom = a;
+        W.split = parts > 1 ? 1 : 0;
+        const int64_t c0 = total * q / parts, c1 = total * (q + 1) / parts;
+        for (int w = 0; w <= kWaves; ++w)
+          W.wb[w] = std::min(std::max(cut(c0 + (c1 - c0) * w / kWaves), bb), be);
+        if (q == 0) W.wb[0] = bb;
+        if (q == parts - 1) W.wb[kWaves] = be;
+        P->work.push_back(W);
+      }
+      P->any_split |= parts > 1;
+    }
+  }
 }
 
 }  // namespace sho
