@@ -48,6 +48,12 @@ struct sho_plan_s {
   sho::BundleRec *d_bundles = nullptr;
   sho::WorkRec *d_work = nullptr;
   double *d_tab = nullptr;
+  int32_t *d_run_atom = nullptr;
+  int32_t *d_row_runs = nullptr;
+  sho::RowRec *d_rows = nullptr;
+  int64_t *d_u2_off = nullptr;
+  int32_t *d_nu_atoms = nullptr;
+  double *d_u2 = nullptr;  // expansion plane partials, allocated on first use
   int64_t device_bytes = 0;
   int64_t stored_bytes = 0;
 };
@@ -71,6 +77,15 @@ void free_plan_device(sho_plan_s *p) {
   if (p->d_bundles) (void)hipFree(p->d_bundles);
   if (p->d_work) (void)hipFree(p->d_work);
   if (p->d_tab) (void)hipFree(p->d_tab);
+  for (void *q : {(void *)p->d_run_atom, (void *)p->d_row_runs, (void *)p->d_rows,
+                  (void *)p->d_u2_off, (void *)p->d_nu_atoms, (void *)p->d_u2})
+    if (q) (void)hipFree(q);
+  p->d_run_atom = nullptr;
+  p->d_row_runs = nullptr;
+  p->d_rows = nullptr;
+  p->d_u2_off = nullptr;
+  p->d_nu_atoms = nullptr;
+  p->d_u2 = nullptr;
   p->d_atoms = nullptr;
   p->d_lines = nullptr;
   p->d_bundles = nullptr;
@@ -94,6 +109,36 @@ sho::KArgs make_args(const sho_plan_s *p, const Group &g) {
   const double h = p->hp.grid.h;
   K.h3 = h * h * h;
   return K;
+}
+
+sho::EArgs make_eargs(const sho_plan_s *p) {
+  sho::EArgs E;
+  E.atoms = p->d_atoms;
+  E.lines = p->d_lines;
+  E.run_atom = p->d_run_atom;
+  E.row_runs = p->d_row_runs;
+  E.rows = p->d_rows;
+  E.u2_off = p->d_u2_off;
+  E.nu_atoms = p->d_nu_atoms;
+  E.tab = p->d_tab;
+  E.nrows = (int32_t)p->hp.rows.size();
+  E.natoms_u2 = (int32_t)p->hp.nu_atoms.size();
+  E.nx = p->hp.grid.n[0];
+  E.B = p->hp.nbands;
+  E.tbe_shift = p->hp.nbands > 32 ? 6 : 5;
+  E.ntiles = (p->hp.nbands + (1 << E.tbe_shift) - 1) >> E.tbe_shift;
+  E.ntiles_u2 = (p->hp.nbands + 31) / 32;
+  E.nu_max = p->hp.nu_max;
+  for (int nu = 0; nu <= SHO_NU_MAX + 1; ++nu) E.nu_begin[nu] = 0;
+  {
+    int nu = 0;
+    for (size_t i = 0; i <= p->hp.nu_atoms.size(); ++i) {
+      const int cur = i < p->hp.nu_atoms.size() ? p->hp.atoms[p->hp.nu_atoms[i]].nu
+                                                : SHO_NU_MAX + 1;
+      while (nu <= cur && nu <= SHO_NU_MAX + 1) E.nu_begin[nu++] = (int32_t)i;
+    }
+  }
+  return E;
 }
 
 // A device buffer of at least `bytes` bytes must start at ptr: checked
@@ -162,6 +207,7 @@ sho_status sho_plan_create(const sho_grid *grid, int32_t natoms,
       return fail(SHO_E_BOX, "coefficient tile too large for the workgroup LDS");
     }
     sho::build_work(&p->hp, tbs, sho::kTargetPoints);
+    sho::build_rows(&p->hp);
     *out = p;
     return SHO_OK;
   }
@@ -184,6 +230,7 @@ sho_status sho_plan_create(const sho_grid *grid, int32_t natoms,
     return fail(SHO_E_BOX, "coefficient tile too large for the workgroup LDS");
   }
   sho::build_work(&p->hp, tbs, sho::kTargetPoints);
+  sho::build_rows(&p->hp);
 
   // group work items by nu (one launch per group); items are sorted by nu
   const auto &work = p->hp.work;
@@ -201,6 +248,11 @@ sho_status sho_plan_create(const sho_grid *grid, int32_t natoms,
       (e = upload(&p->d_lines, p->hp.lines, &p->device_bytes)) != hipSuccess ||
       (e = upload(&p->d_bundles, p->hp.bundles, &p->device_bytes)) != hipSuccess ||
       (e = upload(&p->d_work, p->hp.work, &p->device_bytes)) != hipSuccess ||
+      (e = upload(&p->d_run_atom, p->hp.run_atom, &p->device_bytes)) != hipSuccess ||
+      (e = upload(&p->d_row_runs, p->hp.row_runs, &p->device_bytes)) != hipSuccess ||
+      (e = upload(&p->d_rows, p->hp.rows, &p->device_bytes)) != hipSuccess ||
+      (e = upload(&p->d_u2_off, p->hp.u2_off, &p->device_bytes)) != hipSuccess ||
+      (e = upload(&p->d_nu_atoms, p->hp.nu_atoms, &p->device_bytes)) != hipSuccess ||
       (e = hipMalloc((void **)&p->d_tab,
                      std::max<int64_t>(p->hp.table_doubles, 1) * sizeof(double))) !=
           hipSuccess) {
@@ -335,11 +387,20 @@ sho_status sho_plan_expand(sho_plan_t p, const double *c, double *psi,
       (const char *)psi < (const char *)c + coeff_bytes(p))
     return fail(SHO_E_INVALID, "psi and c overlap");
   hipStream_t s = (hipStream_t)stream;
-  for (const Group &g : p->groups) {
-    sho::KArgs K = make_args(p, g);
-    hipError_t e = sho::launch_expand(g.nu, K, c, psi, s);
-    if (e != hipSuccess) return hip_fail(e, "expand launch");
+  if (!p->d_u2) {
+    hipError_t e = hipMalloc((void **)&p->d_u2,
+                             std::max<int64_t>(p->hp.u2_doubles, 1) * sizeof(double));
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      p->d_u2 = nullptr;
+      return e == hipErrorOutOfMemory ? fail(SHO_E_NOMEM, "device allocation failed")
+                                      : hip_fail(e, "expansion scratch");
+    }
+    p->device_bytes += std::max<int64_t>(p->hp.u2_doubles, 1) * sizeof(double);
   }
+  sho::EArgs E = make_eargs(p);
+  hipError_t e = sho::launch_expand_rows(E, c, p->d_u2, psi, s);
+  if (e != hipSuccess) return hip_fail(e, "expand launch");
   return SHO_OK;
 }
 

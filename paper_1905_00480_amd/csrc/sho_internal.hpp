@@ -91,6 +91,20 @@ struct WorkRec {
 };
 static_assert(sizeof(WorkRec) == 4 * (kWaves + 3), "WorkRec layout");
 
+// Expansion work: one memory row (z, y) with the runs of every atom that fall
+// into it.  One workgroup owns the row (per x chunk and band tile), so global
+// memory sees one plain read and one plain write of it.
+struct RowRec {
+  int32_t row;        // (z mod nz) * ny + (y mod ny)
+  int32_t run_begin;  // into the row-ordered run index list
+  int32_t nruns;
+  int32_t pad;
+};
+static_assert(sizeof(RowRec) == 16, "RowRec layout");
+
+// Rows handled by one expansion workgroup.
+constexpr int kRowsPerGroup = 1;
+
 // Host-side plan contents (built without any device call).
 struct HostPlan {
   sho_grid grid{};
@@ -105,6 +119,13 @@ struct HostPlan {
   std::vector<LineRec> lines;
   std::vector<BundleRec> bundles;
   std::vector<WorkRec> work;           // sorted by nu, then atom
+  std::vector<int32_t> run_atom;       // atom of every run
+  std::vector<int32_t> row_runs;       // run indices grouped by memory row
+  std::vector<RowRec> rows;            // non-empty rows, XCD-aware order
+  std::vector<int64_t> u2_off;         // [natoms] first double of the atom's
+                                       // per-plane expansion partials
+  std::vector<int32_t> nu_atoms;       // atoms with a support, sorted by nu
+  int64_t u2_doubles = 0;
   std::vector<double> support_centre;  // [natoms][3], fixed at creation
   std::vector<int64_t> coeff_off;      // [natoms+1] in doubles
   int64_t coeff_rows = 0;
@@ -138,6 +159,11 @@ int choose_tb_shift(int nbands, int nu_max, size_t lds_limit);
 // Bundles (with 64 >> tb_shift slots) and work items: atoms of more than
 // `target_points` support points are shared by several workgroups.
 void build_work(HostPlan *P, int tb_shift, int64_t target_points);
+
+// Expansion tables: runs grouped by memory row, rows interleaved over the
+// eight XCDs so that all rows of one plane share an L2, per-atom offsets of
+// the plane partials U2[jz][pair][band].
+void build_rows(HostPlan *P);
 
 // Largest table extent the kernels accept per axis.
 constexpr int32_t kMaxTable = 512;

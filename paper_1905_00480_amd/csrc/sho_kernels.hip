@@ -17,8 +17,10 @@
 //   y pass  T2[nx][ny] += phi_ny(y) T1[nx]            registers
 //   z pass  C[nx,ny,nz] += phi_nz(z) T2[nx][ny]       at each plane change:
 //                                                     slots folded, LDS tile
-// Expansion (step 3) runs the passes backwards and adds into psi with
-// global_atomic_add_f64 (supports of different atoms overlap).
+// Expansion (step 3) runs the passes backwards: the z pass per atom plane
+// (plane partials U2), then one workgroup per memory row adds the y and x
+// passes of every run that falls into the row, so that each value of psi is
+// read and written once with plain loads and stores, in a fixed order.
 // The 1D functions are sampled once per plan into small per-atom tables by
 // the normalised three-term recurrence (the monic recurrence of sec. 3.7
 // rescaled so that every phi_n has unit L2 norm).
@@ -29,6 +31,9 @@
 namespace sho {
 
 constexpr int kBlock = 64 * kWaves;
+
+#define SHO_NU_CASES(X) \
+  X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10)
 constexpr int kBatch = 8;  // loads in flight per lane and batch
 
 // waves per SIMD the register allocator must allow (4 keeps <= 128 VGPRs)
@@ -299,92 +304,196 @@ __attribute__((amdgpu_waves_per_eu(waves_per_eu(NU + 1)))) void k_project(
   }
 }
 
-// -------------------------------------------------------------- expansion --
+// --------------------------------------------------- expansion by rows --
+
+// Plane partials of the expansion, U2[jz][q][b] = sum_nz phi_nz(z_jz) C[nx,ny,nz][b]
+// for every plane jz of every atom (pairs q: ny outer, nx inner).  One
+// workgroup per (atom, tile of 32 bands).
+constexpr int kU2Tile = 32;
 
 template <int NU>
-__global__ __launch_bounds__(kBlock)
-__attribute__((amdgpu_waves_per_eu(waves_per_eu(NU + 1)))) void k_expand(
-    KArgs K, const double *__restrict__ c, double *psi) {
+__global__ __launch_bounds__(256) void k_u2(EArgs E, const double *__restrict__ c,
+                                            double *__restrict__ u2) {
   constexpr int NF = NU + 1;
-  constexpr int NP = NF * (NF + 1) / 2;
   constexpr int NS = NF * (NF + 1) * (NF + 2) / 6;
-  extern __shared__ double cin[];
-  const cptr<WorkRec> W = as_const(K.work) + blockIdx.x;
-  const int tile = blockIdx.y;
-  const AtomRec A = load_uniform(K.atoms + W->atom);
-  const int TB = 1 << K.tb_shift;
-  for (int t = threadIdx.x; t < NS * TB; t += blockDim.x) {
-    const int n = t >> K.tb_shift;
-    const int bb = tile * TB + (t & (TB - 1));
-    cin[t] = bb < K.B ? c[(A.coeff_row + n) * K.B + bb] : 0.0;
+  constexpr int NP = NF * (NF + 1) / 2;
+  __shared__ double cs[NS * kU2Tile];
+  const int a = E.nu_atoms[E.nu_begin[NU] + blockIdx.x];
+  const AtomRec A = load_uniform(E.atoms + a);
+  const int b0 = blockIdx.y * kU2Tile;
+  for (int t = threadIdx.x; t < NS * kU2Tile; t += blockDim.x) {
+    const int n = t / kU2Tile, bl = t % kU2Tile;
+    cs[t] = (b0 + bl < E.B) ? c[(A.coeff_row + n) * E.B + b0 + bl] : 0.0;
   }
   __syncthreads();
-
-  const int w = wave_id();
-  const Lanes L = lane_geometry(K, tile);
-  const int nfp = A.tab_nfp;
-  const cptr<double> tx = as_const(K.tab) + A.tab_off;
-  const double *ty = K.tab + A.tab_off + (int64_t)A.mx * nfp;
-  const cptr<double> tz = tx + (int64_t)(A.mx + A.my) * nfp;
-  const int b1 = W->wb[w + 1];
-
-  double U2[NP];
-  int cur_jz = -1;
-  for (int bi = W->wb[w]; bi < b1; ++bi) {
-    const BundleRec bd = load_uniform(K.bundles + bi);
-    if (bd.jz != cur_jz) {
-      // z pass for the new plane: U2[nx][ny] = sum_nz phi_nz(z) C[nx,ny,nz]
-      cur_jz = bd.jz;
-      const cptr<double> fz = tz + cur_jz * nfp;
+  const double *tz = E.tab + A.tab_off + (int64_t)(A.mx + A.my) * A.tab_nfp;
+  double *dst = u2 + E.u2_off[a];
+  // thread = (plane jz, band bl); it writes all pairs of that plane and band
+  for (int t = threadIdx.x; t < A.mz * kU2Tile; t += blockDim.x) {
+    const int bl = t % kU2Tile;
+    const int jz = t / kU2Tile;
+    if (b0 + bl >= E.B) continue;
+    double fz[NF];
 #pragma unroll
-      for (int q = 0; q < NP; ++q) U2[q] = 0.0;
-      int idx = 0;
-#pragma unroll
-      for (int nz = 0; nz < NF; ++nz) {
-        const double fv = fz[nz];
-        int q = 0;
-#pragma unroll
-        for (int ny = 0; ny < NF; ++ny) {
-#pragma unroll
-          for (int nx = 0; nx < NF - ny; ++nx, ++q) {
-            if (nx + ny + nz <= NU) {
-              U2[q] = fma(fv, cin[idx * TB + L.bl], U2[q]);
-              ++idx;
-            }
-          }
-        }
-      }
-    }
-    const RunState rs = run_state(K, L, psi, bd);
-    // y pass: U1[nx] = sum_ny phi_ny(y) U2[nx][ny] for this lane's run
-    double U1[NF];
-#pragma unroll
-    for (int n = 0; n < NF; ++n) U1[n] = 0.0;
-    const double *fy = ty + rs.jy * nfp;
+    for (int n = 0; n < NF; ++n) fz[n] = tz[(int64_t)jz * A.tab_nfp + n];
+    double *out = dst + (int64_t)jz * NP * E.B + b0 + bl;
     int q = 0;
 #pragma unroll
     for (int ny = 0; ny < NF; ++ny) {
-      const double fv = fy[ny];
 #pragma unroll
-      for (int nx = 0; nx < NF - ny; ++nx, ++q) U1[nx] = fma(fv, U2[q], U1[nx]);
-    }
-    // x pass: psi(x) += sum_nx phi_nx(x) U1[nx]
-    double *dst = const_cast<double *>(rs.base);
-    const bool live = rs.active && L.bok;
-    for (int jb = bd.jlo; jb <= bd.jhi; jb += kBatch) {
+      for (int nx = 0; nx < NF - ny; ++nx, ++q) {
+        double acc = 0.0;
+        // C index of (nx, ny, nz): nz-major, then ny, nx fastest
+        int idx = nx;
+        int rowcnt = 0;
 #pragma unroll
-      for (int u = 0; u < kBatch; ++u) {
-        const int jx = jb + u;
-        if (jx <= bd.jhi) {
-          const cptr<double> f = tx + jx * nfp;
-          double v = 0.0;
+        for (int nz = 0; nz < NF; ++nz) {
+          if (nx + ny + nz <= NU) {
+            // offset of (0, ny, nz) within the nz-major order
+            int base = 0;
 #pragma unroll
-          for (int n = 0; n < NF; ++n) v = fma(f[n], U1[n], v);
-          const int k = jx - rs.jx0;
-          if (live && k >= 0 && k < rs.len) unsafeAtomicAdd(dst + k * K.B, v);
+            for (int k = 0; k < nz; ++k) base += (NU - k + 1) * (NU - k + 2) / 2;
+#pragma unroll
+            for (int j = 0; j < ny; ++j) base += NU - nz - j + 1;
+            acc = fma(fz[nz], cs[(base + nx) * kU2Tile + bl], acc);
+          }
         }
+        (void)idx;
+        (void)rowcnt;
+        out[(int64_t)q * E.B] = acc;
       }
     }
+  }
+}
+
+// Doubles of one row chunk held in LDS by the row kernel, and of each wave's
+// staging area for 1D table rows.
+constexpr int kRowChunkDoubles = 2048;
+constexpr int kStageDoubles = 256;  // 256/nfp table rows (32 or 16 points)
+constexpr int kRowWaves = 4;
+constexpr int kRowBlock = 64 * kRowWaves;
+
+// Adds the contribution of one run, clipped to x in [xa, xb), into the LDS
+// copy of the row chunk that starts at memory x = xc0:
+//   U1[nx] = sum_ny phi_ny(y) U2[jz][nx,ny],  psi(x) += sum_nx phi_nx(x) U1[nx].
+// Lanes are (x phase, band); phase xp takes the points xa+xp, xa+xp+XP, ...
+// The x-table rows of up to 256/nfp points are first copied into the wave's
+// LDS staging area with one vector load per lane, issued together with the
+// U2 loads, so a run costs one memory latency.
+template <int NU, int XP>
+__device__ inline void add_run(const EArgs &E, const AtomRec &A,
+                               const LineRec &ln, const double *u2a, int xa,
+                               int xb, int xc0, double *rowbuf, double *stage,
+                               int TB, int xp, int bl, int bc) {
+  constexpr int NF = NU + 1;
+  constexpr int NP = NF * (NF + 1) / 2;
+  const int nfp = A.tab_nfp;
+  const int lane = threadIdx.x & 63;
+  const double *tx = E.tab + A.tab_off;
+  const cptr<double> fy = as_const(E.tab) + A.tab_off + (int64_t)(A.mx + ln.jy) * nfp;
+  const double *ub = u2a + (int64_t)ln.jz * NP * E.B + bc;
+  const int jshift = ln.jx0 - ln.x0m;  // table index of memory x
+  double u2v[NP];
+#pragma unroll
+  for (int q = 0; q < NP; ++q) u2v[q] = ub[(int64_t)q * E.B];
+  double U1[NF];
+  bool first = true;
+  const int stage_pts = kStageDoubles / nfp;
+  for (int xs = xa; xs < xb; xs += stage_pts) {
+    const int npt = min(stage_pts, xb - xs);
+    // stage rows jshift+xs .. +npt-1 (npt*nfp doubles, <= 4 per lane)
+    const int nd = npt * nfp;
+    const double *src = tx + (int64_t)(xs + jshift) * nfp;
+    double tmp[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int i = lane * 4 + k;
+      tmp[k] = i < nd ? src[i] : 0.0;
+    }
+    if (first) {
+#pragma unroll
+      for (int n = 0; n < NF; ++n) U1[n] = 0.0;
+      int q = 0;
+#pragma unroll
+      for (int ny = 0; ny < NF; ++ny) {
+        const double fv = fy[ny];
+#pragma unroll
+        for (int nx = 0; nx < NF - ny; ++nx, ++q) U1[nx] = fma(fv, u2v[q], U1[nx]);
+      }
+      first = false;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) stage[lane * 4 + k] = tmp[k];
+    for (int x = xs; x < xs + npt; x += XP) {
+      const int xl = x + xp;
+      const double *f = stage + (min(xl, xs + npt - 1) - xs) * nfp;
+      double val = 0.0;
+#pragma unroll
+      for (int n = 0; n < NF; ++n) val = fma(f[n], U1[n], val);
+      if (xl < xs + npt) atomicAdd(&rowbuf[(xl - xc0) * TB + bl], val);
+    }
+  }
+}
+
+// One workgroup per (memory row, x chunk, band tile): the chunk of psi is read
+// into LDS once, every run of any atom that falls into it adds its part
+// (waves take runs round robin), and the chunk is written back once.  No two
+// workgroups touch the same values, so global memory sees plain loads and
+// stores only.  Small workgroups let several of them, in different phases
+// (load, add, store), share a CU.
+template <int XP, int NUMAX>
+__global__ __launch_bounds__(kRowBlock) void k_expand_rows(EArgs E,
+                                                          const double *__restrict__ u2,
+                                                          double *psi) {
+  extern __shared__ double lds[];
+  double *rowbuf = lds;
+  const RowRec rr = load_uniform(E.rows + blockIdx.x);
+  if (rr.row < 0) return;
+  const int w = wave_id();
+  double *stage = lds + kRowChunkDoubles + w * kStageDoubles;
+  const int TB = 1 << E.tbe_shift;
+  const int xchunk = kRowChunkDoubles >> E.tbe_shift;
+  const int xc0 = (int)blockIdx.y * xchunk;
+  const int xc1 = min(xc0 + xchunk, E.nx);
+  const int tile = blockIdx.z;
+  const int64_t rowoff = (int64_t)rr.row * E.nx;
+  const int nval = (xc1 - xc0) << E.tbe_shift;
+  for (int t = threadIdx.x; t < nval; t += blockDim.x) {
+    const int x = t >> E.tbe_shift;
+    const int b = tile * TB + (t & (TB - 1));
+    rowbuf[t] = b < E.B ? psi[(rowoff + xc0 + x) * E.B + b] : 0.0;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int xp = lane >> E.tbe_shift;
+  const int bl = lane & (TB - 1);
+  const int b = tile * TB + bl;
+  const int bc = b < E.B ? b : E.B - 1;
+  const cptr<int32_t> runs = as_const(E.row_runs) + rr.run_begin;
+  for (int i = w; i < rr.nruns; i += kRowWaves) {
+    const int run = runs[i];
+    const LineRec ln = load_uniform(E.lines + run);
+    const int xa = max((int)ln.x0m, xc0);
+    const int xb = min((int)ln.x0m + ln.len, xc1);
+    if (xa >= xb) continue;
+    const int a = as_const(E.run_atom)[run];
+    const AtomRec A = load_uniform(E.atoms + a);
+    const double *u2a = u2 + as_const(E.u2_off)[a];
+    switch (A.nu) {
+#define X(N)                                                                  \
+  case N:                                                                     \
+    if constexpr (N <= NUMAX)                                                 \
+      add_run<N, XP>(E, A, ln, u2a, xa, xb, xc0, rowbuf, stage, TB, xp, bl, bc); \
+    break;
+      X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10)
+#undef X
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < nval; t += blockDim.x) {
+    const int x = t >> E.tbe_shift;
+    const int b = tile * TB + (t & (TB - 1));
+    if (b < E.B) psi[(rowoff + xc0 + x) * E.B + b] = rowbuf[t];
   }
 }
 
@@ -500,14 +609,6 @@ static hipError_t launch_project_nu(const KArgs &K, const double *psi,
   return hipGetLastError();
 }
 
-template <int NU>
-static hipError_t launch_expand_nu(const KArgs &K, const double *c,
-                                   double *psi, hipStream_t s) {
-  const size_t shm = lds_tile_bytes(NU + 1, 1 << K.tb_shift);
-  hipLaunchKernelGGL(k_expand<NU>, grid_of(K), dim3(kBlock), shm, s, K, c, psi);
-  return hipGetLastError();
-}
-
 template <int NU1>
 static hipError_t launch_force_nu(const KArgs &K, const double *psi,
                                   const double *w, double *grad,
@@ -517,23 +618,11 @@ static hipError_t launch_force_nu(const KArgs &K, const double *psi,
   return hipGetLastError();
 }
 
-#define SHO_NU_CASES(X) \
-  X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10)
 
 hipError_t launch_project(int nu, const KArgs &K, const double *psi, double *c,
                           hipStream_t s) {
   switch (nu) {
 #define X(N) case N: return launch_project_nu<N>(K, psi, c, s);
-    SHO_NU_CASES(X)
-#undef X
-  }
-  return hipErrorInvalidValue;
-}
-
-hipError_t launch_expand(int nu, const KArgs &K, const double *c, double *psi,
-                         hipStream_t s) {
-  switch (nu) {
-#define X(N) case N: return launch_expand_nu<N>(K, c, psi, s);
     SHO_NU_CASES(X)
 #undef X
   }
@@ -548,6 +637,45 @@ hipError_t launch_force(int nu, const KArgs &K, const double *psi,
 #undef X
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_expand_rows(const EArgs &E, const double *c, double *u2,
+                              double *psi, hipStream_t s) {
+  for (int nu = 0; nu <= SHO_NU_MAX; ++nu) {
+    const int cnt = E.nu_begin[nu + 1] - E.nu_begin[nu];
+    if (cnt <= 0) continue;
+    const dim3 g((unsigned)cnt, (unsigned)E.ntiles_u2);
+    switch (nu) {
+#define X(N)                                                            \
+  case N:                                                               \
+    hipLaunchKernelGGL(k_u2<N>, g, dim3(256), 0, s, E, c, u2);          \
+    break;
+      SHO_NU_CASES(X)
+#undef X
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (E.nrows > 0) {
+    const int xchunk = kRowChunkDoubles >> E.tbe_shift;
+    const dim3 g((unsigned)E.nrows, (unsigned)((E.nx + xchunk - 1) / xchunk),
+                 (unsigned)E.ntiles);
+    const size_t shm = (kRowChunkDoubles + kRowWaves * kStageDoubles) * sizeof(double);
+    switch (E.nu_max) {
+#define X(N)                                                                      \
+  case N:                                                                         \
+    if (E.tbe_shift == 6)                                                         \
+      hipLaunchKernelGGL((k_expand_rows<1, N>), g, dim3(kRowBlock), shm, s, E, u2, psi); \
+    else                                                                          \
+      hipLaunchKernelGGL((k_expand_rows<2, N>), g, dim3(kRowBlock), shm, s, E, u2, psi); \
+    break;
+      SHO_NU_CASES(X)
+#undef X
+      default:
+        return hipErrorInvalidValue;
+    }
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_tables(const AtomRec *atoms, int32_t natoms, double h,

@@ -23,13 +23,36 @@ struct KArgs {
   double h3;
 };
 
+// Argument block of the row-owner expansion.
+struct EArgs {
+  const AtomRec *atoms;
+  const LineRec *lines;
+  const int32_t *run_atom;
+  const int32_t *row_runs;
+  const RowRec *rows;
+  const int64_t *u2_off;
+  const int32_t *nu_atoms;
+  const double *tab;
+  int32_t nrows;        // entries of rows (a multiple of kRowsPerGroup)
+  int32_t natoms_u2;    // entries of nu_atoms
+  int32_t nx;
+  int32_t B;
+  int32_t tbe_shift;    // log2(bands per x phase): 5 or 6
+  int32_t ntiles;       // band tiles of the row kernel
+  int32_t ntiles_u2;    // band tiles (of 32) of the plane-partial kernel
+  int32_t nu_max;       // largest nu among the atoms
+  int32_t nu_begin[SHO_NU_MAX + 2];  // nu_atoms[nu_begin[nu] .. nu_begin[nu+1])
+};
+
 // Samples the 1D tables of every atom (rows padded with zeros).
 hipError_t launch_tables(const AtomRec *atoms, int32_t natoms, double h,
                          double *tab, int32_t mmax, hipStream_t s);
 hipError_t launch_project(int nu, const KArgs &K, const double *psi, double *c,
                           hipStream_t s);
-hipError_t launch_expand(int nu, const KArgs &K, const double *c, double *psi,
-                         hipStream_t s);
+// Expansion by rows: plane partials U2 from c, then every memory row adds the
+// contributions of all runs that fall into it.  u2: E's u2 buffer.
+hipError_t launch_expand_rows(const EArgs &E, const double *c, double *u2,
+                              double *psi, hipStream_t s);
 // grad must be zeroed first (launch_fill)
 hipError_t launch_force(int nu, const KArgs &K, const double *psi,
                         const double *w, double *grad, hipStream_t s);

@@ -314,4 +314,68 @@ void build_work(HostPlan *P, int tb_shift, int64_t target_points) {
   }
 }
 
+void build_rows(HostPlan *P) {
+  const int64_t nrows_grid = (int64_t)P->grid.n[2] * P->grid.n[1];
+  P->run_atom.assign(P->lines.size(), -1);
+  for (int32_t a = 0; a < P->natoms; ++a) {
+    const AtomRec &A = P->atoms[a];
+    for (int32_t r = A.line_begin; r < A.line_begin + A.nlines; ++r) P->run_atom[r] = a;
+  }
+  // counting sort of runs by memory row (stable: atom order, then run order)
+  std::vector<int32_t> count(nrows_grid + 1, 0);
+  for (const LineRec &L : P->lines) count[L.row + 1]++;
+  for (int64_t r = 0; r < nrows_grid; ++r) count[r + 1] += count[r];
+  P->row_runs.assign(P->lines.size(), 0);
+  std::vector<int32_t> fill(count.begin(), count.end() - 1);
+  for (int32_t i = 0; i < (int32_t)P->lines.size(); ++i)
+    P->row_runs[fill[P->lines[i].row]++] = i;
+  // non-empty rows, one list per plane class z mod 8, interleaved in groups
+  // of kRowsPerGroup so that workgroup g (dispatched to XCD g mod 8) works on
+  // planes of one class
+  std::vector<std::vector<RowRec>> cls(8);
+  for (int64_t r = 0; r < nrows_grid; ++r) {
+    const int32_t n = count[r + 1] - count[r];
+    if (!n) continue;
+    const int32_t z = (int32_t)(r / P->grid.n[1]);
+    cls[z % 8].push_back(RowRec{(int32_t)r, count[r], n, 0});
+  }
+  P->rows.clear();
+  std::vector<size_t> at(8, 0);
+  for (bool any = true; any;) {
+    any = false;
+    for (int k = 0; k < 8; ++k) {
+      for (int j = 0; j < kRowsPerGroup; ++j) {
+        if (at[k] < cls[k].size()) {
+          P->rows.push_back(cls[k][at[k]++]);
+          any = true;
+        } else {
+          // pad the group so the next group starts on the next XCD
+          P->rows.push_back(RowRec{-1, 0, 0, 0});
+        }
+      }
+    }
+  }
+  // drop trailing groups made only of padding
+  while (!P->rows.empty() && P->rows.size() >= (size_t)kRowsPerGroup) {
+    bool empty = true;
+    for (size_t j = P->rows.size() - kRowsPerGroup; j < P->rows.size(); ++j)
+      empty &= P->rows[j].row < 0;
+    if (!empty) break;
+    P->rows.resize(P->rows.size() - kRowsPerGroup);
+  }
+  // plane partials: per atom mz planes x pairs x bands
+  P->u2_off.assign(P->natoms, 0);
+  P->u2_doubles = 0;
+  for (int32_t a = 0; a < P->natoms; ++a) {
+    const AtomRec &A = P->atoms[a];
+    const int64_t np = (int64_t)(A.nu + 1) * (A.nu + 2) / 2;
+    P->u2_off[a] = P->u2_doubles;
+    P->u2_doubles += (int64_t)A.mz * np * P->nbands;
+  }
+  P->nu_atoms.clear();
+  for (int32_t nu = 0; nu <= SHO_NU_MAX; ++nu)
+    for (int32_t a = 0; a < P->natoms; ++a)
+      if (P->atoms[a].nu == nu && P->atoms[a].npoints > 0) P->nu_atoms.push_back(a);
+}
+
 }  // namespace sho
