@@ -11,11 +11,21 @@ placement, 2 Bohr minimum separation), sigma = 0.6 Bohr, nu_max = 5 (56
 functions), 32 real FP64 bands psi ~ N(0,1) (synthetic, seeded).
 
 Metric: projected gridpoint*bands per second = sum_a |S_a| * B per step / time.
-The JSON line also carries the roofline of the dominant kernel (algorithmic
-HBM bytes per launch / its mean event-timed duration vs 8 TB/s) and the CPU
-oracle timed on a bounded sample of the same workload.
+
+Kernels of a step and their algorithmic HBM bytes per launch:
+  project        box reads sum_a |S_a| B 8 + coefficient writes
+  expand_planes  coefficient reads + plane-partial writes (U2)
+  expand_rows    read + write of every touched row chunk (2 * points * B * 8)
+                 + plane-partial reads
+The roofline object is the dominant (longest) kernel's bytes over its mean
+duration, both measured in this run with HIP events that the library records
+around its own launches on the launch stream, against 8 TB/s.  `traffic` is
+the dominant kernel's HBM bytes per launch from rocprofv3 FETCH_SIZE /
+WRITE_SIZE counters (profiles/traffic.json), reported only while the kernel
+source is the one the counters were taken with.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -27,6 +37,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+KERNEL_SRC = os.path.join(ROOT, "paper_1905_00480_amd", "csrc", "sho_kernels.hip")
+TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
 
 
 def parse():
@@ -35,12 +47,31 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample")
     ap.add_argument("--copy-calib", action="store_true",
                     help="first run a plain 1 GiB elementwise copy kernel (reads 1 GiB, "
                          "writes 1 GiB) so that profiler byte counters can be scaled")
     return ap.parse_args()
+
+
+def kernel_source_sha():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from committed counter runs, if they
+    were taken with the current kernel source."""
+    try:
+        with open(TRAFFIC) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    rec = t.get("kernels", {}).get(kernel)
+    if not rec or t.get("kernel_source_sha") != kernel_source_sha():
+        return None
+    return rec.get("hbm_bytes_per_launch")
 
 
 def cpu_baseline(s, psi, c, target_s):
@@ -62,9 +93,11 @@ def cpu_baseline(s, psi, c, target_s):
         oracle.expand(*sub.geometry(), csub, out)
         return time.perf_counter() - t0, atoms
 
-    t, atoms = run(2)
-    k = int(np.clip(2 * target_s / max(t, 1e-3), 2, s.natoms))
+    k = 16
     t, atoms = run(k)
+    while t < target_s / 3 and k < s.natoms:
+        k = int(min(s.natoms, max(2 * k, k * target_s / max(t, 1e-3) * 0.9)))
+        t, atoms = run(k)
     pts = sum(len(oracle.support(s.n, s.h, s.periodic, s.pos[a],
                                  oracle.box_radius(s.sigma[a], s.numax[a], s.h))[1])
               for a in atoms)
@@ -93,24 +126,21 @@ def main():
     s = wl.scale()
     psi_h = wl.psi_for(s)
     c_h = wl.coeffs_for(s)
+    t0 = time.perf_counter()
     plan = bd.Plan.from_system(s)
+    plan_s = time.perf_counter() - t0
     psi = torch.from_numpy(psi_h).to(dev)
     c = torch.empty(plan.coeff_doubles, dtype=torch.float64, device=dev)
     out = torch.zeros_like(psi)
     B = s.nbands
-    S = plan.support_points
+    info = plan.info
+    S = info["support_points"]
     units = S * B  # gridpoint*bands per step
     stream = torch.cuda.current_stream()
 
-    def step(ev=None):
-        if ev is not None:
-            ev[0].record(stream)
+    def step():
         plan.project(psi, c)
-        if ev is not None:
-            ev[1].record(stream)
         plan.expand(c, out)
-        if ev is not None:
-            ev[2].record(stream)
 
     if args.copy_calib:
         x = torch.ones(1 << 27, dtype=torch.float64, device=dev)
@@ -122,30 +152,42 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)]
-           for _ in range(args.steps)]
+    # timed region: exactly `steps` steps
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
+    w0 = time.perf_counter()
     t_start.record(stream)
-    for k in range(args.steps):
-        step(evs[k])
+    for _ in range(args.steps):
+        step()
     t_end.record(stream)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    total_ms = t_start.elapsed_time(t_end)
-    prj_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
-    add_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
-    ms_per_step = total_ms / args.steps
+    wall = time.perf_counter() - w0
+    ms_per_step = t_start.elapsed_time(t_end) / args.steps
+
+    # per-kernel durations: a second pass with the library's launch events
+    plan.profile(True)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    prof = plan.profile_read()
+    plan.profile(False)
 
     coeff_bytes = plan.coeff_doubles * 8
-    prj_bytes = S * B * 8 + coeff_bytes          # psi box reads + c write
-    add_bytes = 2 * S * B * 8 + coeff_bytes      # psi box read+write + c read
-    prj_gbs = prj_bytes / (prj_ms * 1e-3) / 1e9
-    add_gbs = add_bytes / (add_ms * 1e-3) / 1e9
-    dom = ("expand", add_bytes, add_ms, add_gbs) if add_ms >= prj_ms else \
-          ("project", prj_bytes, prj_ms, prj_gbs)
+    u2_bytes = info["expand_scratch_doubles"] * 8
+    kbytes = {
+        "project": S * B * 8 + coeff_bytes,
+        "expand_planes": coeff_bytes + u2_bytes,
+        "expand_rows": 2 * info["expand_points"] * B * 8 + u2_bytes,
+    }
+    kernels = {}
+    for k, nbytes in kbytes.items():
+        n, ms = prof[k]
+        kernels[k] = {"launches": n, "ms": ms, "bytes": nbytes,
+                      "GB/s": nbytes / (ms * 1e-3) / 1e9 if ms > 0 else None}
+    dom = max(kernels, key=lambda k: kernels[k]["ms"])
+    d = kernels[dom]
+    traffic = measured_traffic(dom)
 
     rec = {
         "metric": "projected gridpoint*bands/s",
@@ -163,14 +205,15 @@ def main():
         "config": {"workload": "scale: periodic 128^3, h=0.2 Bohr, 512 atoms (RSA 2 Bohr), "
                                "sigma=0.6, nu_max=5 (56 functions), 32 FP64 bands; "
                                "step = projection + expansion",
-                   "global_batch": B, "support_points": S, "grid": list(s.n),
-                   "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "kernel": dom[0], "achieved": dom[3],
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dom[3] / HBM_PEAK_GBS,
-                     "traffic": None, "algorithmic_bytes_per_launch": dom[1],
-                     "launch_ms": dom[2]},
-        "kernels": {"project": {"ms": prj_ms, "GB/s": prj_gbs, "bytes": prj_bytes},
-                    "expand": {"ms": add_ms, "GB/s": add_gbs, "bytes": add_bytes}},
+                   "bands": B, "support_points": S,
+                   "union_points": info["union_points"], "grid": list(s.n)},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": d["GB/s"],
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": d["GB/s"] / HBM_PEAK_GBS, "traffic": traffic,
+                     "algorithmic_bytes_per_launch": d["bytes"], "launch_ms": d["ms"]},
+        "kernels": kernels,
+        "per_atom_box_GB/s": 3 * S * B * 8 / (ms_per_step * 1e-3) / 1e9,
+        "plan_build_s": plan_s,
         "wall_s_timed": wall,
     }
     if not args.no_cpu_baseline:

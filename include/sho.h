@@ -108,6 +108,10 @@ typedef struct sho_plan_info {
   int64_t planes;          /* z planes over all supports */
   int64_t device_bytes;    /* device memory owned by the plan */
   int64_t stored_bytes;    /* of which stored projector tables */
+  int64_t union_points;    /* distinct grid points covered by any support */
+  int64_t expand_points;   /* grid points the expansion reads and writes
+                              (whole row chunks that some support touches) */
+  int64_t expand_scratch_doubles; /* plane partials of the expansion */
 } sho_plan_info;
 
 /* N_SHO(nu) = (nu+1)(nu+2)(nu+3)/6 (sec. 2.5); -1 if nu < 0. */
@@ -184,6 +188,26 @@ sho_status sho_force(const sho_grid *grid, int32_t natoms, const double *pos,
                      const double *sigma, const int32_t *numax, int32_t nbands,
                      const double *psi, const double *w, double *grad,
                      uint32_t flags, void *stream);
+
+/*
+ * Kernel timing for benchmarks: while enabled, every kernel launch made with
+ * this plan is bracketed by HIP events recorded on the call's stream.
+ * sho_plan_profile(plan, 1) clears and starts recording, (plan, 0) stops.
+ * sho_plan_profile_read waits for the recorded events and returns, per
+ * kernel kind, the number of launches and their mean duration in ms:
+ *   SHO_KERNEL_PROJECT, SHO_KERNEL_EXPAND_PLANES (z pass of the expansion),
+ *   SHO_KERNEL_EXPAND_ROWS (y and x passes), SHO_KERNEL_FORCE.
+ * counts and mean_ms: host arrays [SHO_KERNEL_KINDS].  Not for use inside a
+ * captured graph.
+ */
+#define SHO_KERNEL_PROJECT 0
+#define SHO_KERNEL_EXPAND_PLANES 1
+#define SHO_KERNEL_EXPAND_ROWS 2
+#define SHO_KERNEL_FORCE 3
+#define SHO_KERNEL_KINDS 4
+sho_status sho_plan_profile(sho_plan_t plan, int32_t enable);
+sho_status sho_plan_profile_read(sho_plan_t plan, int64_t *counts,
+                                 double *mean_ms);
 
 /* Drop every plan held by the stateless cache (waits for the device). */
 sho_status sho_cache_clear(void);

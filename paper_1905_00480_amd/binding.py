@@ -37,8 +37,9 @@ EXPORTS = (
     "sho_plan_get_info", "sho_plan_coeff_offsets", "sho_plan_support_counts",
     "sho_plan_set_centres", "sho_plan_project", "sho_plan_expand",
     "sho_plan_force", "sho_project", "sho_expand", "sho_force",
-    "sho_cache_clear",
+    "sho_cache_clear", "sho_plan_profile", "sho_plan_profile_read",
 )
+KERNEL_KINDS = ("project", "expand_planes", "expand_rows", "force")
 
 
 class ShoError(RuntimeError):
@@ -58,7 +59,9 @@ class sho_plan_info(ctypes.Structure):
                 ("coeff_rows", ctypes.c_int64), ("coeff_doubles", ctypes.c_int64),
                 ("support_points", ctypes.c_int64), ("lines", ctypes.c_int64),
                 ("planes", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
-                ("stored_bytes", ctypes.c_int64)]
+                ("stored_bytes", ctypes.c_int64), ("union_points", ctypes.c_int64),
+                ("expand_points", ctypes.c_int64),
+                ("expand_scratch_doubles", ctypes.c_int64)]
 
 
 _lib = None
@@ -102,6 +105,8 @@ def load_library(path=None):
     lib.sho_expand.argtypes = geo + [_vp, _vp, ctypes.c_uint32, _vp]
     lib.sho_force.argtypes = geo + [_vp, _vp, _vp, ctypes.c_uint32, _vp]
     lib.sho_cache_clear.argtypes = []
+    lib.sho_plan_profile.argtypes = [P, ctypes.c_int32]
+    lib.sho_plan_profile_read.argtypes = [P, _i64p, _dp]
     for name in EXPORTS:
         if name not in ("sho_nsho", "sho_last_error"):
             getattr(lib, name).restype = ctypes.c_int32
@@ -232,6 +237,18 @@ class Plan:
             _dev(w, self.coeff_doubles, "w"), _dev(grad, 3 * self.natoms, "grad"),
             _stream(stream)))
         return grad
+
+    def profile(self, enable=True):
+        """Start (clear) or stop per-kernel event timing of this plan."""
+        _check(self._lib.sho_plan_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        """{kind: (launches, mean ms)} of the calls made while profiling."""
+        cnt = np.zeros(len(KERNEL_KINDS), dtype=np.int64)
+        ms = np.zeros(len(KERNEL_KINDS))
+        _check(self._lib.sho_plan_profile_read(self._h, cnt.ctypes.data_as(_i64p),
+                                               ms.ctypes.data_as(_dp)))
+        return {k: (int(cnt[i]), float(ms[i])) for i, k in enumerate(KERNEL_KINDS)}
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -30,6 +30,11 @@ sho_status hip_fail(hipError_t e, const char *what) {
               std::string(what) + ": " + hipGetErrorString(e));
 }
 
+struct ProfEvent {
+  int kind;
+  hipEvent_t a, b;
+};
+
 struct Group {
   int32_t nu;
   int32_t work_begin;  // into the device work-item array
@@ -54,6 +59,8 @@ struct sho_plan_s {
   int64_t *d_u2_off = nullptr;
   int32_t *d_nu_atoms = nullptr;
   double *d_u2 = nullptr;  // expansion plane partials, allocated on first use
+  bool prof_on = false;
+  std::vector<ProfEvent> prof;
   int64_t device_bytes = 0;
   int64_t stored_bytes = 0;
 };
@@ -109,6 +116,29 @@ sho::KArgs make_args(const sho_plan_s *p, const Group &g) {
   const double h = p->hp.grid.h;
   K.h3 = h * h * h;
   return K;
+}
+
+void prof_clear(sho_plan_s *p) {
+  for (ProfEvent &ev : p->prof) {
+    (void)hipEventDestroy(ev.a);
+    (void)hipEventDestroy(ev.b);
+  }
+  p->prof.clear();
+}
+
+// Runs f (a sequence of launches on s), bracketed by events when profiling.
+template <typename F>
+hipError_t timed(sho_plan_s *p, int kind, hipStream_t s, F &&f) {
+  if (!p->prof_on) return f();
+  ProfEvent ev{kind, nullptr, nullptr};
+  hipError_t e = hipEventCreate(&ev.a);
+  if (e == hipSuccess) e = hipEventCreate(&ev.b);
+  if (e == hipSuccess) e = hipEventRecord(ev.a, s);
+  if (e != hipSuccess) return e;
+  e = f();
+  hipError_t e2 = hipEventRecord(ev.b, s);
+  p->prof.push_back(ev);
+  return e != hipSuccess ? e : e2;
 }
 
 sho::EArgs make_eargs(const sho_plan_s *p) {
@@ -281,6 +311,7 @@ sho_status sho_plan_destroy(sho_plan_t p) {
     delete p;
     return SHO_OK;
   }
+  prof_clear(p);
   int cur = 0;
   (void)hipGetDevice(&cur);
   if (cur != p->device) (void)hipSetDevice(p->device);
@@ -289,6 +320,32 @@ sho_status sho_plan_destroy(sho_plan_t p) {
   if (cur != p->device) (void)hipSetDevice(cur);
   delete p;
   if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+  return SHO_OK;
+}
+
+sho_status sho_plan_profile(sho_plan_t p, int32_t enable) {
+  if (!p) return fail(SHO_E_INVALID, "NULL plan");
+  if (p->hp.flags & SHO_FLAG_HOST_ONLY)
+    return fail(SHO_E_INVALID, "host-only plan cannot run kernels");
+  if (enable) prof_clear(p);
+  p->prof_on = enable != 0;
+  return SHO_OK;
+}
+
+sho_status sho_plan_profile_read(sho_plan_t p, int64_t *counts, double *mean_ms) {
+  if (!p || !counts || !mean_ms) return fail(SHO_E_INVALID, "NULL argument");
+  double sum[SHO_KERNEL_KINDS] = {0, 0, 0, 0};
+  for (int k = 0; k < SHO_KERNEL_KINDS; ++k) counts[k] = 0;
+  for (ProfEvent &ev : p->prof) {
+    float ms = 0.f;
+    hipError_t e = hipEventSynchronize(ev.b);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev.a, ev.b);
+    if (e != hipSuccess) return hip_fail(e, "profile events");
+    sum[ev.kind] += ms;
+    counts[ev.kind]++;
+  }
+  for (int k = 0; k < SHO_KERNEL_KINDS; ++k)
+    mean_ms[k] = counts[k] ? sum[k] / (double)counts[k] : 0.0;
   return SHO_OK;
 }
 
@@ -305,6 +362,11 @@ sho_status sho_plan_get_info(sho_plan_t p, sho_plan_info *info) {
   info->planes = (int64_t)p->hp.planes.size();
   info->device_bytes = p->device_bytes;
   info->stored_bytes = p->stored_bytes;
+  info->union_points = p->hp.union_points;
+  // the row kernel moves whole chunks of touched rows: with 32 or 64 bands
+  // per tile a chunk spans 64 or 32 points (2048 doubles)
+  info->expand_points = p->hp.rows_touched * (int64_t)p->hp.grid.n[0];
+  info->expand_scratch_doubles = p->hp.u2_doubles;
   return SHO_OK;
 }
 
@@ -367,11 +429,15 @@ sho_status sho_plan_project(sho_plan_t p, const double *psi, double *c,
     hipError_t e = sho::launch_fill(c, p->hp.coeff_rows * p->hp.nbands, 0.0, s);
     if (e != hipSuccess) return hip_fail(e, "fill");
   }
-  for (const Group &g : p->groups) {
-    sho::KArgs K = make_args(p, g);
-    hipError_t e = sho::launch_project(g.nu, K, psi, c, s);
-    if (e != hipSuccess) return hip_fail(e, "project launch");
-  }
+  hipError_t e = timed(p, SHO_KERNEL_PROJECT, s, [&]() {
+    for (const Group &g : p->groups) {
+      sho::KArgs K = make_args(p, g);
+      hipError_t e1 = sho::launch_project(g.nu, K, psi, c, s);
+      if (e1 != hipSuccess) return e1;
+    }
+    return hipSuccess;
+  });
+  if (e != hipSuccess) return hip_fail(e, "project launch");
   return SHO_OK;
 }
 
@@ -399,7 +465,11 @@ sho_status sho_plan_expand(sho_plan_t p, const double *c, double *psi,
     p->device_bytes += std::max<int64_t>(p->hp.u2_doubles, 1) * sizeof(double);
   }
   sho::EArgs E = make_eargs(p);
-  hipError_t e = sho::launch_expand_rows(E, c, p->d_u2, psi, s);
+  hipError_t e = timed(p, SHO_KERNEL_EXPAND_PLANES, s,
+                       [&]() { return sho::launch_expand_planes(E, c, p->d_u2, s); });
+  if (e == hipSuccess)
+    e = timed(p, SHO_KERNEL_EXPAND_ROWS, s,
+              [&]() { return sho::launch_rows(E, p->d_u2, psi, s); });
   if (e != hipSuccess) return hip_fail(e, "expand launch");
   return SHO_OK;
 }
@@ -416,11 +486,15 @@ sho_status sho_plan_force(sho_plan_t p, const double *psi, const double *w,
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = sho::launch_fill(grad, 3 * (int64_t)p->hp.natoms, 0.0, s);
   if (e != hipSuccess) return hip_fail(e, "fill");
-  for (const Group &g : p->groups) {
-    sho::KArgs K = make_args(p, g);
-    e = sho::launch_force(g.nu, K, psi, w, grad, s);
-    if (e != hipSuccess) return hip_fail(e, "force launch");
-  }
+  e = timed(p, SHO_KERNEL_FORCE, s, [&]() {
+    for (const Group &g : p->groups) {
+      sho::KArgs K = make_args(p, g);
+      hipError_t e1 = sho::launch_force(g.nu, K, psi, w, grad, s);
+      if (e1 != hipSuccess) return e1;
+    }
+    return hipSuccess;
+  });
+  if (e != hipSuccess) return hip_fail(e, "force launch");
   return SHO_OK;
 }
 

@@ -126,6 +126,8 @@ struct HostPlan {
                                        // per-plane expansion partials
   std::vector<int32_t> nu_atoms;       // atoms with a support, sorted by nu
   int64_t u2_doubles = 0;
+  int64_t union_points = 0;   // distinct grid points covered by any support
+  int64_t rows_touched = 0;   // memory rows with at least one run
   std::vector<double> support_centre;  // [natoms][3], fixed at creation
   std::vector<int64_t> coeff_off;      // [natoms+1] in doubles
   int64_t coeff_rows = 0;

@@ -639,8 +639,8 @@ hipError_t launch_force(int nu, const KArgs &K, const double *psi,
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_expand_rows(const EArgs &E, const double *c, double *u2,
-                              double *psi, hipStream_t s) {
+hipError_t launch_expand_planes(const EArgs &E, const double *c, double *u2,
+                                hipStream_t s) {
   for (int nu = 0; nu <= SHO_NU_MAX; ++nu) {
     const int cnt = E.nu_begin[nu + 1] - E.nu_begin[nu];
     if (cnt <= 0) continue;
@@ -656,6 +656,11 @@ hipError_t launch_expand_rows(const EArgs &E, const double *c, double *u2,
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
+  return hipSuccess;
+}
+
+hipError_t launch_rows(const EArgs &E, const double *u2, double *psi,
+                       hipStream_t s) {
   if (E.nrows > 0) {
     const int xchunk = kRowChunkDoubles >> E.tbe_shift;
     const dim3 g((unsigned)E.nrows, (unsigned)((E.nx + xchunk - 1) / xchunk),
@@ -676,6 +681,13 @@ hipError_t launch_expand_rows(const EArgs &E, const double *c, double *u2,
     }
   }
   return hipGetLastError();
+}
+
+hipError_t launch_expand_rows(const EArgs &E, const double *c, double *u2,
+                              double *psi, hipStream_t s) {
+  hipError_t e = launch_expand_planes(E, c, u2, s);
+  if (e != hipSuccess) return e;
+  return launch_rows(E, u2, psi, s);
 }
 
 hipError_t launch_tables(const AtomRec *atoms, int32_t natoms, double h,

@@ -53,6 +53,11 @@ hipError_t launch_project(int nu, const KArgs &K, const double *psi, double *c,
 // contributions of all runs that fall into it.  u2: E's u2 buffer.
 hipError_t launch_expand_rows(const EArgs &E, const double *c, double *u2,
                               double *psi, hipStream_t s);
+// The two halves of launch_expand_rows.
+hipError_t launch_expand_planes(const EArgs &E, const double *c, double *u2,
+                                hipStream_t s);
+hipError_t launch_rows(const EArgs &E, const double *u2, double *psi,
+                       hipStream_t s);
 // grad must be zeroed first (launch_fill)
 hipError_t launch_force(int nu, const KArgs &K, const double *psi,
                         const double *w, double *grad, hipStream_t s);

@@ -329,6 +329,20 @@ void build_rows(HostPlan *P) {
   std::vector<int32_t> fill(count.begin(), count.end() - 1);
   for (int32_t i = 0; i < (int32_t)P->lines.size(); ++i)
     P->row_runs[fill[P->lines[i].row]++] = i;
+  // distinct covered points: union of the runs' x ranges per row
+  P->union_points = 0;
+  P->rows_touched = 0;
+  std::vector<uint8_t> mark(P->grid.n[0]);
+  for (int64_t r = 0; r < nrows_grid; ++r) {
+    if (count[r + 1] == count[r]) continue;
+    P->rows_touched++;
+    std::fill(mark.begin(), mark.end(), 0);
+    for (int32_t k = count[r]; k < count[r + 1]; ++k) {
+      const LineRec &L = P->lines[P->row_runs[k]];
+      for (int x = L.x0m; x < L.x0m + L.len; ++x) mark[x] = 1;
+    }
+    for (uint8_t m : mark) P->union_points += m;
+  }
   // non-empty rows, one list per plane class z mod 8, interleaved in groups
   // of kRowsPerGroup so that workgroup g (dispatched to XCD g mod 8) works on
   // planes of one class
