@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-stored", action="store_true",
+                    help="skip timing the stored-projector baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample")
     ap.add_argument("--copy-calib", action="store_true",
@@ -106,6 +108,40 @@ def cpu_baseline(s, psi, c, target_s):
             "kind": "oracle",
             "sample": "%d of %d atoms (all %d bands, full grid), projection + expansion, "
                       "%.1f s" % (len(atoms), s.natoms, s.nbands, t)}
+
+
+def stored_baseline(bd, s, psi, c, out, args):
+    """The same step with the projector values sampled once into HBM and read
+    back (SHO_FLAG_STORED), timed like the main step."""
+    import torch
+    plan = bd.Plan.from_system(s, flags=bd.FLAG_STORED)
+
+    def step():
+        plan.project(psi, c)
+        plan.expand(c, out)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for _ in range(args.steps):
+        step()
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / args.steps
+    plan.profile(True)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    prof = plan.profile_read()
+    plan.close()
+    S = plan.support_points
+    return {"value": S * s.nbands / (ms * 1e-3), "unit": "gridpoint*bands/s",
+            "ms_per_step": ms, "stored_bytes": plan.info["stored_bytes"],
+            "project_ms": prof["project"][1], "expand_ms": prof["expand_rows"][1]}
 
 
 def main():
@@ -216,6 +252,8 @@ def main():
         "plan_build_s": plan_s,
         "wall_s_timed": wall,
     }
+    if not args.no_stored:
+        rec["stored_baseline"] = stored_baseline(bd, s, psi, c, out, args)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(s, psi_h, c_h, args.cpu_seconds)
     plan.close()

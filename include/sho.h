@@ -79,9 +79,15 @@ typedef int32_t sho_status;
 #define SHO_NU_MAX 10
 
 /* Plan flags */
-#define SHO_FLAG_STORED 0x1u              /* precompute P_an(i) into device
-                                             memory and read it back in every
-                                             call (bandwidth baseline) */
+#define SHO_FLAG_STORED 0x1u              /* precompute P_an(i) for every
+                                             support point into device memory
+                                             (N_SHO doubles per point) and read
+                                             it back in every projection and
+                                             expansion: the stored-projector
+                                             bandwidth baseline (sec. 6, the
+                                             paper's USU kernels); nu <= 5.
+                                             The derivative still generates
+                                             its functions. */
 #define SHO_FLAG_ALLOW_UNDERSAMPLED 0x2u  /* skip the sampling bound check */
 #define SHO_FLAG_HOST_ONLY 0x4u           /* geometry and sizes only: no device
                                              call, no device memory; the

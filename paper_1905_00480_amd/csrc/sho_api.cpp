@@ -59,6 +59,8 @@ struct sho_plan_s {
   int64_t *d_u2_off = nullptr;
   int32_t *d_nu_atoms = nullptr;
   double *d_u2 = nullptr;  // expansion plane partials, allocated on first use
+  double *d_stored = nullptr;     // stored projectors (SHO_FLAG_STORED)
+  int64_t *d_run_poff = nullptr;
   bool prof_on = false;
   std::vector<ProfEvent> prof;
   int64_t device_bytes = 0;
@@ -93,6 +95,10 @@ void free_plan_device(sho_plan_s *p) {
   p->d_u2_off = nullptr;
   p->d_nu_atoms = nullptr;
   p->d_u2 = nullptr;
+  if (p->d_stored) (void)hipFree(p->d_stored);
+  if (p->d_run_poff) (void)hipFree(p->d_run_poff);
+  p->d_stored = nullptr;
+  p->d_run_poff = nullptr;
   p->d_atoms = nullptr;
   p->d_lines = nullptr;
   p->d_bundles = nullptr;
@@ -107,6 +113,8 @@ sho::KArgs make_args(const sho_plan_s *p, const Group &g) {
   K.bundles = p->d_bundles;
   K.work = p->d_work + g.work_begin;
   K.tab = p->d_tab;
+  K.stored = p->d_stored;
+  K.run_poff = p->d_run_poff;
   K.nwork = g.count;
   K.nx = p->hp.grid.n[0];
   K.B = p->hp.nbands;
@@ -218,8 +226,6 @@ sho_status sho_plan_create(const sho_grid *grid, int32_t natoms,
                            int32_t nbands, uint32_t flags, sho_plan_t *out) {
   if (!out) return fail(SHO_E_INVALID, "out must not be NULL");
   *out = nullptr;
-  if (flags & SHO_FLAG_STORED)
-    return fail(SHO_E_INVALID, "stored-projector plans are not available yet");
   sho_plan_s *p = new (std::nothrow) sho_plan_s();
   if (!p) return fail(SHO_E_NOMEM, "host allocation failed");
   std::string msg;
@@ -295,6 +301,21 @@ sho_status sho_plan_create(const sho_grid *grid, int32_t natoms,
   p->device_bytes += std::max<int64_t>(p->hp.table_doubles, 1) * sizeof(double);
   e = sho::launch_tables(p->d_atoms, p->hp.natoms, p->hp.grid.h, p->d_tab, p->hp.m_max,
                          nullptr);
+  if (e == hipSuccess && (flags & SHO_FLAG_STORED)) {
+    sho::build_stored_offsets(&p->hp);
+    e = upload(&p->d_run_poff, p->hp.run_poff, &p->device_bytes);
+    if (e == hipSuccess)
+      e = hipMalloc((void **)&p->d_stored,
+                    std::max<int64_t>(p->hp.stored_doubles, 1) * sizeof(double));
+    if (e == hipSuccess) {
+      p->stored_bytes = std::max<int64_t>(p->hp.stored_doubles, 1) * sizeof(double);
+      p->device_bytes += p->stored_bytes;
+      Group all{0, 0, 0};
+      sho::KArgs K = make_args(p, all);
+      e = sho::launch_store(K, p->d_run_atom, (int32_t)p->hp.lines.size(), p->d_stored,
+                            nullptr);
+    }
+  }
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     free_plan_device(p);
@@ -387,6 +408,8 @@ sho_status sho_plan_set_centres(sho_plan_t p, const double *pos, void *stream) {
   if (!p || (!pos && p->hp.natoms)) return fail(SHO_E_INVALID, "NULL plan or pos");
   if (p->hp.flags & SHO_FLAG_HOST_ONLY)
     return fail(SHO_E_INVALID, "host-only plan has no device tables");
+  if (p->hp.flags & SHO_FLAG_STORED)
+    return fail(SHO_E_INVALID, "stored-projector plans cannot move their centres");
   for (int32_t a = 0; a < p->hp.natoms; ++a)
     for (int d = 0; d < 3; ++d)
       if (!std::isfinite(pos[3 * a + d]))
@@ -432,7 +455,9 @@ sho_status sho_plan_project(sho_plan_t p, const double *psi, double *c,
   hipError_t e = timed(p, SHO_KERNEL_PROJECT, s, [&]() {
     for (const Group &g : p->groups) {
       sho::KArgs K = make_args(p, g);
-      hipError_t e1 = sho::launch_project(g.nu, K, psi, c, s);
+      hipError_t e1 = (p->hp.flags & SHO_FLAG_STORED)
+                          ? sho::launch_project_stored(g.nu, K, psi, c, s)
+                          : sho::launch_project(g.nu, K, psi, c, s);
       if (e1 != hipSuccess) return e1;
     }
     return hipSuccess;
@@ -453,6 +478,18 @@ sho_status sho_plan_expand(sho_plan_t p, const double *c, double *psi,
       (const char *)psi < (const char *)c + coeff_bytes(p))
     return fail(SHO_E_INVALID, "psi and c overlap");
   hipStream_t s = (hipStream_t)stream;
+  if (p->hp.flags & SHO_FLAG_STORED) {
+    hipError_t e = timed(p, SHO_KERNEL_EXPAND_ROWS, s, [&]() {
+      for (const Group &g : p->groups) {
+        sho::KArgs K = make_args(p, g);
+        hipError_t e1 = sho::launch_expand_stored(g.nu, K, c, psi, s);
+        if (e1 != hipSuccess) return e1;
+      }
+      return hipSuccess;
+    });
+    if (e != hipSuccess) return hip_fail(e, "expand launch");
+    return SHO_OK;
+  }
   if (!p->d_u2) {
     hipError_t e = hipMalloc((void **)&p->d_u2,
                              std::max<int64_t>(p->hp.u2_doubles, 1) * sizeof(double));

@@ -126,6 +126,9 @@ struct HostPlan {
                                        // per-plane expansion partials
   std::vector<int32_t> nu_atoms;       // atoms with a support, sorted by nu
   int64_t u2_doubles = 0;
+  std::vector<int64_t> run_poff;      // stored projectors: first double of
+                                      // each run's [len][N_SHO] block
+  int64_t stored_doubles = 0;
   int64_t union_points = 0;   // distinct grid points covered by any support
   int64_t rows_touched = 0;   // memory rows with at least one run
   std::vector<double> support_centre;  // [natoms][3], fixed at creation
@@ -166,6 +169,12 @@ void build_work(HostPlan *P, int tb_shift, int64_t target_points);
 // eight XCDs so that all rows of one plane share an L2, per-atom offsets of
 // the plane partials U2[jz][pair][band].
 void build_rows(HostPlan *P);
+
+// Offsets of the stored projector blocks (SHO_FLAG_STORED plans).
+void build_stored_offsets(HostPlan *P);
+
+// Largest nu the stored-projector variant supports (56 functions).
+constexpr int32_t kStoredNuMax = 5;
 
 // Largest table extent the kernels accept per axis.
 constexpr int32_t kMaxTable = 512;

@@ -497,6 +497,136 @@ __global__ __launch_bounds__(kRowBlock) void k_expand_rows(EArgs E,
   }
 }
 
+// ------------------------------------------------- stored projectors --
+
+// P[run][k][n] = phi_nx(x) phi_ny(y) phi_nz(z) at point k of the run, for all
+// n of the atom's basis (nz-major order).  One workgroup per run.
+__global__ __launch_bounds__(256) void k_store(KArgs K, const int32_t *__restrict__ run_atom,
+                                               double *__restrict__ stored) {
+  const int run = blockIdx.x;
+  const LineRec ln = K.lines[run];
+  const AtomRec A = K.atoms[run_atom[run]];
+  const int nu = A.nu;
+  const int ns = (nu + 1) * (nu + 2) * (nu + 3) / 6;
+  const int nfp = A.tab_nfp;
+  const double *tx = K.tab + A.tab_off;
+  const double *fy = tx + (int64_t)(A.mx + ln.jy) * nfp;
+  const double *fz = tx + (int64_t)(A.mx + A.my + ln.jz) * nfp;
+  double *out = stored + K.run_poff[run];
+  for (int t = threadIdx.x; t < ln.len * ns; t += blockDim.x) {
+    const int k = t / ns;
+    int n = t - k * ns;
+    int nz = 0;
+    while (n >= (nu - nz + 1) * (nu - nz + 2) / 2) {
+      n -= (nu - nz + 1) * (nu - nz + 2) / 2;
+      ++nz;
+    }
+    int ny = 0;
+    while (n >= nu - nz - ny + 1) {
+      n -= nu - nz - ny + 1;
+      ++ny;
+    }
+    const int nx = n;
+    const double *fx = tx + (int64_t)(ln.jx0 + k) * nfp;
+    out[t] = fx[nx] * fy[ny] * fz[nz];
+  }
+}
+
+// c[n] = h^3 sum_i P[i][n] psi(i): every lane accumulates all N_SHO
+// coefficients of its band over the points of its runs, reading each point's
+// stored row (the same address for all lanes of a slot).
+template <int NU>
+__global__ __launch_bounds__(kBlock) void k_project_stored(
+    KArgs K, const double *__restrict__ psi, double *__restrict__ c) {
+  constexpr int NF = NU + 1;
+  constexpr int NS = NF * (NF + 1) * (NF + 2) / 6;
+  extern __shared__ double cacc[];
+  const cptr<WorkRec> W = as_const(K.work) + blockIdx.x;
+  const int tile = blockIdx.y;
+  const AtomRec A = load_uniform(K.atoms + W->atom);
+  const int TB = 1 << K.tb_shift;
+  for (int t = threadIdx.x; t < NS * TB; t += blockDim.x) cacc[t] = 0.0;
+  __syncthreads();
+  const int w = wave_id();
+  const Lanes L = lane_geometry(K, tile);
+  double acc[NS];
+#pragma unroll
+  for (int n = 0; n < NS; ++n) acc[n] = 0.0;
+  const int b1 = W->wb[w + 1];
+  for (int bi = W->wb[w]; bi < b1; ++bi) {
+    const BundleRec bd = load_uniform(K.bundles + bi);
+    const RunState rs = run_state(K, L, psi, bd);
+    const int run = bd.run0 + min(L.slot, bd.nruns - 1);
+    const double *prow0 = K.stored + K.run_poff[run];
+    for (int jx = bd.jlo; jx <= bd.jhi; ++jx) {
+      const int k = jx - rs.jx0;
+      const bool ok = rs.active && k >= 0 && k < rs.len;
+      const int kc = min(max(k, 0), rs.len - 1);
+      const double v = ok ? rs.base[kc * K.B] : 0.0;
+      const double *prow = prow0 + (int64_t)kc * NS;
+#pragma unroll
+      for (int n = 0; n < NS; ++n) acc[n] = fma(prow[n], v, acc[n]);
+    }
+  }
+  // fold the slots, then one LDS add per coefficient and lane
+  for (int s = 32; s >= TB; s >>= 1) {
+#pragma unroll
+    for (int n = 0; n < NS; ++n) acc[n] += __shfl_xor(acc[n], s);
+  }
+  if (L.slot == 0 && L.bok) {
+#pragma unroll
+    for (int n = 0; n < NS; ++n) atomicAdd(&cacc[n * TB + L.bl], acc[n]);
+  }
+  __syncthreads();
+  const bool split = W->split != 0;
+  for (int t = threadIdx.x; t < NS * TB; t += blockDim.x) {
+    const int n = t >> K.tb_shift;
+    const int bb = tile * TB + (t & (TB - 1));
+    if (bb >= K.B) continue;
+    double *dst = c + (A.coeff_row + n) * K.B + bb;
+    if (split)
+      unsafeAtomicAdd(dst, K.h3 * cacc[t]);
+    else
+      *dst = K.h3 * cacc[t];
+  }
+}
+
+// psi(i) += sum_n P[i][n] c[n]: every lane keeps its band's coefficients in
+// registers and adds into psi with global FP64 atomics (supports overlap).
+template <int NU>
+__global__ __launch_bounds__(kBlock) void k_expand_stored(
+    KArgs K, const double *__restrict__ c, double *psi) {
+  constexpr int NF = NU + 1;
+  constexpr int NS = NF * (NF + 1) * (NF + 2) / 6;
+  const cptr<WorkRec> W = as_const(K.work) + blockIdx.x;
+  const int tile = blockIdx.y;
+  const AtomRec A = load_uniform(K.atoms + W->atom);
+  const int w = wave_id();
+  const Lanes L = lane_geometry(K, tile);
+  double cr[NS];
+#pragma unroll
+  for (int n = 0; n < NS; ++n) cr[n] = c[(A.coeff_row + n) * K.B + L.bc];
+  const int b1 = W->wb[w + 1];
+  for (int bi = W->wb[w]; bi < b1; ++bi) {
+    const BundleRec bd = load_uniform(K.bundles + bi);
+    const RunState rs = run_state(K, L, psi, bd);
+    const int run = bd.run0 + min(L.slot, bd.nruns - 1);
+    const double *prow0 = K.stored + K.run_poff[run];
+    double *dst = const_cast<double *>(rs.base);
+    const bool live = rs.active && L.bok;
+    for (int jx = bd.jlo; jx <= bd.jhi; ++jx) {
+      const int k = jx - rs.jx0;
+      const bool ok = live && k >= 0 && k < rs.len;
+      const int kc = min(max(k, 0), rs.len - 1);
+      const double *prow = prow0 + (int64_t)kc * NS;
+      double v = 0.0;
+#pragma unroll
+      for (int n = 0; n < NS; ++n) v = fma(prow[n], cr[n], v);
+      if (ok) unsafeAtomicAdd(dst + kc * K.B, v);
+    }
+  }
+}
+
 // ------------------------------------------------------------- derivative --
 
 // Index of (nx, ny, nz) in the nz-major / ny / nx-fastest order at cut-off nu.
@@ -688,6 +818,42 @@ hipError_t launch_expand_rows(const EArgs &E, const double *c, double *u2,
   hipError_t e = launch_expand_planes(E, c, u2, s);
   if (e != hipSuccess) return e;
   return launch_rows(E, u2, psi, s);
+}
+
+#define SHO_STORED_NU_CASES(X) X(0) X(1) X(2) X(3) X(4) X(5)
+
+hipError_t launch_store(const KArgs &K, const int32_t *run_atom, int32_t nruns,
+                        double *stored, hipStream_t s) {
+  if (nruns <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_store, dim3((unsigned)nruns), dim3(256), 0, s, K, run_atom, stored);
+  return hipGetLastError();
+}
+
+hipError_t launch_project_stored(int nu, const KArgs &K, const double *psi,
+                                 double *c, hipStream_t s) {
+  switch (nu) {
+#define X(N)                                                                 \
+  case N:                                                                    \
+    hipLaunchKernelGGL(k_project_stored<N>, grid_of(K), dim3(kBlock),        \
+                       lds_tile_bytes(N + 1, 1 << K.tb_shift), s, K, psi, c); \
+    return hipGetLastError();
+    SHO_STORED_NU_CASES(X)
+#undef X
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_expand_stored(int nu, const KArgs &K, const double *c,
+                                double *psi, hipStream_t s) {
+  switch (nu) {
+#define X(N)                                                                    \
+  case N:                                                                       \
+    hipLaunchKernelGGL(k_expand_stored<N>, grid_of(K), dim3(kBlock), 0, s, K, c, psi); \
+    return hipGetLastError();
+    SHO_STORED_NU_CASES(X)
+#undef X
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_tables(const AtomRec *atoms, int32_t natoms, double h,

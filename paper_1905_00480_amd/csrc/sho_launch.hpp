@@ -14,6 +14,8 @@ struct KArgs {
   const BundleRec *bundles;
   const WorkRec *work;       // work items of this launch (one nu)
   const double *tab;         // 1D tables of all atoms
+  const double *stored;      // stored projectors (SHO_FLAG_STORED plans)
+  const int64_t *run_poff;   // per run: first double of its stored block
   int32_t nwork;
   int32_t nx;                // grid points along x
   int32_t B;                 // bands: stride of one grid point
@@ -58,6 +60,14 @@ hipError_t launch_expand_planes(const EArgs &E, const double *c, double *u2,
                                 hipStream_t s);
 hipError_t launch_rows(const EArgs &E, const double *u2, double *psi,
                        hipStream_t s);
+// Stored-projector baseline: sample P_an at every support point, then
+// project / expand by reading them back (nu <= 5).
+hipError_t launch_store(const KArgs &K, const int32_t *run_atom, int32_t nruns,
+                        double *stored, hipStream_t s);
+hipError_t launch_project_stored(int nu, const KArgs &K, const double *psi,
+                                 double *c, hipStream_t s);
+hipError_t launch_expand_stored(int nu, const KArgs &K, const double *c,
+                                double *psi, hipStream_t s);
 // grad must be zeroed first (launch_fill)
 hipError_t launch_force(int nu, const KArgs &K, const double *psi,
                         const double *w, double *grad, hipStream_t s);

@@ -92,6 +92,13 @@ sho_status build_host_plan(const sho_grid *grid, int32_t natoms,
       *msg = buf;
       return SHO_E_INVALID;
     }
+    if ((flags & SHO_FLAG_STORED) && nu > kStoredNuMax) {
+      snprintf(buf, sizeof buf,
+               "atom %d: nu_max %d above %d, the stored-projector limit", a, nu,
+               kStoredNuMax);
+      *msg = buf;
+      return SHO_E_NU_RANGE;
+    }
     if (nu < 0 || nu > SHO_NU_MAX) {
       snprintf(buf, sizeof buf, "atom %d: nu_max %d outside 0..%d", a, nu,
                SHO_NU_MAX);
@@ -312,6 +319,21 @@ void build_work(HostPlan *P, int tb_shift, int64_t target_points) {
       P->any_split |= parts > 1;
     }
   }
+}
+
+void build_stored_offsets(HostPlan *P) {
+  P->run_poff.assign(P->lines.size() + 1, 0);
+  int64_t off = 0;
+  for (int32_t a = 0; a < P->natoms; ++a) {
+    const AtomRec &A = P->atoms[a];
+    const int64_t ns = nsho(A.nu);
+    for (int32_t r = A.line_begin; r < A.line_begin + A.nlines; ++r) {
+      P->run_poff[r] = off;
+      off += (int64_t)P->lines[r].len * ns;
+    }
+  }
+  P->run_poff[P->lines.size()] = off;
+  P->stored_doubles = off;
 }
 
 void build_rows(HostPlan *P) {

@@ -78,6 +78,10 @@ def test_argument_errors():
                                           [[200.0, 0.8, 0.8]], [0.6], [3], 1,
                                           rbox=[120.0], flags=bd.FLAG_HOST_ONLY))
     _expect(bd.SHO_E_INVALID, lambda: mk(rbox=[1.0, -1.0]))
+    # stored projector tables are offered up to nu = 5 only
+    _expect(bd.SHO_E_NU_RANGE, lambda: mk(numax=[5, 6],
+                                          flags=bd.FLAG_HOST_ONLY | bd.FLAG_STORED))
+    mk(numax=[5, 4], flags=bd.FLAG_HOST_ONLY | bd.FLAG_STORED).close()
 
 
 def test_host_only_plan_refuses_compute():
