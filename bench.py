@@ -49,6 +49,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stored", action="store_true",
                     help="skip timing the stored-projector baseline")
+    ap.add_argument("--no-batching", action="store_true",
+                    help="skip the uneven-atom batching workload")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the request-stream (serving) workload")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-warmup", type=int, default=200)
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample")
     ap.add_argument("--copy-calib", action="store_true",
@@ -144,6 +150,86 @@ def stored_baseline(bd, s, psi, c, out, args):
             "project_ms": prof["project"][1], "expand_ms": prof["expand_rows"][1]}
 
 
+def _time_steps(step, steps, warmup):
+    """Mean ms per step over `steps` back-to-back steps after `warmup`, and the
+    per-step distribution (events between steps)."""
+    import torch
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record(stream)
+    for i in range(steps):
+        step()
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
+    return ev[0].elapsed_time(ev[-1]) / steps, per
+
+
+def batching(bd, wl, args):
+    """Uneven atoms (periodic 160^3, h = 0.18, 2048 atoms, nu 3..9, sigma
+    0.4..1.2, 64 bands): the batched single launch (default, then tuned), its
+    captured graph, and the per-atom launch schedule it must beat."""
+    import torch
+    dev = torch.device("cuda:0")
+    s = wl.batching()
+    psi = torch.from_numpy(wl.psi_for(s)).to(dev)
+    out = torch.zeros_like(psi)
+    plan = bd.Plan.from_system(s)
+    c = torch.empty(plan.coeff_doubles, dtype=torch.float64, device=dev)
+    units = plan.support_points * s.nbands
+    steps = max(3, args.steps // 4)
+    res = {"workload": "batching: periodic 160^3, h=0.18 Bohr, 2048 atoms uniform, "
+                       "nu_max 3..9, sigma 0.4..1.2 Bohr, 64 FP64 bands; step = "
+                       "projection + expansion",
+           "support_points": plan.support_points, "union_points": plan.info["union_points"],
+           "steps": steps}
+
+    def step():
+        plan.project(psi, c)
+        plan.expand(c, out)
+
+    ms, _ = _time_steps(step, steps, 1)
+    res["default"] = {"schedule": plan.schedule(), "ms_per_step": ms,
+                      "value": units / (ms * 1e-3)}
+    tune = plan.tune(psi, c, reps=2)
+    ms, per = _time_steps(step, steps, 1)
+    plan.profile(True)
+    step()
+    torch.cuda.synchronize()
+    prof = plan.profile_read()
+    plan.profile(False)
+    res["tuned"] = {"schedule": plan.schedule(), "tune": tune, "ms_per_step": ms,
+                    "value": units / (ms * 1e-3),
+                    "project_ms": prof["project"][1],
+                    "expand_planes_ms": prof["expand_planes"][1],
+                    "expand_rows_ms": prof["expand_rows"][1],
+                    "project_per_atom_box_GB/s":
+                        (units * 8 + plan.coeff_doubles * 8) / (prof["project"][1] * 1e-3) / 1e9}
+    g = plan.graph(psi, c, out)
+    ms, _ = _time_steps(g.launch, steps, 1)
+    res["graph"] = {"ms_per_step": ms, "value": units / (ms * 1e-3)}
+    g.close()
+    plan.close()
+    ref = bd.Plan.from_system(s, flags=bd.FLAG_PER_ATOM)
+
+    def ref_step():
+        ref.project(psi, c)
+        ref.expand(c, out)
+
+    ms, _ = _time_steps(ref_step, max(2, steps // 2), 1)
+    ref.close()
+    res["per_atom_launches"] = {"ms_per_step": ms, "value": units / (ms * 1e-3),
+                                "launches_per_step": 2 * s.natoms}
+    res["speedup_vs_per_atom"] = res["per_atom_launches"]["ms_per_step"] / min(
+        res["tuned"]["ms_per_step"], res["graph"]["ms_per_step"])
+    del psi, out, c
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -185,21 +271,10 @@ def main():
             torch.mul(x, 1.0, out=y)
         torch.cuda.synchronize()
         del x, y
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    # timed region: exactly `steps` steps
-    t_start = torch.cuda.Event(enable_timing=True)
-    t_end = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
+    # timed region: exactly `steps` steps, events between the steps
     w0 = time.perf_counter()
-    t_start.record(stream)
-    for _ in range(args.steps):
-        step()
-    t_end.record(stream)
-    torch.cuda.synchronize()
+    ms_per_step, per_step = _time_steps(step, args.steps, args.warmup)
     wall = time.perf_counter() - w0
-    ms_per_step = t_start.elapsed_time(t_end) / args.steps
 
     # per-kernel durations: a second pass with the library's launch events
     plan.profile(True)
@@ -250,10 +325,16 @@ def main():
         "kernels": kernels,
         "per_atom_box_GB/s": 3 * S * B * 8 / (ms_per_step * 1e-3) / 1e9,
         "plan_build_s": plan_s,
-        "wall_s_timed": wall,
+        "wall_s_incl_warmup": wall,
+        "step_ms_p10_p50_p90": [float(np.percentile(per_step, q)) for q in (10, 50, 90)],
     }
     if not args.no_stored:
         rec["stored_baseline"] = stored_baseline(bd, s, psi, c, out, args)
+    if not args.no_batching:
+        rec["batching"] = batching(bd, wl, args)
+    if not args.no_serving:
+        from paper_1905_00480_amd import serve
+        rec["serving"] = serve.compare(requests=args.serve_requests, warmup=args.serve_warmup)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(s, psi_h, c_h, args.cpu_seconds)
     plan.close()

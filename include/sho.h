@@ -93,6 +93,18 @@ typedef int32_t sho_status;
                                              call, no device memory; the
                                              compute calls refuse such a plan
                                              (for sizing and admission) */
+#define SHO_FLAG_PER_ATOM 0x8u            /* reference schedule: one launch per
+                                             atom for the projection, the
+                                             derivative and an atom-owner
+                                             expansion (global atomics); the
+                                             batched schedules are measured
+                                             against it */
+
+/* Projection launch schedules (sho_plan_set_schedule, sho_plan_tune) */
+#define SHO_SCHED_BY_NU 0      /* one launch per cut-off nu */
+#define SHO_SCHED_SINGLE 1     /* one launch over all work items, atoms in
+                                  Morton order of their centres */
+#define SHO_SCHED_SINGLE_LPT 2 /* one launch, work items by falling cost */
 
 typedef struct sho_grid {
   int32_t n[3];        /* points along x, y, z */
@@ -112,7 +124,10 @@ typedef struct sho_plan_info {
   int64_t support_points;  /* sum_a |S_a| */
   int64_t lines;           /* (z, y) lines over all supports */
   int64_t planes;          /* z planes over all supports */
-  int64_t device_bytes;    /* device memory owned by the plan */
+  int64_t device_bytes;    /* device memory owned by the plan; for a
+                              SHO_FLAG_HOST_ONLY plan, what a device plan of
+                              the same geometry and flags would own once it
+                              has run every call (admission estimate) */
   int64_t stored_bytes;    /* of which stored projector tables */
   int64_t union_points;    /* distinct grid points covered by any support */
   int64_t expand_points;   /* grid points the expansion reads and writes
@@ -214,6 +229,123 @@ sho_status sho_force(const sho_grid *grid, int32_t natoms, const double *pos,
 sho_status sho_plan_profile(sho_plan_t plan, int32_t enable);
 sho_status sho_plan_profile_read(sho_plan_t plan, int64_t *counts,
                                  double *mean_ms);
+
+/*
+ * Work decomposition of the projection (sec. 6 measures prj and add over
+ * many atoms of one system; these calls batch them).  A work item is one
+ * atom, or a share of an atom of more than target_points support points;
+ * band_tile bands share a lane slot (power of two <= 64, 0 keeps the current
+ * tile).  Plans with several cut-offs start with SHO_SCHED_SINGLE, others
+ * with SHO_SCHED_BY_NU, target_points 16384 and the widest tile that fits.
+ * set_schedule waits for the device (the work tables are replaced);
+ * graphs made before it must be made again (sho_graph_launch refuses them).
+ */
+sho_status sho_plan_set_schedule(sho_plan_t plan, int32_t schedule,
+                                 int32_t band_tile, int64_t target_points);
+sho_status sho_plan_get_schedule(sho_plan_t plan, int32_t *schedule,
+                                 int32_t *band_tile, int64_t *target_points);
+
+typedef struct sho_tune_result {
+  int32_t schedule;      /* chosen SHO_SCHED_* */
+  int32_t band_tile;     /* chosen bands per lane slot */
+  int64_t target_points; /* chosen work item size */
+  double ms;             /* mean projection time of the choice */
+  double ms_before;      /* of the schedule the plan had before */
+  int32_t candidates;    /* schedules timed */
+  int32_t pad;
+} sho_tune_result;
+
+/*
+ * Autotuner: times the projection of psi into c (both device buffers of the
+ * plan's sizes; c is overwritten) under every schedule x work item size
+ * {8192, 16384, 32768} x band tile {current, half}, reps launches each after
+ * one warm-up, on stream, and keeps the fastest.  Synchronous.  result may
+ * be NULL.  Refused (SHO_E_INVALID) on stored and per-atom plans.
+ */
+sho_status sho_plan_tune(sho_plan_t plan, const double *psi, double *c,
+                         int32_t reps, void *stream, sho_tune_result *result);
+
+/*
+ * One captured HIP graph of project(psi -> c) followed by expand(c -> out)
+ * (out accumulates, as in sho_plan_expand), replayable with one launch call.
+ * The buffers are fixed at creation and must outlive the graph; psi and out
+ * may be the same buffer.  The graph holds only kernel nodes (coefficients
+ * are cleared by a fill kernel).  Destroy graphs before their plan; a graph
+ * is refused after its plan's schedule changed.
+ */
+typedef struct sho_graph_s *sho_graph_t;
+sho_status sho_graph_create(sho_plan_t plan, const double *psi, double *c,
+                            double *out, sho_graph_t *graph);
+sho_status sho_graph_launch(sho_graph_t graph, void *stream);
+sho_status sho_graph_destroy(sho_graph_t graph);
+
+/*
+ * Request server.  Systems (geometry, bands, host inputs psi and w) are
+ * registered once; requests name a system and a job:
+ *   SHO_JOB_PROJECT  c    <- project(psi)
+ *   SHO_JOB_EXPAND   out  <- expand(w)        (out cleared first)
+ *   SHO_JOB_FORCE    grad <- force(psi, w)
+ * all on the system's resident buffers.  A system is made resident (plan
+ * tables + psi, out, w, c, grad in device memory: its charge) on its first
+ * request; when the charges would exceed budget_bytes, least recently used
+ * other systems are evicted first.  A system whose charge alone exceeds the
+ * budget is refused with SHO_E_BUDGET.  Requests of one system run in
+ * submission order on one of nstreams streams (1..16, default priority);
+ * different systems overlap.  plan_flags go to every plan (0, or
+ * SHO_FLAG_PER_ATOM for the per-request reference); SHO_FLAG_HOST_ONLY makes
+ * a server that only does the admission bookkeeping (no device use; every
+ * request completes at once).
+ *
+ * submit is asynchronous (it waits only for evictions and admissions);
+ * request_info returns the submit and completion times in seconds since the
+ * server was made (t_done < 0 while running; completion is taken by a
+ * polling thread when the request's event fires).  read copies a resident
+ * system's latest output of a job into host memory (c: coeff_doubles, out:
+ * grid * nbands, grad: natoms * 3) after that system's requests finished.
+ * The host inputs are copied at registration into pinned host buffers that
+ * the server owns; with psi or w NULL they start zeroed, and
+ * sho_server_inputs returns the buffers so that the caller can fill them in
+ * place (before the system's first request, or while it is not resident).
+ * clock returns the server's time (seconds since creation, the clock of
+ * request_info).  One server may be driven from one thread at a time.
+ */
+#define SHO_JOB_PROJECT 0
+#define SHO_JOB_EXPAND 1
+#define SHO_JOB_FORCE 2
+
+typedef struct sho_server_s *sho_server_t;
+
+typedef struct sho_server_stats {
+  int64_t budget_bytes;
+  int64_t resident_bytes;       /* sum of the resident systems' charges */
+  int64_t peak_resident_bytes;
+  int64_t requests, completed;
+  int64_t admissions, evictions, rejected;
+  int32_t systems, resident_systems;
+} sho_server_stats;
+
+sho_status sho_server_create(int64_t budget_bytes, int32_t nstreams,
+                             uint32_t plan_flags, sho_server_t *server);
+sho_status sho_server_add_system(sho_server_t server, const sho_grid *grid,
+                                 int32_t natoms, const double *pos,
+                                 const double *sigma, const int32_t *numax,
+                                 int32_t nbands, const double *psi,
+                                 const double *w, int32_t *system);
+sho_status sho_server_submit(sho_server_t server, int32_t system, int32_t job,
+                             int64_t *request);
+sho_status sho_server_drain(sho_server_t server);
+sho_status sho_server_request_info(sho_server_t server, int64_t request,
+                                   int32_t *system, int32_t *job,
+                                   double *t_submit, double *t_done);
+sho_status sho_server_read(sho_server_t server, int32_t system, int32_t job,
+                           double *host);
+sho_status sho_server_get_stats(sho_server_t server, sho_server_stats *stats);
+sho_status sho_server_system_info(sho_server_t server, int32_t system,
+                                  int64_t *charge_bytes, int32_t *resident);
+sho_status sho_server_inputs(sho_server_t server, int32_t system, double **psi,
+                             double **w);
+sho_status sho_server_clock(sho_server_t server, double *now);
+sho_status sho_server_destroy(sho_server_t server);
 
 /* Drop every plan held by the stateless cache (waits for the device). */
 sho_status sho_cache_clear(void);

@@ -30,6 +30,11 @@ SHO_NU_MAX = 10
 FLAG_STORED = 0x1
 FLAG_ALLOW_UNDERSAMPLED = 0x2
 FLAG_HOST_ONLY = 0x4
+FLAG_PER_ATOM = 0x8
+SCHED_BY_NU = 0
+SCHED_SINGLE = 1
+SCHED_SINGLE_LPT = 2
+SCHEDULES = (SCHED_BY_NU, SCHED_SINGLE, SCHED_SINGLE_LPT)
 
 # every symbol include/sho.h declares
 EXPORTS = (
@@ -38,7 +43,14 @@ EXPORTS = (
     "sho_plan_set_centres", "sho_plan_project", "sho_plan_expand",
     "sho_plan_force", "sho_project", "sho_expand", "sho_force",
     "sho_cache_clear", "sho_plan_profile", "sho_plan_profile_read",
+    "sho_plan_set_schedule", "sho_plan_get_schedule", "sho_plan_tune",
+    "sho_graph_create", "sho_graph_launch", "sho_graph_destroy",
+    "sho_server_create", "sho_server_add_system", "sho_server_submit",
+    "sho_server_drain", "sho_server_request_info", "sho_server_read",
+    "sho_server_get_stats", "sho_server_system_info", "sho_server_inputs",
+    "sho_server_clock", "sho_server_destroy",
 )
+JOB_PROJECT, JOB_EXPAND, JOB_FORCE = 0, 1, 2
 KERNEL_KINDS = ("project", "expand_planes", "expand_rows", "force")
 
 
@@ -62,6 +74,21 @@ class sho_plan_info(ctypes.Structure):
                 ("stored_bytes", ctypes.c_int64), ("union_points", ctypes.c_int64),
                 ("expand_points", ctypes.c_int64),
                 ("expand_scratch_doubles", ctypes.c_int64)]
+
+
+class sho_tune_result(ctypes.Structure):
+    _fields_ = [("schedule", ctypes.c_int32), ("band_tile", ctypes.c_int32),
+                ("target_points", ctypes.c_int64), ("ms", ctypes.c_double),
+                ("ms_before", ctypes.c_double), ("candidates", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
+
+
+class sho_server_stats(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_int64), ("resident_bytes", ctypes.c_int64),
+                ("peak_resident_bytes", ctypes.c_int64), ("requests", ctypes.c_int64),
+                ("completed", ctypes.c_int64), ("admissions", ctypes.c_int64),
+                ("evictions", ctypes.c_int64), ("rejected", ctypes.c_int64),
+                ("systems", ctypes.c_int32), ("resident_systems", ctypes.c_int32)]
 
 
 _lib = None
@@ -107,6 +134,27 @@ def load_library(path=None):
     lib.sho_cache_clear.argtypes = []
     lib.sho_plan_profile.argtypes = [P, ctypes.c_int32]
     lib.sho_plan_profile_read.argtypes = [P, _i64p, _dp]
+    lib.sho_plan_set_schedule.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64]
+    lib.sho_plan_get_schedule.argtypes = [P, _i32p, _i32p, _i64p]
+    lib.sho_plan_tune.argtypes = [P, _vp, _vp, ctypes.c_int32, _vp,
+                                  ctypes.POINTER(sho_tune_result)]
+    lib.sho_graph_create.argtypes = [P, _vp, _vp, _vp, ctypes.POINTER(_vp)]
+    lib.sho_graph_launch.argtypes = [_vp, _vp]
+    lib.sho_graph_destroy.argtypes = [_vp]
+    lib.sho_server_create.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32,
+                                      ctypes.POINTER(_vp)]
+    lib.sho_server_add_system.argtypes = [P, G, ctypes.c_int32, _dp, _dp, _i32p,
+                                          ctypes.c_int32, _dp, _dp, _i32p]
+    lib.sho_server_submit.argtypes = [P, ctypes.c_int32, ctypes.c_int32, _i64p]
+    lib.sho_server_drain.argtypes = [P]
+    lib.sho_server_request_info.argtypes = [P, ctypes.c_int64, _i32p, _i32p, _dp, _dp]
+    lib.sho_server_read.argtypes = [P, ctypes.c_int32, ctypes.c_int32, _dp]
+    lib.sho_server_get_stats.argtypes = [P, ctypes.POINTER(sho_server_stats)]
+    lib.sho_server_system_info.argtypes = [P, ctypes.c_int32, _i64p, _i32p]
+    lib.sho_server_inputs.argtypes = [P, ctypes.c_int32, ctypes.POINTER(_dp),
+                                      ctypes.POINTER(_dp)]
+    lib.sho_server_clock.argtypes = [P, _dp]
+    lib.sho_server_destroy.argtypes = [P]
     for name in EXPORTS:
         if name not in ("sho_nsho", "sho_last_error"):
             getattr(lib, name).restype = ctypes.c_int32
@@ -238,6 +286,29 @@ class Plan:
             _stream(stream)))
         return grad
 
+    def set_schedule(self, schedule, band_tile=0, target_points=16384):
+        _check(self._lib.sho_plan_set_schedule(self._h, int(schedule), int(band_tile),
+                                               int(target_points)))
+
+    def schedule(self):
+        """(schedule, band_tile, target_points) of the projection."""
+        sc, bt, tp = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+        _check(self._lib.sho_plan_get_schedule(self._h, ctypes.byref(sc), ctypes.byref(bt),
+                                               ctypes.byref(tp)))
+        return sc.value, bt.value, tp.value
+
+    def tune(self, psi, c, reps=3, stream=None):
+        """Time the projection schedules on psi -> c and keep the fastest."""
+        r = sho_tune_result()
+        _check(self._lib.sho_plan_tune(
+            self._h, _dev(psi, self.psi_numel, "psi"), _dev(c, self.coeff_doubles, "c"),
+            int(reps), _stream(stream), ctypes.byref(r)))
+        return {k: getattr(r, k) for k, _ in sho_tune_result._fields_ if k != "pad"}
+
+    def graph(self, psi, c, out):
+        """A replayable graph of project(psi -> c) then expand(c -> out)."""
+        return Graph(self, psi, c, out)
+
     def profile(self, enable=True):
         """Start (clear) or stop per-kernel event timing of this plan."""
         _check(self._lib.sho_plan_profile(self._h, 1 if enable else 0))
@@ -253,6 +324,131 @@ class Plan:
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             _check(self._lib.sho_plan_destroy(self._h))
+        self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Graph:
+    """Captured project -> expand of a plan on fixed buffers (sho_graph_*).
+    Holds references to the plan and the buffers so that they outlive it."""
+
+    def __init__(self, plan, psi, c, out):
+        self._lib = plan._lib
+        self._keep = (plan, psi, c, out)
+        h = ctypes.c_void_p()
+        _check(self._lib.sho_graph_create(
+            plan._h, _dev(psi, plan.psi_numel, "psi"), _dev(c, plan.coeff_doubles, "c"),
+            _dev(out, plan.psi_numel, "out"), ctypes.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None):
+        _check(self._lib.sho_graph_launch(self._h, _stream(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(self._lib.sho_graph_destroy(self._h))
+        self._h = ctypes.c_void_p()
+        self._keep = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Request server over resident systems (sho_server_*).  Systems are
+    workloads.System-like objects (n, h, periodic, pos, sigma, numax,
+    nbands)."""
+
+    def __init__(self, budget_bytes, nstreams=4, flags=0):
+        self._lib = load_library()
+        h = ctypes.c_void_p()
+        _check(self._lib.sho_server_create(int(budget_bytes), int(nstreams), int(flags),
+                                           ctypes.byref(h)))
+        self._h = h
+        self._shapes = []
+
+    def add(self, s, psi=None, w=None):
+        """Register a system; psi / w (host arrays) are copied, or left zero
+        for filling in place through inputs()."""
+        grid = make_grid(s.n, s.h, s.periodic)
+        pos = _host_f64(s.pos, (-1, 3))
+        na = pos.shape[0]
+        sig = _host_f64(s.sigma, (na,))
+        nu = _host_i32(s.numax, (na,))
+        ncoef = _ncoeff(nu, s.nbands)
+        npsi = int(np.prod(s.n)) * int(s.nbands)
+        pp = None if psi is None else _host_f64(psi, (npsi,))
+        ww = None if w is None else _host_f64(w, (ncoef,))
+        sid = ctypes.c_int32()
+        _check(self._lib.sho_server_add_system(
+            self._h, ctypes.byref(grid), na, pos.ctypes.data_as(_dp), sig.ctypes.data_as(_dp),
+            nu.ctypes.data_as(_i32p), int(s.nbands),
+            None if pp is None else pp.ctypes.data_as(_dp),
+            None if ww is None else ww.ctypes.data_as(_dp), ctypes.byref(sid)))
+        self._shapes.append((npsi, ncoef, na))
+        return sid.value
+
+    def inputs(self, sid):
+        """numpy views of the system's pinned psi and w input buffers."""
+        pp, ww = _dp(), _dp()
+        _check(self._lib.sho_server_inputs(self._h, int(sid), ctypes.byref(pp),
+                                           ctypes.byref(ww)))
+        npsi, ncoef, _ = self._shapes[sid]
+        if not pp:
+            return None, None
+        return (np.ctypeslib.as_array(pp, shape=(npsi,)),
+                np.ctypeslib.as_array(ww, shape=(max(ncoef, 1),))[:ncoef])
+
+    def submit(self, sid, job):
+        rid = ctypes.c_int64()
+        _check(self._lib.sho_server_submit(self._h, int(sid), int(job), ctypes.byref(rid)))
+        return rid.value
+
+    def drain(self):
+        _check(self._lib.sho_server_drain(self._h))
+
+    def clock(self):
+        t = ctypes.c_double()
+        _check(self._lib.sho_server_clock(self._h, ctypes.byref(t)))
+        return t.value
+
+    def request_info(self, rid):
+        sy, jb = ctypes.c_int32(), ctypes.c_int32()
+        ts, td = ctypes.c_double(), ctypes.c_double()
+        _check(self._lib.sho_server_request_info(self._h, int(rid), ctypes.byref(sy),
+                                                 ctypes.byref(jb), ctypes.byref(ts),
+                                                 ctypes.byref(td)))
+        return sy.value, jb.value, ts.value, td.value
+
+    def read(self, sid, job):
+        npsi, ncoef, na = self._shapes[sid]
+        n = {JOB_PROJECT: ncoef, JOB_EXPAND: npsi, JOB_FORCE: 3 * na}[job]
+        out = np.empty(max(n, 1))
+        _check(self._lib.sho_server_read(self._h, int(sid), int(job), out.ctypes.data_as(_dp)))
+        return out[:n]
+
+    def stats(self):
+        st = sho_server_stats()
+        _check(self._lib.sho_server_get_stats(self._h, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in sho_server_stats._fields_}
+
+    def system_info(self, sid):
+        ch, rs = ctypes.c_int64(), ctypes.c_int32()
+        _check(self._lib.sho_server_system_info(self._h, int(sid), ctypes.byref(ch),
+                                                ctypes.byref(rs)))
+        return ch.value, bool(rs.value)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(self._lib.sho_server_destroy(self._h))
         self._h = ctypes.c_void_p()
 
     def __del__(self):

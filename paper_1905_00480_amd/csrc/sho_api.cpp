@@ -17,8 +17,10 @@
 #include "sho_launch.hpp"
 
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
+
+namespace sho {
 
 sho_status fail(sho_status code, const std::string &msg) {
   g_err = msg;
@@ -26,9 +28,16 @@ sho_status fail(sho_status code, const std::string &msg) {
 }
 
 sho_status hip_fail(hipError_t e, const char *what) {
-  return fail(SHO_E_DEVICE,
-              std::string(what) + ": " + hipGetErrorString(e));
+  (void)hipGetLastError();
+  return fail(SHO_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
+
+}  // namespace sho
+
+namespace {
+
+using sho::fail;
+using sho::hip_fail;
 
 struct ProfEvent {
   int kind;
@@ -61,6 +70,14 @@ struct sho_plan_s {
   double *d_u2 = nullptr;  // expansion plane partials, allocated on first use
   double *d_stored = nullptr;     // stored projectors (SHO_FLAG_STORED)
   int64_t *d_run_poff = nullptr;
+  int64_t *d_atom_poff = nullptr;
+  int64_t *d_atom_pbeg = nullptr;
+  int32_t *d_pidx = nullptr;
+  sho::StoredItem *d_sitems = nullptr;
+  std::vector<Group> sgroups;     // stored work items by nu
+  sho::WorkRec *d_work_single = nullptr;  // all items, one-launch order
+  int64_t sched_version = 0;      // bumped whenever the work items change
+  int64_t sched_bytes = 0;        // device bytes of the schedule tables
   bool prof_on = false;
   std::vector<ProfEvent> prof;
   int64_t device_bytes = 0;
@@ -85,6 +102,8 @@ void free_plan_device(sho_plan_s *p) {
   if (p->d_lines) (void)hipFree(p->d_lines);
   if (p->d_bundles) (void)hipFree(p->d_bundles);
   if (p->d_work) (void)hipFree(p->d_work);
+  if (p->d_work_single) (void)hipFree(p->d_work_single);
+  p->d_work_single = nullptr;
   if (p->d_tab) (void)hipFree(p->d_tab);
   for (void *q : {(void *)p->d_run_atom, (void *)p->d_row_runs, (void *)p->d_rows,
                   (void *)p->d_u2_off, (void *)p->d_nu_atoms, (void *)p->d_u2})
@@ -95,15 +114,64 @@ void free_plan_device(sho_plan_s *p) {
   p->d_u2_off = nullptr;
   p->d_nu_atoms = nullptr;
   p->d_u2 = nullptr;
-  if (p->d_stored) (void)hipFree(p->d_stored);
-  if (p->d_run_poff) (void)hipFree(p->d_run_poff);
+  for (void *q : {(void *)p->d_stored, (void *)p->d_run_poff, (void *)p->d_atom_poff,
+                  (void *)p->d_atom_pbeg, (void *)p->d_pidx, (void *)p->d_sitems})
+    if (q) (void)hipFree(q);
   p->d_stored = nullptr;
   p->d_run_poff = nullptr;
+  p->d_atom_poff = nullptr;
+  p->d_atom_pbeg = nullptr;
+  p->d_pidx = nullptr;
+  p->d_sitems = nullptr;
   p->d_atoms = nullptr;
   p->d_lines = nullptr;
   p->d_bundles = nullptr;
   p->d_work = nullptr;
   p->d_tab = nullptr;
+}
+
+// (Re)uploads the schedule-dependent tables: bundles and both work-item
+// orders; regroups the items by nu.
+hipError_t upload_schedule(sho_plan_s *p) {
+  for (void **q : {(void **)&p->d_bundles, (void **)&p->d_work, (void **)&p->d_work_single}) {
+    if (*q) (void)hipFree(*q);
+    *q = nullptr;
+  }
+  hipError_t e;
+  int64_t &bytes = p->sched_bytes;
+  bytes = 0;
+  if ((e = upload(&p->d_bundles, p->hp.bundles, &bytes)) != hipSuccess ||
+      (e = upload(&p->d_work, p->hp.work, &bytes)) != hipSuccess ||
+      (e = upload(&p->d_work_single, p->hp.work_single, &bytes)) != hipSuccess)
+    return e;
+  p->groups.clear();
+  const auto &work = p->hp.work;
+  for (size_t i = 0; i < work.size();) {
+    const int32_t nu = p->hp.atoms[work[i].atom].nu;
+    Group g{nu, (int32_t)i, 0};
+    while (i < work.size() && p->hp.atoms[work[i].atom].nu == nu) {
+      g.count++;
+      ++i;
+    }
+    p->groups.push_back(g);
+  }
+  p->sched_version++;
+  return hipSuccess;
+}
+
+sho::SArgs make_sargs(const sho_plan_s *p, const Group &g) {
+  sho::SArgs S;
+  S.atoms = p->d_atoms;
+  S.P = p->d_stored;
+  S.atom_poff = p->d_atom_poff;
+  S.atom_pbeg = p->d_atom_pbeg;
+  S.pidx = p->d_pidx;
+  S.items = p->d_sitems + g.work_begin;
+  S.nitems = g.count;
+  S.B = p->hp.nbands;
+  const double h = p->hp.grid.h;
+  S.h3 = h * h * h;
+  return S;
 }
 
 sho::KArgs make_args(const sho_plan_s *p, const Group &g) {
@@ -136,8 +204,8 @@ void prof_clear(sho_plan_s *p) {
 
 // Runs f (a sequence of launches on s), bracketed by events when profiling.
 template <typename F>
-hipError_t timed(sho_plan_s *p, int kind, hipStream_t s, F &&f) {
-  if (!p->prof_on) return f();
+hipError_t timed(sho_plan_s *p, bool prof, int kind, hipStream_t s, F &&f) {
+  if (!prof) return f();
   ProfEvent ev{kind, nullptr, nullptr};
   hipError_t e = hipEventCreate(&ev.a);
   if (e == hipSuccess) e = hipEventCreate(&ev.b);
@@ -206,8 +274,148 @@ int64_t psi_bytes(const sho_plan_s *p) {
          p->hp.nbands * (int64_t)sizeof(double);
 }
 
+// Device bytes a plan of this geometry allocates (tables, work items, 1D
+// tables, expansion scratch, stored tables), each rounded up as the
+// allocations are.
+int64_t estimate_device_bytes(const sho::HostPlan &hp) {
+  auto b = [](int64_t n, int64_t size) { return std::max<int64_t>(n, 1) * size; };
+  const int64_t nl = (int64_t)hp.lines.size();
+  int64_t t = b(hp.natoms, sizeof(sho::AtomRec)) + b(nl, sizeof(sho::LineRec)) +
+              b((int64_t)hp.bundles.size(), sizeof(sho::BundleRec)) +
+              2 * b((int64_t)hp.work.size(), sizeof(sho::WorkRec)) +
+              b(hp.table_doubles, 8) + 2 * b(nl, 4) +
+              b((int64_t)hp.rows.size(), sizeof(sho::RowRec)) + b(hp.natoms, 8) +
+              b(hp.natoms, 4) + b(hp.u2_doubles, 8);
+  if (hp.flags & SHO_FLAG_STORED) {
+    int64_t stored = 0;
+    for (const auto &A : hp.atoms) stored += (int64_t)A.npoints * sho::nsho(A.nu);
+    const int64_t items = (hp.support_points + sho::kStoredChunk - 1) / sho::kStoredChunk +
+                          hp.natoms;
+    t += b(stored, 8) + b(nl + 1, 8) + 2 * b(hp.natoms + 1, 8) + b(hp.support_points, 4) +
+         b(items, sizeof(sho::StoredItem));
+  }
+  return t;
+}
+
+// Plans with several cut-offs run the projection as one launch.
+int32_t default_schedule(const sho::HostPlan &hp) {
+  for (const auto &A : hp.atoms)
+    if (A.npoints > 0 && A.nu != hp.atoms[0].nu) return sho::kSchedSingle;
+  return sho::kSchedByNu;
+}
+
 int64_t coeff_bytes(const sho_plan_s *p) {
   return p->hp.coeff_rows * p->hp.nbands * (int64_t)sizeof(double);
+}
+
+// Item range of atom a in `work` (per-atom launches).
+Group atom_group(const sho_plan_s *p, int32_t a) {
+  const int32_t b = p->hp.atom_work[a];
+  int32_t n = 0;  // the items of one atom are contiguous
+  while (b + n < (int32_t)p->hp.work.size() && p->hp.work[b + n].atom == a) ++n;
+  return Group{p->hp.atoms[a].nu, b, n};
+}
+
+sho_status check_project(const sho_plan_s *p, const double *psi, const double *c) {
+  if (!p) return fail(SHO_E_INVALID, "NULL plan");
+  if (p->hp.flags & SHO_FLAG_HOST_ONLY)
+    return fail(SHO_E_INVALID, "host-only plan cannot run kernels");
+  if (p->hp.coeff_rows == 0) return SHO_OK;
+  if (!device_range_ok(psi, psi_bytes(p)) || !device_range_ok(c, coeff_bytes(p)))
+    return fail(SHO_E_INVALID, "psi and c must be device buffers of the plan's sizes");
+  if ((const char *)c < (const char *)psi + psi_bytes(p) &&
+      (const char *)psi < (const char *)c + coeff_bytes(p))
+    return fail(SHO_E_INVALID, "psi and c overlap");
+  return SHO_OK;
+}
+
+// Expansion scratch (plane partials), allocated on first use.
+sho_status ensure_u2(sho_plan_s *p) {
+  if (p->d_u2 || (p->hp.flags & (SHO_FLAG_STORED | SHO_FLAG_PER_ATOM))) return SHO_OK;
+  const int64_t n = std::max<int64_t>(p->hp.u2_doubles, 1) * sizeof(double);
+  hipError_t e = hipMalloc((void **)&p->d_u2, n);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    p->d_u2 = nullptr;
+    return e == hipErrorOutOfMemory ? fail(SHO_E_NOMEM, "device allocation failed")
+                                    : hip_fail(e, "expansion scratch");
+  }
+  p->device_bytes += n;
+  return SHO_OK;
+}
+
+// The projection's launches on s (arguments already checked).
+hipError_t run_project(sho_plan_s *p, const double *psi, double *c, hipStream_t s,
+                       bool prof) {
+  // atoms whose support missed the grid entirely keep zero coefficients;
+  // atoms shared by several work items (and every stored point chunk) are
+  // summed into zeroed coefficients
+  bool zero = p->hp.any_split || (p->hp.flags & SHO_FLAG_STORED);
+  for (const auto &A : p->hp.atoms) zero |= (A.npoints == 0);
+  if (zero) {
+    hipError_t e = sho::launch_fill(c, p->hp.coeff_rows * p->hp.nbands, 0.0, s);
+    if (e != hipSuccess) return e;
+  }
+  return timed(p, prof, SHO_KERNEL_PROJECT, s, [&]() {
+    if (p->hp.flags & SHO_FLAG_STORED) {
+      for (const Group &g : p->sgroups) {
+        hipError_t e1 = sho::launch_project_stored(g.nu, make_sargs(p, g), psi, c, s);
+        if (e1 != hipSuccess) return e1;
+      }
+      return hipSuccess;
+    }
+    if (p->hp.flags & SHO_FLAG_PER_ATOM) {
+      for (int32_t a = 0; a < p->hp.natoms; ++a) {
+        const Group g = atom_group(p, a);
+        if (!g.count) continue;
+        hipError_t e1 = sho::launch_project(g.nu, make_args(p, g), psi, c, s);
+        if (e1 != hipSuccess) return e1;
+      }
+      return hipSuccess;
+    }
+    if (p->hp.sched != sho::kSchedByNu) {
+      sho::KArgs K = make_args(p, Group{p->hp.nu_max, 0, (int32_t)p->hp.work_single.size()});
+      K.work = p->d_work_single;
+      return sho::launch_project_any(p->hp.nu_max, K, psi, c, s);
+    }
+    for (const Group &g : p->groups) {
+      hipError_t e1 = sho::launch_project(g.nu, make_args(p, g), psi, c, s);
+      if (e1 != hipSuccess) return e1;
+    }
+    return hipSuccess;
+  });
+}
+
+// The expansion's launches on s (arguments checked, scratch allocated).
+hipError_t run_expand(sho_plan_s *p, const double *c, double *psi, hipStream_t s,
+                      bool prof) {
+  if (p->hp.flags & SHO_FLAG_STORED) {
+    return timed(p, prof, SHO_KERNEL_EXPAND_ROWS, s, [&]() {
+      for (const Group &g : p->sgroups) {
+        hipError_t e1 = sho::launch_expand_stored(g.nu, make_sargs(p, g), c, psi, s);
+        if (e1 != hipSuccess) return e1;
+      }
+      return hipSuccess;
+    });
+  }
+  if (p->hp.flags & SHO_FLAG_PER_ATOM) {
+    return timed(p, prof, SHO_KERNEL_EXPAND_ROWS, s, [&]() {
+      for (int32_t a = 0; a < p->hp.natoms; ++a) {
+        const Group g = atom_group(p, a);
+        if (!g.count) continue;
+        hipError_t e1 = sho::launch_expand_atomic(g.nu, make_args(p, g), c, psi, s);
+        if (e1 != hipSuccess) return e1;
+      }
+      return hipSuccess;
+    });
+  }
+  sho::EArgs E = make_eargs(p);
+  hipError_t e = timed(p, prof, SHO_KERNEL_EXPAND_PLANES, s,
+                       [&]() { return sho::launch_expand_planes(E, c, p->d_u2, s); });
+  if (e == hipSuccess)
+    e = timed(p, prof, SHO_KERNEL_EXPAND_ROWS, s,
+              [&]() { return sho::launch_rows(E, p->d_u2, psi, s); });
+  return e;
 }
 
 }  // namespace
@@ -242,7 +450,7 @@ sho_status sho_plan_create(const sho_grid *grid, int32_t natoms,
       delete p;
       return fail(SHO_E_BOX, "coefficient tile too large for the workgroup LDS");
     }
-    sho::build_work(&p->hp, tbs, sho::kTargetPoints);
+    sho::build_work(&p->hp, tbs, sho::kTargetPoints, default_schedule(p->hp));
     sho::build_rows(&p->hp);
     *out = p;
     return SHO_OK;
@@ -265,25 +473,12 @@ sho_status sho_plan_create(const sho_grid *grid, int32_t natoms,
     delete p;
     return fail(SHO_E_BOX, "coefficient tile too large for the workgroup LDS");
   }
-  sho::build_work(&p->hp, tbs, sho::kTargetPoints);
+  sho::build_work(&p->hp, tbs, sho::kTargetPoints, default_schedule(p->hp));
   sho::build_rows(&p->hp);
-
-  // group work items by nu (one launch per group); items are sorted by nu
-  const auto &work = p->hp.work;
-  for (size_t i = 0; i < work.size();) {
-    const int32_t nu = p->hp.atoms[work[i].atom].nu;
-    Group g{nu, (int32_t)i, 0};
-    while (i < work.size() && p->hp.atoms[work[i].atom].nu == nu) {
-      g.count++;
-      ++i;
-    }
-    p->groups.push_back(g);
-  }
   std::vector<double> no_tab;
   if ((e = upload(&p->d_atoms, p->hp.atoms, &p->device_bytes)) != hipSuccess ||
       (e = upload(&p->d_lines, p->hp.lines, &p->device_bytes)) != hipSuccess ||
-      (e = upload(&p->d_bundles, p->hp.bundles, &p->device_bytes)) != hipSuccess ||
-      (e = upload(&p->d_work, p->hp.work, &p->device_bytes)) != hipSuccess ||
+      (e = upload_schedule(p)) != hipSuccess ||
       (e = upload(&p->d_run_atom, p->hp.run_atom, &p->device_bytes)) != hipSuccess ||
       (e = upload(&p->d_row_runs, p->hp.row_runs, &p->device_bytes)) != hipSuccess ||
       (e = upload(&p->d_rows, p->hp.rows, &p->device_bytes)) != hipSuccess ||
@@ -302,17 +497,29 @@ sho_status sho_plan_create(const sho_grid *grid, int32_t natoms,
   e = sho::launch_tables(p->d_atoms, p->hp.natoms, p->hp.grid.h, p->d_tab, p->hp.m_max,
                          nullptr);
   if (e == hipSuccess && (flags & SHO_FLAG_STORED)) {
-    sho::build_stored_offsets(&p->hp);
-    e = upload(&p->d_run_poff, p->hp.run_poff, &p->device_bytes);
-    if (e == hipSuccess)
-      e = hipMalloc((void **)&p->d_stored,
-                    std::max<int64_t>(p->hp.stored_doubles, 1) * sizeof(double));
-    if (e == hipSuccess) {
-      p->stored_bytes = std::max<int64_t>(p->hp.stored_doubles, 1) * sizeof(double);
-      p->device_bytes += p->stored_bytes;
+    sho::HostPlan &hp = p->hp;
+    sho::build_stored(&hp, sho::kStoredChunk);
+    for (size_t i = 0; i < hp.sitems.size();) {
+      const int32_t nu = hp.atoms[hp.sitems[i].atom].nu;
+      Group g{nu, (int32_t)i, 0};
+      while (i < hp.sitems.size() && hp.atoms[hp.sitems[i].atom].nu == nu) {
+        g.count++;
+        ++i;
+      }
+      p->sgroups.push_back(g);
+    }
+    const int64_t sb = std::max<int64_t>(hp.stored_doubles, 1) * sizeof(double);
+    if ((e = upload(&p->d_run_poff, hp.run_poff, &p->device_bytes)) == hipSuccess &&
+        (e = upload(&p->d_atom_poff, hp.atom_poff, &p->device_bytes)) == hipSuccess &&
+        (e = upload(&p->d_atom_pbeg, hp.atom_pbeg, &p->device_bytes)) == hipSuccess &&
+        (e = upload(&p->d_pidx, hp.pidx, &p->device_bytes)) == hipSuccess &&
+        (e = upload(&p->d_sitems, hp.sitems, &p->device_bytes)) == hipSuccess &&
+        (e = hipMalloc((void **)&p->d_stored, sb)) == hipSuccess) {
+      p->stored_bytes = sb;
+      p->device_bytes += sb;
       Group all{0, 0, 0};
       sho::KArgs K = make_args(p, all);
-      e = sho::launch_store(K, p->d_run_atom, (int32_t)p->hp.lines.size(), p->d_stored,
+      e = sho::launch_store(K, p->d_run_atom, (int32_t)hp.lines.size(), p->d_stored,
                             nullptr);
     }
   }
@@ -381,7 +588,8 @@ sho_status sho_plan_get_info(sho_plan_t p, sho_plan_info *info) {
   info->support_points = p->hp.support_points;
   info->lines = (int64_t)p->hp.lines.size();
   info->planes = (int64_t)p->hp.planes.size();
-  info->device_bytes = p->device_bytes;
+  info->device_bytes = (p->hp.flags & SHO_FLAG_HOST_ONLY) ? estimate_device_bytes(p->hp)
+                                                          : p->device_bytes + p->sched_bytes;
   info->stored_bytes = p->stored_bytes;
   info->union_points = p->hp.union_points;
   // the row kernel moves whole chunks of touched rows: with 32 or 64 bands
@@ -434,79 +642,19 @@ sho_status sho_plan_set_centres(sho_plan_t p, const double *pos, void *stream) {
 
 sho_status sho_plan_project(sho_plan_t p, const double *psi, double *c,
                             void *stream) {
-  if (!p) return fail(SHO_E_INVALID, "NULL plan");
-  if (p->hp.flags & SHO_FLAG_HOST_ONLY)
-    return fail(SHO_E_INVALID, "host-only plan cannot run kernels");
-  if (p->hp.coeff_rows == 0) return SHO_OK;
-  if (!device_range_ok(psi, psi_bytes(p)) || !device_range_ok(c, coeff_bytes(p)))
-    return fail(SHO_E_INVALID, "psi and c must be device buffers of the plan's sizes");
-  if ((const char *)c < (const char *)psi + psi_bytes(p) &&
-      (const char *)psi < (const char *)c + coeff_bytes(p))
-    return fail(SHO_E_INVALID, "psi and c overlap");
-  hipStream_t s = (hipStream_t)stream;
-  // atoms whose support missed the grid entirely keep zero coefficients;
-  // atoms shared by several work items are summed into zeroed coefficients
-  bool empty = p->hp.any_split;
-  for (const auto &A : p->hp.atoms) empty |= (A.npoints == 0);
-  if (empty) {
-    hipError_t e = sho::launch_fill(c, p->hp.coeff_rows * p->hp.nbands, 0.0, s);
-    if (e != hipSuccess) return hip_fail(e, "fill");
-  }
-  hipError_t e = timed(p, SHO_KERNEL_PROJECT, s, [&]() {
-    for (const Group &g : p->groups) {
-      sho::KArgs K = make_args(p, g);
-      hipError_t e1 = (p->hp.flags & SHO_FLAG_STORED)
-                          ? sho::launch_project_stored(g.nu, K, psi, c, s)
-                          : sho::launch_project(g.nu, K, psi, c, s);
-      if (e1 != hipSuccess) return e1;
-    }
-    return hipSuccess;
-  });
+  sho_status st = check_project(p, psi, c);
+  if (st != SHO_OK || p->hp.coeff_rows == 0) return st;
+  hipError_t e = run_project(p, psi, c, (hipStream_t)stream, p->prof_on);
   if (e != hipSuccess) return hip_fail(e, "project launch");
   return SHO_OK;
 }
 
 sho_status sho_plan_expand(sho_plan_t p, const double *c, double *psi,
                            void *stream) {
-  if (!p) return fail(SHO_E_INVALID, "NULL plan");
-  if (p->hp.flags & SHO_FLAG_HOST_ONLY)
-    return fail(SHO_E_INVALID, "host-only plan cannot run kernels");
-  if (p->hp.coeff_rows == 0) return SHO_OK;
-  if (!device_range_ok(psi, psi_bytes(p)) || !device_range_ok(c, coeff_bytes(p)))
-    return fail(SHO_E_INVALID, "psi and c must be device buffers of the plan's sizes");
-  if ((const char *)c < (const char *)psi + psi_bytes(p) &&
-      (const char *)psi < (const char *)c + coeff_bytes(p))
-    return fail(SHO_E_INVALID, "psi and c overlap");
-  hipStream_t s = (hipStream_t)stream;
-  if (p->hp.flags & SHO_FLAG_STORED) {
-    hipError_t e = timed(p, SHO_KERNEL_EXPAND_ROWS, s, [&]() {
-      for (const Group &g : p->groups) {
-        sho::KArgs K = make_args(p, g);
-        hipError_t e1 = sho::launch_expand_stored(g.nu, K, c, psi, s);
-        if (e1 != hipSuccess) return e1;
-      }
-      return hipSuccess;
-    });
-    if (e != hipSuccess) return hip_fail(e, "expand launch");
-    return SHO_OK;
-  }
-  if (!p->d_u2) {
-    hipError_t e = hipMalloc((void **)&p->d_u2,
-                             std::max<int64_t>(p->hp.u2_doubles, 1) * sizeof(double));
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      p->d_u2 = nullptr;
-      return e == hipErrorOutOfMemory ? fail(SHO_E_NOMEM, "device allocation failed")
-                                      : hip_fail(e, "expansion scratch");
-    }
-    p->device_bytes += std::max<int64_t>(p->hp.u2_doubles, 1) * sizeof(double);
-  }
-  sho::EArgs E = make_eargs(p);
-  hipError_t e = timed(p, SHO_KERNEL_EXPAND_PLANES, s,
-                       [&]() { return sho::launch_expand_planes(E, c, p->d_u2, s); });
-  if (e == hipSuccess)
-    e = timed(p, SHO_KERNEL_EXPAND_ROWS, s,
-              [&]() { return sho::launch_rows(E, p->d_u2, psi, s); });
+  sho_status st = check_project(p, psi, c);
+  if (st != SHO_OK || p->hp.coeff_rows == 0) return st;
+  if ((st = ensure_u2(p)) != SHO_OK) return st;
+  hipError_t e = run_expand(p, c, psi, (hipStream_t)stream, p->prof_on);
   if (e != hipSuccess) return hip_fail(e, "expand launch");
   return SHO_OK;
 }
@@ -523,15 +671,192 @@ sho_status sho_plan_force(sho_plan_t p, const double *psi, const double *w,
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = sho::launch_fill(grad, 3 * (int64_t)p->hp.natoms, 0.0, s);
   if (e != hipSuccess) return hip_fail(e, "fill");
-  e = timed(p, SHO_KERNEL_FORCE, s, [&]() {
+  e = timed(p, p->prof_on, SHO_KERNEL_FORCE, s, [&]() {
+    if (p->hp.flags & SHO_FLAG_PER_ATOM) {
+      for (int32_t a = 0; a < p->hp.natoms; ++a) {
+        const Group g = atom_group(p, a);
+        if (!g.count) continue;
+        hipError_t e1 = sho::launch_force(g.nu, make_args(p, g), psi, w, grad, s);
+        if (e1 != hipSuccess) return e1;
+      }
+      return hipSuccess;
+    }
     for (const Group &g : p->groups) {
-      sho::KArgs K = make_args(p, g);
-      hipError_t e1 = sho::launch_force(g.nu, K, psi, w, grad, s);
+      hipError_t e1 = sho::launch_force(g.nu, make_args(p, g), psi, w, grad, s);
       if (e1 != hipSuccess) return e1;
     }
     return hipSuccess;
   });
   if (e != hipSuccess) return hip_fail(e, "force launch");
+  return SHO_OK;
+}
+
+sho_status sho_plan_set_schedule(sho_plan_t p, int32_t schedule, int32_t band_tile,
+                                 int64_t target_points) {
+  if (!p) return fail(SHO_E_INVALID, "NULL plan");
+  if (schedule < 0 || schedule >= sho::kSchedCount)
+    return fail(SHO_E_INVALID, "unknown schedule");
+  if (target_points < 256 || target_points > (int64_t)1 << 30)
+    return fail(SHO_E_INVALID, "target_points outside [256, 2^30]");
+  int tbs = -1;
+  for (int k = 0; k <= 6; ++k)
+    if ((1 << k) == band_tile) tbs = k;
+  if (band_tile == 0) tbs = p->hp.tb_shift;
+  if (tbs < 0) return fail(SHO_E_INVALID, "band_tile must be 0 or a power of two <= 64");
+  const size_t limit = (p->hp.flags & SHO_FLAG_HOST_ONLY) ? 65536 - 1024 : p->lds_limit;
+  if (sho::lds_tile_bytes(p->hp.nu_max + 2, 1 << tbs) > limit)
+    return fail(SHO_E_BOX, "band tile too wide for the workgroup LDS");
+  if (!(p->hp.flags & SHO_FLAG_HOST_ONLY)) {
+    hipError_t e = hipDeviceSynchronize();  // tables may be in use
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+  }
+  sho::build_work(&p->hp, tbs, target_points, schedule);
+  if (p->hp.flags & SHO_FLAG_HOST_ONLY) return SHO_OK;
+  hipError_t e = upload_schedule(p);
+  if (e != hipSuccess) return hip_fail(e, "schedule upload");
+  return SHO_OK;
+}
+
+sho_status sho_plan_get_schedule(sho_plan_t p, int32_t *schedule, int32_t *band_tile,
+                                 int64_t *target_points) {
+  if (!p || !schedule || !band_tile || !target_points)
+    return fail(SHO_E_INVALID, "NULL argument");
+  *schedule = p->hp.sched;
+  *band_tile = 1 << p->hp.tb_shift;
+  *target_points = p->hp.target_points;
+  return SHO_OK;
+}
+
+sho_status sho_plan_tune(sho_plan_t p, const double *psi, double *c, int32_t reps,
+                         void *stream, sho_tune_result *result) {
+  sho_status st = check_project(p, psi, c);
+  if (st != SHO_OK) return st;
+  if (reps < 1 || reps > 1000) return fail(SHO_E_INVALID, "reps outside 1..1000");
+  if (p->hp.flags & (SHO_FLAG_STORED | SHO_FLAG_PER_ATOM))
+    return fail(SHO_E_INVALID, "stored and per-atom plans have a fixed schedule");
+  hipStream_t s = (hipStream_t)stream;
+  struct Cand {
+    int32_t sched, tbs;
+    int64_t target;
+  };
+  std::vector<Cand> cands;
+  const int32_t tb0 = p->hp.tb_shift;
+  for (int32_t sc = 0; sc < sho::kSchedCount; ++sc)
+    for (int64_t tp : {(int64_t)8192, (int64_t)16384, (int64_t)32768})
+      for (int32_t tb = tb0; tb >= std::max(0, tb0 - 1); --tb) cands.push_back({sc, tb, tp});
+  const Cand before{p->hp.sched, tb0, p->hp.target_points};
+  hipEvent_t ea = nullptr, eb = nullptr;
+  hipError_t e = hipEventCreate(&ea);
+  if (e == hipSuccess) e = hipEventCreate(&eb);
+  auto time_current = [&](double *ms) -> hipError_t {
+    hipError_t e1 = run_project(p, psi, c, s, false);  // warm-up
+    if (e1 == hipSuccess) e1 = hipEventRecord(ea, s);
+    for (int r = 0; r < reps && e1 == hipSuccess; ++r) e1 = run_project(p, psi, c, s, false);
+    if (e1 == hipSuccess) e1 = hipEventRecord(eb, s);
+    if (e1 == hipSuccess) e1 = hipEventSynchronize(eb);
+    float t = 0.f;
+    if (e1 == hipSuccess) e1 = hipEventElapsedTime(&t, ea, eb);
+    *ms = (double)t / reps;
+    return e1;
+  };
+  double best = 1e300, ms_before = 0.0;
+  Cand pick = before;
+  if (e == hipSuccess) e = time_current(&ms_before);
+  best = ms_before;
+  int32_t tried = 1;
+  for (const Cand &cd : cands) {
+    if (e != hipSuccess) break;
+    if (cd.sched == before.sched && cd.tbs == before.tbs && cd.target == before.target)
+      continue;
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) break;
+    sho::build_work(&p->hp, cd.tbs, cd.target, cd.sched);
+    if ((e = upload_schedule(p)) != hipSuccess) break;
+    double ms = 0.0;
+    if ((e = time_current(&ms)) != hipSuccess) break;
+    ++tried;
+    if (ms < best) {
+      best = ms;
+      pick = cd;
+    }
+  }
+  if (ea) (void)hipEventDestroy(ea);
+  if (eb) (void)hipEventDestroy(eb);
+  if (e != hipSuccess) return hip_fail(e, "tuning");
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "tuning");
+  sho::build_work(&p->hp, pick.tbs, pick.target, pick.sched);
+  if ((e = upload_schedule(p)) != hipSuccess) return hip_fail(e, "schedule upload");
+  if (result) {
+    result->schedule = pick.sched;
+    result->band_tile = 1 << pick.tbs;
+    result->target_points = pick.target;
+    result->ms = best;
+    result->ms_before = ms_before;
+    result->candidates = tried;
+  }
+  return SHO_OK;
+}
+
+// ------------------------------------------------------------- graphs --
+
+struct sho_graph_s {
+  sho_plan_t plan = nullptr;
+  int64_t sched_version = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+sho_status sho_graph_create(sho_plan_t p, const double *psi, double *c, double *out,
+                            sho_graph_t *g) {
+  if (!g) return fail(SHO_E_INVALID, "NULL graph output");
+  *g = nullptr;
+  sho_status st = check_project(p, psi, c);
+  if (st != SHO_OK) return st;
+  if (!device_range_ok(out, psi_bytes(p)))
+    return fail(SHO_E_INVALID, "out must be a device buffer of the grid's size");
+  if ((const char *)c < (const char *)out + psi_bytes(p) &&
+      (const char *)out < (const char *)c + coeff_bytes(p))
+    return fail(SHO_E_INVALID, "out and c overlap");
+  if (!(p->hp.flags & SHO_FLAG_STORED) && (st = ensure_u2(p)) != SHO_OK) return st;
+  sho_graph_s *G = new (std::nothrow) sho_graph_s();
+  if (!G) return fail(SHO_E_NOMEM, "host allocation failed");
+  G->plan = p;
+  G->sched_version = p->sched_version;
+  hipStream_t cs = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    hipError_t e1 = p->hp.coeff_rows ? run_project(p, psi, c, cs, false) : hipSuccess;
+    if (e1 == hipSuccess && p->hp.coeff_rows) e1 = run_expand(p, c, out, cs, false);
+    e = hipStreamEndCapture(cs, &G->graph);
+    if (e1 != hipSuccess) e = e1;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&G->exec, G->graph, nullptr, nullptr, 0);
+  if (cs) (void)hipStreamDestroy(cs);
+  if (e != hipSuccess) {
+    if (G->exec) (void)hipGraphExecDestroy(G->exec);
+    if (G->graph) (void)hipGraphDestroy(G->graph);
+    delete G;
+    return hip_fail(e, "graph capture");
+  }
+  *g = G;
+  return SHO_OK;
+}
+
+sho_status sho_graph_launch(sho_graph_t g, void *stream) {
+  if (!g) return fail(SHO_E_INVALID, "NULL graph");
+  if (g->plan->sched_version != g->sched_version)
+    return fail(SHO_E_INVALID, "the plan's schedule changed after the graph was made");
+  hipError_t e = hipGraphLaunch(g->exec, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "graph launch");
+  return SHO_OK;
+}
+
+sho_status sho_graph_destroy(sho_graph_t g) {
+  if (!g) return SHO_OK;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
   return SHO_OK;
 }
 

@@ -106,6 +106,14 @@ static_assert(sizeof(RowRec) == 16, "RowRec layout");
 constexpr int kRowsPerGroup = 1;
 
 // Host-side plan contents (built without any device call).
+// A chunk of one atom's stored points [k0, k1) (stored-projector kernels).
+struct StoredItem {
+  int32_t atom;
+  int32_t k0, k1;
+  int32_t pad;
+};
+static_assert(sizeof(StoredItem) == 16, "StoredItem layout");
+
 struct HostPlan {
   sho_grid grid{};
   int32_t natoms = 0;
@@ -118,7 +126,12 @@ struct HostPlan {
   std::vector<PlaneRec> planes;
   std::vector<LineRec> lines;
   std::vector<BundleRec> bundles;
-  std::vector<WorkRec> work;           // sorted by nu, then atom
+  std::vector<WorkRec> work;           // by nu, then atoms in space order
+  std::vector<int32_t> atom_work;      // [natoms+1] first item of each atom
+                                       // in `work` (count: next - first)
+  std::vector<WorkRec> work_single;    // the same items for one launch
+  int32_t sched = 0;                   // kSched* of the projection
+  int64_t target_points = 0;           // work item size of the schedule
   std::vector<int32_t> run_atom;       // atom of every run
   std::vector<int32_t> row_runs;       // run indices grouped by memory row
   std::vector<RowRec> rows;            // non-empty rows, XCD-aware order
@@ -128,6 +141,10 @@ struct HostPlan {
   int64_t u2_doubles = 0;
   std::vector<int64_t> run_poff;      // stored projectors: first double of
                                       // each run's [len][N_SHO] block
+  std::vector<int64_t> atom_poff;     // [natoms+1] first double of each atom
+  std::vector<int64_t> atom_pbeg;     // [natoms+1] first stored point
+  std::vector<int32_t> pidx;          // grid memory index of every point
+  std::vector<StoredItem> sitems;     // point chunks, sorted by nu
   int64_t stored_doubles = 0;
   int64_t union_points = 0;   // distinct grid points covered by any support
   int64_t rows_touched = 0;   // memory rows with at least one run
@@ -161,17 +178,32 @@ inline size_t lds_tile_bytes(int nf, int tb) {
 // per slot does not.
 int choose_tb_shift(int nbands, int nu_max, size_t lds_limit);
 
+// Projection launch schedules.
+constexpr int32_t kSchedByNu = 0;       // one launch per cut-off
+constexpr int32_t kSchedSingle = 1;     // one launch, items in space order
+constexpr int32_t kSchedSingleLpt = 2;  // one launch, items by falling cost
+constexpr int32_t kSchedCount = 3;
+
 // Bundles (with 64 >> tb_shift slots) and work items: atoms of more than
-// `target_points` support points are shared by several workgroups.
-void build_work(HostPlan *P, int tb_shift, int64_t target_points);
+// `target_points` support points are shared by several workgroups.  Atoms
+// are visited in Morton order of their centres, so that workgroups running
+// at the same time read neighbouring parts of psi (shared in L2 and the
+// memory-side cache where supports overlap).  `sched` fixes the order of
+// work_single.
+void build_work(HostPlan *P, int tb_shift, int64_t target_points, int32_t sched);
 
 // Expansion tables: runs grouped by memory row, rows interleaved over the
 // eight XCDs so that all rows of one plane share an L2, per-atom offsets of
 // the plane partials U2[jz][pair][band].
 void build_rows(HostPlan *P);
 
-// Offsets of the stored projector blocks (SHO_FLAG_STORED plans).
-void build_stored_offsets(HostPlan *P);
+// Layout of the stored projector tables (SHO_FLAG_STORED plans): the points
+// of every atom in run order, each with its N_SHO values; chunks of at most
+// `chunk` points per work item.
+void build_stored(HostPlan *P, int32_t chunk);
+
+// Points per stored-projector work item.
+constexpr int32_t kStoredChunk = 1024;
 
 // Largest nu the stored-projector variant supports (56 functions).
 constexpr int32_t kStoredNuMax = 5;

@@ -274,16 +274,15 @@ __device__ inline void project_bundles(const KArgs &K, const AtomRec &A,
   flush_plane<NU>(tz + cur_jz * nfp, T2, cacc, L);
 }
 
+// One work item of the projection: zero the LDS tile, stream the item's
+// bundles, write (or, for a shared atom, add) h^3 C into c.
 template <int NU>
-__global__ __launch_bounds__(kBlock)
-__attribute__((amdgpu_waves_per_eu(waves_per_eu(NU + 1)))) void k_project(
-    KArgs K, const double *__restrict__ psi, double *__restrict__ c) {
+__device__ inline void project_item(const KArgs &K, cptr<WorkRec> W, const AtomRec &A,
+                                    const double *__restrict__ psi,
+                                    double *__restrict__ c, double *cacc) {
   constexpr int NF = NU + 1;
   constexpr int NS = NF * (NF + 1) * (NF + 2) / 6;
-  extern __shared__ double cacc[];
-  const cptr<WorkRec> W = as_const(K.work) + blockIdx.x;
   const int tile = blockIdx.y;
-  const AtomRec A = load_uniform(K.atoms + W->atom);
   const int TB = 1 << K.tb_shift;
   for (int t = threadIdx.x; t < NS * TB; t += blockDim.x) cacc[t] = 0.0;
   __syncthreads();
@@ -301,6 +300,124 @@ __attribute__((amdgpu_waves_per_eu(waves_per_eu(NU + 1)))) void k_project(
       unsafeAtomicAdd(dst, K.h3 * cacc[t]);
     else
       *dst = K.h3 * cacc[t];
+  }
+}
+
+template <int NU>
+__global__ __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(waves_per_eu(NU + 1)))) void k_project(
+    KArgs K, const double *__restrict__ psi, double *__restrict__ c) {
+  extern __shared__ double cacc[];
+  const cptr<WorkRec> W = as_const(K.work) + blockIdx.x;
+  const AtomRec A = load_uniform(K.atoms + W->atom);
+  project_item<NU>(K, W, A, psi, c, cacc);
+}
+
+// All cut-offs in one launch: the item's atom selects the instantiation
+// (a wave-uniform branch).  Registers are those of the largest case, so the
+// single launch serves plans whose cut-offs differ.
+template <int NUMAX>
+__global__ __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(waves_per_eu(NUMAX + 1)))) void k_project_any(
+    KArgs K, const double *__restrict__ psi, double *__restrict__ c) {
+  extern __shared__ double cacc[];
+  const cptr<WorkRec> W = as_const(K.work) + blockIdx.x;
+  const AtomRec A = load_uniform(K.atoms + W->atom);
+  switch (A.nu) {
+#define X(N)                                                  \
+  case N:                                                     \
+    if constexpr (N <= NUMAX) project_item<N>(K, W, A, psi, c, cacc); \
+    break;
+    SHO_NU_CASES(X)
+#undef X
+  }
+}
+
+// Expansion of one atom's box with global FP64 atomics (atom-owner form):
+// the z pass into registers per plane, the y pass per run, the x pass adds
+// into psi.  Used by the per-atom launch schedule.
+template <int NU>
+__global__ __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(waves_per_eu(NU + 1)))) void k_expand_atomic(
+    KArgs K, const double *__restrict__ c, double *psi) {
+  constexpr int NF = NU + 1;
+  constexpr int NP = NF * (NF + 1) / 2;
+  constexpr int NS = NF * (NF + 1) * (NF + 2) / 6;
+  extern __shared__ double cin[];
+  const cptr<WorkRec> W = as_const(K.work) + blockIdx.x;
+  const int tile = blockIdx.y;
+  const AtomRec A = load_uniform(K.atoms + W->atom);
+  const int TB = 1 << K.tb_shift;
+  for (int t = threadIdx.x; t < NS * TB; t += blockDim.x) {
+    const int n = t >> K.tb_shift;
+    const int bb = tile * TB + (t & (TB - 1));
+    cin[t] = bb < K.B ? c[(A.coeff_row + n) * K.B + bb] : 0.0;
+  }
+  __syncthreads();
+  const int w = wave_id();
+  const Lanes L = lane_geometry(K, tile);
+  const int nfp = A.tab_nfp;
+  const cptr<double> tx = as_const(K.tab) + A.tab_off;
+  const double *ty = K.tab + A.tab_off + (int64_t)A.mx * nfp;
+  const cptr<double> tz = tx + (int64_t)(A.mx + A.my) * nfp;
+  const int b1 = W->wb[w + 1];
+  double U2[NP];
+  int cur_jz = -1;
+  for (int bi = W->wb[w]; bi < b1; ++bi) {
+    const BundleRec bd = load_uniform(K.bundles + bi);
+    if (bd.jz != cur_jz) {
+      // z pass: U2[nx][ny] = sum_nz phi_nz(z) C[nx,ny,nz]
+      cur_jz = bd.jz;
+      const cptr<double> fz = tz + cur_jz * nfp;
+#pragma unroll
+      for (int q = 0; q < NP; ++q) U2[q] = 0.0;
+      int idx = 0;
+#pragma unroll
+      for (int nz = 0; nz < NF; ++nz) {
+        const double fv = fz[nz];
+        int q = 0;
+#pragma unroll
+        for (int ny = 0; ny < NF; ++ny) {
+#pragma unroll
+          for (int nx = 0; nx < NF - ny; ++nx, ++q) {
+            if (nx + ny + nz <= NU) {
+              U2[q] = fma(fv, cin[idx * TB + L.bl], U2[q]);
+              ++idx;
+            }
+          }
+        }
+      }
+    }
+    const RunState rs = run_state(K, L, psi, bd);
+    // y pass: U1[nx] = sum_ny phi_ny(y) U2[nx][ny] for this lane's run
+    double U1[NF];
+#pragma unroll
+    for (int n = 0; n < NF; ++n) U1[n] = 0.0;
+    const double *fy = ty + rs.jy * nfp;
+    int q = 0;
+#pragma unroll
+    for (int ny = 0; ny < NF; ++ny) {
+      const double fv = fy[ny];
+#pragma unroll
+      for (int nx = 0; nx < NF - ny; ++nx, ++q) U1[nx] = fma(fv, U2[q], U1[nx]);
+    }
+    // x pass: psi(x) += sum_nx phi_nx(x) U1[nx]
+    double *dst = const_cast<double *>(rs.base);
+    const bool live = rs.active && L.bok;
+    for (int jb = bd.jlo; jb <= bd.jhi; jb += kBatch) {
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        const int jx = jb + u;
+        if (jx <= bd.jhi) {
+          const cptr<double> f = tx + jx * nfp;
+          double v = 0.0;
+#pragma unroll
+          for (int n = 0; n < NF; ++n) v = fma(f[n], U1[n], v);
+          const int k = jx - rs.jx0;
+          if (live && k >= 0 && k < rs.len) unsafeAtomicAdd(dst + k * K.B, v);
+        }
+      }
+    }
   }
 }
 
@@ -532,97 +649,144 @@ __global__ __launch_bounds__(256) void k_store(KArgs K, const int32_t *__restric
   }
 }
 
-// c[n] = h^3 sum_i P[i][n] psi(i): every lane accumulates all N_SHO
-// coefficients of its band over the points of its runs, reading each point's
-// stored row (the same address for all lanes of a slot).
+// The stored forms are dense contractions per atom, run on FP64 MFMA
+// (v_mfma_f64_16x16x4f64, D[16][16] += A[16][4] B[4][16]).  Lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16]; it receives D[4 (l / 16) + r][l % 16]
+// in accumulator register r.
+typedef double dx4 __attribute__((ext_vector_type(4)));
+
+__device__ inline dx4 mfma_f64(double a, double b, dx4 d) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, d, 0, 0, 0);
+}
+
+constexpr int kStoredBlock = 256;  // 4 waves
+constexpr int kStoredTile = 32;    // bands per workgroup (two 16-band MFMA columns)
+
+// c[n][b] += h^3 sum_k P[k][n] psi(k)[b] over the item's points k: MFMA with
+// i = n (16 per block), j = b, and four points per step along the sum.  Each
+// wave takes every fourth step; the waves meet in LDS, then one atomic add
+// per coefficient and band goes to c.
 template <int NU>
-__global__ __launch_bounds__(kBlock) void k_project_stored(
-    KArgs K, const double *__restrict__ psi, double *__restrict__ c) {
-  constexpr int NF = NU + 1;
-  constexpr int NS = NF * (NF + 1) * (NF + 2) / 6;
-  extern __shared__ double cacc[];
-  const cptr<WorkRec> W = as_const(K.work) + blockIdx.x;
-  const int tile = blockIdx.y;
-  const AtomRec A = load_uniform(K.atoms + W->atom);
-  const int TB = 1 << K.tb_shift;
-  for (int t = threadIdx.x; t < NS * TB; t += blockDim.x) cacc[t] = 0.0;
-  __syncthreads();
+__global__ __launch_bounds__(kStoredBlock) void k_project_stored(
+    SArgs S, const double *__restrict__ psi, double *__restrict__ c) {
+  constexpr int NS = (NU + 1) * (NU + 2) * (NU + 3) / 6;
+  constexpr int NBN = (NS + 15) / 16;
+  constexpr int U = 2;  // steps in flight per wave
+  __shared__ double red[NBN * 16 * kStoredTile];
+  const StoredItem it = load_uniform(S.items + blockIdx.x);
+  const int a = it.atom;
+  const int lane = threadIdx.x & 63;
   const int w = wave_id();
-  const Lanes L = lane_geometry(K, tile);
-  double acc[NS];
+  const int q = lane >> 4, col = lane & 15;
+  const int b0 = blockIdx.y * kStoredTile;
+  const int bA = b0 + col, bB = b0 + 16 + col;
+  const bool okA = bA < S.B, okB = bB < S.B;
+  const double *P = S.P + S.atom_poff[a];
+  const int32_t *pidx = S.pidx + S.atom_pbeg[a];
+  for (int t = threadIdx.x; t < NBN * 16 * kStoredTile; t += kStoredBlock) red[t] = 0.0;
+  dx4 acc[NBN][2];
 #pragma unroll
-  for (int n = 0; n < NS; ++n) acc[n] = 0.0;
-  const int b1 = W->wb[w + 1];
-  for (int bi = W->wb[w]; bi < b1; ++bi) {
-    const BundleRec bd = load_uniform(K.bundles + bi);
-    const RunState rs = run_state(K, L, psi, bd);
-    const int run = bd.run0 + min(L.slot, bd.nruns - 1);
-    const double *prow0 = K.stored + K.run_poff[run];
-    for (int jx = bd.jlo; jx <= bd.jhi; ++jx) {
-      const int k = jx - rs.jx0;
-      const bool ok = rs.active && k >= 0 && k < rs.len;
-      const int kc = min(max(k, 0), rs.len - 1);
-      const double v = ok ? rs.base[kc * K.B] : 0.0;
-      const double *prow = prow0 + (int64_t)kc * NS;
+  for (int nb = 0; nb < NBN; ++nb) acc[nb][0] = acc[nb][1] = dx4{0.0, 0.0, 0.0, 0.0};
+  for (int k = it.k0 + 4 * w; k < it.k1; k += 4 * 4 * U) {
+    double av[U][NBN], vA[U], vB[U];
 #pragma unroll
-      for (int n = 0; n < NS; ++n) acc[n] = fma(prow[n], v, acc[n]);
+    for (int u = 0; u < U; ++u) {
+      const int kp = k + 16 * u + q;
+      const bool ok = kp < it.k1;
+      const int kc = ok ? kp : it.k1 - 1;
+      const double *prow = P + (int64_t)kc * NS;
+      const double *vrow = psi + (int64_t)pidx[kc] * S.B;
+#pragma unroll
+      for (int nb = 0; nb < NBN; ++nb) {
+        const int n = nb * 16 + col;
+        av[u][nb] = (ok && n < NS) ? prow[n] : 0.0;
+      }
+      vA[u] = (ok && okA) ? vrow[bA] : 0.0;
+      vB[u] = (ok && okB) ? vrow[bB] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+      for (int nb = 0; nb < NBN; ++nb) {
+        acc[nb][0] = mfma_f64(av[u][nb], vA[u], acc[nb][0]);
+        acc[nb][1] = mfma_f64(av[u][nb], vB[u], acc[nb][1]);
+      }
     }
   }
-  // fold the slots, then one LDS add per coefficient and lane
-  for (int s = 32; s >= TB; s >>= 1) {
+  __syncthreads();
 #pragma unroll
-    for (int n = 0; n < NS; ++n) acc[n] += __shfl_xor(acc[n], s);
-  }
-  if (L.slot == 0 && L.bok) {
+  for (int nb = 0; nb < NBN; ++nb) {
 #pragma unroll
-    for (int n = 0; n < NS; ++n) atomicAdd(&cacc[n * TB + L.bl], acc[n]);
+    for (int r = 0; r < 4; ++r) {
+      const int n = nb * 16 + 4 * q + r;
+      atomicAdd(&red[n * kStoredTile + col], acc[nb][0][r]);
+      atomicAdd(&red[n * kStoredTile + 16 + col], acc[nb][1][r]);
+    }
   }
   __syncthreads();
-  const bool split = W->split != 0;
-  for (int t = threadIdx.x; t < NS * TB; t += blockDim.x) {
-    const int n = t >> K.tb_shift;
-    const int bb = tile * TB + (t & (TB - 1));
-    if (bb >= K.B) continue;
-    double *dst = c + (A.coeff_row + n) * K.B + bb;
-    if (split)
-      unsafeAtomicAdd(dst, K.h3 * cacc[t]);
-    else
-      *dst = K.h3 * cacc[t];
+  const int64_t row0 = S.atoms[a].coeff_row;
+  for (int t = threadIdx.x; t < NS * kStoredTile; t += kStoredBlock) {
+    const int n = t / kStoredTile;
+    const int b = b0 + (t % kStoredTile);
+    if (b < S.B) unsafeAtomicAdd(c + (row0 + n) * S.B + b, S.h3 * red[t]);
   }
 }
 
-// psi(i) += sum_n P[i][n] c[n]: every lane keeps its band's coefficients in
-// registers and adds into psi with global FP64 atomics (supports overlap).
+// psi(k)[b] += sum_n P[k][n] c[n][b]: MFMA with i = point (16 per tile),
+// j = band and four coefficients per step along the sum; the atom's
+// coefficients stay in registers.  Overlapping atoms meet in global FP64
+// atomics.
 template <int NU>
-__global__ __launch_bounds__(kBlock) void k_expand_stored(
-    KArgs K, const double *__restrict__ c, double *psi) {
-  constexpr int NF = NU + 1;
-  constexpr int NS = NF * (NF + 1) * (NF + 2) / 6;
-  const cptr<WorkRec> W = as_const(K.work) + blockIdx.x;
-  const int tile = blockIdx.y;
-  const AtomRec A = load_uniform(K.atoms + W->atom);
+__global__ __launch_bounds__(kStoredBlock) void k_expand_stored(
+    SArgs S, const double *__restrict__ c, double *psi) {
+  constexpr int NS = (NU + 1) * (NU + 2) * (NU + 3) / 6;
+  constexpr int NK = (NS + 3) / 4;
+  const StoredItem it = load_uniform(S.items + blockIdx.x);
+  const int a = it.atom;
+  const int lane = threadIdx.x & 63;
   const int w = wave_id();
-  const Lanes L = lane_geometry(K, tile);
-  double cr[NS];
+  const int q = lane >> 4, col = lane & 15;
+  const int b0 = blockIdx.y * kStoredTile;
+  const int bA = b0 + col, bB = b0 + 16 + col;
+  const bool okA = bA < S.B, okB = bB < S.B;
+  const double *P = S.P + S.atom_poff[a];
+  const int32_t *pidx = S.pidx + S.atom_pbeg[a];
+  const int64_t row0 = S.atoms[a].coeff_row;
+  double cA[NK], cB[NK];
 #pragma unroll
-  for (int n = 0; n < NS; ++n) cr[n] = c[(A.coeff_row + n) * K.B + L.bc];
-  const int b1 = W->wb[w + 1];
-  for (int bi = W->wb[w]; bi < b1; ++bi) {
-    const BundleRec bd = load_uniform(K.bundles + bi);
-    const RunState rs = run_state(K, L, psi, bd);
-    const int run = bd.run0 + min(L.slot, bd.nruns - 1);
-    const double *prow0 = K.stored + K.run_poff[run];
-    double *dst = const_cast<double *>(rs.base);
-    const bool live = rs.active && L.bok;
-    for (int jx = bd.jlo; jx <= bd.jhi; ++jx) {
-      const int k = jx - rs.jx0;
-      const bool ok = live && k >= 0 && k < rs.len;
-      const int kc = min(max(k, 0), rs.len - 1);
-      const double *prow = prow0 + (int64_t)kc * NS;
-      double v = 0.0;
+  for (int m = 0; m < NK; ++m) {
+    const int n = 4 * m + q;
+    cA[m] = (n < NS && okA) ? c[(row0 + n) * S.B + bA] : 0.0;
+    cB[m] = (n < NS && okB) ? c[(row0 + n) * S.B + bB] : 0.0;
+  }
+  for (int k = it.k0 + 16 * w; k < it.k1; k += 16 * 4) {
+    const int kp = k + col;
+    const bool ok = kp < it.k1;
+    const double *prow = P + (int64_t)(ok ? kp : it.k1 - 1) * NS;
+    double av[NK];
 #pragma unroll
-      for (int n = 0; n < NS; ++n) v = fma(prow[n], cr[n], v);
-      if (ok) unsafeAtomicAdd(dst + kc * K.B, v);
+    for (int m = 0; m < NK; ++m) {
+      const int n = 4 * m + q;
+      av[m] = (ok && n < NS) ? prow[n] : 0.0;
+    }
+    int32_t mi[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int kr = k + 4 * q + r;
+      mi[r] = kr < it.k1 ? pidx[kr] : -1;
+    }
+    dx4 dA = {0.0, 0.0, 0.0, 0.0}, dB = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int m = 0; m < NK; ++m) {
+      dA = mfma_f64(av[m], cA[m], dA);
+      dB = mfma_f64(av[m], cB[m], dB);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      if (mi[r] < 0) continue;
+      double *dst = psi + (int64_t)mi[r] * S.B;
+      if (okA) unsafeAtomicAdd(dst + bA, dA[r]);
+      if (okB) unsafeAtomicAdd(dst + bB, dB[r]);
     }
   }
 }
@@ -749,6 +913,44 @@ static hipError_t launch_force_nu(const KArgs &K, const double *psi,
 }
 
 
+template <int NUMAX>
+static hipError_t launch_project_any_nu(const KArgs &K, const double *psi,
+                                        double *c, hipStream_t s) {
+  const size_t shm = lds_tile_bytes(NUMAX + 1, 1 << K.tb_shift);
+  hipLaunchKernelGGL(k_project_any<NUMAX>, grid_of(K), dim3(kBlock), shm, s, K, psi, c);
+  return hipGetLastError();
+}
+
+hipError_t launch_project_any(int nu_max, const KArgs &K, const double *psi,
+                              double *c, hipStream_t s) {
+  if (K.nwork <= 0) return hipSuccess;
+  switch (nu_max) {
+#define X(N) case N: return launch_project_any_nu<N>(K, psi, c, s);
+    SHO_NU_CASES(X)
+#undef X
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int NU>
+static hipError_t launch_expand_atomic_nu(const KArgs &K, const double *c,
+                                          double *psi, hipStream_t s) {
+  const size_t shm = lds_tile_bytes(NU + 1, 1 << K.tb_shift);
+  hipLaunchKernelGGL(k_expand_atomic<NU>, grid_of(K), dim3(kBlock), shm, s, K, c, psi);
+  return hipGetLastError();
+}
+
+hipError_t launch_expand_atomic(int nu, const KArgs &K, const double *c,
+                                double *psi, hipStream_t s) {
+  if (K.nwork <= 0) return hipSuccess;
+  switch (nu) {
+#define X(N) case N: return launch_expand_atomic_nu<N>(K, c, psi, s);
+    SHO_NU_CASES(X)
+#undef X
+  }
+  return hipErrorInvalidValue;
+}
+
 hipError_t launch_project(int nu, const KArgs &K, const double *psi, double *c,
                           hipStream_t s) {
   switch (nu) {
@@ -829,13 +1031,18 @@ hipError_t launch_store(const KArgs &K, const int32_t *run_atom, int32_t nruns,
   return hipGetLastError();
 }
 
-hipError_t launch_project_stored(int nu, const KArgs &K, const double *psi,
+static dim3 stored_grid(const SArgs &S) {
+  return dim3((unsigned)S.nitems, (unsigned)((S.B + kStoredTile - 1) / kStoredTile));
+}
+
+hipError_t launch_project_stored(int nu, const SArgs &S, const double *psi,
                                  double *c, hipStream_t s) {
+  if (S.nitems <= 0) return hipSuccess;
   switch (nu) {
-#define X(N)                                                                 \
-  case N:                                                                    \
-    hipLaunchKernelGGL(k_project_stored<N>, grid_of(K), dim3(kBlock),        \
-                       lds_tile_bytes(N + 1, 1 << K.tb_shift), s, K, psi, c); \
+#define X(N)                                                                   \
+  case N:                                                                      \
+    hipLaunchKernelGGL(k_project_stored<N>, stored_grid(S), dim3(kStoredBlock), 0, s, S, \
+                       psi, c);                                                \
     return hipGetLastError();
     SHO_STORED_NU_CASES(X)
 #undef X
@@ -843,12 +1050,14 @@ hipError_t launch_project_stored(int nu, const KArgs &K, const double *psi,
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_expand_stored(int nu, const KArgs &K, const double *c,
+hipError_t launch_expand_stored(int nu, const SArgs &S, const double *c,
                                 double *psi, hipStream_t s) {
+  if (S.nitems <= 0) return hipSuccess;
   switch (nu) {
-#define X(N)                                                                    \
-  case N:                                                                       \
-    hipLaunchKernelGGL(k_expand_stored<N>, grid_of(K), dim3(kBlock), 0, s, K, c, psi); \
+#define X(N)                                                                  \
+  case N:                                                                     \
+    hipLaunchKernelGGL(k_expand_stored<N>, stored_grid(S), dim3(kStoredBlock), 0, s, S, \
+                       c, psi);                                               \
     return hipGetLastError();
     SHO_STORED_NU_CASES(X)
 #undef X

@@ -3,9 +3,16 @@
 
 #include <hip/hip_runtime_api.h>
 
+#include <string>
+
 #include "sho_internal.hpp"
 
 namespace sho {
+
+// Sets the calling thread's message (sho_last_error) and returns code.
+sho_status fail(sho_status code, const std::string &msg);
+// SHO_E_DEVICE with the runtime's message for e (clears the sticky error).
+sho_status hip_fail(hipError_t e, const char *what);
 
 // Argument block of the projection / expansion / derivative kernels.
 struct KArgs {
@@ -46,11 +53,30 @@ struct EArgs {
   int32_t nu_begin[SHO_NU_MAX + 2];  // nu_atoms[nu_begin[nu] .. nu_begin[nu+1])
 };
 
+// Argument block of the stored-projector kernels.
+struct SArgs {
+  const AtomRec *atoms;
+  const double *P;           // stored projector values
+  const int64_t *atom_poff;  // [natoms] first double of each atom's block
+  const int64_t *atom_pbeg;  // [natoms] first stored point of each atom
+  const int32_t *pidx;       // grid memory index of every stored point
+  const StoredItem *items;   // work items of this launch (one nu)
+  int32_t nitems;
+  int32_t B;
+  double h3;
+};
+
 // Samples the 1D tables of every atom (rows padded with zeros).
 hipError_t launch_tables(const AtomRec *atoms, int32_t natoms, double h,
                          double *tab, int32_t mmax, hipStream_t s);
 hipError_t launch_project(int nu, const KArgs &K, const double *psi, double *c,
                           hipStream_t s);
+// Work items of any cut-off up to nu_max in one launch.
+hipError_t launch_project_any(int nu_max, const KArgs &K, const double *psi,
+                              double *c, hipStream_t s);
+// Atom-owner expansion with global atomics (work items of one nu).
+hipError_t launch_expand_atomic(int nu, const KArgs &K, const double *c,
+                                double *psi, hipStream_t s);
 // Expansion by rows: plane partials U2 from c, then every memory row adds the
 // contributions of all runs that fall into it.  u2: E's u2 buffer.
 hipError_t launch_expand_rows(const EArgs &E, const double *c, double *u2,
@@ -64,9 +90,10 @@ hipError_t launch_rows(const EArgs &E, const double *u2, double *psi,
 // project / expand by reading them back (nu <= 5).
 hipError_t launch_store(const KArgs &K, const int32_t *run_atom, int32_t nruns,
                         double *stored, hipStream_t s);
-hipError_t launch_project_stored(int nu, const KArgs &K, const double *psi,
+// c must be zeroed first (launch_fill): every item adds its chunk's share.
+hipError_t launch_project_stored(int nu, const SArgs &S, const double *psi,
                                  double *c, hipStream_t s);
-hipError_t launch_expand_stored(int nu, const KArgs &K, const double *c,
+hipError_t launch_expand_stored(int nu, const SArgs &S, const double *c,
                                 double *psi, hipStream_t s);
 // grad must be zeroed first (launch_fill)
 hipError_t launch_force(int nu, const KArgs &K, const double *psi,

@@ -66,7 +66,7 @@ sho_status build_host_plan(const sho_grid *grid, int32_t natoms,
     return SHO_E_INVALID;
   }
   const uint32_t known =
-      SHO_FLAG_STORED | SHO_FLAG_ALLOW_UNDERSAMPLED | SHO_FLAG_HOST_ONLY;
+      SHO_FLAG_STORED | SHO_FLAG_ALLOW_UNDERSAMPLED | SHO_FLAG_HOST_ONLY | SHO_FLAG_PER_ATOM;
   if (flags & ~known) {
     *msg = "unknown flag bits";
     return SHO_E_INVALID;
@@ -250,11 +250,35 @@ int choose_tb_shift(int nbands, int nu_max, size_t lds_limit) {
   return shift;
 }
 
-void build_work(HostPlan *P, int tb_shift, int64_t target_points) {
+namespace {
+
+// 3D Morton key of a point given in cells of four grid points per axis.
+uint64_t morton_key(const HostPlan *P, int32_t a) {
+  uint64_t key = 0;
+  uint32_t q[3];
+  for (int d = 0; d < 3; ++d) {
+    const int32_t n = P->grid.n[d];
+    int64_t i = (int64_t)std::floor(P->support_centre[3 * a + d] / P->grid.h);
+    if (P->grid.periodic[d]) i = ((i % n) + n) % n;
+    i = std::min<int64_t>(std::max<int64_t>(i, 0), n - 1);
+    q[d] = (uint32_t)(i >> 2);
+  }
+  for (int bit = 0; bit < 16; ++bit)
+    for (int d = 0; d < 3; ++d)
+      key |= (uint64_t)((q[d] >> bit) & 1u) << (3 * bit + (2 - d));
+  return key;
+}
+
+}  // namespace
+
+void build_work(HostPlan *P, int tb_shift, int64_t target_points, int32_t sched) {
   const int slots = 64 >> tb_shift;
   P->tb_shift = tb_shift;
+  P->sched = sched;
+  P->target_points = target_points;
   P->bundles.clear();
   P->work.clear();
+  P->work_single.clear();
   P->any_split = false;
   // bundles: the runs of each atom plane, ordered by their first x index so
   // that runs of similar extent share a bundle, in groups of `slots`
@@ -291,9 +315,20 @@ void build_work(HostPlan *P, int tb_shift, int64_t target_points) {
     }
   }
   atom_bundle_begin[P->natoms] = (int32_t)P->bundles.size();
+  // atoms in Morton order of their centres
+  std::vector<int32_t> order(P->natoms);
+  std::vector<uint64_t> key(P->natoms);
+  for (int32_t a = 0; a < P->natoms; ++a) {
+    order[a] = a;
+    key[a] = morton_key(P, a);
+  }
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t x, int32_t y) { return key[x] < key[y]; });
   // work items, grouped by nu
+  std::vector<int32_t> first(P->natoms, 0), count(P->natoms, 0);
+  std::vector<int64_t> item_cost;
   for (int32_t nu = 0; nu <= SHO_NU_MAX; ++nu) {
-    for (int32_t a = 0; a < P->natoms; ++a) {
+    for (int32_t a : order) {
       const AtomRec &A = P->atoms[a];
       if (A.nu != nu || A.npoints == 0) continue;
       const int32_t bb = atom_bundle_begin[a], be = atom_bundle_begin[a + 1];
@@ -305,6 +340,8 @@ void build_work(HostPlan *P, int tb_shift, int64_t target_points) {
       auto cut = [&](int64_t target) {
         return bb + (int32_t)(std::lower_bound(cum.begin(), cum.end(), target) - cum.begin());
       };
+      first[a] = (int32_t)P->work.size();
+      count[a] = (int32_t)parts;
       for (int64_t q = 0; q < parts; ++q) {
         WorkRec W;
         W.atom = a;
@@ -315,25 +352,65 @@ void build_work(HostPlan *P, int tb_shift, int64_t target_points) {
         if (q == 0) W.wb[0] = bb;
         if (q == parts - 1) W.wb[kWaves] = be;
         P->work.push_back(W);
+        // cost of the item: x steps of its waves times the functions per step
+        item_cost.push_back((cum[W.wb[kWaves] - bb] - cum[W.wb[0] - bb]) * (nu + 2));
       }
       P->any_split |= parts > 1;
     }
   }
+  P->atom_work.assign(P->natoms + 1, (int32_t)P->work.size());
+  for (int32_t a = 0; a < P->natoms; ++a)
+    P->atom_work[a] = count[a] ? first[a] : (int32_t)P->work.size();
+  // one launch: all items in space order, or by decreasing cost
+  for (int32_t a : order)
+    for (int32_t i = 0; i < count[a]; ++i) P->work_single.push_back(P->work[first[a] + i]);
+  if (sched == kSchedSingleLpt) {
+    std::vector<int32_t> idx(P->work.size());
+    for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int32_t)i;
+    std::stable_sort(idx.begin(), idx.end(),
+                     [&](int32_t x, int32_t y) { return item_cost[x] > item_cost[y]; });
+    P->work_single.clear();
+    for (int32_t i : idx) P->work_single.push_back(P->work[i]);
+  }
 }
 
-void build_stored_offsets(HostPlan *P) {
+void build_stored(HostPlan *P, int32_t chunk) {
+  const int32_t nx = P->grid.n[0];
   P->run_poff.assign(P->lines.size() + 1, 0);
+  P->atom_poff.assign(P->natoms + 1, 0);
+  P->atom_pbeg.assign(P->natoms + 1, 0);
+  P->pidx.clear();
+  P->pidx.reserve(P->support_points);
   int64_t off = 0;
   for (int32_t a = 0; a < P->natoms; ++a) {
     const AtomRec &A = P->atoms[a];
     const int64_t ns = nsho(A.nu);
+    P->atom_poff[a] = off;
+    P->atom_pbeg[a] = (int64_t)P->pidx.size();
     for (int32_t r = A.line_begin; r < A.line_begin + A.nlines; ++r) {
+      const LineRec &L = P->lines[r];
       P->run_poff[r] = off;
-      off += (int64_t)P->lines[r].len * ns;
+      off += (int64_t)L.len * ns;
+      for (int32_t k = 0; k < L.len; ++k)
+        P->pidx.push_back(L.row * nx + L.x0m + k);
     }
   }
+  P->atom_poff[P->natoms] = off;
+  P->atom_pbeg[P->natoms] = (int64_t)P->pidx.size();
   P->run_poff[P->lines.size()] = off;
   P->stored_doubles = off;
+  // work items: chunks of each atom's points, atoms ordered by nu
+  std::vector<int32_t> order(P->natoms);
+  for (int32_t a = 0; a < P->natoms; ++a) order[a] = a;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+    return P->atoms[x].nu < P->atoms[y].nu;
+  });
+  P->sitems.clear();
+  for (int32_t a : order) {
+    const int32_t np = (int32_t)(P->atom_pbeg[a + 1] - P->atom_pbeg[a]);
+    for (int32_t k = 0; k < np; k += chunk)
+      P->sitems.push_back(StoredItem{a, k, std::min(np, k + chunk), 0});
+  }
 }
 
 void build_rows(HostPlan *P) {

@@ -1,0 +1,492 @@
+// sho_server.cpp -- request server over many resident systems (C ABI).
+//
+// Every registered system keeps a pinned host copy of its inputs (psi and
+// the coefficients w that expansion and derivative requests use).  On its
+// first request, or after an eviction, it is admitted: a plan is built, its
+// device buffers are allocated and the inputs are copied up on the system's
+// stream.  The resident set is bounded by a byte budget; when an admission
+// does not fit, the least recently used other systems are evicted (their
+// last request is waited for, their device memory freed; inputs are never
+// modified on the device, so nothing is copied back).
+//
+// Requests of one system run in submission order on the stream the system
+// was given at admission (the least loaded one); systems overlap across
+// streams.  A poller thread timestamps every request when its completion
+// event has fired, without taking the admission lock, so that latencies are
+// not inflated by a concurrent admission.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "sho_launch.hpp"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct Sys {
+  sho_grid grid{};
+  int32_t natoms = 0, nbands = 0;
+  std::vector<double> pos, sigma;
+  std::vector<int32_t> numax;
+  int64_t psi_doubles = 0, coeff_doubles = 0;
+  int64_t charge = 0;  // bytes charged against the budget while resident
+  double *h_psi = nullptr, *h_w = nullptr;  // pinned inputs
+  // resident state
+  bool resident = false;
+  sho_plan_t plan = nullptr;
+  double *d_psi = nullptr, *d_w = nullptr, *d_c = nullptr, *d_grad = nullptr,
+         *d_out = nullptr;
+  int stream = 0;
+  hipEvent_t last = nullptr;  // after the latest request of this system
+  uint64_t last_use = 0;
+  std::atomic<int32_t> inflight{0};
+  int64_t done_by_job[3] = {0, 0, 0};
+};
+
+struct Req {
+  int64_t id = 0;
+  Sys *sysp = nullptr;
+  int32_t sys = 0, job = 0;
+  int32_t stream = 0;
+  sho_status status = SHO_OK;
+  double t_submit = 0.0;
+  std::atomic<double> t_done{-1.0};
+  hipEvent_t ev = nullptr;
+};
+
+}  // namespace
+
+struct sho_server_s {
+  int64_t budget = 0;
+  uint32_t flags = 0;
+  bool dry = false;  // SHO_FLAG_HOST_ONLY: admission bookkeeping only
+  std::vector<hipStream_t> streams;
+  std::vector<int32_t> stream_load;  // resident systems per stream
+  std::deque<std::unique_ptr<Sys>> systems;
+  std::deque<std::unique_ptr<Req>> reqs;  // stable addresses
+  int64_t resident_bytes = 0, peak_bytes = 0;
+  int64_t admissions = 0, evictions = 0, rejected = 0;
+  uint64_t tick = 0;
+  Clock::time_point t0 = Clock::now();
+  std::mutex mu;  // systems, admission, submission
+
+  // completion poller
+  std::mutex pmu;
+  std::condition_variable pcv;
+  std::vector<Req *> pending;
+  std::atomic<int64_t> completed{0};
+  std::atomic<bool> stop{false};
+  std::thread poller;
+
+  double now() const {
+    return std::chrono::duration<double>(Clock::now() - t0).count();
+  }
+};
+
+namespace {
+
+using sho::fail;
+using sho::hip_fail;
+
+void poll_loop(sho_server_s *S) {
+  std::vector<Req *> mine;
+  for (;;) {
+    {
+      std::unique_lock<std::mutex> lk(S->pmu);
+      S->pcv.wait_for(lk, std::chrono::milliseconds(2),
+                      [&] { return S->stop.load() || !S->pending.empty(); });
+      mine.insert(mine.end(), S->pending.begin(), S->pending.end());
+      S->pending.clear();
+      if (S->stop.load() && mine.empty()) return;
+    }
+    bool any = false;
+    for (Req *&r : mine) {
+      const hipError_t q = hipEventQuery(r->ev);
+      if (q == hipErrorNotReady) continue;
+      const double t = S->now();
+      if (q != hipSuccess) (void)hipGetLastError();
+      (void)hipEventDestroy(r->ev);
+      r->ev = nullptr;
+      if (q != hipSuccess) r->status = SHO_E_DEVICE;
+      r->t_done.store(t);
+      r->sysp->inflight--;
+      S->completed++;
+      r = nullptr;
+      any = true;
+    }
+    mine.erase(std::remove(mine.begin(), mine.end(), nullptr), mine.end());
+    if (!any && !mine.empty()) std::this_thread::sleep_for(std::chrono::microseconds(20));
+    if (S->stop.load() && mine.empty()) {
+      std::lock_guard<std::mutex> lk(S->pmu);
+      if (S->pending.empty()) return;
+    }
+  }
+}
+
+void free_resident(sho_server_s *S, Sys &y) {
+  if (!S->dry) {
+    if (y.last) (void)hipEventSynchronize(y.last);
+    for (double *q : {y.d_psi, y.d_w, y.d_c, y.d_grad, y.d_out})
+      if (q) (void)hipFree(q);
+    if (y.plan) (void)sho_plan_destroy(y.plan);
+    if (y.last) (void)hipEventDestroy(y.last);
+    S->stream_load[y.stream]--;
+  }
+  y.d_psi = y.d_w = y.d_c = y.d_grad = y.d_out = nullptr;
+  y.plan = nullptr;
+  y.last = nullptr;
+  y.resident = false;
+  S->resident_bytes -= y.charge;
+}
+
+// Makes room for `need` bytes by evicting least recently used systems other
+// than `keep`.  Returns false if even an empty device would not do.
+bool make_room(sho_server_s *S, int64_t need, int32_t keep) {
+  if (need > S->budget) return false;
+  while (S->resident_bytes + need > S->budget) {
+    Sys *victim = nullptr;
+    for (size_t k = 0; k < S->systems.size(); ++k) {
+      Sys &y = *S->systems[k];
+      if ((int32_t)k == keep || !y.resident) continue;
+      if (!victim || y.last_use < victim->last_use) victim = &y;
+    }
+    if (!victim) return false;
+    free_resident(S, *victim);
+    S->evictions++;
+  }
+  return true;
+}
+
+sho_status admit(sho_server_s *S, int32_t id) {
+  Sys &y = *S->systems[id];
+  if (!make_room(S, y.charge, id)) {
+    S->rejected++;
+    return fail(SHO_E_BUDGET, "system needs " + std::to_string(y.charge) +
+                                  " bytes of a budget of " + std::to_string(S->budget));
+  }
+  if (!S->dry) {
+    int best = 0;
+    for (size_t k = 1; k < S->streams.size(); ++k)
+      if (S->stream_load[k] < S->stream_load[best]) best = (int)k;
+    y.stream = best;
+    S->stream_load[best]++;
+    hipStream_t st = S->streams[best];
+    sho_status r = sho_plan_create(&y.grid, y.natoms, y.pos.data(), y.sigma.data(),
+                                   y.numax.data(), nullptr, y.nbands, S->flags, &y.plan);
+    hipError_t e = hipSuccess;
+    const size_t pb = y.psi_doubles * sizeof(double), cb = std::max<int64_t>(y.coeff_doubles, 1) * 8;
+    if (r == SHO_OK) {
+      if ((e = hipMalloc((void **)&y.d_psi, pb)) == hipSuccess &&
+          (e = hipMalloc((void **)&y.d_out, pb)) == hipSuccess &&
+          (e = hipMalloc((void **)&y.d_w, cb)) == hipSuccess &&
+          (e = hipMalloc((void **)&y.d_c, cb)) == hipSuccess &&
+          (e = hipMalloc((void **)&y.d_grad, std::max(3 * y.natoms, 1) * sizeof(double))) ==
+              hipSuccess &&
+          (e = hipEventCreateWithFlags(&y.last, hipEventDisableTiming)) == hipSuccess &&
+          (e = hipMemcpyAsync(y.d_psi, y.h_psi, pb, hipMemcpyHostToDevice, st)) == hipSuccess)
+        e = hipMemcpyAsync(y.d_w, y.h_w, y.coeff_doubles * sizeof(double),
+                           hipMemcpyHostToDevice, st);
+    }
+    if (r != SHO_OK || e != hipSuccess) {
+      const std::string why = r != SHO_OK ? std::string(sho_last_error()) : "";
+      y.resident = true;  // so that free_resident releases what exists
+      S->resident_bytes += y.charge;
+      free_resident(S, y);
+      if (r != SHO_OK) return fail(r, "admission: " + why);
+      return e == hipErrorOutOfMemory ? fail(SHO_E_NOMEM, "admission: device allocation failed")
+                                      : hip_fail(e, "admission");
+    }
+  }
+  y.resident = true;
+  S->resident_bytes += y.charge;
+  S->peak_bytes = std::max(S->peak_bytes, S->resident_bytes);
+  S->admissions++;
+  return SHO_OK;
+}
+
+sho_status launch_job(sho_server_s *S, Sys &y, int32_t job) {
+  hipStream_t st = S->streams[y.stream];
+  sho_status r = SHO_OK;
+  if (job == SHO_JOB_PROJECT) {
+    r = sho_plan_project(y.plan, y.d_psi, y.d_c, st);
+  } else if (job == SHO_JOB_EXPAND) {
+    hipError_t e = sho::launch_fill(y.d_out, y.psi_doubles, 0.0, st);
+    if (e != hipSuccess) return hip_fail(e, "fill");
+    r = sho_plan_expand(y.plan, y.d_w, y.d_out, st);
+  } else {
+    r = sho_plan_force(y.plan, y.d_psi, y.d_w, y.d_grad, st);
+  }
+  return r;
+}
+
+}  // namespace
+
+extern "C" {
+
+sho_status sho_server_create(int64_t budget_bytes, int32_t nstreams, uint32_t plan_flags,
+                             sho_server_t *out) {
+  if (!out) return fail(SHO_E_INVALID, "out must not be NULL");
+  *out = nullptr;
+  if (budget_bytes <= 0) return fail(SHO_E_INVALID, "budget must be positive");
+  if (nstreams < 1 || nstreams > 16) return fail(SHO_E_INVALID, "nstreams outside 1..16");
+  if (plan_flags & ~(uint32_t)(SHO_FLAG_HOST_ONLY | SHO_FLAG_PER_ATOM | SHO_FLAG_STORED |
+                               SHO_FLAG_ALLOW_UNDERSAMPLED))
+    return fail(SHO_E_INVALID, "unknown plan flags");
+  std::unique_ptr<sho_server_s> S(new (std::nothrow) sho_server_s());
+  if (!S) return fail(SHO_E_NOMEM, "host allocation failed");
+  S->budget = budget_bytes;
+  S->flags = plan_flags;
+  S->dry = (plan_flags & SHO_FLAG_HOST_ONLY) != 0;
+  if (!S->dry) {
+    for (int i = 0; i < nstreams; ++i) {
+      hipStream_t st = nullptr;
+      hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+      if (e != hipSuccess) {
+        for (hipStream_t q : S->streams) (void)hipStreamDestroy(q);
+        return hip_fail(e, "stream creation");
+      }
+      S->streams.push_back(st);
+    }
+    S->stream_load.assign(nstreams, 0);
+    S->poller = std::thread(poll_loop, S.get());
+  }
+  *out = S.release();
+  return SHO_OK;
+}
+
+sho_status sho_server_add_system(sho_server_t S, const sho_grid *grid, int32_t natoms,
+                                 const double *pos, const double *sigma,
+                                 const int32_t *numax, int32_t nbands,
+                                 const double *psi, const double *w, int32_t *id) {
+  if (!S || !id) return fail(SHO_E_INVALID, "NULL server or id");
+  // validate and size with a host-only plan of the same flags
+  sho_plan_t hp = nullptr;
+  sho_status r = sho_plan_create(grid, natoms, pos, sigma, numax, nullptr, nbands,
+                                 S->flags | SHO_FLAG_HOST_ONLY, &hp);
+  if (r != SHO_OK) return r;
+  sho_plan_info info;
+  r = sho_plan_get_info(hp, &info);
+  (void)sho_plan_destroy(hp);
+  if (r != SHO_OK) return r;
+  std::unique_ptr<Sys> y(new (std::nothrow) Sys());
+  if (!y) return fail(SHO_E_NOMEM, "host allocation failed");
+  y->grid = *grid;
+  y->natoms = natoms;
+  y->nbands = nbands;
+  y->pos.assign(pos, pos + 3 * (size_t)natoms);
+  y->sigma.assign(sigma, sigma + natoms);
+  y->numax.assign(numax, numax + natoms);
+  y->psi_doubles = (int64_t)grid->n[0] * grid->n[1] * grid->n[2] * nbands;
+  y->coeff_doubles = info.coeff_doubles;
+  // plan tables + psi + out + w + c + grad, each rounded up to 4 KiB
+  auto pg = [](int64_t b) { return (b + 4095) / 4096 * 4096; };
+  y->charge = pg(info.device_bytes) + 2 * pg(y->psi_doubles * 8) +
+              2 * pg(std::max<int64_t>(y->coeff_doubles, 1) * 8) + pg(24 * std::max(natoms, 1));
+  if (!S->dry) {
+    hipError_t e = hipHostMalloc((void **)&y->h_psi, y->psi_doubles * sizeof(double));
+    if (e == hipSuccess)
+      e = hipHostMalloc((void **)&y->h_w, std::max<int64_t>(y->coeff_doubles, 1) * 8);
+    if (e != hipSuccess) {
+      if (y->h_psi) (void)hipHostFree(y->h_psi);
+      return e == hipErrorOutOfMemory ? fail(SHO_E_NOMEM, "pinned host allocation failed")
+                                      : hip_fail(e, "pinned host allocation");
+    }
+    if (psi)
+      std::memcpy(y->h_psi, psi, y->psi_doubles * sizeof(double));
+    else
+      std::memset(y->h_psi, 0, y->psi_doubles * sizeof(double));
+    if (w)
+      std::memcpy(y->h_w, w, y->coeff_doubles * sizeof(double));
+    else
+      std::memset(y->h_w, 0, std::max<int64_t>(y->coeff_doubles, 1) * sizeof(double));
+  }
+  std::lock_guard<std::mutex> lk(S->mu);
+  *id = (int32_t)S->systems.size();
+  S->systems.push_back(std::move(y));
+  return SHO_OK;
+}
+
+sho_status sho_server_submit(sho_server_t S, int32_t sys, int32_t job, int64_t *request) {
+  if (!S) return fail(SHO_E_INVALID, "NULL server");
+  if (job < 0 || job > 2) return fail(SHO_E_INVALID, "unknown job");
+  std::lock_guard<std::mutex> lk(S->mu);
+  if (sys < 0 || sys >= (int32_t)S->systems.size())
+    return fail(SHO_E_INVALID, "unknown system");
+  const double t_submit = S->now();
+  Sys &y = *S->systems[sys];
+  if (!y.resident) {
+    sho_status r = admit(S, sys);
+    if (r != SHO_OK) return r;
+  }
+  y.last_use = ++S->tick;
+  std::unique_ptr<Req> q(new (std::nothrow) Req());
+  if (!q) return fail(SHO_E_NOMEM, "host allocation failed");
+  q->id = (int64_t)S->reqs.size();
+  q->sys = sys;
+  q->sysp = &y;
+  q->job = job;
+  q->t_submit = t_submit;
+  q->stream = y.stream;
+  if (S->dry) {
+    q->t_done.store(t_submit);
+    y.done_by_job[job]++;
+    S->completed++;
+  } else {
+    sho_status r = launch_job(S, y, job);
+    if (r != SHO_OK) return r;
+    hipStream_t st = S->streams[y.stream];
+    hipError_t e = hipEventCreateWithFlags(&q->ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(q->ev, st);
+    if (e == hipSuccess) e = hipEventRecord(y.last, st);
+    if (e != hipSuccess) {
+      if (q->ev) (void)hipEventDestroy(q->ev);
+      return hip_fail(e, "completion event");
+    }
+    y.inflight++;
+    y.done_by_job[job]++;
+  }
+  if (request) *request = q->id;
+  Req *raw = q.get();
+  S->reqs.push_back(std::move(q));
+  if (!S->dry) {
+    std::lock_guard<std::mutex> pl(S->pmu);
+    S->pending.push_back(raw);
+    S->pcv.notify_one();
+  }
+  return SHO_OK;
+}
+
+sho_status sho_server_drain(sho_server_t S) {
+  if (!S) return fail(SHO_E_INVALID, "NULL server");
+  if (S->dry) return SHO_OK;
+  for (hipStream_t st : S->streams) {
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "drain");
+  }
+  int64_t total = 0;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    total = (int64_t)S->reqs.size();
+  }
+  while (S->completed.load() < total) std::this_thread::sleep_for(std::chrono::microseconds(50));
+  return SHO_OK;
+}
+
+sho_status sho_server_request_info(sho_server_t S, int64_t request, int32_t *sys,
+                                   int32_t *job, double *t_submit, double *t_done) {
+  if (!S || !sys || !job || !t_submit || !t_done) return fail(SHO_E_INVALID, "NULL argument");
+  std::lock_guard<std::mutex> lk(S->mu);
+  if (request < 0 || request >= (int64_t)S->reqs.size())
+    return fail(SHO_E_INVALID, "unknown request");
+  const Req &q = *S->reqs[request];
+  *sys = q.sys;
+  *job = q.job;
+  *t_submit = q.t_submit;
+  *t_done = q.t_done.load();
+  return q.status;
+}
+
+sho_status sho_server_read(sho_server_t S, int32_t sys, int32_t what, double *host) {
+  if (!S || !host) return fail(SHO_E_INVALID, "NULL argument");
+  std::lock_guard<std::mutex> lk(S->mu);
+  if (sys < 0 || sys >= (int32_t)S->systems.size())
+    return fail(SHO_E_INVALID, "unknown system");
+  Sys &y = *S->systems[sys];
+  if (S->dry || !y.resident) return fail(SHO_E_INVALID, "system is not resident");
+  const double *src = nullptr;
+  int64_t n = 0;
+  if (what == SHO_JOB_PROJECT) {
+    src = y.d_c;
+    n = y.coeff_doubles;
+  } else if (what == SHO_JOB_EXPAND) {
+    src = y.d_out;
+    n = y.psi_doubles;
+  } else if (what == SHO_JOB_FORCE) {
+    src = y.d_grad;
+    n = 3 * (int64_t)y.natoms;
+  } else {
+    return fail(SHO_E_INVALID, "unknown output");
+  }
+  hipError_t e = hipEventSynchronize(y.last);
+  if (e == hipSuccess && n) e = hipMemcpy(host, src, n * sizeof(double), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "read");
+  return SHO_OK;
+}
+
+sho_status sho_server_get_stats(sho_server_t S, sho_server_stats *st) {
+  if (!S || !st) return fail(SHO_E_INVALID, "NULL argument");
+  std::lock_guard<std::mutex> lk(S->mu);
+  st->budget_bytes = S->budget;
+  st->resident_bytes = S->resident_bytes;
+  st->peak_resident_bytes = S->peak_bytes;
+  st->requests = (int64_t)S->reqs.size();
+  st->completed = S->completed.load();
+  st->admissions = S->admissions;
+  st->evictions = S->evictions;
+  st->rejected = S->rejected;
+  int32_t res = 0;
+  for (const auto &y : S->systems) res += y->resident ? 1 : 0;
+  st->systems = (int32_t)S->systems.size();
+  st->resident_systems = res;
+  return SHO_OK;
+}
+
+sho_status sho_server_system_info(sho_server_t S, int32_t sys, int64_t *charge_bytes,
+                                  int32_t *resident) {
+  if (!S || !charge_bytes || !resident) return fail(SHO_E_INVALID, "NULL argument");
+  std::lock_guard<std::mutex> lk(S->mu);
+  if (sys < 0 || sys >= (int32_t)S->systems.size())
+    return fail(SHO_E_INVALID, "unknown system");
+  *charge_bytes = S->systems[sys]->charge;
+  *resident = S->systems[sys]->resident ? 1 : 0;
+  return SHO_OK;
+}
+
+sho_status sho_server_inputs(sho_server_t S, int32_t sys, double **psi, double **w) {
+  if (!S || !psi || !w) return fail(SHO_E_INVALID, "NULL argument");
+  std::lock_guard<std::mutex> lk(S->mu);
+  if (sys < 0 || sys >= (int32_t)S->systems.size())
+    return fail(SHO_E_INVALID, "unknown system");
+  *psi = S->systems[sys]->h_psi;
+  *w = S->systems[sys]->h_w;
+  return SHO_OK;
+}
+
+sho_status sho_server_clock(sho_server_t S, double *now) {
+  if (!S || !now) return fail(SHO_E_INVALID, "NULL argument");
+  *now = S->now();
+  return SHO_OK;
+}
+
+sho_status sho_server_destroy(sho_server_t S) {
+  if (!S) return SHO_OK;
+  sho_status r = SHO_OK;
+  if (!S->dry) {
+    r = sho_server_drain(S);
+    S->stop.store(true);
+    S->pcv.notify_one();
+    if (S->poller.joinable()) S->poller.join();
+  }
+  for (auto &y : S->systems) {
+    if (y->resident) free_resident(S, *y);
+    if (y->h_psi) (void)hipHostFree(y->h_psi);
+    if (y->h_w) (void)hipHostFree(y->h_w);
+  }
+  for (hipStream_t st : S->streams) (void)hipStreamDestroy(st);
+  delete S;
+  return r;
+}
+
+}  // extern "C"

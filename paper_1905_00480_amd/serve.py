@@ -1,0 +1,140 @@
+"""Request-stream driver of the library's server (sho_server_*).
+
+A pool of systems is registered once; requests (project, expand or force on
+one system of the pool) arrive as a Poisson stream and are submitted at their
+arrival times.  The server keeps systems resident under an HBM byte budget
+(least recently used ones are evicted), runs the requests of one system in
+order on one stream and overlaps different systems over several streams.
+Latency of a request = completion (taken by the server when the request's
+event fires) - arrival.  The per-request reference is the same server with
+one stream (FIFO) and per-atom launches (SHO_FLAG_PER_ATOM).
+
+Inputs are synthetic: psi and the expansion / derivative weights w are a
+seeded block of 2^20 standard normal values tiled over each buffer.
+"""
+import time
+
+import numpy as np
+
+from . import binding as bd
+from . import workloads as wl
+
+BLOCK = 1 << 20
+
+
+def _tile_fill(dst, seed):
+    block = np.random.default_rng(seed).standard_normal(BLOCK)
+    n = dst.shape[0]
+    k = n // BLOCK
+    if k:
+        dst[:k * BLOCK].reshape(k, BLOCK)[:] = block
+    dst[k * BLOCK:] = block[:n - k * BLOCK]
+
+
+def register(server, pool, seed=4):
+    """Add every system of the pool and fill its inputs in place."""
+    sids = []
+    for k, s in enumerate(pool):
+        sid = server.add(s)
+        psi, w = server.inputs(sid)
+        if psi is not None:
+            _tile_fill(psi, seed * 7919 + 2 * k)
+            _tile_fill(w, seed * 7919 + 2 * k + 1)
+        sids.append(sid)
+    return sids
+
+
+def units_of(pool):
+    """sum_a |S_a| * B of every system (gridpoint*bands of one request)."""
+    out = []
+    for s in pool:
+        p = bd.Plan(s.n, s.h, s.periodic, s.pos, s.sigma, s.numax, s.nbands,
+                    flags=bd.FLAG_HOST_ONLY)
+        out.append(p.support_points * s.nbands)
+        p.close()
+    return np.array(out, dtype=np.float64)
+
+
+def run(server, sids, units, rate_hz=200.0, warmup=200, requests=2000, seed=4):
+    """Submit a Poisson stream (warm-up requests first, not measured) and
+    return throughput and latency percentiles of the measured requests."""
+    count = warmup + requests
+    arrivals, kinds, rng = wl.poisson_arrivals(rate_hz, count, seed)
+    which = rng.integers(0, len(sids), size=count)
+    base_srv = server.clock()
+    base = time.perf_counter()
+    rids = []
+    for i in range(count):
+        target = base + arrivals[i]
+        while True:
+            d = target - time.perf_counter()
+            if d <= 0:
+                break
+            time.sleep(d if d > 2e-3 else 0)
+        rids.append(server.submit(sids[which[i]], int(kinds[i])))
+    server.drain()
+    lat, done, jobs = [], [], []
+    for i in range(warmup, count):
+        _, job, _, t_done = server.request_info(rids[i])
+        lat.append(t_done - (base_srv + arrivals[i]))
+        done.append(t_done)
+        jobs.append(job)
+    lat = np.array(lat)
+    span = max(done) - (base_srv + arrivals[warmup])
+    work = float(units[which[warmup:]].sum())
+    st = server.stats()
+    return {"requests": requests, "warmup": warmup, "rate_hz": rate_hz,
+            "span_s": span, "req_per_s": requests / span,
+            "gridpoint*bands/s": work / span,
+            "latency_ms_p50": 1e3 * float(np.percentile(lat, 50)),
+            "latency_ms_p99": 1e3 * float(np.percentile(lat, 99)),
+            "latency_ms_mean": 1e3 * float(lat.mean()),
+            "jobs": {j: int(np.sum(np.array(jobs) == k))
+                     for k, j in enumerate(("project", "expand", "force"))},
+            "admissions": st["admissions"], "evictions": st["evictions"],
+            "peak_resident_GB": st["peak_resident_bytes"] / 1e9}
+
+
+def compare(budget_bytes=64 << 30, nstreams=4, rate_hz=200.0, warmup=200, requests=2000,
+            seed=4, nsystems=32):
+    """The batched server and the per-request reference on the same stream of
+    requests over the same pool."""
+    pool = wl.serving_pool(seed=seed, nsystems=nsystems)
+    units = units_of(pool)
+    res = {"pool": {"systems": len(pool),
+                    "psi_GB": float(sum(np.prod(s.n) * s.nbands * 8 for s in pool)) / 1e9},
+           "budget_GB": budget_bytes / 1e9}
+    for name, streams, flags in (("batched", nstreams, 0),
+                                 ("per_request_plain", 1, bd.FLAG_PER_ATOM)):
+        srv = bd.Server(budget_bytes, streams, flags)
+        t0 = time.perf_counter()
+        sids = register(srv, pool, seed)
+        reg_s = time.perf_counter() - t0
+        r = run(srv, sids, units, rate_hz, warmup, requests, seed)
+        r["streams"] = streams
+        r["register_s"] = reg_s
+        srv.close()
+        res[name] = r
+    res["p99_ratio_plain_over_batched"] = (res["per_request_plain"]["latency_ms_p99"] /
+                                           res["batched"]["latency_ms_p99"])
+    return res
+
+
+def main():
+    import argparse
+    import json
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--budget-gb", type=float, default=64.0)
+    ap.add_argument("--streams", type=int, default=4)
+    ap.add_argument("--rate", type=float, default=200.0)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--requests", type=int, default=2000)
+    ap.add_argument("--systems", type=int, default=32)
+    a = ap.parse_args()
+    bd.load_library()
+    print(json.dumps(compare(int(a.budget_gb * (1 << 30)), a.streams, a.rate, a.warmup,
+                             a.requests, nsystems=a.systems)), flush=True)
+
+
+if __name__ == "__main__":
+    main()

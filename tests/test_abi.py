@@ -84,6 +84,29 @@ def test_argument_errors():
     mk(numax=[5, 4], flags=bd.FLAG_HOST_ONLY | bd.FLAG_STORED).close()
 
 
+def test_schedule_arguments_host_only():
+    """Schedules can be set on host-only plans (sizing); bad values refused."""
+    _lib()
+    s = wl.small_mixed()
+    s.numax = np.array([0, 3, 6, 9, 10, 7, 4, 8])
+    p = _host_plan(s, flags=bd.FLAG_PER_ATOM)
+    sc, tile, tp = p.schedule()
+    assert sc == bd.SCHED_SINGLE and tp == 16384 and tile & (tile - 1) == 0
+    for sched in bd.SCHEDULES:
+        p.set_schedule(sched, tile // 2, 4096)
+        assert p.schedule() == (sched, tile // 2, 4096)
+    _expect(bd.SHO_E_INVALID, lambda: p.set_schedule(3, 0, 4096))
+    _expect(bd.SHO_E_INVALID, lambda: p.set_schedule(0, 3, 4096))
+    _expect(bd.SHO_E_INVALID, lambda: p.set_schedule(0, 0, 10))
+    # nu_max + 1 = 11 coefficients tile (364 functions) at twice the widest
+    # tile no longer fits 63 KiB of LDS
+    _expect(bd.SHO_E_BOX, lambda: p.set_schedule(0, 2 * tile, 4096))
+    p.close()
+    one = _host_plan(wl.small_periodic(natoms=3))
+    assert one.schedule()[0] == bd.SCHED_BY_NU
+    one.close()
+
+
 def test_host_only_plan_refuses_compute():
     lib = _lib()
     s = wl.small_periodic(natoms=2)

@@ -1,0 +1,107 @@
+"""Admission bookkeeping of the request server on the CPU (a server made
+with SHO_FLAG_HOST_ONLY sizes every system with a host-only plan and runs the
+budget / least-recently-used logic without touching a device)."""
+import numpy as np
+import pytest
+
+from paper_1905_00480_amd import binding as bd
+from paper_1905_00480_amd import workloads as wl
+
+
+def _server(budget, systems):
+    bd.load_library()
+    srv = bd.Server(budget, 1, bd.FLAG_HOST_ONLY)
+    sids = [srv.add(s) for s in systems]
+    return srv, sids
+
+
+def _systems():
+    return [wl.small_periodic(seed=30 + k, natoms=2 + k, nbands=8 * (k + 1)) for k in range(4)]
+
+
+def _expect(code, fn):
+    with pytest.raises(bd.ShoError) as ei:
+        fn()
+    assert ei.value.code == code, str(ei.value)
+
+
+def test_charge_covers_buffers_and_tables():
+    systems = _systems()
+    srv, sids = _server(1 << 40, systems)
+    for s, sid in zip(systems, sids):
+        charge, resident = srv.system_info(sid)
+        assert not resident
+        psi = int(np.prod(s.n)) * s.nbands * 8
+        p = bd.Plan(s.n, s.h, s.periodic, s.pos, s.sigma, s.numax, s.nbands,
+                    flags=bd.FLAG_HOST_ONLY)
+        tables = p.info["device_bytes"]
+        assert tables > 0
+        assert charge >= 2 * psi + 2 * p.coeff_doubles * 8 + tables
+        assert charge <= 2 * psi + 2 * p.coeff_doubles * 8 + tables + 10 * 4096
+        p.close()
+    srv.close()
+
+
+def test_lru_eviction_order_and_stats():
+    systems = _systems()
+    probe, sids = _server(1 << 40, systems)
+    charges = [probe.system_info(i)[0] for i in sids]
+    probe.close()
+    # room for the two largest systems but not three
+    budget = sorted(charges)[-1] + sorted(charges)[-2]
+    srv, sids = _server(budget, systems)
+    srv.submit(sids[3], bd.JOB_PROJECT)
+    srv.submit(sids[2], bd.JOB_FORCE)
+    assert [srv.system_info(i)[1] for i in sids] == [False, False, True, True]
+    srv.submit(sids[3], bd.JOB_EXPAND)       # 3 is now the most recent
+    srv.submit(sids[1], bd.JOB_PROJECT)      # evicts 2 (least recently used)
+    assert [srv.system_info(i)[1] for i in sids] == [False, True, False, True]
+    st = srv.stats()
+    assert st["admissions"] == 3 and st["evictions"] == 1 and st["rejected"] == 0
+    assert st["requests"] == 4 and st["completed"] == 4
+    assert st["resident_bytes"] == charges[1] + charges[3] <= budget
+    assert st["peak_resident_bytes"] <= budget
+    # a request to a resident system admits nothing
+    srv.submit(sids[1], bd.JOB_FORCE)
+    assert srv.stats()["admissions"] == 3
+    srv.close()
+
+
+def test_budget_refusals():
+    systems = _systems()
+    srv, sids = _server(1 << 40, systems)
+    big = srv.system_info(sids[3])[0]
+    srv.close()
+    srv, sids = _server(big - 1, systems)
+    _expect(bd.SHO_E_BUDGET, lambda: srv.submit(sids[3], bd.JOB_PROJECT))
+    assert srv.stats()["rejected"] == 1
+    srv.submit(sids[0], bd.JOB_PROJECT)          # others still served
+    _expect(bd.SHO_E_INVALID, lambda: srv.submit(7, bd.JOB_PROJECT))
+    _expect(bd.SHO_E_INVALID, lambda: srv.submit(sids[0], 3))
+    _expect(bd.SHO_E_INVALID, lambda: srv.read(sids[0], bd.JOB_PROJECT))  # no device
+    srv.close()
+    _expect(bd.SHO_E_INVALID, lambda: bd.Server(0, 1, bd.FLAG_HOST_ONLY))
+    _expect(bd.SHO_E_INVALID, lambda: bd.Server(1 << 30, 0, bd.FLAG_HOST_ONLY))
+    _expect(bd.SHO_E_INVALID, lambda: bd.Server(1 << 30, 1, bd.FLAG_HOST_ONLY | 0x100))
+
+
+def test_invalid_system_is_refused_at_registration():
+    bd.load_library()
+    srv = bd.Server(1 << 30, 1, bd.FLAG_HOST_ONLY)
+    s = wl.small_periodic(natoms=2)
+    s.sigma = np.array([0.05, 0.6])   # h = 0.2 undersamples sigma = 0.05
+    _expect(bd.SHO_E_UNDERSAMPLED, lambda: srv.add(s))
+    assert srv.stats()["systems"] == 0
+    srv.close()
+
+
+def test_serving_pool_sizes():
+    """The serving pool follows its recipe (N in 32..160 step 16, atoms
+    clamped to 16..4096, B in {8..128})."""
+    pool = wl.serving_pool()
+    assert len(pool) == 32
+    for s in pool:
+        assert s.n[0] % 16 == 0 and 32 <= s.n[0] <= 160 and s.n[0] == s.n[1] == s.n[2]
+        assert 16 <= s.natoms <= 4096 and s.nbands in (8, 16, 32, 64, 128)
+        assert np.all((s.numax >= 3) & (s.numax <= 9))
+        assert np.all((s.sigma >= 0.4) & (s.sigma <= 1.2))
