@@ -105,6 +105,9 @@ typedef int32_t sho_status;
 #define SHO_SCHED_SINGLE 1     /* one launch over all work items, atoms in
                                   Morton order of their centres */
 #define SHO_SCHED_SINGLE_LPT 2 /* one launch, work items by falling cost */
+#define SHO_SCHED_XCD 4        /* flag for any of the above: consecutive items
+                                  of the order run on the same XCD (shared
+                                  L2), each XCD taking one eighth */
 
 typedef struct sho_grid {
   int32_t n[3];        /* points along x, y, z */
@@ -232,7 +235,8 @@ sho_status sho_plan_profile_read(sho_plan_t plan, int64_t *counts,
 
 /*
  * Work decomposition of the projection (sec. 6 measures prj and add over
- * many atoms of one system; these calls batch them).  A work item is one
+ * many atoms of one system; these calls batch them).  schedule is one of
+ * SHO_SCHED_BY_NU, _SINGLE, _SINGLE_LPT, optionally | SHO_SCHED_XCD.  A work item is one
  * atom, or a share of an atom of more than target_points support points;
  * band_tile bands share a lane slot (power of two <= 64, 0 keeps the current
  * tile).  Plans with several cut-offs start with SHO_SCHED_SINGLE, others
@@ -257,7 +261,8 @@ typedef struct sho_tune_result {
 
 /*
  * Autotuner: times the projection of psi into c (both device buffers of the
- * plan's sizes; c is overwritten) under every schedule x work item size
+ * plan's sizes; c is overwritten) under every schedule (with and without
+ * SHO_SCHED_XCD) x work item size
  * {8192, 16384, 32768} x band tile {current, half}, reps launches each after
  * one warm-up, on stream, and keeps the fastest.  Synchronous.  result may
  * be NULL.  Refused (SHO_E_INVALID) on stored and per-atom plans.

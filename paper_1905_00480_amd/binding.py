@@ -34,7 +34,9 @@ FLAG_PER_ATOM = 0x8
 SCHED_BY_NU = 0
 SCHED_SINGLE = 1
 SCHED_SINGLE_LPT = 2
-SCHEDULES = (SCHED_BY_NU, SCHED_SINGLE, SCHED_SINGLE_LPT)
+SCHED_XCD = 4
+SCHEDULES = (SCHED_BY_NU, SCHED_SINGLE, SCHED_SINGLE_LPT,
+             SCHED_BY_NU | SCHED_XCD, SCHED_SINGLE | SCHED_XCD, SCHED_SINGLE_LPT | SCHED_XCD)
 
 # every symbol include/sho.h declares
 EXPORTS = (

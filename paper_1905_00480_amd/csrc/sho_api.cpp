@@ -75,7 +75,7 @@ struct sho_plan_s {
   int32_t *d_pidx = nullptr;
   sho::StoredItem *d_sitems = nullptr;
   std::vector<Group> sgroups;     // stored work items by nu
-  sho::WorkRec *d_work_single = nullptr;  // all items, one-launch order
+  sho::WorkRec *d_work_proj = nullptr;  // the projection's launch order
   int64_t sched_version = 0;      // bumped whenever the work items change
   int64_t sched_bytes = 0;        // device bytes of the schedule tables
   bool prof_on = false;
@@ -102,8 +102,8 @@ void free_plan_device(sho_plan_s *p) {
   if (p->d_lines) (void)hipFree(p->d_lines);
   if (p->d_bundles) (void)hipFree(p->d_bundles);
   if (p->d_work) (void)hipFree(p->d_work);
-  if (p->d_work_single) (void)hipFree(p->d_work_single);
-  p->d_work_single = nullptr;
+  if (p->d_work_proj) (void)hipFree(p->d_work_proj);
+  p->d_work_proj = nullptr;
   if (p->d_tab) (void)hipFree(p->d_tab);
   for (void *q : {(void *)p->d_run_atom, (void *)p->d_row_runs, (void *)p->d_rows,
                   (void *)p->d_u2_off, (void *)p->d_nu_atoms, (void *)p->d_u2})
@@ -133,7 +133,7 @@ void free_plan_device(sho_plan_s *p) {
 // (Re)uploads the schedule-dependent tables: bundles and both work-item
 // orders; regroups the items by nu.
 hipError_t upload_schedule(sho_plan_s *p) {
-  for (void **q : {(void **)&p->d_bundles, (void **)&p->d_work, (void **)&p->d_work_single}) {
+  for (void **q : {(void **)&p->d_bundles, (void **)&p->d_work, (void **)&p->d_work_proj}) {
     if (*q) (void)hipFree(*q);
     *q = nullptr;
   }
@@ -142,7 +142,7 @@ hipError_t upload_schedule(sho_plan_s *p) {
   bytes = 0;
   if ((e = upload(&p->d_bundles, p->hp.bundles, &bytes)) != hipSuccess ||
       (e = upload(&p->d_work, p->hp.work, &bytes)) != hipSuccess ||
-      (e = upload(&p->d_work_single, p->hp.work_single, &bytes)) != hipSuccess)
+      (e = upload(&p->d_work_proj, p->hp.work_proj, &bytes)) != hipSuccess)
     return e;
   p->groups.clear();
   const auto &work = p->hp.work;
@@ -373,13 +373,11 @@ hipError_t run_project(sho_plan_s *p, const double *psi, double *c, hipStream_t 
       }
       return hipSuccess;
     }
-    if (p->hp.sched != sho::kSchedByNu) {
-      sho::KArgs K = make_args(p, Group{p->hp.nu_max, 0, (int32_t)p->hp.work_single.size()});
-      K.work = p->d_work_single;
-      return sho::launch_project_any(p->hp.nu_max, K, psi, c, s);
-    }
-    for (const Group &g : p->groups) {
-      hipError_t e1 = sho::launch_project(g.nu, make_args(p, g), psi, c, s);
+    for (const sho::ProjGroup &pg : p->hp.proj_groups) {
+      sho::KArgs K = make_args(p, Group{pg.nu, 0, pg.count});
+      K.work = p->d_work_proj + pg.begin;
+      hipError_t e1 = pg.nu < 0 ? sho::launch_project_any(p->hp.nu_max, K, psi, c, s)
+                                : sho::launch_project(pg.nu, K, psi, c, s);
       if (e1 != hipSuccess) return e1;
     }
     return hipSuccess;
@@ -694,8 +692,7 @@ sho_status sho_plan_force(sho_plan_t p, const double *psi, const double *w,
 sho_status sho_plan_set_schedule(sho_plan_t p, int32_t schedule, int32_t band_tile,
                                  int64_t target_points) {
   if (!p) return fail(SHO_E_INVALID, "NULL plan");
-  if (schedule < 0 || schedule >= sho::kSchedCount)
-    return fail(SHO_E_INVALID, "unknown schedule");
+  if (!sho::sched_valid(schedule)) return fail(SHO_E_INVALID, "unknown schedule");
   if (target_points < 256 || target_points > (int64_t)1 << 30)
     return fail(SHO_E_INVALID, "target_points outside [256, 2^30]");
   int tbs = -1;
@@ -741,7 +738,7 @@ sho_status sho_plan_tune(sho_plan_t p, const double *psi, double *c, int32_t rep
   };
   std::vector<Cand> cands;
   const int32_t tb0 = p->hp.tb_shift;
-  for (int32_t sc = 0; sc < sho::kSchedCount; ++sc)
+  for (int32_t sc : {0, 1, 2, 4, 5, 6})
     for (int64_t tp : {(int64_t)8192, (int64_t)16384, (int64_t)32768})
       for (int32_t tb = tb0; tb >= std::max(0, tb0 - 1); --tb) cands.push_back({sc, tb, tp});
   const Cand before{p->hp.sched, tb0, p->hp.target_points};

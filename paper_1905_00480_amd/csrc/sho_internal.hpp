@@ -114,6 +114,14 @@ struct StoredItem {
 };
 static_assert(sizeof(StoredItem) == 16, "StoredItem layout");
 
+// One projection launch: items [begin, begin+count) of work_proj, all of
+// cut-off nu (nu = -1: any cut-off up to nu_max, one launch).
+struct ProjGroup {
+  int32_t nu;
+  int32_t begin;
+  int32_t count;
+};
+
 struct HostPlan {
   sho_grid grid{};
   int32_t natoms = 0;
@@ -129,7 +137,8 @@ struct HostPlan {
   std::vector<WorkRec> work;           // by nu, then atoms in space order
   std::vector<int32_t> atom_work;      // [natoms+1] first item of each atom
                                        // in `work` (count: next - first)
-  std::vector<WorkRec> work_single;    // the same items for one launch
+  std::vector<WorkRec> work_proj;      // the projection's launch order
+  std::vector<ProjGroup> proj_groups;  // its launches
   int32_t sched = 0;                   // kSched* of the projection
   int64_t target_points = 0;           // work item size of the schedule
   std::vector<int32_t> run_atom;       // atom of every run
@@ -182,14 +191,22 @@ int choose_tb_shift(int nbands, int nu_max, size_t lds_limit);
 constexpr int32_t kSchedByNu = 0;       // one launch per cut-off
 constexpr int32_t kSchedSingle = 1;     // one launch, items in space order
 constexpr int32_t kSchedSingleLpt = 2;  // one launch, items by falling cost
-constexpr int32_t kSchedCount = 3;
+constexpr int32_t kSchedXcd = 4;        // flag: deal items to the 8 XCDs in
+                                        // contiguous blocks of the order
+constexpr int32_t kSchedCount = 3;      // base schedules
+constexpr int32_t kXcds = 8;            // dispatch interleaves workgroups
+                                        // over the XCDs by linear id
+
+inline bool sched_valid(int32_t s) { return s >= 0 && (s & ~kSchedXcd) < kSchedCount; }
 
 // Bundles (with 64 >> tb_shift slots) and work items: atoms of more than
 // `target_points` support points are shared by several workgroups.  Atoms
 // are visited in Morton order of their centres, so that workgroups running
 // at the same time read neighbouring parts of psi (shared in L2 and the
 // memory-side cache where supports overlap).  `sched` fixes the order of
-// work_single.
+// work_proj and its launches; with kSchedXcd, workgroup b of a launch of n
+// items runs item (b mod 8) * ceil(n/8) + b / 8 (padding items have atom -1),
+// so that each XCD works through one contiguous eighth of the order.
 void build_work(HostPlan *P, int tb_shift, int64_t target_points, int32_t sched);
 
 // Expansion tables: runs grouped by memory row, rows interleaved over the

@@ -61,6 +61,25 @@ __device__ inline T load_uniform(const T *p) {
   return out;
 }
 
+// dst[t] = value(t) for t < count, with U global loads in flight per thread
+// (all loads of a round are issued before the first LDS write waits).
+template <int U, typename F>
+__device__ inline void fill_lds(double *dst, int count, F &&value) {
+  for (int t0 = 0; t0 < count; t0 += U * (int)blockDim.x) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int t = t0 + u * (int)blockDim.x + (int)threadIdx.x;
+      v[u] = t < count ? value(t) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int t = t0 + u * (int)blockDim.x + (int)threadIdx.x;
+      if (t < count) dst[t] = v[u];
+    }
+  }
+}
+
 // ---------------------------------------------------------------- tables --
 
 // Row j of axis d of atom a: phi_n(u), u = (i0_d + j)*h - centre_d, for
@@ -309,6 +328,7 @@ __attribute__((amdgpu_waves_per_eu(waves_per_eu(NU + 1)))) void k_project(
     KArgs K, const double *__restrict__ psi, double *__restrict__ c) {
   extern __shared__ double cacc[];
   const cptr<WorkRec> W = as_const(K.work) + blockIdx.x;
+  if (W->atom < 0) return;  // padding of an XCD-dealt launch
   const AtomRec A = load_uniform(K.atoms + W->atom);
   project_item<NU>(K, W, A, psi, c, cacc);
 }
@@ -322,6 +342,7 @@ __attribute__((amdgpu_waves_per_eu(waves_per_eu(NUMAX + 1)))) void k_project_any
     KArgs K, const double *__restrict__ psi, double *__restrict__ c) {
   extern __shared__ double cacc[];
   const cptr<WorkRec> W = as_const(K.work) + blockIdx.x;
+  if (W->atom < 0) return;  // padding of an XCD-dealt launch
   const AtomRec A = load_uniform(K.atoms + W->atom);
   switch (A.nu) {
 #define X(N)                                                  \
@@ -348,11 +369,11 @@ __attribute__((amdgpu_waves_per_eu(waves_per_eu(NU + 1)))) void k_expand_atomic(
   const int tile = blockIdx.y;
   const AtomRec A = load_uniform(K.atoms + W->atom);
   const int TB = 1 << K.tb_shift;
-  for (int t = threadIdx.x; t < NS * TB; t += blockDim.x) {
+  fill_lds<4>(cin, NS * TB, [&](int t) {
     const int n = t >> K.tb_shift;
     const int bb = tile * TB + (t & (TB - 1));
-    cin[t] = bb < K.B ? c[(A.coeff_row + n) * K.B + bb] : 0.0;
-  }
+    return bb < K.B ? c[(A.coeff_row + n) * K.B + bb] : 0.0;
+  });
   __syncthreads();
   const int w = wave_id();
   const Lanes L = lane_geometry(K, tile);
@@ -438,10 +459,10 @@ __global__ __launch_bounds__(256) void k_u2(EArgs E, const double *__restrict__ 
   const int a = E.nu_atoms[E.nu_begin[NU] + blockIdx.x];
   const AtomRec A = load_uniform(E.atoms + a);
   const int b0 = blockIdx.y * kU2Tile;
-  for (int t = threadIdx.x; t < NS * kU2Tile; t += blockDim.x) {
+  fill_lds<8>(cs, NS * kU2Tile, [&](int t) {
     const int n = t / kU2Tile, bl = t % kU2Tile;
-    cs[t] = (b0 + bl < E.B) ? c[(A.coeff_row + n) * E.B + b0 + bl] : 0.0;
-  }
+    return (b0 + bl < E.B) ? c[(A.coeff_row + n) * E.B + b0 + bl] : 0.0;
+  });
   __syncthreads();
   const double *tz = E.tab + A.tab_off + (int64_t)(A.mx + A.my) * A.tab_nfp;
   double *dst = u2 + E.u2_off[a];
@@ -575,11 +596,11 @@ __global__ __launch_bounds__(kRowBlock) void k_expand_rows(EArgs E,
   const int tile = blockIdx.z;
   const int64_t rowoff = (int64_t)rr.row * E.nx;
   const int nval = (xc1 - xc0) << E.tbe_shift;
-  for (int t = threadIdx.x; t < nval; t += blockDim.x) {
+  fill_lds<kRowChunkDoubles / kRowBlock>(rowbuf, nval, [&](int t) {
     const int x = t >> E.tbe_shift;
     const int b = tile * TB + (t & (TB - 1));
-    rowbuf[t] = b < E.B ? psi[(rowoff + xc0 + x) * E.B + b] : 0.0;
-  }
+    return b < E.B ? psi[(rowoff + xc0 + x) * E.B + b] : 0.0;
+  });
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const int xp = lane >> E.tbe_shift;
@@ -607,10 +628,19 @@ __global__ __launch_bounds__(kRowBlock) void k_expand_rows(EArgs E,
     }
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < nval; t += blockDim.x) {
+  constexpr int kPer = kRowChunkDoubles / kRowBlock;
+  double v[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int t = u * kRowBlock + (int)threadIdx.x;
+    v[u] = t < nval ? rowbuf[t] : 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int t = u * kRowBlock + (int)threadIdx.x;
     const int x = t >> E.tbe_shift;
     const int b = tile * TB + (t & (TB - 1));
-    if (b < E.B) psi[(rowoff + xc0 + x) * E.B + b] = rowbuf[t];
+    if (t < nval && b < E.B) psi[(rowoff + xc0 + x) * E.B + b] = v[u];
   }
 }
 

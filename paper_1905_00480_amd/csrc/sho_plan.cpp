@@ -278,7 +278,8 @@ void build_work(HostPlan *P, int tb_shift, int64_t target_points, int32_t sched)
   P->target_points = target_points;
   P->bundles.clear();
   P->work.clear();
-  P->work_single.clear();
+  P->work_proj.clear();
+  P->proj_groups.clear();
   P->any_split = false;
   // bundles: the runs of each atom plane, ordered by their first x index so
   // that runs of similar extent share a bundle, in groups of `slots`
@@ -361,16 +362,49 @@ void build_work(HostPlan *P, int tb_shift, int64_t target_points, int32_t sched)
   P->atom_work.assign(P->natoms + 1, (int32_t)P->work.size());
   for (int32_t a = 0; a < P->natoms; ++a)
     P->atom_work[a] = count[a] ? first[a] : (int32_t)P->work.size();
-  // one launch: all items in space order, or by decreasing cost
-  for (int32_t a : order)
-    for (int32_t i = 0; i < count[a]; ++i) P->work_single.push_back(P->work[first[a] + i]);
-  if (sched == kSchedSingleLpt) {
-    std::vector<int32_t> idx(P->work.size());
-    for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int32_t)i;
-    std::stable_sort(idx.begin(), idx.end(),
-                     [&](int32_t x, int32_t y) { return item_cost[x] > item_cost[y]; });
-    P->work_single.clear();
-    for (int32_t i : idx) P->work_single.push_back(P->work[i]);
+  // the projection's launches
+  const int32_t base = sched & ~kSchedXcd;
+  std::vector<WorkRec> order_items;
+  std::vector<ProjGroup> groups;
+  if (base == kSchedByNu) {
+    order_items = P->work;
+    for (size_t i = 0; i < order_items.size();) {
+      const int32_t nu = P->atoms[order_items[i].atom].nu;
+      ProjGroup g{nu, (int32_t)i, 0};
+      while (i < order_items.size() && P->atoms[order_items[i].atom].nu == nu) {
+        ++g.count;
+        ++i;
+      }
+      groups.push_back(g);
+    }
+  } else {
+    for (int32_t a : order)
+      for (int32_t i = 0; i < count[a]; ++i) order_items.push_back(P->work[first[a] + i]);
+    if (base == kSchedSingleLpt) {
+      std::vector<int32_t> idx(P->work.size());
+      for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int32_t)i;
+      std::stable_sort(idx.begin(), idx.end(),
+                       [&](int32_t x, int32_t y) { return item_cost[x] > item_cost[y]; });
+      order_items.clear();
+      for (int32_t i : idx) order_items.push_back(P->work[i]);
+    }
+    if (!order_items.empty()) groups.push_back(ProjGroup{-1, 0, (int32_t)order_items.size()});
+  }
+  if (!(sched & kSchedXcd)) {
+    P->work_proj = order_items;
+    P->proj_groups = groups;
+    return;
+  }
+  WorkRec pad{};
+  pad.atom = -1;
+  for (const ProjGroup &g : groups) {
+    const int32_t per = (g.count + kXcds - 1) / kXcds;
+    ProjGroup ng{g.nu, (int32_t)P->work_proj.size(), per * kXcds};
+    for (int32_t b = 0; b < per * kXcds; ++b) {
+      const int32_t src = (b % kXcds) * per + b / kXcds;
+      P->work_proj.push_back(src < g.count ? order_items[g.begin + src] : pad);
+    }
+    P->proj_groups.push_back(ng);
   }
 }
 

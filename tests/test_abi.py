@@ -96,6 +96,8 @@ def test_schedule_arguments_host_only():
         p.set_schedule(sched, tile // 2, 4096)
         assert p.schedule() == (sched, tile // 2, 4096)
     _expect(bd.SHO_E_INVALID, lambda: p.set_schedule(3, 0, 4096))
+    _expect(bd.SHO_E_INVALID, lambda: p.set_schedule(7, 0, 4096))
+    _expect(bd.SHO_E_INVALID, lambda: p.set_schedule(8, 0, 4096))
     _expect(bd.SHO_E_INVALID, lambda: p.set_schedule(0, 3, 4096))
     _expect(bd.SHO_E_INVALID, lambda: p.set_schedule(0, 0, 10))
     # nu_max + 1 = 11 coefficients tile (364 functions) at twice the widest
