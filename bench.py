@@ -53,6 +53,8 @@ def parse():
                     help="skip the uneven-atom batching workload")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the request-stream (serving) workload")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the plan's default schedule (no autotuning)")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-warmup", type=int, default=200)
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
@@ -150,6 +152,10 @@ def stored_baseline(bd, s, psi, c, out, args):
             "project_ms": prof["project"][1], "expand_ms": prof["expand_rows"][1]}
 
 
+def _log(msg):
+    print("bench: " + msg, file=sys.stderr, flush=True)
+
+
 def _time_steps(step, steps, warmup):
     """Mean ms per step over `steps` back-to-back steps after `warmup`, and the
     per-step distribution (events between steps)."""
@@ -219,6 +225,8 @@ def batching(bd, wl, args):
         ref.project(psi, c)
         ref.expand(c, out)
 
+    _log("batching: batched %.2f ms, graph %.2f ms per step; timing per-atom launches"
+         % (res["tuned"]["ms_per_step"], res["graph"]["ms_per_step"]))
     ms, _ = _time_steps(ref_step, max(2, steps // 2), 1)
     ref.close()
     res["per_atom_launches"] = {"ms_per_step": ms, "value": units / (ms * 1e-3),
@@ -272,7 +280,7 @@ def main():
         torch.cuda.synchronize()
         del x, y
     # plan set-up: the autotuner picks the projection schedule (untimed)
-    tune = plan.tune(psi, c, reps=3)
+    tune = None if args.no_tune else plan.tune(psi, c, reps=3)
     # timed region: exactly `steps` steps, events between the steps
     w0 = time.perf_counter()
     ms_per_step, per_step = _time_steps(step, args.steps, args.warmup)
@@ -328,17 +336,23 @@ def main():
         "per_atom_box_GB/s": 3 * S * B * 8 / (ms_per_step * 1e-3) / 1e9,
         "plan_build_s": plan_s,
         "tune": tune,
+        "schedule": plan.schedule(),
         "wall_s_incl_warmup": wall,
         "step_ms_p10_p50_p90": [float(np.percentile(per_step, q)) for q in (10, 50, 90)],
     }
+    _log("scale workload: %.3f ms per step" % ms_per_step)
     if not args.no_stored:
         rec["stored_baseline"] = stored_baseline(bd, s, psi, c, out, args)
+    if not args.no_stored:
+        _log("stored baseline: %.3f ms per step" % rec["stored_baseline"]["ms_per_step"])
     if not args.no_batching:
         rec["batching"] = batching(bd, wl, args)
+        _log("batching workload done")
     if not args.no_serving:
         from paper_1905_00480_amd import serve
         rec["serving"] = serve.compare(requests=args.serve_requests, warmup=args.serve_warmup)
     if not args.no_cpu_baseline:
+        _log("timing the CPU oracle")
         rec["cpu_baseline"] = cpu_baseline(s, psi_h, c_h, args.cpu_seconds)
     plan.close()
     print(json.dumps(rec), flush=True)

@@ -7,12 +7,14 @@ so that ``workloads`` can be used without torch or a built library.
 """
 import importlib
 
-__all__ = ["binding", "workloads", "Plan", "project", "expand", "force"]
+__all__ = ["binding", "workloads", "autograd", "serve", "Plan", "Graph", "Server",
+           "project", "expand", "force"]
 
 
 def __getattr__(name):
-    if name in ("binding", "workloads", "build"):
+    if name in ("binding", "workloads", "build", "autograd", "serve"):
         return importlib.import_module("." + name, __name__)
-    if name in ("Plan", "project", "expand", "force", "load_library", "ShoError"):
+    if name in ("Plan", "Graph", "Server", "project", "expand", "force", "load_library",
+                "ShoError"):
         return getattr(importlib.import_module(".binding", __name__), name)
     raise AttributeError(name)

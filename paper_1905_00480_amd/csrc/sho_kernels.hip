@@ -681,7 +681,7 @@ __global__ __launch_bounds__(256) void k_store(KArgs K, const int32_t *__restric
 
 // The stored forms are dense contractions per atom, run on FP64 MFMA
 // (v_mfma_f64_16x16x4f64, D[16][16] += A[16][4] B[4][16]).  Lane l supplies
-// A[l % 16][l / 16] and B[l / 16][l % 16]; it receives D[4 (l / 16) + r][l % 16]
+// A[l % 16][l / 16] and B[l / 16][l % 16]; it receives D[4 r + l / 16][l % 16]
 // in accumulator register r.
 typedef double dx4 __attribute__((ext_vector_type(4)));
 
@@ -748,7 +748,7 @@ __global__ __launch_bounds__(kStoredBlock) void k_project_stored(
   for (int nb = 0; nb < NBN; ++nb) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int n = nb * 16 + 4 * q + r;
+      const int n = nb * 16 + 4 * r + q;
       atomicAdd(&red[n * kStoredTile + col], acc[nb][0][r]);
       atomicAdd(&red[n * kStoredTile + 16 + col], acc[nb][1][r]);
     }
@@ -802,7 +802,7 @@ __global__ __launch_bounds__(kStoredBlock) void k_expand_stored(
     int32_t mi[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int kr = k + 4 * q + r;
+      const int kr = k + 4 * r + q;
       mi[r] = kr < it.k1 ? pidx[kr] : -1;
     }
     dx4 dA = {0.0, 0.0, 0.0, 0.0}, dB = {0.0, 0.0, 0.0, 0.0};

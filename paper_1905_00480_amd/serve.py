@@ -12,6 +12,7 @@ one stream (FIFO) and per-atom launches (SHO_FLAG_PER_ATOM).
 Inputs are synthetic: psi and the expansion / derivative weights w are a
 seeded block of 2^20 standard normal values tiled over each buffer.
 """
+import sys
 import time
 
 import numpy as np
@@ -20,6 +21,10 @@ from . import binding as bd
 from . import workloads as wl
 
 BLOCK = 1 << 20
+
+
+def _log(msg):
+    print("serve: " + msg, file=sys.stderr, flush=True)
 
 
 def _tile_fill(dst, seed):
@@ -72,6 +77,9 @@ def run(server, sids, units, rate_hz=200.0, warmup=200, requests=2000, seed=4):
                 break
             time.sleep(d if d > 2e-3 else 0)
         rids.append(server.submit(sids[which[i]], int(kinds[i])))
+        if (i + 1) % 500 == 0:
+            _log("%d of %d requests submitted (%.1f s behind schedule)"
+                 % (i + 1, count, time.perf_counter() - target))
     server.drain()
     lat, done, jobs = [], [], []
     for i in range(warmup, count):
@@ -101,6 +109,7 @@ def compare(budget_bytes=64 << 30, nstreams=4, rate_hz=200.0, warmup=200, reques
     requests over the same pool."""
     pool = wl.serving_pool(seed=seed, nsystems=nsystems)
     units = units_of(pool)
+    _log("pool of %d systems sized" % len(pool))
     res = {"pool": {"systems": len(pool),
                     "psi_GB": float(sum(np.prod(s.n) * s.nbands * 8 for s in pool)) / 1e9},
            "budget_GB": budget_bytes / 1e9}
@@ -110,7 +119,10 @@ def compare(budget_bytes=64 << 30, nstreams=4, rate_hz=200.0, warmup=200, reques
         t0 = time.perf_counter()
         sids = register(srv, pool, seed)
         reg_s = time.perf_counter() - t0
+        _log("%s: registered in %.1f s" % (name, reg_s))
         r = run(srv, sids, units, rate_hz, warmup, requests, seed)
+        _log("%s: %d requests, p50 %.2f ms, p99 %.2f ms, %.1f req/s"
+             % (name, requests, r["latency_ms_p50"], r["latency_ms_p99"], r["req_per_s"]))
         r["streams"] = streams
         r["register_s"] = reg_s
         srv.close()
