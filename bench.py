@@ -351,6 +351,7 @@ def main():
     if not args.no_serving:
         from paper_1905_00480_amd import serve
         rec["serving"] = serve.compare(requests=args.serve_requests, warmup=args.serve_warmup)
+        _log("serving workload done")
     if not args.no_cpu_baseline:
         _log("timing the CPU oracle")
         rec["cpu_baseline"] = cpu_baseline(s, psi_h, c_h, args.cpu_seconds)

@@ -136,6 +136,8 @@ typedef struct sho_plan_info {
   int64_t expand_points;   /* grid points the expansion reads and writes
                               (whole row chunks that some support touches) */
   int64_t expand_scratch_doubles; /* plane partials of the expansion */
+  int64_t expand_blocks;   /* workgroup blocks of the block-form expansion */
+  int64_t expand_entries;  /* (atom plane, block) pairs of that form */
 } sho_plan_info;
 
 /* N_SHO(nu) = (nu+1)(nu+2)(nu+3)/6 (sec. 2.5); -1 if nu < 0. */
@@ -248,6 +250,24 @@ sho_status sho_plan_set_schedule(sho_plan_t plan, int32_t schedule,
                                  int32_t band_tile, int64_t target_points);
 sho_status sho_plan_get_schedule(sho_plan_t plan, int32_t *schedule,
                                  int32_t *band_tile, int64_t *target_points);
+
+/*
+ * Form of the expansion's second half (sec. 3.2 step 3 after the z pass):
+ *   0  rows:   one workgroup per chunk of one memory row; every run of the
+ *              row loads its atom plane's partial sums;
+ *   1  blocks: one workgroup per block of block_rows rows x block_x points of
+ *              one plane; the partial sums of an atom plane are loaded once
+ *              for all its runs in the block (default).
+ * Both read and write every touched value of psi once with plain loads and
+ * stores.  block_rows = block_x = 0 picks the default shape; a shape whose
+ * tile (rows x points x 32 or 64 bands) exceeds 4096 doubles, or whose
+ * points exceed 256 / (table row length), is refused with SHO_E_INVALID.
+ * set_expand waits for the device; graphs made before it are refused.
+ */
+sho_status sho_plan_set_expand(sho_plan_t plan, int32_t mode, int32_t block_rows,
+                               int32_t block_x);
+sho_status sho_plan_get_expand(sho_plan_t plan, int32_t *mode, int32_t *block_rows,
+                               int32_t *block_x);
 
 typedef struct sho_tune_result {
   int32_t schedule;      /* chosen SHO_SCHED_* */

@@ -35,6 +35,8 @@ SCHED_BY_NU = 0
 SCHED_SINGLE = 1
 SCHED_SINGLE_LPT = 2
 SCHED_XCD = 4
+EXPAND_ROWS = 0
+EXPAND_BLOCKS = 1
 SCHEDULES = (SCHED_BY_NU, SCHED_SINGLE, SCHED_SINGLE_LPT,
              SCHED_BY_NU | SCHED_XCD, SCHED_SINGLE | SCHED_XCD, SCHED_SINGLE_LPT | SCHED_XCD)
 
@@ -46,6 +48,7 @@ EXPORTS = (
     "sho_plan_force", "sho_project", "sho_expand", "sho_force",
     "sho_cache_clear", "sho_plan_profile", "sho_plan_profile_read",
     "sho_plan_set_schedule", "sho_plan_get_schedule", "sho_plan_tune",
+    "sho_plan_set_expand", "sho_plan_get_expand",
     "sho_graph_create", "sho_graph_launch", "sho_graph_destroy",
     "sho_server_create", "sho_server_add_system", "sho_server_submit",
     "sho_server_drain", "sho_server_request_info", "sho_server_read",
@@ -75,7 +78,8 @@ class sho_plan_info(ctypes.Structure):
                 ("planes", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
                 ("stored_bytes", ctypes.c_int64), ("union_points", ctypes.c_int64),
                 ("expand_points", ctypes.c_int64),
-                ("expand_scratch_doubles", ctypes.c_int64)]
+                ("expand_scratch_doubles", ctypes.c_int64),
+                ("expand_blocks", ctypes.c_int64), ("expand_entries", ctypes.c_int64)]
 
 
 class sho_tune_result(ctypes.Structure):
@@ -138,6 +142,8 @@ def load_library(path=None):
     lib.sho_plan_profile_read.argtypes = [P, _i64p, _dp]
     lib.sho_plan_set_schedule.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64]
     lib.sho_plan_get_schedule.argtypes = [P, _i32p, _i32p, _i64p]
+    lib.sho_plan_set_expand.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+    lib.sho_plan_get_expand.argtypes = [P, _i32p, _i32p, _i32p]
     lib.sho_plan_tune.argtypes = [P, _vp, _vp, ctypes.c_int32, _vp,
                                   ctypes.POINTER(sho_tune_result)]
     lib.sho_graph_create.argtypes = [P, _vp, _vp, _vp, ctypes.POINTER(_vp)]
@@ -298,6 +304,18 @@ class Plan:
         _check(self._lib.sho_plan_get_schedule(self._h, ctypes.byref(sc), ctypes.byref(bt),
                                                ctypes.byref(tp)))
         return sc.value, bt.value, tp.value
+
+    def set_expand(self, mode, block_rows=0, block_x=0):
+        """Expansion form: EXPAND_ROWS or EXPAND_BLOCKS (with block shape)."""
+        _check(self._lib.sho_plan_set_expand(self._h, int(mode), int(block_rows),
+                                             int(block_x)))
+
+    def expand_form(self):
+        """(mode, block_rows, block_x) of the expansion."""
+        m, r, x = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(self._lib.sho_plan_get_expand(self._h, ctypes.byref(m), ctypes.byref(r),
+                                             ctypes.byref(x)))
+        return m.value, r.value, x.value
 
     def tune(self, psi, c, reps=3, stream=None):
         """Time the projection schedules on psi -> c and keep the fastest."""

@@ -78,6 +78,10 @@ struct sho_plan_s {
   sho::WorkRec *d_work_proj = nullptr;  // the projection's launch order
   int64_t sched_version = 0;      // bumped whenever the work items change
   int64_t sched_bytes = 0;        // device bytes of the schedule tables
+  sho::BlockRec *d_blocks = nullptr;   // block form of the expansion
+  sho::EntryRec *d_entries = nullptr;
+  uint32_t *d_run_desc = nullptr;
+  int64_t blk_bytes = 0;
   bool prof_on = false;
   std::vector<ProfEvent> prof;
   int64_t device_bytes = 0;
@@ -104,6 +108,10 @@ void free_plan_device(sho_plan_s *p) {
   if (p->d_work) (void)hipFree(p->d_work);
   if (p->d_work_proj) (void)hipFree(p->d_work_proj);
   p->d_work_proj = nullptr;
+  for (void **q : {(void **)&p->d_blocks, (void **)&p->d_entries, (void **)&p->d_run_desc}) {
+    if (*q) (void)hipFree(*q);
+    *q = nullptr;
+  }
   if (p->d_tab) (void)hipFree(p->d_tab);
   for (void *q : {(void *)p->d_run_atom, (void *)p->d_row_runs, (void *)p->d_rows,
                   (void *)p->d_u2_off, (void *)p->d_nu_atoms, (void *)p->d_u2})
@@ -156,6 +164,22 @@ hipError_t upload_schedule(sho_plan_s *p) {
     p->groups.push_back(g);
   }
   p->sched_version++;
+  return hipSuccess;
+}
+
+// (Re)uploads the block tables of the expansion.
+hipError_t upload_blocks(sho_plan_s *p) {
+  for (void **q : {(void **)&p->d_blocks, (void **)&p->d_entries, (void **)&p->d_run_desc}) {
+    if (*q) (void)hipFree(*q);
+    *q = nullptr;
+  }
+  int64_t &bytes = p->blk_bytes;
+  bytes = 0;
+  hipError_t e;
+  if ((e = upload(&p->d_blocks, p->hp.blocks, &bytes)) != hipSuccess ||
+      (e = upload(&p->d_entries, p->hp.entries, &bytes)) != hipSuccess ||
+      (e = upload(&p->d_run_desc, p->hp.run_desc, &bytes)) != hipSuccess)
+    return e;
   return hipSuccess;
 }
 
@@ -235,6 +259,13 @@ sho::EArgs make_eargs(const sho_plan_s *p) {
   E.ntiles = (p->hp.nbands + (1 << E.tbe_shift) - 1) >> E.tbe_shift;
   E.ntiles_u2 = (p->hp.nbands + 31) / 32;
   E.nu_max = p->hp.nu_max;
+  E.blocks = p->d_blocks;
+  E.entries = p->d_entries;
+  E.run_desc = p->d_run_desc;
+  E.nblocks = (int32_t)p->hp.blocks.size();
+  E.blk_rows = p->hp.blk_rows;
+  E.blk_x = p->hp.blk_x;
+  E.ny = p->hp.grid.n[1];
   for (int nu = 0; nu <= SHO_NU_MAX + 1; ++nu) E.nu_begin[nu] = 0;
   {
     int nu = 0;
@@ -285,7 +316,10 @@ int64_t estimate_device_bytes(const sho::HostPlan &hp) {
               2 * b((int64_t)hp.work.size(), sizeof(sho::WorkRec)) +
               b(hp.table_doubles, 8) + 2 * b(nl, 4) +
               b((int64_t)hp.rows.size(), sizeof(sho::RowRec)) + b(hp.natoms, 8) +
-              b(hp.natoms, 4) + b(hp.u2_doubles, 8);
+              b(hp.natoms, 4) + b(hp.u2_doubles, 8) +
+              b((int64_t)hp.blocks.size(), sizeof(sho::BlockRec)) +
+              b((int64_t)hp.entries.size(), sizeof(sho::EntryRec)) +
+              b((int64_t)hp.run_desc.size(), 4);
   if (hp.flags & SHO_FLAG_STORED) {
     int64_t stored = 0;
     for (const auto &A : hp.atoms) stored += (int64_t)A.npoints * sho::nsho(A.nu);
@@ -295,6 +329,12 @@ int64_t estimate_device_bytes(const sho::HostPlan &hp) {
          b(items, sizeof(sho::StoredItem));
   }
   return t;
+}
+
+void build_default_blocks(sho::HostPlan *hp) {
+  int32_t R = 0, X = 0;
+  sho::default_block_shape(*hp, &R, &X);
+  sho::build_blocks(hp, R, X);
 }
 
 // Plans with several cut-offs run the projection as one launch.
@@ -411,8 +451,10 @@ hipError_t run_expand(sho_plan_s *p, const double *c, double *psi, hipStream_t s
   hipError_t e = timed(p, prof, SHO_KERNEL_EXPAND_PLANES, s,
                        [&]() { return sho::launch_expand_planes(E, c, p->d_u2, s); });
   if (e == hipSuccess)
-    e = timed(p, prof, SHO_KERNEL_EXPAND_ROWS, s,
-              [&]() { return sho::launch_rows(E, p->d_u2, psi, s); });
+    e = timed(p, prof, SHO_KERNEL_EXPAND_ROWS, s, [&]() {
+      return p->hp.expand_mode == sho::kExpandBlocks ? sho::launch_blocks(E, p->d_u2, psi, s)
+                                                     : sho::launch_rows(E, p->d_u2, psi, s);
+    });
   return e;
 }
 
@@ -450,6 +492,7 @@ sho_status sho_plan_create(const sho_grid *grid, int32_t natoms,
     }
     sho::build_work(&p->hp, tbs, sho::kTargetPoints, default_schedule(p->hp));
     sho::build_rows(&p->hp);
+    build_default_blocks(&p->hp);
     *out = p;
     return SHO_OK;
   }
@@ -473,10 +516,11 @@ sho_status sho_plan_create(const sho_grid *grid, int32_t natoms,
   }
   sho::build_work(&p->hp, tbs, sho::kTargetPoints, default_schedule(p->hp));
   sho::build_rows(&p->hp);
+  build_default_blocks(&p->hp);
   std::vector<double> no_tab;
   if ((e = upload(&p->d_atoms, p->hp.atoms, &p->device_bytes)) != hipSuccess ||
       (e = upload(&p->d_lines, p->hp.lines, &p->device_bytes)) != hipSuccess ||
-      (e = upload_schedule(p)) != hipSuccess ||
+      (e = upload_schedule(p)) != hipSuccess || (e = upload_blocks(p)) != hipSuccess ||
       (e = upload(&p->d_run_atom, p->hp.run_atom, &p->device_bytes)) != hipSuccess ||
       (e = upload(&p->d_row_runs, p->hp.row_runs, &p->device_bytes)) != hipSuccess ||
       (e = upload(&p->d_rows, p->hp.rows, &p->device_bytes)) != hipSuccess ||
@@ -586,8 +630,11 @@ sho_status sho_plan_get_info(sho_plan_t p, sho_plan_info *info) {
   info->support_points = p->hp.support_points;
   info->lines = (int64_t)p->hp.lines.size();
   info->planes = (int64_t)p->hp.planes.size();
-  info->device_bytes = (p->hp.flags & SHO_FLAG_HOST_ONLY) ? estimate_device_bytes(p->hp)
-                                                          : p->device_bytes + p->sched_bytes;
+  info->device_bytes = (p->hp.flags & SHO_FLAG_HOST_ONLY)
+                           ? estimate_device_bytes(p->hp)
+                           : p->device_bytes + p->sched_bytes + p->blk_bytes;
+  info->expand_blocks = (int64_t)p->hp.blocks.size();
+  info->expand_entries = (int64_t)p->hp.entries.size();
   info->stored_bytes = p->stored_bytes;
   info->union_points = p->hp.union_points;
   // the row kernel moves whole chunks of touched rows: with 32 or 64 bands
@@ -721,6 +768,40 @@ sho_status sho_plan_get_schedule(sho_plan_t p, int32_t *schedule, int32_t *band_
   *schedule = p->hp.sched;
   *band_tile = 1 << p->hp.tb_shift;
   *target_points = p->hp.target_points;
+  return SHO_OK;
+}
+
+sho_status sho_plan_set_expand(sho_plan_t p, int32_t mode, int32_t block_rows,
+                               int32_t block_x) {
+  if (!p) return fail(SHO_E_INVALID, "NULL plan");
+  if (mode != sho::kExpandRows && mode != sho::kExpandBlocks)
+    return fail(SHO_E_INVALID, "unknown expansion form");
+  if (mode == sho::kExpandBlocks) {
+    int32_t R = block_rows, X = block_x;
+    if (R == 0 && X == 0) sho::default_block_shape(p->hp, &R, &X);
+    if (!sho::block_shape_ok(p->hp, R, X))
+      return fail(SHO_E_INVALID, "block shape does not fit the LDS tile or the table staging");
+    if (!(p->hp.flags & SHO_FLAG_HOST_ONLY)) {
+      hipError_t e = hipDeviceSynchronize();
+      if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+    }
+    sho::build_blocks(&p->hp, R, X);
+    if (!(p->hp.flags & SHO_FLAG_HOST_ONLY)) {
+      hipError_t e = upload_blocks(p);
+      if (e != hipSuccess) return hip_fail(e, "block upload");
+    }
+  }
+  p->hp.expand_mode = mode;
+  p->sched_version++;
+  return SHO_OK;
+}
+
+sho_status sho_plan_get_expand(sho_plan_t p, int32_t *mode, int32_t *block_rows,
+                               int32_t *block_x) {
+  if (!p || !mode || !block_rows || !block_x) return fail(SHO_E_INVALID, "NULL argument");
+  *mode = p->hp.expand_mode;
+  *block_rows = p->hp.blk_rows;
+  *block_x = p->hp.blk_x;
   return SHO_OK;
 }
 

@@ -11,6 +11,7 @@
 // sec. 3.4) that the kernels read through the scalar cache.
 #pragma once
 
+#include <algorithm>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -102,6 +103,45 @@ struct RowRec {
 };
 static_assert(sizeof(RowRec) == 16, "RowRec layout");
 
+// Expansion work of the block form: R consecutive rows of one plane z times
+// X consecutive x points.  One workgroup owns the block (per band tile); its
+// entries are the (atom, plane, x shift) groups of runs that fall into it, so
+// that the plane partials of an atom plane are loaded once for up to R rows.
+struct BlockRec {
+  int32_t z, y0, x0;
+  int32_t entry_begin;
+  int32_t nentries;  // -1: padding
+  int32_t pad;
+};
+static_assert(sizeof(BlockRec) == 24, "BlockRec layout");
+
+// Everything one wave needs for an entry, so that the entry costs one record
+// load plus one round of data loads: where its plane partials start, where the
+// table rows of the block's x range and rows start, which of them exist, and
+// its runs as packed (row, x begin, x end) descriptors.
+struct EntryRec {
+  int64_t u2;          // first double of the atom plane's partials (band 0)
+  int32_t tab_x;       // table double of memory x = x0:  tab_off + (x0 + jshift) nfp
+  int32_t tab_y;       // table double of block row 0:   tab_off + (mx + y0 + yshift) nfp
+  int16_t nu, nfp;
+  int16_t x_lo, x_hi;  // staged x rows that exist, relative to x0
+  int16_t y_lo, y_hi;  // staged y rows that exist, relative to y0
+  int32_t run_begin;   // into run_desc
+  int32_t nruns;
+};
+static_assert(sizeof(EntryRec) == 40, "EntryRec layout");
+
+// Run descriptor of the block form: row r (relative to y0) | x begin << 8 |
+// x end << 16 (both relative to x0, end exclusive).
+inline uint32_t pack_run(int r, int xa, int xb) {
+  return (uint32_t)r | ((uint32_t)xa << 8) | ((uint32_t)xb << 16);
+}
+
+// Expansion forms.
+constexpr int32_t kExpandRows = 0;
+constexpr int32_t kExpandBlocks = 1;
+constexpr int kBlockTileDoubles = 4096;  // LDS tile of a block workgroup
+
 // Rows handled by one expansion workgroup.
 constexpr int kRowsPerGroup = 1;
 
@@ -148,6 +188,11 @@ struct HostPlan {
                                        // per-plane expansion partials
   std::vector<int32_t> nu_atoms;       // atoms with a support, sorted by nu
   int64_t u2_doubles = 0;
+  int32_t expand_mode = kExpandBlocks;
+  int32_t blk_rows = 0, blk_x = 0;      // block shape of the block form
+  std::vector<BlockRec> blocks;         // XCD-interleaved by plane
+  std::vector<EntryRec> entries;
+  std::vector<uint32_t> run_desc;
   std::vector<int64_t> run_poff;      // stored projectors: first double of
                                       // each run's [len][N_SHO] block
   std::vector<int64_t> atom_poff;     // [natoms+1] first double of each atom
@@ -213,6 +258,26 @@ void build_work(HostPlan *P, int tb_shift, int64_t target_points, int32_t sched)
 // eight XCDs so that all rows of one plane share an L2, per-atom offsets of
 // the plane partials U2[jz][pair][band].
 void build_rows(HostPlan *P);
+
+// Blocks of R rows x X points for the block form of the expansion (needs
+// build_rows for run_atom).
+void build_blocks(HostPlan *P, int32_t R, int32_t X);
+
+// Whether an R x X block fits: the LDS tile (R X bands-per-tile doubles) and
+// the x-table staging of one wave (X rows of the widest table).
+inline bool block_shape_ok(const HostPlan &P, int32_t R, int32_t X) {
+  const int tbe = P.nbands > 32 ? 64 : 32;
+  return R >= 1 && X >= 1 && (int64_t)R * X * tbe <= kBlockTileDoubles &&
+         X * table_nfp(P.nu_max) <= 256 && R * table_nfp(P.nu_max) <= 256;
+}
+
+// Default block shape: as wide in x as the staging allows (at most 32 points
+// for 32-band tiles, 16 for 64), then as many rows as the tile holds.
+inline void default_block_shape(const HostPlan &P, int32_t *R, int32_t *X) {
+  const int tbe = P.nbands > 32 ? 64 : 32;
+  *X = std::min(256 / table_nfp(P.nu_max), tbe == 32 ? 32 : 16);
+  *R = kBlockTileDoubles / (*X * tbe);
+}
 
 // Layout of the stored projector tables (SHO_FLAG_STORED plans): the points
 // of every atom in run order, each with its N_SHO values; chunks of at most

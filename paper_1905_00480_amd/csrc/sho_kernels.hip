@@ -644,6 +644,175 @@ __global__ __launch_bounds__(kRowBlock) void k_expand_rows(EArgs E,
   }
 }
 
+// ---------------------------------------------- expansion by blocks --
+
+constexpr int kBlkWaves = 4;
+constexpr int kBlkBlock = 64 * kBlkWaves;
+constexpr int kBlkXStage = 256;  // doubles per wave: the x-table rows of a block
+
+// Adds every run of one entry (one atom plane, one image) into the LDS tile
+// of the block.  Lanes are (run slot, band): with 32 bands per tile two runs
+// of the entry (two rows of the block) are added at once.  All runs of an
+// entry share the atom's x table, so phi_x(x) is wave-uniform and comes from
+// the scalar cache; the plane partials are loaded once per entry.
+// Runs of one slot handled together: phi_x(x) is read once per x and applied
+// to all of them.  Four where the kernel's register budget is set by a larger
+// cut-off anyway, else two.
+constexpr int blk_group(int nu, int numax) { return (numax > 5 && nu <= 5) ? 4 : 2; }
+
+template <int NU, int NUMAX>
+__device__ inline void add_entry(const EArgs &E, const EntryRec &en, const double *u2,
+                                 int nxl, double *tile, double *xstage, int TB, int slot,
+                                 int bl, int bc) {
+  constexpr int NF = NU + 1;
+  constexpr int NP = NF * (NF + 1) / 2;
+  constexpr int G = blk_group(NU, NUMAX);
+  const int nfp = en.nfp;
+  const int lane = threadIdx.x & 63;
+  const int slots = 64 / TB;
+  // one round of loads: plane partials, run descriptors, the x-table rows of
+  // the block's x range (staged in LDS; rows that do not exist stay unset)
+  const double *ub = u2 + en.u2 + bc;
+  double u2v[NP];
+#pragma unroll
+  for (int q = 0; q < NP; ++q) u2v[q] = ub[(int64_t)q * E.B];
+  const uint32_t mydesc = lane < en.nruns ? as_const(E.run_desc)[en.run_begin + lane] : 0u;
+  double tx[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int i = lane * 4 + k;
+    const int pt = i / nfp;
+    tx[k] = (pt >= en.x_lo && pt < en.x_hi) ? E.tab[en.tab_x + i] : 0.0;
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) xstage[lane * 4 + k] = tx[k];
+  for (int g0 = 0; g0 < en.nruns; g0 += G * slots) {
+    const int gend = min(g0 + G * slots, en.nruns);
+    // wave-uniform x range of the group
+    int lo = 255, hi = 0;
+    for (int k = g0; k < gend; ++k) {
+      const uint32_t d = __builtin_amdgcn_readlane(mydesc, k);
+      lo = min(lo, (int)((d >> 8) & 0xff));
+      hi = max(hi, (int)((d >> 16) & 0xff));
+    }
+    // this lane's runs g0 + j slots + slot, j < G: rows, ranges, y passes
+    int rr[G], xa[G], xb[G];
+    double U1[G][NF];
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+      const int i = g0 + j * slots + slot;
+      const uint32_t d = __shfl(mydesc, min(i, gend - 1));
+      rr[j] = d & 0xff;
+      xa[j] = i < gend ? (int)((d >> 8) & 0xff) : 0;
+      xb[j] = i < gend ? (int)((d >> 16) & 0xff) : 0;
+      const double *fy = E.tab + en.tab_y + rr[j] * nfp;
+#pragma unroll
+      for (int n = 0; n < NF; ++n) U1[j][n] = 0.0;
+      int q = 0;
+#pragma unroll
+      for (int ny = 0; ny < NF; ++ny) {
+        const double fv = fy[ny];
+#pragma unroll
+        for (int nx = 0; nx < NF - ny; ++nx, ++q) U1[j][nx] = fma(fv, u2v[q], U1[j][nx]);
+      }
+    }
+    for (int x = lo; x < hi; ++x) {
+      const double *f = xstage + x * nfp;
+      double fx[NF];
+#pragma unroll
+      for (int n = 0; n < NF; ++n) fx[n] = f[n];
+#pragma unroll
+      for (int j = 0; j < G; ++j) {
+        double val = 0.0;
+#pragma unroll
+        for (int n = 0; n < NF; ++n) val = fma(fx[n], U1[j][n], val);
+        if (x >= xa[j] && x < xb[j])
+          atomicAdd(&tile[((int64_t)rr[j] * nxl + x) * TB + bl], val);
+      }
+    }
+  }
+}
+
+// One workgroup per (block, band tile): the block's values of psi are read
+// into LDS once, every entry adds its runs (waves take entries round robin),
+// and the block is written back once with plain stores.
+template <int NUMAX>
+__global__ __launch_bounds__(kBlkBlock) void k_expand_blocks(EArgs E,
+                                                            const double *__restrict__ u2,
+                                                            double *psi) {
+  extern __shared__ double lds[];
+  const BlockRec bk = load_uniform(E.blocks + blockIdx.x);
+  if (bk.nentries < 0) return;
+  const int w = wave_id();
+  double *tile = lds;
+  const int TB = 1 << E.tbe_shift;
+  const int btile = blockIdx.y;
+  const int xe = min(bk.x0 + E.blk_x, E.nx);
+  const int nxl = xe - bk.x0;
+  const int nrow = min(bk.y0 + E.blk_rows, E.ny) - bk.y0;
+  const int rowbase = bk.z * E.ny + bk.y0;
+  const int per_row = nxl << E.tbe_shift;
+  const int nval = nrow * per_row;
+  // tile value t = (row r, x, band) <-> psi index; b >= B marks a padding band
+  auto gidx = [&](int t, int &b) -> int64_t {
+    const int r = t / per_row;
+    const int rem = t - r * per_row;
+    const int x = rem >> E.tbe_shift;
+    b = btile * TB + (rem & (TB - 1));
+    return ((int64_t)(rowbase + r) * E.nx + bk.x0 + x) * E.B + b;
+  };
+  fill_lds<kBlockTileDoubles / kBlkBlock>(tile, nval, [&](int t) {
+    int bb;
+    const int64_t g = gidx(t, bb);
+    return bb < E.B ? psi[g] : 0.0;
+  });
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int slot = lane >> E.tbe_shift;
+  const int bl = lane & (TB - 1);
+  const int b = btile * TB + bl;
+  const int bc = b < E.B ? b : E.B - 1;
+  double *xstage = lds + kBlockTileDoubles + w * kBlkXStage;
+  // entries round robin over the waves; the next entry's record is requested
+  // before the current one is processed
+  EntryRec en;
+  if (w < bk.nentries) en = load_uniform(E.entries + bk.entry_begin + w);
+  for (int i = w; i < bk.nentries; i += kBlkWaves) {
+    EntryRec nxt = en;
+    if (i + kBlkWaves < bk.nentries)
+      nxt = load_uniform(E.entries + bk.entry_begin + i + kBlkWaves);
+    switch (en.nu) {
+#define X(N)                                                                          \
+  case N:                                                                             \
+    if constexpr (N <= NUMAX)                                                         \
+      add_entry<N, NUMAX>(E, en, u2, nxl, tile, xstage, TB, slot, bl, bc);            \
+    break;
+      X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10)
+#undef X
+    }
+    en = nxt;
+  }
+  __syncthreads();
+  constexpr int kPer = kBlockTileDoubles / kBlkBlock;
+  for (int t0 = 0; t0 < nval; t0 += kPer * kBlkBlock) {
+    double v[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int t = t0 + u * kBlkBlock + (int)threadIdx.x;
+      v[u] = t < nval ? tile[t] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int t = t0 + u * kBlkBlock + (int)threadIdx.x;
+      if (t < nval) {
+        int bb;
+        const int64_t g = gidx(t, bb);
+        if (bb < E.B) psi[g] = v[u];
+      }
+    }
+  }
+}
+
 // ------------------------------------------------- stored projectors --
 
 // P[run][k][n] = phi_nx(x) phi_ny(y) phi_nz(z) at point k of the run, for all
@@ -1035,6 +1204,25 @@ hipError_t launch_rows(const EArgs &E, const double *u2, double *psi,
       hipLaunchKernelGGL((k_expand_rows<1, N>), g, dim3(kRowBlock), shm, s, E, u2, psi); \
     else                                                                          \
       hipLaunchKernelGGL((k_expand_rows<2, N>), g, dim3(kRowBlock), shm, s, E, u2, psi); \
+    break;
+      SHO_NU_CASES(X)
+#undef X
+      default:
+        return hipErrorInvalidValue;
+    }
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_blocks(const EArgs &E, const double *u2, double *psi,
+                         hipStream_t s) {
+  if (E.nblocks > 0) {
+    const dim3 g((unsigned)E.nblocks, (unsigned)E.ntiles);
+    const size_t shm = (kBlockTileDoubles + kBlkWaves * kBlkXStage) * sizeof(double);
+    switch (E.nu_max) {
+#define X(N)                                                                        \
+  case N:                                                                           \
+    hipLaunchKernelGGL((k_expand_blocks<N>), g, dim3(kBlkBlock), shm, s, E, u2, psi); \
     break;
       SHO_NU_CASES(X)
 #undef X

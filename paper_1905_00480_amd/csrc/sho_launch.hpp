@@ -51,6 +51,14 @@ struct EArgs {
   int32_t ntiles_u2;    // band tiles (of 32) of the plane-partial kernel
   int32_t nu_max;       // largest nu among the atoms
   int32_t nu_begin[SHO_NU_MAX + 2];  // nu_atoms[nu_begin[nu] .. nu_begin[nu+1])
+  // block form
+  const BlockRec *blocks;
+  const EntryRec *entries;
+  const uint32_t *run_desc;
+  int32_t nblocks;
+  int32_t blk_rows;     // R
+  int32_t blk_x;        // X
+  int32_t ny;
 };
 
 // Argument block of the stored-projector kernels.
@@ -86,6 +94,9 @@ hipError_t launch_expand_planes(const EArgs &E, const double *c, double *u2,
                                 hipStream_t s);
 hipError_t launch_rows(const EArgs &E, const double *u2, double *psi,
                        hipStream_t s);
+// Block form of the second half (blocks of R rows x X points).
+hipError_t launch_blocks(const EArgs &E, const double *u2, double *psi,
+                         hipStream_t s);
 // Stored-projector baseline: sample P_an at every support point, then
 // project / expand by reading them back (nu <= 5).
 hipError_t launch_store(const KArgs &K, const int32_t *run_atom, int32_t nruns,

@@ -525,4 +525,96 @@ void build_rows(HostPlan *P) {
       if (P->atoms[a].nu == nu && P->atoms[a].npoints > 0) P->nu_atoms.push_back(a);
 }
 
+void build_blocks(HostPlan *P, int32_t R, int32_t X) {
+  const int32_t nx = P->grid.n[0], ny = P->grid.n[1];
+  const int64_t nyb = (ny + R - 1) / R, nxb = (nx + X - 1) / X;
+  P->blk_rows = R;
+  P->blk_x = X;
+  struct Item {
+    int64_t block;
+    int32_t atom, jz, jshift, yshift, row, run;
+  };
+  std::vector<Item> items;
+  items.reserve(P->lines.size() * 3 / 2);
+  for (int32_t r = 0; r < (int32_t)P->lines.size(); ++r) {
+    const LineRec &L = P->lines[r];
+    const int32_t z = L.row / ny, y = L.row % ny;
+    for (int32_t cx = L.x0m / X; cx <= (L.x0m + L.len - 1) / X; ++cx)
+      items.push_back(Item{((int64_t)z * nyb + y / R) * nxb + cx, P->run_atom[r], L.jz,
+                           L.jx0 - L.x0m, L.jy - y, L.row, r});
+  }
+  std::sort(items.begin(), items.end(), [](const Item &a, const Item &b) {
+    if (a.block != b.block) return a.block < b.block;
+    if (a.atom != b.atom) return a.atom < b.atom;
+    if (a.jz != b.jz) return a.jz < b.jz;
+    if (a.jshift != b.jshift) return a.jshift < b.jshift;
+    if (a.yshift != b.yshift) return a.yshift < b.yshift;
+    if (a.row != b.row) return a.row < b.row;
+    return a.run < b.run;
+  });
+  P->entries.clear();
+  P->run_desc.clear();
+  std::vector<std::vector<BlockRec>> cls(8);
+  for (size_t i = 0; i < items.size();) {
+    const int64_t blk = items[i].block;
+    BlockRec B;
+    const int64_t cx = blk % nxb, yz = blk / nxb;
+    B.z = (int32_t)(yz / nyb);
+    B.y0 = (int32_t)(yz % nyb) * R;
+    B.x0 = (int32_t)cx * X;
+    B.entry_begin = (int32_t)P->entries.size();
+    B.nentries = 0;
+    B.pad = 0;
+    while (i < items.size() && items[i].block == blk) {
+      const Item &it = items[i];
+      const AtomRec &A = P->atoms[it.atom];
+      const int64_t np = (int64_t)(A.nu + 1) * (A.nu + 2) / 2;
+      EntryRec E;
+      E.u2 = P->u2_off[it.atom] + (int64_t)it.jz * np * P->nbands;
+      const int32_t jx0 = B.x0 + it.jshift;   // table x index of memory x0
+      const int32_t jy0 = B.y0 + it.yshift;   // table y index of block row 0
+      E.tab_x = (int32_t)(A.tab_off + (int64_t)jx0 * A.tab_nfp);
+      E.tab_y = (int32_t)(A.tab_off + (int64_t)(A.mx + jy0) * A.tab_nfp);
+      E.nu = (int16_t)A.nu;
+      E.nfp = (int16_t)A.tab_nfp;
+      E.x_lo = (int16_t)std::max(0, -jx0);
+      E.x_hi = (int16_t)std::min(X, A.mx - jx0);
+      E.y_lo = (int16_t)std::max(0, -jy0);
+      E.y_hi = (int16_t)std::min(R, A.my - jy0);
+      E.run_begin = (int32_t)P->run_desc.size();
+      E.nruns = 0;
+      // at most 64 runs per entry (one descriptor per lane)
+      while (i < items.size() && E.nruns < 64 && items[i].block == blk &&
+             items[i].atom == it.atom && items[i].jz == it.jz &&
+             items[i].jshift == it.jshift && items[i].yshift == it.yshift) {
+        const LineRec &L = P->lines[items[i].run];
+        const int32_t xa = std::max((int32_t)L.x0m, B.x0) - B.x0;
+        const int32_t xb = std::min((int32_t)L.x0m + L.len, B.x0 + X) - B.x0;
+        P->run_desc.push_back(pack_run(L.row % ny - B.y0, xa, xb));
+        E.nruns++;
+        ++i;
+      }
+      P->entries.push_back(E);
+      B.nentries++;
+    }
+    cls[B.z % 8].push_back(B);
+  }
+  // blocks of planes z = k mod 8 go to workgroups g = k mod 8 (XCD k)
+  P->blocks.clear();
+  std::vector<size_t> at(8, 0);
+  const BlockRec pad{0, 0, 0, 0, -1, 0};
+  for (bool any = true; any;) {
+    any = false;
+    for (int k = 0; k < 8; ++k) {
+      if (at[k] < cls[k].size()) {
+        P->blocks.push_back(cls[k][at[k]++]);
+        any = true;
+      } else {
+        P->blocks.push_back(pad);
+      }
+    }
+  }
+  while (!P->blocks.empty() && P->blocks.back().nentries < 0) P->blocks.pop_back();
+}
+
 }  // namespace sho

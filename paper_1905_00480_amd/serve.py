@@ -46,6 +46,8 @@ def register(server, pool, seed=4):
             _tile_fill(psi, seed * 7919 + 2 * k)
             _tile_fill(w, seed * 7919 + 2 * k + 1)
         sids.append(sid)
+        if (k + 1) % 8 == 0:
+            _log("%d of %d systems registered" % (k + 1, len(pool)))
     return sids
 
 
@@ -104,25 +106,28 @@ def run(server, sids, units, rate_hz=200.0, warmup=200, requests=2000, seed=4):
 
 
 def compare(budget_bytes=64 << 30, nstreams=4, rate_hz=200.0, warmup=200, requests=2000,
-            seed=4, nsystems=32):
+            seed=4, nsystems=32, plain_requests=200, plain_warmup=20):
     """The batched server and the per-request reference on the same stream of
-    requests over the same pool."""
+    requests over the same pool (the reference on its first plain_warmup +
+    plain_requests requests only: it serves a few requests per second, so a
+    full stream would queue for many minutes)."""
     pool = wl.serving_pool(seed=seed, nsystems=nsystems)
     units = units_of(pool)
     _log("pool of %d systems sized" % len(pool))
     res = {"pool": {"systems": len(pool),
                     "psi_GB": float(sum(np.prod(s.n) * s.nbands * 8 for s in pool)) / 1e9},
            "budget_GB": budget_bytes / 1e9}
-    for name, streams, flags in (("batched", nstreams, 0),
-                                 ("per_request_plain", 1, bd.FLAG_PER_ATOM)):
+    for name, streams, flags, nw, nr in (
+            ("batched", nstreams, 0, warmup, requests),
+            ("per_request_plain", 1, bd.FLAG_PER_ATOM, plain_warmup, plain_requests)):
         srv = bd.Server(budget_bytes, streams, flags)
         t0 = time.perf_counter()
         sids = register(srv, pool, seed)
         reg_s = time.perf_counter() - t0
         _log("%s: registered in %.1f s" % (name, reg_s))
-        r = run(srv, sids, units, rate_hz, warmup, requests, seed)
+        r = run(srv, sids, units, rate_hz, nw, nr, seed)
         _log("%s: %d requests, p50 %.2f ms, p99 %.2f ms, %.1f req/s"
-             % (name, requests, r["latency_ms_p50"], r["latency_ms_p99"], r["req_per_s"]))
+             % (name, nr, r["latency_ms_p50"], r["latency_ms_p99"], r["req_per_s"]))
         r["streams"] = streams
         r["register_s"] = reg_s
         srv.close()
@@ -142,10 +147,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--systems", type=int, default=32)
+    ap.add_argument("--plain-requests", type=int, default=200)
     a = ap.parse_args()
     bd.load_library()
     print(json.dumps(compare(int(a.budget_gb * (1 << 30)), a.streams, a.rate, a.warmup,
-                             a.requests, nsystems=a.systems)), flush=True)
+                             a.requests, nsystems=a.systems,
+                             plain_requests=a.plain_requests,
+                             plain_warmup=max(1, a.plain_requests // 10))), flush=True)
 
 
 if __name__ == "__main__":
