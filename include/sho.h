@@ -358,6 +358,9 @@ sho_status sho_server_add_system(sho_server_t server, const sho_grid *grid,
                                  const double *w, int32_t *system);
 sho_status sho_server_submit(sho_server_t server, int32_t system, int32_t job,
                              int64_t *request);
+/* Make a system resident now (admission as for a request, inputs uploaded,
+ * waits for the upload); for loading systems before a request stream. */
+sho_status sho_server_prefetch(sho_server_t server, int32_t system);
 sho_status sho_server_drain(sho_server_t server);
 sho_status sho_server_request_info(sho_server_t server, int64_t request,
                                    int32_t *system, int32_t *job,

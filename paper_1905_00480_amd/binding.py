@@ -53,7 +53,7 @@ EXPORTS = (
     "sho_server_create", "sho_server_add_system", "sho_server_submit",
     "sho_server_drain", "sho_server_request_info", "sho_server_read",
     "sho_server_get_stats", "sho_server_system_info", "sho_server_inputs",
-    "sho_server_clock", "sho_server_destroy",
+    "sho_server_clock", "sho_server_destroy", "sho_server_prefetch",
 )
 JOB_PROJECT, JOB_EXPAND, JOB_FORCE = 0, 1, 2
 KERNEL_KINDS = ("project", "expand_planes", "expand_rows", "force")
@@ -155,6 +155,7 @@ def load_library(path=None):
                                           ctypes.c_int32, _dp, _dp, _i32p]
     lib.sho_server_submit.argtypes = [P, ctypes.c_int32, ctypes.c_int32, _i64p]
     lib.sho_server_drain.argtypes = [P]
+    lib.sho_server_prefetch.argtypes = [P, ctypes.c_int32]
     lib.sho_server_request_info.argtypes = [P, ctypes.c_int64, _i32p, _i32p, _dp, _dp]
     lib.sho_server_read.argtypes = [P, ctypes.c_int32, ctypes.c_int32, _dp]
     lib.sho_server_get_stats.argtypes = [P, ctypes.POINTER(sho_server_stats)]
@@ -434,6 +435,10 @@ class Server:
 
     def drain(self):
         _check(self._lib.sho_server_drain(self._h))
+
+    def prefetch(self, sid):
+        """Make the system resident now (waits for its upload)."""
+        _check(self._lib.sho_server_prefetch(self._h, int(sid)))
 
     def clock(self):
         t = ctypes.c_double()

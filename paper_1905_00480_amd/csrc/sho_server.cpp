@@ -104,9 +104,12 @@ void poll_loop(sho_server_s *S) {
   std::vector<Req *> mine;
   for (;;) {
     {
+      // block only while nothing is outstanding; otherwise just take what
+      // was submitted since the last scan
       std::unique_lock<std::mutex> lk(S->pmu);
-      S->pcv.wait_for(lk, std::chrono::milliseconds(2),
-                      [&] { return S->stop.load() || !S->pending.empty(); });
+      if (mine.empty())
+        S->pcv.wait_for(lk, std::chrono::milliseconds(2),
+                        [&] { return S->stop.load() || !S->pending.empty(); });
       mine.insert(mine.end(), S->pending.begin(), S->pending.end());
       S->pending.clear();
       if (S->stop.load() && mine.empty()) return;
@@ -364,6 +367,25 @@ sho_status sho_server_submit(sho_server_t S, int32_t sys, int32_t job, int64_t *
     std::lock_guard<std::mutex> pl(S->pmu);
     S->pending.push_back(raw);
     S->pcv.notify_one();
+  }
+  return SHO_OK;
+}
+
+sho_status sho_server_prefetch(sho_server_t S, int32_t sys) {
+  if (!S) return fail(SHO_E_INVALID, "NULL server");
+  std::lock_guard<std::mutex> lk(S->mu);
+  if (sys < 0 || sys >= (int32_t)S->systems.size())
+    return fail(SHO_E_INVALID, "unknown system");
+  Sys &y = *S->systems[sys];
+  if (!y.resident) {
+    sho_status r = admit(S, sys);
+    if (r != SHO_OK) return r;
+  }
+  y.last_use = ++S->tick;
+  if (!S->dry) {
+    hipError_t e = hipEventRecord(y.last, S->streams[y.stream]);
+    if (e == hipSuccess) e = hipEventSynchronize(y.last);
+    if (e != hipSuccess) return hip_fail(e, "prefetch");
   }
   return SHO_OK;
 }

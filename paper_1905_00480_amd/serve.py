@@ -62,10 +62,22 @@ def units_of(pool):
     return np.array(out, dtype=np.float64)
 
 
-def run(server, sids, units, rate_hz=200.0, warmup=200, requests=2000, seed=4):
+def run(server, sids, units, rate_hz=200.0, warmup=200, requests=2000, seed=4,
+        preload=True):
     """Submit a Poisson stream (warm-up requests first, not measured) and
-    return throughput and latency percentiles of the measured requests."""
+    return throughput and latency percentiles of the measured requests.  With
+    preload, every system that fits the budget is made resident first (as a
+    service loads its systems before it takes requests)."""
     count = warmup + requests
+    if preload:
+        t0 = time.perf_counter()
+        for sid in sids:
+            try:
+                server.prefetch(sid)
+            except bd.ShoError as e:
+                if e.code != bd.SHO_E_BUDGET:
+                    raise
+        _log("preloaded %d systems in %.1f s" % (len(sids), time.perf_counter() - t0))
     arrivals, kinds, rng = wl.poisson_arrivals(rate_hz, count, seed)
     which = rng.integers(0, len(sids), size=count)
     base_srv = server.clock()

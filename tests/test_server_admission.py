@@ -67,6 +67,24 @@ def test_lru_eviction_order_and_stats():
     srv.close()
 
 
+def test_prefetch_admits_and_evicts():
+    systems = _systems()
+    probe, sids = _server(1 << 40, systems)
+    charges = [probe.system_info(i)[0] for i in sids]
+    probe.close()
+    srv, sids = _server(charges[0] + charges[1], systems)
+    srv.prefetch(sids[0])
+    srv.prefetch(sids[1])
+    assert [srv.system_info(i)[1] for i in sids] == [True, True, False, False]
+    srv.prefetch(sids[0])                    # already resident: refreshes its use
+    srv.prefetch(sids[2]) if charges[2] <= charges[1] else None
+    st = srv.stats()
+    assert st["requests"] == 0 and st["peak_resident_bytes"] <= charges[0] + charges[1]
+    if charges[2] <= charges[1]:
+        assert srv.system_info(sids[1])[1] is False and srv.system_info(sids[0])[1]
+    srv.close()
+
+
 def test_budget_refusals():
     systems = _systems()
     srv, sids = _server(1 << 40, systems)
