@@ -14,9 +14,10 @@ Metric: projected gridpoint*bands per second = sum_a |S_a| * B per step / time.
 
 Kernels of a step and their algorithmic HBM bytes per launch:
   project        box reads sum_a |S_a| B 8 + coefficient writes
-  expand_planes  coefficient reads + plane-partial writes (U2)
-  expand_rows    read + write of every touched row chunk (2 * points * B * 8)
-                 + plane-partial reads
+  expand_z       coefficient reads + plane-partial writes (U2, z pass)
+  expand_xy      read + write of every grid value some support covers
+                 (2 * union points * B * 8) + plane-partial reads (y and x
+                 passes; the blocks it moves also hold a few uncovered values)
 The roofline object is the dominant (longest) kernel's bytes over its mean
 duration, both measured in this run with HIP events that the library records
 around its own launches on the launch stream, against 8 TB/s.  `traffic` is
@@ -149,7 +150,7 @@ def stored_baseline(bd, s, psi, c, out, args):
     S = plan.support_points
     return {"value": S * s.nbands / (ms * 1e-3), "unit": "gridpoint*bands/s",
             "ms_per_step": ms, "stored_bytes": plan.info["stored_bytes"],
-            "project_ms": prof["project"][1], "expand_ms": prof["expand_rows"][1]}
+            "project_ms": prof["project"][1], "expand_ms": prof["expand_xy"][1]}
 
 
 def _log(msg):
@@ -210,8 +211,8 @@ def batching(bd, wl, args):
     res["tuned"] = {"schedule": plan.schedule(), "tune": tune, "ms_per_step": ms,
                     "value": units / (ms * 1e-3),
                     "project_ms": prof["project"][1],
-                    "expand_planes_ms": prof["expand_planes"][1],
-                    "expand_rows_ms": prof["expand_rows"][1],
+                    "expand_z_ms": prof["expand_z"][1],
+                    "expand_xy_ms": prof["expand_xy"][1],
                     "project_per_atom_box_GB/s":
                         (units * 8 + plan.coeff_doubles * 8) / (prof["project"][1] * 1e-3) / 1e9}
     g = plan.graph(psi, c, out)
@@ -298,8 +299,8 @@ def main():
     u2_bytes = info["expand_scratch_doubles"] * 8
     kbytes = {
         "project": S * B * 8 + coeff_bytes,
-        "expand_planes": coeff_bytes + u2_bytes,
-        "expand_rows": 2 * info["expand_points"] * B * 8 + u2_bytes,
+        "expand_z": coeff_bytes + u2_bytes,
+        "expand_xy": 2 * info["union_points"] * B * 8 + u2_bytes,
     }
     kernels = {}
     for k, nbytes in kbytes.items():

@@ -133,8 +133,9 @@ typedef struct sho_plan_info {
                               has run every call (admission estimate) */
   int64_t stored_bytes;    /* of which stored projector tables */
   int64_t union_points;    /* distinct grid points covered by any support */
-  int64_t expand_points;   /* grid points the expansion reads and writes
-                              (whole row chunks that some support touches) */
+  int64_t expand_points;   /* grid points the expansion reads and writes:
+                              the blocks (block form) or whole rows (row
+                              form) that some support touches */
   int64_t expand_scratch_doubles; /* plane partials of the expansion */
   int64_t expand_blocks;   /* workgroup blocks of the block-form expansion */
   int64_t expand_entries;  /* (atom plane, block) pairs of that form */
@@ -221,14 +222,15 @@ sho_status sho_force(const sho_grid *grid, int32_t natoms, const double *pos,
  * sho_plan_profile(plan, 1) clears and starts recording, (plan, 0) stops.
  * sho_plan_profile_read waits for the recorded events and returns, per
  * kernel kind, the number of launches and their mean duration in ms:
- *   SHO_KERNEL_PROJECT, SHO_KERNEL_EXPAND_PLANES (z pass of the expansion),
- *   SHO_KERNEL_EXPAND_ROWS (y and x passes), SHO_KERNEL_FORCE.
+ *   SHO_KERNEL_PROJECT, SHO_KERNEL_EXPAND_Z (z pass of the expansion),
+ *   SHO_KERNEL_EXPAND_XY (y and x passes, in either form; the whole
+ *   expansion for stored and per-atom plans), SHO_KERNEL_FORCE.
  * counts and mean_ms: host arrays [SHO_KERNEL_KINDS].  Not for use inside a
  * captured graph.
  */
 #define SHO_KERNEL_PROJECT 0
-#define SHO_KERNEL_EXPAND_PLANES 1
-#define SHO_KERNEL_EXPAND_ROWS 2
+#define SHO_KERNEL_EXPAND_Z 1
+#define SHO_KERNEL_EXPAND_XY 2
 #define SHO_KERNEL_FORCE 3
 #define SHO_KERNEL_KINDS 4
 sho_status sho_plan_profile(sho_plan_t plan, int32_t enable);

@@ -56,7 +56,7 @@ EXPORTS = (
     "sho_server_clock", "sho_server_destroy", "sho_server_prefetch",
 )
 JOB_PROJECT, JOB_EXPAND, JOB_FORCE = 0, 1, 2
-KERNEL_KINDS = ("project", "expand_planes", "expand_rows", "force")
+KERNEL_KINDS = ("project", "expand_z", "expand_xy", "force")
 
 
 class ShoError(RuntimeError):

@@ -428,7 +428,7 @@ hipError_t run_project(sho_plan_s *p, const double *psi, double *c, hipStream_t 
 hipError_t run_expand(sho_plan_s *p, const double *c, double *psi, hipStream_t s,
                       bool prof) {
   if (p->hp.flags & SHO_FLAG_STORED) {
-    return timed(p, prof, SHO_KERNEL_EXPAND_ROWS, s, [&]() {
+    return timed(p, prof, SHO_KERNEL_EXPAND_XY, s, [&]() {
       for (const Group &g : p->sgroups) {
         hipError_t e1 = sho::launch_expand_stored(g.nu, make_sargs(p, g), c, psi, s);
         if (e1 != hipSuccess) return e1;
@@ -437,7 +437,7 @@ hipError_t run_expand(sho_plan_s *p, const double *c, double *psi, hipStream_t s
     });
   }
   if (p->hp.flags & SHO_FLAG_PER_ATOM) {
-    return timed(p, prof, SHO_KERNEL_EXPAND_ROWS, s, [&]() {
+    return timed(p, prof, SHO_KERNEL_EXPAND_XY, s, [&]() {
       for (int32_t a = 0; a < p->hp.natoms; ++a) {
         const Group g = atom_group(p, a);
         if (!g.count) continue;
@@ -448,10 +448,10 @@ hipError_t run_expand(sho_plan_s *p, const double *c, double *psi, hipStream_t s
     });
   }
   sho::EArgs E = make_eargs(p);
-  hipError_t e = timed(p, prof, SHO_KERNEL_EXPAND_PLANES, s,
+  hipError_t e = timed(p, prof, SHO_KERNEL_EXPAND_Z, s,
                        [&]() { return sho::launch_expand_planes(E, c, p->d_u2, s); });
   if (e == hipSuccess)
-    e = timed(p, prof, SHO_KERNEL_EXPAND_ROWS, s, [&]() {
+    e = timed(p, prof, SHO_KERNEL_EXPAND_XY, s, [&]() {
       return p->hp.expand_mode == sho::kExpandBlocks ? sho::launch_blocks(E, p->d_u2, psi, s)
                                                      : sho::launch_rows(E, p->d_u2, psi, s);
     });
@@ -639,7 +639,9 @@ sho_status sho_plan_get_info(sho_plan_t p, sho_plan_info *info) {
   info->union_points = p->hp.union_points;
   // the row kernel moves whole chunks of touched rows: with 32 or 64 bands
   // per tile a chunk spans 64 or 32 points (2048 doubles)
-  info->expand_points = p->hp.rows_touched * (int64_t)p->hp.grid.n[0];
+  info->expand_points = p->hp.expand_mode == sho::kExpandBlocks
+                            ? p->hp.block_points
+                            : p->hp.rows_touched * (int64_t)p->hp.grid.n[0];
   info->expand_scratch_doubles = p->hp.u2_doubles;
   return SHO_OK;
 }

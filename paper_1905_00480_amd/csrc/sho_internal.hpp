@@ -190,6 +190,7 @@ struct HostPlan {
   int64_t u2_doubles = 0;
   int32_t expand_mode = kExpandBlocks;
   int32_t blk_rows = 0, blk_x = 0;      // block shape of the block form
+  int64_t block_points = 0;             // grid points inside the blocks
   std::vector<BlockRec> blocks;         // XCD-interleaved by plane
   std::vector<EntryRec> entries;
   std::vector<uint32_t> run_desc;

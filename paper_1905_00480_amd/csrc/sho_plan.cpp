@@ -615,6 +615,10 @@ void build_blocks(HostPlan *P, int32_t R, int32_t X) {
     }
   }
   while (!P->blocks.empty() && P->blocks.back().nentries < 0) P->blocks.pop_back();
+  P->block_points = 0;
+  for (const BlockRec &B : P->blocks)
+    if (B.nentries >= 0)
+      P->block_points += (int64_t)(std::min(B.y0 + R, ny) - B.y0) * (std::min(B.x0 + X, nx) - B.x0);
 }
 
 }  // namespace sho
