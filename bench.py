@@ -54,6 +54,8 @@ def parse():
                     help="skip the uneven-atom batching workload")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the request-stream (serving) workload")
+    ap.add_argument("--no-diff", action="store_true",
+                    help="skip the differentiation (forward + backward) workload")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the plan's default schedule (no autotuning)")
     ap.add_argument("--serve-requests", type=int, default=2000)
@@ -173,6 +175,57 @@ def _time_steps(step, steps, warmup):
     torch.cuda.synchronize()
     per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
     return ev[0].elapsed_time(ev[-1]) / steps, per
+
+
+def ceilings():
+    """In-run memory ceilings: a plain 1 GiB copy (read + write) and a 1 GiB
+    read (sum), timed with events, as achieved GB/s."""
+    import torch
+    x = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    out = {}
+    for name, fn, nbytes in (("copy", lambda: y.copy_(x), 2 << 30),
+                             ("read", lambda: x.sum(), 1 << 30)):
+        ms, _ = _time_steps(fn, 10, 2)
+        out[name + "_GB/s"] = nbytes / (ms * 1e-3) / 1e9
+    del x, y
+    torch.cuda.empty_cache()
+    return out
+
+
+def diff_step(bd, wl, args):
+    """Differentiation workload (isolated 96^3, 256 atoms, nu 6, 16 bands):
+    forward projection and the backward pair (expansion of h^3 dL/dc for
+    dL/dpsi, derivative kernel for dL/dR), as the autograd wrapper runs them."""
+    import torch
+    s = wl.diff()
+    psi = torch.from_numpy(wl.psi_for(s)).cuda()
+    w = torch.from_numpy(wl.coeffs_for(s)).cuda()
+    plan = bd.Plan.from_system(s)
+    c = torch.empty(plan.coeff_doubles, dtype=torch.float64, device="cuda")
+    gpsi = torch.zeros_like(psi)
+    grad = torch.empty((s.natoms, 3), dtype=torch.float64, device="cuda")
+    wh = w * s.h ** 3
+
+    def step():
+        plan.project(psi, c)
+        gpsi.zero_()
+        plan.expand(wh, gpsi)
+        plan.force(psi, w, grad)
+
+    ms, _ = _time_steps(step, args.steps, args.warmup)
+    plan.profile(True)
+    step()
+    torch.cuda.synchronize()
+    prof = plan.profile_read()
+    plan.profile(False)
+    units = plan.support_points * s.nbands
+    plan.close()
+    return {"workload": "diff: isolated 96^3, h=0.2 Bohr, 256 atoms, sigma=0.6, nu_max=6, "
+                        "16 FP64 bands; step = forward projection + backward (expansion "
+                        "of h^3 dL/dc, derivative kernel at nu+1)",
+            "ms_per_step": ms, "gridpoint*bands/s (forward units)": units / (ms * 1e-3),
+            "kernel_ms": {k: round(v[1], 4) for k, v in prof.items() if v[0]}}
 
 
 def batching(bd, wl, args):
@@ -310,6 +363,12 @@ def main():
     dom = max(kernels, key=lambda k: kernels[k]["ms"])
     d = kernels[dom]
     traffic = measured_traffic(dom)
+    ceil = ceilings()
+    # unique-psi floor of the step: every covered value read once by the
+    # projection and read + written once by the expansion, or the x-pass flops
+    union_bytes = info["union_points"] * B * 8
+    xflops = 2 * 6 * S * B * 2  # x passes of projection and expansion, nu = 5
+    floor_ms = max(3 * union_bytes / (HBM_PEAK_GBS * 1e9), xflops / 78.6e12) * 1e3
 
     rec = {
         "metric": "projected gridpoint*bands/s",
@@ -332,7 +391,10 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": d["GB/s"],
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": d["GB/s"] / HBM_PEAK_GBS, "traffic": traffic,
-                     "algorithmic_bytes_per_launch": d["bytes"], "launch_ms": d["ms"]},
+                     "algorithmic_bytes_per_launch": d["bytes"], "launch_ms": d["ms"],
+                     "frac_of_copy_ceiling": d["GB/s"] / ceil["copy_GB/s"]},
+        "ceilings": ceil,
+        "unique_psi_floor_ms_per_step": floor_ms,
         "kernels": kernels,
         "per_atom_box_GB/s": 3 * S * B * 8 / (ms_per_step * 1e-3) / 1e9,
         "plan_build_s": plan_s,
@@ -346,6 +408,9 @@ def main():
         rec["stored_baseline"] = stored_baseline(bd, s, psi, c, out, args)
     if not args.no_stored:
         _log("stored baseline: %.3f ms per step" % rec["stored_baseline"]["ms_per_step"])
+    if not args.no_diff:
+        rec["diff"] = diff_step(bd, wl, args)
+        _log("diff workload: %.3f ms per step" % rec["diff"]["ms_per_step"])
     if not args.no_batching:
         rec["batching"] = batching(bd, wl, args)
         _log("batching workload done")

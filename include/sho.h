@@ -262,8 +262,10 @@ sho_status sho_plan_get_schedule(sho_plan_t plan, int32_t *schedule,
  *              for all its runs in the block (default).
  * Both read and write every touched value of psi once with plain loads and
  * stores.  block_rows = block_x = 0 picks the default shape; a shape whose
- * tile (rows x points x 32 or 64 bands) exceeds 4096 doubles, or whose
- * points exceed 256 / (table row length), is refused with SHO_E_INVALID.
+ * tile (rows x points x bands per tile: 8, 16, 32 or 64, the power of two
+ * that covers nbands, at most 64) exceeds 4096 doubles, or whose rows or
+ * points exceed 256 / (table row length: 8 doubles for nu_max <= 6, else
+ * 16), is refused with SHO_E_INVALID.
  * set_expand waits for the device; graphs made before it are refused.
  */
 sho_status sho_plan_set_expand(sho_plan_t plan, int32_t mode, int32_t block_rows,

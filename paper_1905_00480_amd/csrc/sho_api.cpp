@@ -255,7 +255,7 @@ sho::EArgs make_eargs(const sho_plan_s *p) {
   E.natoms_u2 = (int32_t)p->hp.nu_atoms.size();
   E.nx = p->hp.grid.n[0];
   E.B = p->hp.nbands;
-  E.tbe_shift = p->hp.nbands > 32 ? 6 : 5;
+  E.tbe_shift = sho::expand_tile_shift(p->hp.nbands, p->hp.expand_mode);
   E.ntiles = (p->hp.nbands + (1 << E.tbe_shift) - 1) >> E.tbe_shift;
   E.ntiles_u2 = (p->hp.nbands + 31) / 32;
   E.nu_max = p->hp.nu_max;

@@ -264,20 +264,31 @@ void build_rows(HostPlan *P);
 // build_rows for run_atom).
 void build_blocks(HostPlan *P, int32_t R, int32_t X);
 
+// log2 of the bands per lane slot of the expansion's y/x passes: the row form
+// takes 32 or 64; the block form also 8 or 16, so that few bands still fill
+// the wave with run slots.
+inline int expand_tile_shift(int nbands, int mode) {
+  if (nbands > 32) return 6;
+  if (mode == kExpandRows || nbands > 16) return 5;
+  return nbands > 8 ? 4 : 3;
+}
+
 // Whether an R x X block fits: the LDS tile (R X bands-per-tile doubles) and
 // the x-table staging of one wave (X rows of the widest table).
 inline bool block_shape_ok(const HostPlan &P, int32_t R, int32_t X) {
-  const int tbe = P.nbands > 32 ? 64 : 32;
+  const int tbe = 1 << expand_tile_shift(P.nbands, kExpandBlocks);
   return R >= 1 && X >= 1 && (int64_t)R * X * tbe <= kBlockTileDoubles &&
          X * table_nfp(P.nu_max) <= 256 && R * table_nfp(P.nu_max) <= 256;
 }
 
-// Default block shape: as wide in x as the staging allows (at most 32 points
-// for 32-band tiles, 16 for 64), then as many rows as the tile holds.
+// Default block shape: as wide in x as the staging allows (at most 32 points,
+// 16 for 64-band tiles), then as many rows as the tile holds and the y
+// staging allows.
 inline void default_block_shape(const HostPlan &P, int32_t *R, int32_t *X) {
-  const int tbe = P.nbands > 32 ? 64 : 32;
-  *X = std::min(256 / table_nfp(P.nu_max), tbe == 32 ? 32 : 16);
-  *R = kBlockTileDoubles / (*X * tbe);
+  const int tbe = 1 << expand_tile_shift(P.nbands, kExpandBlocks);
+  const int nfp = table_nfp(P.nu_max);
+  *X = std::min(256 / nfp, tbe == 64 ? 16 : 32);
+  *R = std::min(kBlockTileDoubles / (*X * tbe), 256 / nfp);
 }
 
 // Layout of the stored projector tables (SHO_FLAG_STORED plans): the points

@@ -109,6 +109,23 @@ def test_schedule_arguments_host_only():
     one.close()
 
 
+def test_expand_form_arguments_host_only():
+    _lib()
+    s = wl.scale()
+    p = _host_plan(s)
+    mode, R, X = p.expand_form()
+    assert mode == bd.EXPAND_BLOCKS and R * X * 32 <= 4096 and X * 8 <= 256
+    p.set_expand(bd.EXPAND_ROWS)
+    assert p.expand_form()[0] == bd.EXPAND_ROWS
+    p.set_expand(bd.EXPAND_BLOCKS, 8, 16)
+    assert p.expand_form() == (bd.EXPAND_BLOCKS, 8, 16)
+    _expect(bd.SHO_E_INVALID, lambda: p.set_expand(2))
+    _expect(bd.SHO_E_INVALID, lambda: p.set_expand(bd.EXPAND_BLOCKS, 16, 16))   # 8192 doubles
+    _expect(bd.SHO_E_INVALID, lambda: p.set_expand(bd.EXPAND_BLOCKS, 1, 64))    # staging
+    _expect(bd.SHO_E_INVALID, lambda: p.set_expand(bd.EXPAND_BLOCKS, 0, 4))
+    p.close()
+
+
 def test_host_only_plan_refuses_compute():
     lib = _lib()
     s = wl.small_periodic(natoms=2)

@@ -165,3 +165,34 @@ def test_batching_config_sampled():
                                     with_abs=True)
     _check(out[pts], e_ref, e_abs, "batching expand (sampled points)")
     plan.close()
+
+
+@pytest.mark.parametrize("form", [(0, 0, 0), (1, 0, 0), (1, 1, 1), (1, 2, 16), (1, 16, 8)])
+def test_expansion_forms_match_oracle(mixed, form):
+    """Row form, block form at the default shape and at extreme shapes (one
+    point per block; wide and tall blocks), accumulating into random psi."""
+    bd = _bd()
+    s, psi, cin, _, (e_ref, e_abs), _ = mixed
+    plan = bd.Plan.from_system(s)
+    plan.set_expand(*form)
+    assert plan.expand_form()[0] == form[0]
+    d_acc = _dev(psi)
+    plan.expand(_dev(cin), d_acc)
+    _check(_host(d_acc), e_ref, e_abs, "expand form %s" % (form,))
+    plan.close()
+
+
+def test_expansion_forms_wide_boxes():
+    """Boxes wider than a small periodic cell (several images of one atom in
+    one row and one block)."""
+    bd = _bd()
+    s = wl.make_system("wide", (8, 9, 7), 0.2, (True,) * 3, 3, 0.6, 3, 2, 41)
+    c = wl.coeffs_for(s)
+    e_ref, e_abs = oracle.expand(*s.geometry(), c, np.zeros(s.psi_shape), with_abs=True)
+    for form in ((0, 0, 0), (1, 0, 0), (1, 4, 4), (1, 1, 8)):
+        plan = bd.Plan.from_system(s)
+        plan.set_expand(*form)
+        out = torch.zeros(s.psi_shape, dtype=torch.float64, device="cuda")
+        plan.expand(_dev(c), out)
+        _check(_host(out), e_ref, e_abs, "wide boxes, form %s" % (form,))
+        plan.close()
