@@ -54,6 +54,8 @@ def parse():
                     help="skip the uneven-atom batching workload")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the request-stream (serving) workload")
+    ap.add_argument("--no-paper", action="store_true",
+                    help="skip the paper-geometry table (SHO vs stored, nu_max 0..5)")
     ap.add_argument("--no-diff", action="store_true",
                     help="skip the differentiation (forward + backward) workload")
     ap.add_argument("--no-tune", action="store_true",
@@ -226,6 +228,51 @@ def diff_step(bd, wl, args):
                         "of h^3 dL/dc, derivative kernel at nu+1)",
             "ms_per_step": ms, "gridpoint*bands/s (forward units)": units / (ms * 1e-3),
             "kernel_ms": {k: round(v[1], 4) for k, v in prof.items() if v[0]}}
+
+
+def paper_table(bd, wl, args):
+    """The paper's benchmark geometry (sec. 6: fcc, 64^3 at h = 0.25 A, 650
+    atoms whose 3.55 A spheres reach the grid, 1024 bands) for nu_max 0..5,
+    projection (prj) and expansion (add), with functions generated on the fly
+    (SHO) and read from stored tables (USU), as in the paper's table 1."""
+    import torch
+    s5 = wl.paper_fcc(numax=5)
+    psi = torch.from_numpy(wl.psi_for(s5)).cuda()
+    out = torch.zeros_like(psi)
+    rows = []
+    for nu in range(6):
+        s = wl.paper_fcc(numax=nu)
+        row = {"nu_max": nu, "functions": (nu + 1) * (nu + 2) * (nu + 3) // 6}
+        for tag, flags in (("SHO", 0), ("USU", bd.FLAG_STORED)):
+            plan = bd.Plan.from_system(s, flags=flags)
+            c = torch.zeros(plan.coeff_doubles, dtype=torch.float64, device="cuda")
+            plan.project(psi, c)
+            plan.expand(c, out)
+            torch.cuda.synchronize()
+            plan.profile(True)
+            for _ in range(3):
+                plan.project(psi, c)
+            for _ in range(3):
+                plan.expand(c, out)
+            torch.cuda.synchronize()
+            prof = plan.profile_read()
+            plan.profile(False)
+            row[tag + "prj_ms"] = prof["project"][1]
+            row[tag + "add_ms"] = prof["expand_z"][1] + prof["expand_xy"][1]
+            row["support_points"] = plan.support_points
+            plan.close()
+            del c
+        row["S_prj"] = row["USUprj_ms"] / row["SHOprj_ms"]
+        row["S_add"] = row["USUadd_ms"] / row["SHOadd_ms"]
+        rows.append(row)
+        _log("paper geometry nu_max %d: SHO prj %.2f add %.2f ms, USU prj %.2f add %.2f ms"
+             % (nu, row["SHOprj_ms"], row["SHOadd_ms"], row["USUprj_ms"], row["USUadd_ms"]))
+    del psi, out
+    torch.cuda.empty_cache()
+    return {"workload": "fcc a=4.08 A, isolated 64^3 at h=0.25 A, 650 atoms with 3.55 A "
+                        "projection spheres (11 projections per grid value), sigma=1.6 Bohr, "
+                        "1024 FP64 bands; times per kernel call",
+            "rows": rows}
 
 
 def batching(bd, wl, args):
@@ -411,6 +458,8 @@ def main():
     if not args.no_diff:
         rec["diff"] = diff_step(bd, wl, args)
         _log("diff workload: %.3f ms per step" % rec["diff"]["ms_per_step"])
+    if not args.no_paper:
+        rec["paper_geometry"] = paper_table(bd, wl, args)
     if not args.no_batching:
         rec["batching"] = batching(bd, wl, args)
         _log("batching workload done")

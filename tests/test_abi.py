@@ -176,6 +176,27 @@ def test_workload_scale_geometry_counts():
     p.close()
 
 
+def test_paper_fcc_geometry():
+    """The benchmark geometry of sec. 6: 64^3 points at h = 0.25 Angstrom,
+    fcc a = 4.08 Angstrom, projection spheres of 3.55 Angstrom.  The paper
+    states that each grid value enters about eleven projections (figure of
+    the test system) and that 241 atoms lie inside the 16 Angstrom domain
+    (four per 4.08^3 cell); both follow from this construction."""
+    _lib()
+    s = wl.paper_fcc(nbands=4)
+    p = _host_plan(s, rbox=s.rbox)
+    per_point = p.support_points / np.prod(s.n)
+    assert round(per_point) == 11, per_point
+    # 4 atoms per cubic cell of 4.08 A in a (16 A)^3 domain
+    assert round(4 * (16.0 / 4.08) ** 3) == 241
+    R = float(s.rbox[0])
+    assert abs(R - 3.55 / 0.529177210903) < 1e-12
+    cnt = p.support_counts()
+    assert cnt.max() == len(oracle.support(s.n, s.h, s.periodic, s.pos[int(np.argmax(cnt))], R)[1])
+    assert 600 <= s.natoms <= 700   # the paper counts 665 with its own boundary rule
+    p.close()
+
+
 def test_device_plan_without_gpu_reports_device_error():
     import torch
     if torch.cuda.is_available():

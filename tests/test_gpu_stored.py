@@ -100,3 +100,25 @@ def test_stored_plan_refuses_moving_centres():
         plan.set_centres(s.pos + 0.01)
     assert ei.value.code == bd.SHO_E_INVALID
     plan.close()
+
+
+@pytest.mark.parametrize("nu", [0, 3, 5])
+def test_paper_fcc_geometry_both_forms(nu):
+    """The sec. 6 benchmark geometry (650 atoms, 11 projections per grid
+    value, isolated 64^3) at 4 bands: every coefficient and every expanded
+    value of the on-the-fly and the stored forms against the oracle."""
+    bd = _bd()
+    s = wl.paper_fcc(numax=nu, nbands=4)
+    psi = wl.psi_for(s)
+    w = wl.coeffs_for(s)
+    c_ref, c_abs = oracle.project(*s.geometry(), psi, rbox=s.rbox, with_abs=True)
+    e_ref, e_abs = oracle.expand(*s.geometry(), w, np.zeros(s.psi_shape), rbox=s.rbox,
+                                 with_abs=True)
+    d_psi, d_w = _dev(psi), _dev(w)
+    for flags in (0, bd.FLAG_STORED):
+        plan = bd.Plan.from_system(s, flags=flags)
+        _check(_host(plan.project(d_psi)), c_ref, c_abs, "fcc project flags %d" % flags)
+        e = torch.zeros_like(d_psi)
+        plan.expand(d_w, e)
+        _check(_host(e), e_ref, e_abs, "fcc expand flags %d" % flags)
+        plan.close()
