@@ -199,6 +199,22 @@ sho_status sho_plan_force(sho_plan_t plan, const double *psi,
                           const double *w, double *grad, void *stream);
 
 /*
+ * Non-local application (sec. 3.2, steps 1-3, with the atomic matrices in the
+ * SHO basis of sec. 3.5: a real N_SHO x N_SHO matrix per atom):
+ *   multiply:  d[a][n][b] = sum_m D_a[n][m] c[a][m][b]
+ *   apply:     c <- project(psi); d <- multiply(D, c); out += expand(d)
+ * D: device, per-atom row-major N_SHO(nu_a) x N_SHO(nu_a) blocks in atom
+ * order, first double of atom a at matrix_offsets[a] (host [natoms + 1]).
+ * c, d: device buffers of coeff_doubles (c and d must not overlap; both are
+ * overwritten; out accumulates).  The products run on FP64 matrix cores.
+ */
+sho_status sho_plan_matrix_offsets(sho_plan_t plan, int64_t *off);
+sho_status sho_plan_multiply(sho_plan_t plan, const double *D, const double *c,
+                             double *d, void *stream);
+sho_status sho_plan_apply(sho_plan_t plan, const double *psi, const double *D,
+                          double *c, double *d, double *out, void *stream);
+
+/*
  * Stateless forms: build (or reuse from a small internal cache keyed on the
  * exact argument bytes) a plan for the given geometry, then run the
  * operation on stream.  Same argument meaning as the plan calls above.
@@ -305,6 +321,10 @@ sho_status sho_plan_tune(sho_plan_t plan, const double *psi, double *c,
 typedef struct sho_graph_s *sho_graph_t;
 sho_status sho_graph_create(sho_plan_t plan, const double *psi, double *c,
                             double *out, sho_graph_t *graph);
+/* The same for the whole application: project, multiply, expand. */
+sho_status sho_graph_create_apply(sho_plan_t plan, const double *psi,
+                                  const double *D, double *c, double *d,
+                                  double *out, sho_graph_t *graph);
 sho_status sho_graph_launch(sho_graph_t graph, void *stream);
 sho_status sho_graph_destroy(sho_graph_t graph);
 

@@ -233,3 +233,35 @@ def force(n, h, periodic, pos, sigma, numax, psi, w, rbox=None, spos=None,
     if with_dc:
         out.append(dc)
     return out[0] if len(out) == 1 else tuple(out)
+
+
+def matrix_offsets(numax):
+    """Offsets (doubles) of per-atom N_SHO x N_SHO blocks, atom order."""
+    n = np.array([nsho(int(v)) for v in np.atleast_1d(numax)], dtype=np.int64)
+    return np.concatenate([[0], np.cumsum(n * n)])
+
+
+def apply(n, h, periodic, pos, sigma, numax, psi, D, psi_in, rbox=None, with_abs=False):
+    """Non-local application (sec. 3.2 steps 1-3): c = projection of psi,
+    d_a = D_a c_a (a plain matrix product per atom), psi_out = psi_in +
+    expansion of d.  With ``with_abs`` also the abs-sum of the whole chain,
+    |psi_in| + sum |P| (|D| c_abs), which bounds the rounding of every step."""
+    numax = np.atleast_1d(np.asarray(numax, dtype=np.int32))
+    B = psi.shape[-1]
+    c, c_abs = project(n, h, periodic, pos, sigma, numax, psi, rbox=rbox, with_abs=True)
+    coff = coeff_offsets(numax, B)
+    doff = matrix_offsets(numax)
+    d = np.empty_like(c)
+    d_abs = np.empty_like(c)
+    for a in range(len(numax)):
+        N = nsho(int(numax[a]))
+        Da = np.asarray(D[doff[a]:doff[a + 1]]).reshape(N, N)
+        ca = c[coff[a]:coff[a + 1]].reshape(N, B)
+        d[coff[a]:coff[a + 1]] = (Da @ ca).ravel()
+        d_abs[coff[a]:coff[a + 1]] = (np.abs(Da) @ c_abs[coff[a]:coff[a + 1]].reshape(N, B)).ravel()
+    out = expand(n, h, periodic, pos, sigma, numax, d, psi_in, rbox=rbox)
+    if not with_abs:
+        return out
+    _, out_abs = expand(n, h, periodic, pos, sigma, numax, d_abs, np.abs(psi_in), rbox=rbox,
+                        with_abs=True)
+    return out, out_abs

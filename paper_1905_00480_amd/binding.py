@@ -49,6 +49,8 @@ EXPORTS = (
     "sho_cache_clear", "sho_plan_profile", "sho_plan_profile_read",
     "sho_plan_set_schedule", "sho_plan_get_schedule", "sho_plan_tune",
     "sho_plan_set_expand", "sho_plan_get_expand",
+    "sho_plan_matrix_offsets", "sho_plan_multiply", "sho_plan_apply",
+    "sho_graph_create_apply",
     "sho_graph_create", "sho_graph_launch", "sho_graph_destroy",
     "sho_server_create", "sho_server_add_system", "sho_server_submit",
     "sho_server_drain", "sho_server_request_info", "sho_server_read",
@@ -148,6 +150,10 @@ def load_library(path=None):
                                   ctypes.POINTER(sho_tune_result)]
     lib.sho_graph_create.argtypes = [P, _vp, _vp, _vp, ctypes.POINTER(_vp)]
     lib.sho_graph_launch.argtypes = [_vp, _vp]
+    lib.sho_plan_matrix_offsets.argtypes = [P, _i64p]
+    lib.sho_plan_multiply.argtypes = [P, _vp, _vp, _vp, _vp]
+    lib.sho_plan_apply.argtypes = [P, _vp, _vp, _vp, _vp, _vp, _vp]
+    lib.sho_graph_create_apply.argtypes = [P, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(_vp)]
     lib.sho_graph_destroy.argtypes = [_vp]
     lib.sho_server_create.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32,
                                       ctypes.POINTER(_vp)]
@@ -295,6 +301,41 @@ class Plan:
             _stream(stream)))
         return grad
 
+    def matrix_offsets(self):
+        """Per-atom offsets (doubles) of the atomic matrices in D."""
+        off = np.empty(self.natoms + 1, dtype=np.int64)
+        _check(self._lib.sho_plan_matrix_offsets(self._h, off.ctypes.data_as(_i64p)))
+        return off
+
+    def multiply(self, D, c, d=None, stream=None):
+        """d[a] = D_a c[a] for every atom."""
+        import torch
+        if d is None:
+            d = torch.empty_like(c)
+        nD = int(self.matrix_offsets()[-1])
+        _check(self._lib.sho_plan_multiply(self._h, _dev(D, nD, "D"),
+                                           _dev(c, self.coeff_doubles, "c"),
+                                           _dev(d, self.coeff_doubles, "d"), _stream(stream)))
+        return d
+
+    def apply(self, psi, D, out, c=None, d=None, stream=None):
+        """out += sum_a P_a D_a P_a^T psi (with h^3 in the projection)."""
+        import torch
+        if c is None:
+            c = torch.empty(self.coeff_doubles, dtype=torch.float64, device=psi.device)
+        if d is None:
+            d = torch.empty_like(c)
+        nD = int(self.matrix_offsets()[-1])
+        _check(self._lib.sho_plan_apply(
+            self._h, _dev(psi, self.psi_numel, "psi"), _dev(D, nD, "D"),
+            _dev(c, self.coeff_doubles, "c"), _dev(d, self.coeff_doubles, "d"),
+            _dev(out, self.psi_numel, "out"), _stream(stream)))
+        return out
+
+    def apply_graph(self, psi, D, c, d, out):
+        """A replayable graph of apply (project, multiply, expand)."""
+        return Graph(self, psi, c, out, D=D, d=d)
+
     def set_schedule(self, schedule, band_tile=0, target_points=16384):
         _check(self._lib.sho_plan_set_schedule(self._h, int(schedule), int(band_tile),
                                                int(target_points)))
@@ -358,13 +399,20 @@ class Graph:
     """Captured project -> expand of a plan on fixed buffers (sho_graph_*).
     Holds references to the plan and the buffers so that they outlive it."""
 
-    def __init__(self, plan, psi, c, out):
+    def __init__(self, plan, psi, c, out, D=None, d=None):
         self._lib = plan._lib
-        self._keep = (plan, psi, c, out)
+        self._keep = (plan, psi, c, out, D, d)
         h = ctypes.c_void_p()
-        _check(self._lib.sho_graph_create(
-            plan._h, _dev(psi, plan.psi_numel, "psi"), _dev(c, plan.coeff_doubles, "c"),
-            _dev(out, plan.psi_numel, "out"), ctypes.byref(h)))
+        if D is None:
+            _check(self._lib.sho_graph_create(
+                plan._h, _dev(psi, plan.psi_numel, "psi"), _dev(c, plan.coeff_doubles, "c"),
+                _dev(out, plan.psi_numel, "out"), ctypes.byref(h)))
+        else:
+            nD = int(plan.matrix_offsets()[-1])
+            _check(self._lib.sho_graph_create_apply(
+                plan._h, _dev(psi, plan.psi_numel, "psi"), _dev(D, nD, "D"),
+                _dev(c, plan.coeff_doubles, "c"), _dev(d, plan.coeff_doubles, "d"),
+                _dev(out, plan.psi_numel, "out"), ctypes.byref(h)))
         self._h = h
 
     def launch(self, stream=None):

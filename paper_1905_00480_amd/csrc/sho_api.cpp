@@ -78,6 +78,7 @@ struct sho_plan_s {
   sho::WorkRec *d_work_proj = nullptr;  // the projection's launch order
   int64_t sched_version = 0;      // bumped whenever the work items change
   int64_t sched_bytes = 0;        // device bytes of the schedule tables
+  int64_t *d_doff = nullptr;           // per-atom offsets of the atomic matrices
   sho::BlockRec *d_blocks = nullptr;   // block form of the expansion
   sho::EntryRec *d_entries = nullptr;
   uint32_t *d_run_desc = nullptr;
@@ -122,6 +123,8 @@ void free_plan_device(sho_plan_s *p) {
   p->d_u2_off = nullptr;
   p->d_nu_atoms = nullptr;
   p->d_u2 = nullptr;
+  if (p->d_doff) (void)hipFree(p->d_doff);
+  p->d_doff = nullptr;
   for (void *q : {(void *)p->d_stored, (void *)p->d_run_poff, (void *)p->d_atom_poff,
                   (void *)p->d_atom_pbeg, (void *)p->d_pidx, (void *)p->d_sitems})
     if (q) (void)hipFree(q);
@@ -521,6 +524,7 @@ sho_status sho_plan_create(const sho_grid *grid, int32_t natoms,
   if ((e = upload(&p->d_atoms, p->hp.atoms, &p->device_bytes)) != hipSuccess ||
       (e = upload(&p->d_lines, p->hp.lines, &p->device_bytes)) != hipSuccess ||
       (e = upload_schedule(p)) != hipSuccess || (e = upload_blocks(p)) != hipSuccess ||
+      (e = upload(&p->d_doff, p->hp.dmat_off, &p->device_bytes)) != hipSuccess ||
       (e = upload(&p->d_run_atom, p->hp.run_atom, &p->device_bytes)) != hipSuccess ||
       (e = upload(&p->d_row_runs, p->hp.row_runs, &p->device_bytes)) != hipSuccess ||
       (e = upload(&p->d_rows, p->hp.rows, &p->device_bytes)) != hipSuccess ||
@@ -877,6 +881,61 @@ sho_status sho_plan_tune(sho_plan_t p, const double *psi, double *c, int32_t rep
   return SHO_OK;
 }
 
+sho_status sho_plan_matrix_offsets(sho_plan_t p, int64_t *off) {
+  if (!p || !off) return fail(SHO_E_INVALID, "NULL plan or output");
+  std::memcpy(off, p->hp.dmat_off.data(), p->hp.dmat_off.size() * sizeof(int64_t));
+  return SHO_OK;
+}
+
+namespace {
+
+sho_status check_multiply(const sho_plan_s *p, const double *D, const double *c,
+                          const double *d) {
+  if (!p) return fail(SHO_E_INVALID, "NULL plan");
+  if (p->hp.flags & SHO_FLAG_HOST_ONLY)
+    return fail(SHO_E_INVALID, "host-only plan cannot run kernels");
+  if (p->hp.coeff_rows == 0) return SHO_OK;
+  const int64_t db = p->hp.dmat_off.back() * (int64_t)sizeof(double);
+  if (!device_range_ok(D, db) || !device_range_ok(c, coeff_bytes(p)) ||
+      !device_range_ok(d, coeff_bytes(p)))
+    return fail(SHO_E_INVALID, "D, c and d must be device buffers of the plan's sizes");
+  if ((const char *)c < (const char *)d + coeff_bytes(p) &&
+      (const char *)d < (const char *)c + coeff_bytes(p))
+    return fail(SHO_E_INVALID, "c and d overlap");
+  return SHO_OK;
+}
+
+hipError_t run_multiply(sho_plan_s *p, const double *D, const double *c, double *d,
+                        hipStream_t s) {
+  return sho::launch_multiply(p->d_atoms, p->hp.natoms, p->d_doff, D, c, d, p->hp.nbands, s);
+}
+
+}  // namespace
+
+sho_status sho_plan_multiply(sho_plan_t p, const double *D, const double *c, double *d,
+                             void *stream) {
+  sho_status st = check_multiply(p, D, c, d);
+  if (st != SHO_OK || p->hp.coeff_rows == 0) return st;
+  hipError_t e = run_multiply(p, D, c, d, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "multiply launch");
+  return SHO_OK;
+}
+
+sho_status sho_plan_apply(sho_plan_t p, const double *psi, const double *D, double *c,
+                          double *d, double *out, void *stream) {
+  sho_status st = check_project(p, psi, c);
+  if (st == SHO_OK) st = check_multiply(p, D, c, d);
+  if (st == SHO_OK) st = check_project(p, out, d);
+  if (st != SHO_OK || p->hp.coeff_rows == 0) return st;
+  if ((st = ensure_u2(p)) != SHO_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = run_project(p, psi, c, s, p->prof_on);
+  if (e == hipSuccess) e = run_multiply(p, D, c, d, s);
+  if (e == hipSuccess) e = run_expand(p, d, out, s, p->prof_on);
+  if (e != hipSuccess) return hip_fail(e, "apply launch");
+  return SHO_OK;
+}
+
 // ------------------------------------------------------------- graphs --
 
 struct sho_graph_s {
@@ -886,18 +945,13 @@ struct sho_graph_s {
   hipGraphExec_t exec = nullptr;
 };
 
-sho_status sho_graph_create(sho_plan_t p, const double *psi, double *c, double *out,
-                            sho_graph_t *g) {
-  if (!g) return fail(SHO_E_INVALID, "NULL graph output");
-  *g = nullptr;
-  sho_status st = check_project(p, psi, c);
-  if (st != SHO_OK) return st;
-  if (!device_range_ok(out, psi_bytes(p)))
-    return fail(SHO_E_INVALID, "out must be a device buffer of the grid's size");
-  if ((const char *)c < (const char *)out + psi_bytes(p) &&
-      (const char *)out < (const char *)c + coeff_bytes(p))
-    return fail(SHO_E_INVALID, "out and c overlap");
-  if (!(p->hp.flags & SHO_FLAG_STORED) && (st = ensure_u2(p)) != SHO_OK) return st;
+}  // extern "C"
+
+namespace {
+
+// Captures f(stream) into an instantiated graph owned by a new sho_graph_s.
+template <typename F>
+sho_status capture(sho_plan_t p, F &&f, sho_graph_t *g) {
   sho_graph_s *G = new (std::nothrow) sho_graph_s();
   if (!G) return fail(SHO_E_NOMEM, "host allocation failed");
   G->plan = p;
@@ -906,8 +960,7 @@ sho_status sho_graph_create(sho_plan_t p, const double *psi, double *c, double *
   hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    hipError_t e1 = p->hp.coeff_rows ? run_project(p, psi, c, cs, false) : hipSuccess;
-    if (e1 == hipSuccess && p->hp.coeff_rows) e1 = run_expand(p, c, out, cs, false);
+    hipError_t e1 = p->hp.coeff_rows ? f(cs) : hipSuccess;
     e = hipStreamEndCapture(cs, &G->graph);
     if (e1 != hipSuccess) e = e1;
   }
@@ -921,6 +974,46 @@ sho_status sho_graph_create(sho_plan_t p, const double *psi, double *c, double *
   }
   *g = G;
   return SHO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sho_status sho_graph_create(sho_plan_t p, const double *psi, double *c, double *out,
+                            sho_graph_t *g) {
+  if (!g) return fail(SHO_E_INVALID, "NULL graph output");
+  *g = nullptr;
+  sho_status st = check_project(p, psi, c);
+  if (st != SHO_OK) return st;
+  if (!device_range_ok(out, psi_bytes(p)))
+    return fail(SHO_E_INVALID, "out must be a device buffer of the grid's size");
+  if ((const char *)c < (const char *)out + psi_bytes(p) &&
+      (const char *)out < (const char *)c + coeff_bytes(p))
+    return fail(SHO_E_INVALID, "out and c overlap");
+  if ((st = ensure_u2(p)) != SHO_OK) return st;
+  return capture(p, [&](hipStream_t cs) {
+    hipError_t e1 = run_project(p, psi, c, cs, false);
+    if (e1 == hipSuccess) e1 = run_expand(p, c, out, cs, false);
+    return e1;
+  }, g);
+}
+
+sho_status sho_graph_create_apply(sho_plan_t p, const double *psi, const double *D,
+                                  double *c, double *d, double *out, sho_graph_t *g) {
+  if (!g) return fail(SHO_E_INVALID, "NULL graph output");
+  *g = nullptr;
+  sho_status st = check_project(p, psi, c);
+  if (st == SHO_OK) st = check_multiply(p, D, c, d);
+  if (st == SHO_OK) st = check_project(p, out, d);
+  if (st != SHO_OK) return st;
+  if ((st = ensure_u2(p)) != SHO_OK) return st;
+  return capture(p, [&](hipStream_t cs) {
+    hipError_t e1 = run_project(p, psi, c, cs, false);
+    if (e1 == hipSuccess) e1 = run_multiply(p, D, c, d, cs);
+    if (e1 == hipSuccess) e1 = run_expand(p, d, out, cs, false);
+    return e1;
+  }, g);
 }
 
 sho_status sho_graph_launch(sho_graph_t g, void *stream) {

@@ -205,6 +205,7 @@ struct HostPlan {
   int64_t rows_touched = 0;   // memory rows with at least one run
   std::vector<double> support_centre;  // [natoms][3], fixed at creation
   std::vector<int64_t> coeff_off;      // [natoms+1] in doubles
+  std::vector<int64_t> dmat_off;       // [natoms+1] atomic matrices, doubles
   int64_t coeff_rows = 0;
   int64_t support_points = 0;
   int64_t table_doubles = 0;           // size of the 1D table buffer

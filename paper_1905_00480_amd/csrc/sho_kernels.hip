@@ -990,6 +990,53 @@ __global__ __launch_bounds__(kStoredBlock) void k_expand_stored(
   }
 }
 
+// ------------------------------------------------------- multiplication --
+
+// d[a][n][b] = sum_m D_a[n][m] c[a][m][b] (sec. 3.2 step 2 with the atomic
+// matrix carried into the SHO basis, sec. 3.5): per atom a dense N x N times
+// N x B product, on FP64 MFMA with i = n, j = b and four m per step.  One
+// workgroup per (atom, 32-band tile); wave w takes the 16-row blocks
+// w, w+4, ...
+__global__ __launch_bounds__(kStoredBlock) void k_multiply(const AtomRec *__restrict__ atoms,
+                                                           const int64_t *__restrict__ doff,
+                                                           const double *__restrict__ D,
+                                                           const double *__restrict__ c,
+                                                           double *__restrict__ d, int32_t B) {
+  const int a = blockIdx.x;
+  const int nu = load_uniform(&atoms[a].nu);
+  const int64_t row0 = load_uniform(&atoms[a].coeff_row);
+  const int N = (nu + 1) * (nu + 2) * (nu + 3) / 6;
+  const double *Da = D + doff[a];
+  const int lane = threadIdx.x & 63;
+  const int w = wave_id();
+  const int q = lane >> 4, col = lane & 15;
+  const int b0 = blockIdx.y * kStoredTile;
+  const int bA = b0 + col, bB = b0 + 16 + col;
+  const bool okA = bA < B, okB = bB < B;
+  const int nblk = (N + 15) / 16;
+  for (int nb = w; nb < nblk; nb += 4) {
+    dx4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+    const int n = nb * 16 + col;
+#pragma unroll 4
+    for (int m0 = 0; m0 < N; m0 += 4) {
+      const int m = m0 + q;
+      const double av = (n < N && m < N) ? Da[(int64_t)n * N + m] : 0.0;
+      const double cA = (m < N && okA) ? c[(row0 + m) * B + bA] : 0.0;
+      const double cB = (m < N && okB) ? c[(row0 + m) * B + bB] : 0.0;
+      acc0 = mfma_f64(av, cA, acc0);
+      acc1 = mfma_f64(av, cB, acc1);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int nn = nb * 16 + 4 * r + q;
+      if (nn < N) {
+        if (okA) d[(row0 + nn) * B + bA] = acc0[r];
+        if (okB) d[(row0 + nn) * B + bB] = acc1[r];
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------------- derivative --
 
 // Index of (nx, ny, nz) in the nz-major / ny / nx-fastest order at cut-off nu.
@@ -1281,6 +1328,15 @@ hipError_t launch_expand_stored(int nu, const SArgs &S, const double *c,
 #undef X
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_multiply(const AtomRec *atoms, int32_t natoms, const int64_t *doff,
+                           const double *D, const double *c, double *d, int32_t B,
+                           hipStream_t s) {
+  if (natoms <= 0) return hipSuccess;
+  const dim3 g((unsigned)natoms, (unsigned)((B + kStoredTile - 1) / kStoredTile));
+  hipLaunchKernelGGL(k_multiply, g, dim3(kStoredBlock), 0, s, atoms, doff, D, c, d, B);
+  return hipGetLastError();
 }
 
 hipError_t launch_tables(const AtomRec *atoms, int32_t natoms, double h,

@@ -106,6 +106,10 @@ hipError_t launch_project_stored(int nu, const SArgs &S, const double *psi,
                                  double *c, hipStream_t s);
 hipError_t launch_expand_stored(int nu, const SArgs &S, const double *c,
                                 double *psi, hipStream_t s);
+// d = D c per atom (D: per-atom N x N row-major blocks at doff[a]).
+hipError_t launch_multiply(const AtomRec *atoms, int32_t natoms, const int64_t *doff,
+                           const double *D, const double *c, double *d, int32_t B,
+                           hipStream_t s);
 // grad must be zeroed first (launch_fill)
 hipError_t launch_force(int nu, const KArgs &K, const double *psi,
                         const double *w, double *grad, hipStream_t s);

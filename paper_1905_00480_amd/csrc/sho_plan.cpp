@@ -82,6 +82,7 @@ sho_status build_host_plan(const sho_grid *grid, int32_t natoms,
   P.support_centre.assign(pos, pos + 3 * (size_t)natoms);
   P.coeff_off.resize(natoms + 1);
   P.coeff_off[0] = 0;
+  P.dmat_off.assign(natoms + 1, 0);
 
   for (int32_t a = 0; a < natoms; ++a) {
     const double *c = pos + 3 * a;
@@ -235,6 +236,7 @@ sho_status build_host_plan(const sho_grid *grid, int32_t natoms,
     P.table_doubles += (int64_t)(A.mx + A.my + A.mz) * A.tab_nfp;
     P.coeff_rows += nsho(nu);
     P.coeff_off[a + 1] = P.coeff_rows * nbands;
+    P.dmat_off[a + 1] = P.dmat_off[a] + (int64_t)nsho(nu) * nsho(nu);
     P.support_points += A.npoints;
     P.nu_max = std::max(P.nu_max, nu);
   }

@@ -389,3 +389,48 @@ def test_force_plane_wave_sign():
     for d in range(3):
         assert np.max(np.abs(dc[d, :, 0] + k[d] * c[:, 1])) < 1e-11
         assert np.max(np.abs(dc[d, :, 1] - k[d] * c[:, 0])) < 1e-11
+
+
+def test_apply_orientation_and_identity():
+    """Non-local application (sec. 3.2 steps 1-3).  On a box large enough
+    for the basis to be complete (R = 8 sigma, sigma/h = 3): psi = P_m gives
+    c = e_m, so with a single nonzero D[n][m] = 1 the result is P_n, which
+    fixes the orientation d = D c; with D = I the result is psi itself."""
+    n, h, per = (48, 48, 48), 0.2, (False,) * 3
+    pos = np.array([[4.8, 4.7, 4.9]])
+    sigma, numax = np.array([0.6]), np.array([2], dtype=np.int32)
+    rbox = np.array([8 * 0.6])
+    N = oracle.nsho(2)
+    m, nn = 3, 7
+    em = np.zeros(N)
+    em[m] = 1.0
+    psi = oracle.expand(n, h, per, pos, sigma, numax, em, np.zeros(n[::-1] + (1,)), rbox=rbox)
+    D = np.zeros((N, N))
+    D[nn, m] = 1.0
+    out = oracle.apply(n, h, per, pos, sigma, numax, psi, D.ravel(), np.zeros_like(psi), rbox=rbox)
+    en = np.zeros(N)
+    en[nn] = 1.0
+    want = oracle.expand(n, h, per, pos, sigma, numax, en, np.zeros_like(psi), rbox=rbox)
+    assert np.max(np.abs(out - want)) < 1e-10 * np.max(np.abs(want))
+    ident = oracle.apply(n, h, per, pos, sigma, numax, psi, np.eye(N).ravel(),
+                         np.zeros_like(psi), rbox=rbox)
+    assert np.max(np.abs(ident - psi)) < 1e-10 * np.max(np.abs(psi))
+
+
+def test_apply_self_adjoint_for_symmetric_matrices():
+    """With symmetric atomic matrices the non-local operator is self-adjoint
+    in the grid inner product: <phi, V psi> = <V phi, psi>."""
+    s = wl.small_periodic(natoms=3, nbands=2, numax=3)
+    rng = np.random.default_rng(8)
+    off = oracle.matrix_offsets(s.numax)
+    D = np.empty(off[-1])
+    for a in range(s.natoms):
+        N = oracle.nsho(int(s.numax[a]))
+        M = rng.standard_normal((N, N))
+        D[off[a]:off[a + 1]] = (M + M.T).ravel()
+    psi = rng.standard_normal(s.psi_shape)
+    phi = rng.standard_normal(s.psi_shape)
+    z = np.zeros(s.psi_shape)
+    lhs = np.sum(phi * oracle.apply(*s.geometry(), psi, D, z))
+    rhs = np.sum(oracle.apply(*s.geometry(), phi, D, z) * psi)
+    assert abs(lhs - rhs) <= 1e-12 * (abs(lhs) + abs(rhs))
