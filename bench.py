@@ -195,6 +195,29 @@ def ceilings():
     return out
 
 
+def apply_step(bd, wl, plan, s, psi, args):
+    """The whole non-local application on the scale workload: project, the
+    per-atom product with random atomic matrices (FP64 matrix cores), expand;
+    once through the API calls and once as a captured graph."""
+    import torch
+    off = plan.matrix_offsets()
+    D = torch.from_numpy(np.random.default_rng(11).standard_normal(int(off[-1]))).cuda()
+    c = torch.empty(plan.coeff_doubles, dtype=torch.float64, device="cuda")
+    d = torch.empty_like(c)
+    out = torch.zeros_like(psi)
+    ms, _ = _time_steps(lambda: plan.apply(psi, D, out, c, d), args.steps, args.warmup)
+    g = plan.apply_graph(psi, D, c, d, out)
+    ms_graph, _ = _time_steps(g.launch, args.steps, args.warmup)
+    g.close()
+    # the product alone
+    ms_mul, _ = _time_steps(lambda: plan.multiply(D, c, d), args.steps, args.warmup)
+    nsho = (s.numax + 1) * (s.numax + 2) * (s.numax + 3) // 6
+    flops = float(np.sum(2.0 * nsho.astype(np.float64) ** 2 * s.nbands))
+    return {"ms_per_step": ms, "graph_ms_per_step": ms_graph, "multiply_ms": ms_mul,
+            "multiply_TFLOP/s": flops / (ms_mul * 1e-3) / 1e12,
+            "value": plan.support_points * s.nbands / (ms * 1e-3)}
+
+
 def diff_step(bd, wl, args):
     """Differentiation workload (isolated 96^3, 256 atoms, nu 6, 16 bands):
     forward projection and the backward pair (expansion of h^3 dL/dc for
@@ -451,6 +474,8 @@ def main():
         "step_ms_p10_p50_p90": [float(np.percentile(per_step, q)) for q in (10, 50, 90)],
     }
     _log("scale workload: %.3f ms per step" % ms_per_step)
+    rec["apply"] = apply_step(bd, wl, plan, s, psi, args)
+    _log("non-local application: %.3f ms per step" % rec["apply"]["ms_per_step"])
     if not args.no_stored:
         rec["stored_baseline"] = stored_baseline(bd, s, psi, c, out, args)
     if not args.no_stored:
