@@ -79,6 +79,7 @@ struct sho_plan_s {
   int64_t sched_version = 0;      // bumped whenever the work items change
   int64_t sched_bytes = 0;        // device bytes of the schedule tables
   int64_t *d_doff = nullptr;           // per-atom offsets of the atomic matrices
+  int64_t *d_desc_pbase = nullptr;     // stored plans: block descriptors -> P
   sho::BlockRec *d_blocks = nullptr;   // block form of the expansion
   sho::EntryRec *d_entries = nullptr;
   uint32_t *d_run_desc = nullptr;
@@ -125,6 +126,8 @@ void free_plan_device(sho_plan_s *p) {
   p->d_u2 = nullptr;
   if (p->d_doff) (void)hipFree(p->d_doff);
   p->d_doff = nullptr;
+  if (p->d_desc_pbase) (void)hipFree(p->d_desc_pbase);
+  p->d_desc_pbase = nullptr;
   for (void *q : {(void *)p->d_stored, (void *)p->d_run_poff, (void *)p->d_atom_poff,
                   (void *)p->d_atom_pbeg, (void *)p->d_pidx, (void *)p->d_sitems})
     if (q) (void)hipFree(q);
@@ -172,6 +175,10 @@ hipError_t upload_schedule(sho_plan_s *p) {
 
 // (Re)uploads the block tables of the expansion.
 hipError_t upload_blocks(sho_plan_s *p) {
+  const bool stored = (p->hp.flags & SHO_FLAG_STORED) && !p->hp.run_poff.empty();
+  if (stored) sho::build_desc_pbase(&p->hp);
+  if (p->d_desc_pbase) (void)hipFree(p->d_desc_pbase);
+  p->d_desc_pbase = nullptr;
   for (void **q : {(void **)&p->d_blocks, (void **)&p->d_entries, (void **)&p->d_run_desc}) {
     if (*q) (void)hipFree(*q);
     *q = nullptr;
@@ -182,6 +189,8 @@ hipError_t upload_blocks(sho_plan_s *p) {
   if ((e = upload(&p->d_blocks, p->hp.blocks, &bytes)) != hipSuccess ||
       (e = upload(&p->d_entries, p->hp.entries, &bytes)) != hipSuccess ||
       (e = upload(&p->d_run_desc, p->hp.run_desc, &bytes)) != hipSuccess)
+    return e;
+  if (stored && (e = upload(&p->d_desc_pbase, p->hp.desc_pbase, &bytes)) != hipSuccess)
     return e;
   return hipSuccess;
 }
@@ -258,7 +267,10 @@ sho::EArgs make_eargs(const sho_plan_s *p) {
   E.natoms_u2 = (int32_t)p->hp.nu_atoms.size();
   E.nx = p->hp.grid.n[0];
   E.B = p->hp.nbands;
-  E.tbe_shift = sho::expand_tile_shift(p->hp.nbands, p->hp.expand_mode);
+  E.tbe_shift = sho::expand_tile_shift(p->hp.nbands, p->hp.expand_mode,
+                                       (p->hp.flags & SHO_FLAG_STORED) != 0);
+  E.desc_pbase = p->d_desc_pbase;
+  E.P = p->d_stored;
   E.ntiles = (p->hp.nbands + (1 << E.tbe_shift) - 1) >> E.tbe_shift;
   E.ntiles_u2 = (p->hp.nbands + 31) / 32;
   E.nu_max = p->hp.nu_max;
@@ -431,6 +443,11 @@ hipError_t run_project(sho_plan_s *p, const double *psi, double *c, hipStream_t 
 hipError_t run_expand(sho_plan_s *p, const double *c, double *psi, hipStream_t s,
                       bool prof) {
   if (p->hp.flags & SHO_FLAG_STORED) {
+    if (p->hp.expand_mode == sho::kExpandBlocks) {
+      sho::EArgs E = make_eargs(p);
+      return timed(p, prof, SHO_KERNEL_EXPAND_XY, s,
+                   [&]() { return sho::launch_blocks_stored(E, c, psi, s); });
+    }
     return timed(p, prof, SHO_KERNEL_EXPAND_XY, s, [&]() {
       for (const Group &g : p->sgroups) {
         hipError_t e1 = sho::launch_expand_stored(g.nu, make_sargs(p, g), c, psi, s);
@@ -545,6 +562,7 @@ sho_status sho_plan_create(const sho_grid *grid, int32_t natoms,
   if (e == hipSuccess && (flags & SHO_FLAG_STORED)) {
     sho::HostPlan &hp = p->hp;
     sho::build_stored(&hp, sho::kStoredChunk);
+    e = upload_blocks(p);
     for (size_t i = 0; i < hp.sitems.size();) {
       const int32_t nu = hp.atoms[hp.sitems[i].atom].nu;
       Group g{nu, (int32_t)i, 0};
@@ -555,7 +573,8 @@ sho_status sho_plan_create(const sho_grid *grid, int32_t natoms,
       p->sgroups.push_back(g);
     }
     const int64_t sb = std::max<int64_t>(hp.stored_doubles, 1) * sizeof(double);
-    if ((e = upload(&p->d_run_poff, hp.run_poff, &p->device_bytes)) == hipSuccess &&
+    if (e == hipSuccess &&
+        (e = upload(&p->d_run_poff, hp.run_poff, &p->device_bytes)) == hipSuccess &&
         (e = upload(&p->d_atom_poff, hp.atom_poff, &p->device_bytes)) == hipSuccess &&
         (e = upload(&p->d_atom_pbeg, hp.atom_pbeg, &p->device_bytes)) == hipSuccess &&
         (e = upload(&p->d_pidx, hp.pidx, &p->device_bytes)) == hipSuccess &&

@@ -120,7 +120,8 @@ static_assert(sizeof(BlockRec) == 24, "BlockRec layout");
 // table rows of the block's x range and rows start, which of them exist, and
 // its runs as packed (row, x begin, x end) descriptors.
 struct EntryRec {
-  int64_t u2;          // first double of the atom plane's partials (band 0)
+  int64_t u2;          // first double of the atom plane's partials (band 0);
+                       // stored plans: the atom's first coefficient row
   int32_t tab_x;       // table double of memory x = x0:  tab_off + (x0 + jshift) nfp
   int32_t tab_y;       // table double of block row 0:   tab_off + (mx + y0 + yshift) nfp
   int16_t nu, nfp;
@@ -194,6 +195,8 @@ struct HostPlan {
   std::vector<BlockRec> blocks;         // XCD-interleaved by plane
   std::vector<EntryRec> entries;
   std::vector<uint32_t> run_desc;
+  std::vector<int32_t> run_desc_run;    // the run of every descriptor
+  std::vector<int64_t> desc_pbase;      // stored plans: P double of block x 0
   std::vector<int64_t> run_poff;      // stored projectors: first double of
                                       // each run's [len][N_SHO] block
   std::vector<int64_t> atom_poff;     // [natoms+1] first double of each atom
@@ -268,7 +271,8 @@ void build_blocks(HostPlan *P, int32_t R, int32_t X);
 // log2 of the bands per lane slot of the expansion's y/x passes: the row form
 // takes 32 or 64; the block form also 8 or 16, so that few bands still fill
 // the wave with run slots.
-inline int expand_tile_shift(int nbands, int mode) {
+inline int expand_tile_shift(int nbands, int mode, bool stored = false) {
+  if (stored) return nbands > 16 ? 5 : 4;  // 16-band matrix-core blocks, <= 2
   if (nbands > 32) return 6;
   if (mode == kExpandRows || nbands > 16) return 5;
   return nbands > 8 ? 4 : 3;
@@ -277,7 +281,8 @@ inline int expand_tile_shift(int nbands, int mode) {
 // Whether an R x X block fits: the LDS tile (R X bands-per-tile doubles) and
 // the x-table staging of one wave (X rows of the widest table).
 inline bool block_shape_ok(const HostPlan &P, int32_t R, int32_t X) {
-  const int tbe = 1 << expand_tile_shift(P.nbands, kExpandBlocks);
+  const int tbe = 1 << expand_tile_shift(P.nbands, kExpandBlocks,
+                                         (P.flags & SHO_FLAG_STORED) != 0);
   return R >= 1 && X >= 1 && (int64_t)R * X * tbe <= kBlockTileDoubles &&
          X * table_nfp(P.nu_max) <= 256 && R * table_nfp(P.nu_max) <= 256;
 }
@@ -286,7 +291,8 @@ inline bool block_shape_ok(const HostPlan &P, int32_t R, int32_t X) {
 // 16 for 64-band tiles), then as many rows as the tile holds and the y
 // staging allows.
 inline void default_block_shape(const HostPlan &P, int32_t *R, int32_t *X) {
-  const int tbe = 1 << expand_tile_shift(P.nbands, kExpandBlocks);
+  const int tbe = 1 << expand_tile_shift(P.nbands, kExpandBlocks,
+                                         (P.flags & SHO_FLAG_STORED) != 0);
   const int nfp = table_nfp(P.nu_max);
   *X = std::min(256 / nfp, tbe == 64 ? 16 : 32);
   *R = std::min(kBlockTileDoubles / (*X * tbe), 256 / nfp);
@@ -296,6 +302,10 @@ inline void default_block_shape(const HostPlan &P, int32_t *R, int32_t *X) {
 // of every atom in run order, each with its N_SHO values; chunks of at most
 // `chunk` points per work item.
 void build_stored(HostPlan *P, int32_t chunk);
+
+// Stored plans: for every block run descriptor, the stored-table double of
+// its row at block-local x = 0 (needs build_blocks and build_stored).
+void build_desc_pbase(HostPlan *P);
 
 // Points per stored-projector work item.
 constexpr int32_t kStoredChunk = 1024;

@@ -951,10 +951,11 @@ __global__ __launch_bounds__(kStoredBlock) void k_expand_stored(
   const double *P = S.P + S.atom_poff[a];
   const int32_t *pidx = S.pidx + S.atom_pbeg[a];
   const int64_t row0 = S.atoms[a].coeff_row;
+  // sum over n in the order n = q NK + m: contiguous P reads per lane
   double cA[NK], cB[NK];
 #pragma unroll
   for (int m = 0; m < NK; ++m) {
-    const int n = 4 * m + q;
+    const int n = q * NK + m;
     cA[m] = (n < NS && okA) ? c[(row0 + n) * S.B + bA] : 0.0;
     cB[m] = (n < NS && okB) ? c[(row0 + n) * S.B + bB] : 0.0;
   }
@@ -965,7 +966,7 @@ __global__ __launch_bounds__(kStoredBlock) void k_expand_stored(
     double av[NK];
 #pragma unroll
     for (int m = 0; m < NK; ++m) {
-      const int n = 4 * m + q;
+      const int n = q * NK + m;
       av[m] = (ok && n < NS) ? prow[n] : 0.0;
     }
     int32_t mi[4];
@@ -986,6 +987,125 @@ __global__ __launch_bounds__(kStoredBlock) void k_expand_stored(
       double *dst = psi + (int64_t)mi[r] * S.B;
       if (okA) unsafeAtomicAdd(dst + bA, dA[r]);
       if (okB) unsafeAtomicAdd(dst + bB, dB[r]);
+    }
+  }
+}
+
+// ------------------------------------------ stored, block form expansion --
+
+// Adds the runs of one entry from the stored tables: for 16 points of a run
+// at a time, D[point][band] = sum_n P[point][n] c[n][band] on FP64 MFMA
+// (i = point, j = band, four n per step; the atom's coefficients of this
+// lane's bands stay in registers), then LDS atomic adds into the block tile.
+template <int NU>
+__device__ inline void add_entry_stored(const EArgs &E, const EntryRec &en,
+                                        const double *__restrict__ c, int nxl, double *tile,
+                                        int TB, int btile) {
+  constexpr int NS = (NU + 1) * (NU + 2) * (NU + 3) / 6;
+  constexpr int NK = (NS + 3) / 4;
+  const int lane = threadIdx.x & 63;
+  const int q = lane >> 4, col = lane & 15;
+  const int64_t row0 = en.u2;
+  const int bA = btile * TB + col, bB = bA + 16;
+  const bool okA = bA < E.B, okB = TB > 16 && bB < E.B;
+  // the sum over n runs in the order n = q NK + m (lane quarter q, step m),
+  // so that each lane reads one contiguous stretch of its point's P row
+  double cA[NK], cB[NK];
+#pragma unroll
+  for (int m = 0; m < NK; ++m) {
+    const int n = q * NK + m;
+    cA[m] = (n < NS && okA) ? c[(row0 + n) * E.B + bA] : 0.0;
+    cB[m] = (n < NS && okB) ? c[(row0 + n) * E.B + bB] : 0.0;
+  }
+  const uint32_t mydesc = lane < en.nruns ? as_const(E.run_desc)[en.run_begin + lane] : 0u;
+  const int64_t mybase = lane < en.nruns ? E.desc_pbase[en.run_begin + lane] : 0;
+  for (int i = 0; i < en.nruns; ++i) {
+    const uint32_t d = __builtin_amdgcn_readlane(mydesc, i);
+    const int r = d & 0xff, xa = (d >> 8) & 0xff, xb = (d >> 16) & 0xff;
+    const int64_t pb = ((int64_t)__builtin_amdgcn_readlane((int)(mybase >> 32), i) << 32) |
+                       (uint32_t)__builtin_amdgcn_readlane((int)(mybase & 0xffffffff), i);
+    double *trow = tile + (int64_t)r * nxl * TB;
+    for (int p0 = xa; p0 < xb; p0 += 16) {
+      const int pt = p0 + col;  // A row of this lane
+      const bool ok = pt < xb;
+      const double *prow = E.P + pb + (int64_t)(ok ? pt : xb - 1) * NS;
+      dx4 dA = {0.0, 0.0, 0.0, 0.0}, dB = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int m = 0; m < NK; ++m) {
+        const int n = q * NK + m;
+        const double av = (ok && n < NS) ? prow[n] : 0.0;
+        dA = mfma_f64(av, cA[m], dA);
+        dB = mfma_f64(av, cB[m], dB);
+      }
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int x = p0 + 4 * rr + q;
+        if (x < xb) {
+          atomicAdd(&trow[x * TB + col], dA[rr]);
+          if (TB > 16) atomicAdd(&trow[x * TB + 16 + col], dB[rr]);
+        }
+      }
+    }
+  }
+}
+
+template <int NUMAX>
+__global__ __launch_bounds__(kBlkBlock) void k_expand_blocks_stored(
+    EArgs E, const double *__restrict__ c, double *psi) {
+  extern __shared__ double lds[];
+  const BlockRec bk = load_uniform(E.blocks + blockIdx.x);
+  if (bk.nentries < 0) return;
+  const int w = wave_id();
+  double *tile = lds;
+  const int TB = 1 << E.tbe_shift;
+  const int btile = blockIdx.y;
+  const int xe = min(bk.x0 + E.blk_x, E.nx);
+  const int nxl = xe - bk.x0;
+  const int nrow = min(bk.y0 + E.blk_rows, E.ny) - bk.y0;
+  const int rowbase = bk.z * E.ny + bk.y0;
+  const int per_row = nxl << E.tbe_shift;
+  const int nval = nrow * per_row;
+  auto gidx = [&](int t, int &b) -> int64_t {
+    const int r = t / per_row;
+    const int rem = t - r * per_row;
+    const int x = rem >> E.tbe_shift;
+    b = btile * TB + (rem & (TB - 1));
+    return ((int64_t)(rowbase + r) * E.nx + bk.x0 + x) * E.B + b;
+  };
+  fill_lds<kBlockTileDoubles / kBlkBlock>(tile, nval, [&](int t) {
+    int bb;
+    const int64_t g = gidx(t, bb);
+    return bb < E.B ? psi[g] : 0.0;
+  });
+  __syncthreads();
+  for (int i = w; i < bk.nentries; i += kBlkWaves) {
+    const EntryRec en = load_uniform(E.entries + bk.entry_begin + i);
+    switch (en.nu) {
+#define X(N)                                                                  \
+  case N:                                                                     \
+    if constexpr (N <= NUMAX) add_entry_stored<N>(E, en, c, nxl, tile, TB, btile); \
+    break;
+      X(0) X(1) X(2) X(3) X(4) X(5)
+#undef X
+    }
+  }
+  __syncthreads();
+  constexpr int kPer = kBlockTileDoubles / kBlkBlock;
+  for (int t0 = 0; t0 < nval; t0 += kPer * kBlkBlock) {
+    double v[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int t = t0 + u * kBlkBlock + (int)threadIdx.x;
+      v[u] = t < nval ? tile[t] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int t = t0 + u * kBlkBlock + (int)threadIdx.x;
+      if (t < nval) {
+        int bb;
+        const int64_t g = gidx(t, bb);
+        if (bb < E.B) psi[g] = v[u];
+      }
     }
   }
 }
@@ -1272,6 +1392,25 @@ hipError_t launch_blocks(const EArgs &E, const double *u2, double *psi,
     hipLaunchKernelGGL((k_expand_blocks<N>), g, dim3(kBlkBlock), shm, s, E, u2, psi); \
     break;
       SHO_NU_CASES(X)
+#undef X
+      default:
+        return hipErrorInvalidValue;
+    }
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_blocks_stored(const EArgs &E, const double *c, double *psi,
+                                hipStream_t s) {
+  if (E.nblocks > 0) {
+    const dim3 g((unsigned)E.nblocks, (unsigned)E.ntiles);
+    const size_t shm = kBlockTileDoubles * sizeof(double);
+    switch (E.nu_max) {
+#define X(N)                                                                        \
+  case N:                                                                           \
+    hipLaunchKernelGGL((k_expand_blocks_stored<N>), g, dim3(kBlkBlock), shm, s, E, c, psi); \
+    break;
+      X(0) X(1) X(2) X(3) X(4) X(5)
 #undef X
       default:
         return hipErrorInvalidValue;

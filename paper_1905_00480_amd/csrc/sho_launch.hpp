@@ -55,6 +55,8 @@ struct EArgs {
   const BlockRec *blocks;
   const EntryRec *entries;
   const uint32_t *run_desc;
+  const int64_t *desc_pbase;  // stored plans: per descriptor, P double of x = 0
+  const double *P;            // stored plans: the projector tables
   int32_t nblocks;
   int32_t blk_rows;     // R
   int32_t blk_x;        // X
@@ -97,6 +99,10 @@ hipError_t launch_rows(const EArgs &E, const double *u2, double *psi,
 // Block form of the second half (blocks of R rows x X points).
 hipError_t launch_blocks(const EArgs &E, const double *u2, double *psi,
                          hipStream_t s);
+// Stored plans: the whole expansion in the block form, P_an read from the
+// tables (per-block products on FP64 matrix cores); nu_max <= 5.
+hipError_t launch_blocks_stored(const EArgs &E, const double *c, double *psi,
+                                hipStream_t s);
 // Stored-projector baseline: sample P_an at every support point, then
 // project / expand by reading them back (nu <= 5).
 hipError_t launch_store(const KArgs &K, const int32_t *run_atom, int32_t nruns,

@@ -556,6 +556,7 @@ void build_blocks(HostPlan *P, int32_t R, int32_t X) {
   });
   P->entries.clear();
   P->run_desc.clear();
+  P->run_desc_run.clear();
   std::vector<std::vector<BlockRec>> cls(8);
   for (size_t i = 0; i < items.size();) {
     const int64_t blk = items[i].block;
@@ -593,6 +594,7 @@ void build_blocks(HostPlan *P, int32_t R, int32_t X) {
         const int32_t xa = std::max((int32_t)L.x0m, B.x0) - B.x0;
         const int32_t xb = std::min((int32_t)L.x0m + L.len, B.x0 + X) - B.x0;
         P->run_desc.push_back(pack_run(L.row % ny - B.y0, xa, xb));
+        P->run_desc_run.push_back(items[i].run);
         E.nruns++;
         ++i;
       }
@@ -621,6 +623,22 @@ void build_blocks(HostPlan *P, int32_t R, int32_t X) {
   for (const BlockRec &B : P->blocks)
     if (B.nentries >= 0)
       P->block_points += (int64_t)(std::min(B.y0 + R, ny) - B.y0) * (std::min(B.x0 + X, nx) - B.x0);
+}
+
+void build_desc_pbase(HostPlan *P) {
+  P->desc_pbase.assign(P->run_desc.size(), 0);
+  for (const BlockRec &B : P->blocks) {
+    if (B.nentries < 0) continue;
+    for (int32_t e = B.entry_begin; e < B.entry_begin + B.nentries; ++e) {
+      EntryRec &E = P->entries[e];
+      const int64_t ns = nsho(E.nu);
+      E.u2 = P->atoms[P->run_atom[P->run_desc_run[E.run_begin]]].coeff_row;
+      for (int32_t k = E.run_begin; k < E.run_begin + E.nruns; ++k) {
+        const LineRec &L = P->lines[P->run_desc_run[k]];
+        P->desc_pbase[k] = P->run_poff[P->run_desc_run[k]] + (int64_t)(B.x0 - L.x0m) * ns;
+      }
+    }
+  }
 }
 
 }  // namespace sho

@@ -59,10 +59,13 @@ def test_stored_matches_oracle(which):
     d_psi = _dev(psi)
     c_ref, c_abs = oracle.project(*s.geometry(), psi, with_abs=True)
     _check(_host(plan.project(d_psi)), c_ref, c_abs, which + " stored project")
-    d_acc = d_psi.clone()
-    plan.expand(_dev(c_in), d_acc)
     e_ref, e_abs = oracle.expand(*s.geometry(), c_in, psi, with_abs=True)
-    _check(_host(d_acc), e_ref, e_abs, which + " stored expand")
+    # block form (default) and the atom-owner form with global atomics
+    for form in (1, 0):
+        plan.set_expand(form)
+        d_acc = d_psi.clone()
+        plan.expand(_dev(c_in), d_acc)
+        _check(_host(d_acc), e_ref, e_abs, which + " stored expand, form %d" % form)
     # the derivative is generated on the fly also for stored plans
     g_ref, g_abs = oracle.force(*s.geometry(), psi, c_in, with_abs=True)
     _check(_host(plan.force(d_psi, _dev(c_in))), g_ref, g_abs, which + " stored force")
