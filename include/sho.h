@@ -277,7 +277,9 @@ sho_status sho_plan_get_schedule(sho_plan_t plan, int32_t *schedule,
  *              one plane; the partial sums of an atom plane are loaded once
  *              for all its runs in the block (default).
  * Both read and write every touched value of psi once with plain loads and
- * stores.  block_rows = block_x = 0 picks the default shape; a shape whose
+ * stores.  For SHO_FLAG_STORED plans the forms are: 0 the atom-owner form
+ * (global atomics, default for nu_max > 2), 1 the block form with the
+ * products on matrix cores (default for nu_max <= 2).  block_rows = block_x = 0 picks the default shape; a shape whose
  * tile (rows x points x bands per tile: 8, 16, 32 or 64, the power of two
  * that covers nbands, at most 64) exceeds 4096 doubles, or whose rows or
  * points exceed 256 / (table row length: 8 doubles for nu_max <= 6, else

@@ -350,6 +350,9 @@ void build_default_blocks(sho::HostPlan *hp) {
   int32_t R = 0, X = 0;
   sho::default_block_shape(*hp, &R, &X);
   sho::build_blocks(hp, R, X);
+  // stored plans: the block form wins while the products are short (measured
+  // up to nu_max = 2), the atom-owner form with atomics beyond
+  if ((hp->flags & SHO_FLAG_STORED) && hp->nu_max > 2) hp->expand_mode = sho::kExpandRows;
 }
 
 // Plans with several cut-offs run the projection as one launch.
