@@ -58,6 +58,8 @@ def parse():
                     help="skip the paper-geometry table (SHO vs stored, nu_max 0..5)")
     ap.add_argument("--no-diff", action="store_true",
                     help="skip the differentiation (forward + backward) workload")
+    ap.add_argument("--no-fp32", action="store_true",
+                    help="skip the single-precision scale step")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the plan's default schedule (no autotuning)")
     ap.add_argument("--serve-requests", type=int, default=2000)
@@ -229,6 +231,43 @@ def apply_step(bd, wl, plan, s, psi, args):
     return {"ms_per_step": ms, "graph_ms_per_step": ms_graph, "multiply_ms": ms_mul,
             "multiply_TFLOP/s": flops / (ms_mul * 1e-3) / 1e12,
             "value": plan.support_points * s.nbands / (ms * 1e-3)}
+
+
+def fp32_step(bd, wl, args, ms_fp64):
+    """The scale workload with single-precision bands (SHO_FLAG_FP32, the
+    paper's float kernels): the same 32 bands, tuned, step = projection +
+    expansion; per-kernel times and the expansion's achieved bandwidth."""
+    import torch
+    s = wl.scale()
+    psi = torch.from_numpy(wl.psi_for(s, dtype=np.float32)).cuda()
+    plan = bd.Plan.from_system(s, flags=bd.FLAG_FP32)
+    c = torch.empty(plan.coeff_doubles, dtype=torch.float32, device="cuda")
+    out = torch.zeros_like(psi)
+    tune = None if args.no_tune else plan.tune(psi, c, reps=3)
+
+    def step():
+        plan.project(psi, c)
+        plan.expand(c, out)
+
+    ms, _ = _time_steps(step, args.steps, args.warmup)
+    plan.profile(True)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    prof = plan.profile_read()
+    plan.profile(False)
+    info = plan.info
+    B = s.nbands
+    xy_bytes = 2 * info["union_points"] * B * 4 + info["expand_scratch_doubles"] * 8
+    xy_ms = prof["expand_xy"][1]
+    units = plan.support_points * B
+    plan.close()
+    return {"workload": "scale: periodic 128^3, h=0.2 Bohr, 512 atoms, sigma=0.6, nu_max=5, "
+                        "32 FP32 bands; step = projection + expansion",
+            "dtype": "f32", "ms_per_step": ms, "gridpoint*bands/s": units / (ms * 1e-3),
+            "speedup_vs_fp64": ms_fp64 / ms, "tune": tune,
+            "kernel_ms": {k: round(v[1], 4) for k, v in prof.items() if v[0]},
+            "expand_xy_GB/s": xy_bytes / (xy_ms * 1e-3) / 1e9 if xy_ms > 0 else None}
 
 
 def diff_step(bd, wl, args):
@@ -491,6 +530,9 @@ def main():
     _log("scale workload: %.3f ms per step" % ms_per_step)
     rec["apply"] = apply_step(bd, wl, plan, s, psi, args)
     _log("non-local application: %.3f ms per step" % rec["apply"]["ms_per_step"])
+    if not args.no_fp32:
+        rec["fp32"] = fp32_step(bd, wl, args, ms_per_step)
+        _log("fp32 scale step: %.3f ms" % rec["fp32"]["ms_per_step"])
     if not args.no_stored:
         rec["stored_baseline"] = stored_baseline(bd, s, psi, c, out, args)
     if not args.no_stored:

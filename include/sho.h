@@ -99,6 +99,18 @@ typedef int32_t sho_status;
                                              expansion (global atomics); the
                                              batched schedules are measured
                                              against it */
+#define SHO_FLAG_FP32 0x10u               /* single-precision bands (the
+                                             paper's float kernels, sec. 6):
+                                             psi and c hold floats and go
+                                             through sho_plan_project_f32 /
+                                             sho_plan_expand_f32; nbands must
+                                             be even (adjacent bands are
+                                             processed in pairs); not with
+                                             SHO_FLAG_STORED or
+                                             SHO_FLAG_PER_ATOM.  The FP64
+                                             entry points, the derivative, the
+                                             atomic-matrix product and graphs
+                                             refuse such a plan. */
 
 /* Projection launch schedules (sho_plan_set_schedule, sho_plan_tune) */
 #define SHO_SCHED_BY_NU 0      /* one launch per cut-off nu */
@@ -123,7 +135,8 @@ typedef struct sho_plan_info {
   int32_t nu_max;          /* largest nu_a in the plan */
   int32_t flags;
   int64_t coeff_rows;      /* sum_a N_SHO(nu_a) */
-  int64_t coeff_doubles;   /* coeff_rows * nbands: length of c and w */
+  int64_t coeff_doubles;   /* coeff_rows * nbands: elements of c and w
+                              (floats for SHO_FLAG_FP32 plans) */
   int64_t support_points;  /* sum_a |S_a| */
   int64_t lines;           /* (z, y) lines over all supports */
   int64_t planes;          /* z planes over all supports */
@@ -167,7 +180,7 @@ sho_status sho_plan_destroy(sho_plan_t plan);
 
 sho_status sho_plan_get_info(sho_plan_t plan, sho_plan_info *info);
 
-/* off[a] = first double of atom a's block in c / w, off[natoms] = total.
+/* off[a] = first element of atom a's block in c / w, off[natoms] = total.
  * off: host array [natoms + 1]. */
 sho_status sho_plan_coeff_offsets(sho_plan_t plan, int64_t *off);
 
@@ -192,6 +205,20 @@ sho_status sho_plan_project(sho_plan_t plan, const double *psi, double *c,
  * add in an unspecified order.  psi and c must not overlap. */
 sho_status sho_plan_expand(sho_plan_t plan, const double *c, double *psi,
                            void *stream);
+
+/*
+ * Single precision (SHO_FLAG_FP32 plans), same layouts with float elements:
+ * c[n][b] (device, coeff_doubles floats) <- projection of psi (device,
+ * grid x nbands floats), and psi += expansion of c.  The 1D functions are
+ * the double-precision samples rounded to float; all sums run in float.
+ * Complex bands (Gamma point or isolated systems) are passed as interleaved
+ * (real, imaginary) pairs, i.e. as 2 x nbands real bands, in either
+ * precision: the SHO functions are real, so both parts transform alike.
+ */
+sho_status sho_plan_project_f32(sho_plan_t plan, const float *psi, float *c,
+                                void *stream);
+sho_status sho_plan_expand_f32(sho_plan_t plan, const float *c, float *psi,
+                               void *stream);
 
 /* grad (device, [natoms][3]) <- sum_{n,b} w dc/dR, support frozen.
  * Overwritten.  w has the layout of c. */
@@ -307,9 +334,11 @@ typedef struct sho_tune_result {
  * SHO_SCHED_XCD) x work item size
  * {8192, 16384, 32768} x band tile {current, half}, reps launches each after
  * one warm-up, on stream, and keeps the fastest.  Synchronous.  result may
- * be NULL.  Refused (SHO_E_INVALID) on stored and per-atom plans.
+ * be NULL.  psi and c hold the plan's element type (double, or float for
+ * SHO_FLAG_FP32 plans).  Refused (SHO_E_INVALID) on stored and per-atom
+ * plans.
  */
-sho_status sho_plan_tune(sho_plan_t plan, const double *psi, double *c,
+sho_status sho_plan_tune(sho_plan_t plan, const void *psi, void *c,
                          int32_t reps, void *stream, sho_tune_result *result);
 
 /*

@@ -9,6 +9,9 @@ Layouts (see include/sho.h):
   c, w  float64 tensor with coeff_doubles entries, per-atom blocks
         [N_SHO(nu_a)][B] in atom order (n: nz outer, ny, nx fastest)
   grad  float64 tensor (natoms, 3)
+Plans made with FLAG_FP32 take float32 psi and c of the same layouts (an even
+number of bands); complex bands are passed as torch.view_as_real views, i.e.
+as interleaved (real, imaginary) pairs of 2 x B real bands.
 """
 import ctypes
 import os
@@ -31,6 +34,7 @@ FLAG_STORED = 0x1
 FLAG_ALLOW_UNDERSAMPLED = 0x2
 FLAG_HOST_ONLY = 0x4
 FLAG_PER_ATOM = 0x8
+FLAG_FP32 = 0x10
 SCHED_BY_NU = 0
 SCHED_SINGLE = 1
 SCHED_SINGLE_LPT = 2
@@ -45,6 +49,7 @@ EXPORTS = (
     "sho_nsho", "sho_last_error", "sho_plan_create", "sho_plan_destroy",
     "sho_plan_get_info", "sho_plan_coeff_offsets", "sho_plan_support_counts",
     "sho_plan_set_centres", "sho_plan_project", "sho_plan_expand",
+    "sho_plan_project_f32", "sho_plan_expand_f32",
     "sho_plan_force", "sho_project", "sho_expand", "sho_force",
     "sho_cache_clear", "sho_plan_profile", "sho_plan_profile_read",
     "sho_plan_set_schedule", "sho_plan_get_schedule", "sho_plan_tune",
@@ -134,6 +139,8 @@ def load_library(path=None):
     lib.sho_plan_set_centres.argtypes = [P, _dp, _vp]
     lib.sho_plan_project.argtypes = [P, _vp, _vp, _vp]
     lib.sho_plan_expand.argtypes = [P, _vp, _vp, _vp]
+    lib.sho_plan_project_f32.argtypes = [P, _vp, _vp, _vp]
+    lib.sho_plan_expand_f32.argtypes = [P, _vp, _vp, _vp]
     lib.sho_plan_force.argtypes = [P, _vp, _vp, _vp, _vp]
     geo = [G, ctypes.c_int32, _dp, _dp, _i32p, ctypes.c_int32]
     lib.sho_project.argtypes = geo + [_vp, _vp, ctypes.c_uint32, _vp]
@@ -207,12 +214,13 @@ def _stream(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-def _dev(t, numel, name):
+def _dev(t, numel, name, f32=False):
     import torch
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
         raise TypeError("%s must be a GPU tensor" % name)
-    if t.dtype != torch.float64:
-        raise TypeError("%s must be float64" % name)
+    want = torch.float32 if f32 else torch.float64
+    if t.dtype != want:
+        raise TypeError("%s must be %s" % (name, str(want).split(".")[-1]))
     if not t.is_contiguous():
         raise ValueError("%s must be contiguous" % name)
     if t.numel() != numel:
@@ -246,6 +254,7 @@ class Plan:
             None if self._rbox is None else self._rbox.ctypes.data_as(_dp),
             self.nbands, int(flags), ctypes.byref(handle)))
         self._h = handle
+        self.fp32 = bool(int(flags) & FLAG_FP32)
         info = sho_plan_info()
         _check(lib.sho_plan_get_info(self._h, ctypes.byref(info)))
         self.info = {k: getattr(info, k) for k, _ in sho_plan_info._fields_}
@@ -278,17 +287,20 @@ class Plan:
 
     def project(self, psi, c=None, stream=None):
         import torch
+        f32 = self.fp32
         if c is None:
-            c = torch.empty(self.coeff_doubles, dtype=torch.float64, device=psi.device)
-        _check(self._lib.sho_plan_project(
-            self._h, _dev(psi, self.psi_numel, "psi"),
-            _dev(c, self.coeff_doubles, "c"), _stream(stream)))
+            c = torch.empty(self.coeff_doubles,
+                            dtype=torch.float32 if f32 else torch.float64, device=psi.device)
+        fn = self._lib.sho_plan_project_f32 if f32 else self._lib.sho_plan_project
+        _check(fn(self._h, _dev(psi, self.psi_numel, "psi", f32),
+                  _dev(c, self.coeff_doubles, "c", f32), _stream(stream)))
         return c
 
     def expand(self, c, psi, stream=None):
-        _check(self._lib.sho_plan_expand(
-            self._h, _dev(c, self.coeff_doubles, "c"),
-            _dev(psi, self.psi_numel, "psi"), _stream(stream)))
+        f32 = self.fp32
+        fn = self._lib.sho_plan_expand_f32 if f32 else self._lib.sho_plan_expand
+        _check(fn(self._h, _dev(c, self.coeff_doubles, "c", f32),
+                  _dev(psi, self.psi_numel, "psi", f32), _stream(stream)))
         return psi
 
     def force(self, psi, w, grad=None, stream=None):
@@ -363,7 +375,8 @@ class Plan:
         """Time the projection schedules on psi -> c and keep the fastest."""
         r = sho_tune_result()
         _check(self._lib.sho_plan_tune(
-            self._h, _dev(psi, self.psi_numel, "psi"), _dev(c, self.coeff_doubles, "c"),
+            self._h, _dev(psi, self.psi_numel, "psi", self.fp32),
+            _dev(c, self.coeff_doubles, "c", self.fp32),
             int(reps), _stream(stream), ctypes.byref(r)))
         return {k: getattr(r, k) for k, _ in sho_tune_result._fields_ if k != "pad"}
 

@@ -6,6 +6,7 @@ Objects:
   sho_api.cpp      C ABI layer (host HIP runtime calls)
   sho_server.cpp   request server: admission under a byte budget, streams
   sho_kernels.hip  gfx950 kernels
+  sho_kernels_f32.hip  single-precision projection and expansion kernels
 """
 import os
 import shutil
@@ -45,7 +46,7 @@ def build(verbose: bool = False, jobs: int = 3) -> str:
     cmd = ["g++"] + HOST_FLAGS + ["-c", os.path.join(CSRC, "sho_plan.cpp"), "-o", plan_o]
     procs.append((cmd, subprocess.Popen(cmd)))
     objs.append(plan_o)
-    for src in ("sho_api.cpp", "sho_server.cpp", "sho_kernels.hip"):
+    for src in ("sho_api.cpp", "sho_server.cpp", "sho_kernels.hip", "sho_kernels_f32.hip"):
         o = os.path.join(BUILD, src.rsplit(".", 1)[0] + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
         cmd = [HIPCC] + HIP_FLAGS + lang + ["-c", os.path.join(CSRC, src), "-o", o]

@@ -62,6 +62,8 @@ struct sho_plan_s {
   sho::BundleRec *d_bundles = nullptr;
   sho::WorkRec *d_work = nullptr;
   double *d_tab = nullptr;
+  bool fp32 = false;          // SHO_FLAG_FP32: hp.nbands counts band pairs
+  float *d_tab32 = nullptr;   // FP32 plans: the tables rounded to float
   int32_t *d_run_atom = nullptr;
   int32_t *d_row_runs = nullptr;
   sho::RowRec *d_rows = nullptr;
@@ -115,6 +117,8 @@ void free_plan_device(sho_plan_s *p) {
     *q = nullptr;
   }
   if (p->d_tab) (void)hipFree(p->d_tab);
+  if (p->d_tab32) (void)hipFree(p->d_tab32);
+  p->d_tab32 = nullptr;
   for (void *q : {(void *)p->d_run_atom, (void *)p->d_row_runs, (void *)p->d_rows,
                   (void *)p->d_u2_off, (void *)p->d_nu_atoms, (void *)p->d_u2})
     if (q) (void)hipFree(q);
@@ -374,10 +378,15 @@ Group atom_group(const sho_plan_s *p, int32_t a) {
   return Group{p->hp.atoms[a].nu, b, n};
 }
 
-sho_status check_project(const sho_plan_s *p, const double *psi, const double *c) {
+// Precision of an entry point: 0 double, 1 float, -1 either (the plan's).
+sho_status check_project(const sho_plan_s *p, const void *psi, const void *c,
+                         int want_f32 = 0) {
   if (!p) return fail(SHO_E_INVALID, "NULL plan");
   if (p->hp.flags & SHO_FLAG_HOST_ONLY)
     return fail(SHO_E_INVALID, "host-only plan cannot run kernels");
+  if (want_f32 >= 0 && (want_f32 != 0) != p->fp32)
+    return fail(SHO_E_INVALID, p->fp32 ? "plan holds FP32 bands: use the _f32 entry points"
+                                       : "plan holds FP64 bands: use the FP64 entry points");
   if (p->hp.coeff_rows == 0) return SHO_OK;
   if (!device_range_ok(psi, psi_bytes(p)) || !device_range_ok(c, coeff_bytes(p)))
     return fail(SHO_E_INVALID, "psi and c must be device buffers of the plan's sizes");
@@ -403,8 +412,10 @@ sho_status ensure_u2(sho_plan_s *p) {
 }
 
 // The projection's launches on s (arguments already checked).
-hipError_t run_project(sho_plan_s *p, const double *psi, double *c, hipStream_t s,
+hipError_t run_project(sho_plan_s *p, const void *psi_v, void *c_v, hipStream_t s,
                        bool prof) {
+  const double *psi = static_cast<const double *>(psi_v);
+  double *c = static_cast<double *>(c_v);
   // atoms whose support missed the grid entirely keep zero coefficients;
   // atoms shared by several work items (and every stored point chunk) are
   // summed into zeroed coefficients
@@ -434,8 +445,16 @@ hipError_t run_project(sho_plan_s *p, const double *psi, double *c, hipStream_t 
     for (const sho::ProjGroup &pg : p->hp.proj_groups) {
       sho::KArgs K = make_args(p, Group{pg.nu, 0, pg.count});
       K.work = p->d_work_proj + pg.begin;
-      hipError_t e1 = pg.nu < 0 ? sho::launch_project_any(p->hp.nu_max, K, psi, c, s)
-                                : sho::launch_project(pg.nu, K, psi, c, s);
+      hipError_t e1;
+      if (p->fp32) {
+        const float *pf = static_cast<const float *>(psi_v);
+        float *cf = static_cast<float *>(c_v);
+        e1 = pg.nu < 0 ? sho::launch_project_any_f32(p->hp.nu_max, K, p->d_tab32, pf, cf, s)
+                       : sho::launch_project_f32(pg.nu, K, p->d_tab32, pf, cf, s);
+      } else {
+        e1 = pg.nu < 0 ? sho::launch_project_any(p->hp.nu_max, K, psi, c, s)
+                       : sho::launch_project(pg.nu, K, psi, c, s);
+      }
       if (e1 != hipSuccess) return e1;
     }
     return hipSuccess;
@@ -443,8 +462,24 @@ hipError_t run_project(sho_plan_s *p, const double *psi, double *c, hipStream_t 
 }
 
 // The expansion's launches on s (arguments checked, scratch allocated).
-hipError_t run_expand(sho_plan_s *p, const double *c, double *psi, hipStream_t s,
+hipError_t run_expand(sho_plan_s *p, const void *c_v, void *psi_v, hipStream_t s,
                       bool prof) {
+  const double *c = static_cast<const double *>(c_v);
+  double *psi = static_cast<double *>(psi_v);
+  if (p->fp32) {
+    // FP32 plans: plane partials and the block form only
+    sho::EArgs E = make_eargs(p);
+    float *u2 = reinterpret_cast<float *>(p->d_u2);
+    hipError_t e = timed(p, prof, SHO_KERNEL_EXPAND_Z, s, [&]() {
+      return sho::launch_expand_planes_f32(E, p->d_tab32, static_cast<const float *>(c_v),
+                                           u2, s);
+    });
+    if (e == hipSuccess)
+      e = timed(p, prof, SHO_KERNEL_EXPAND_XY, s, [&]() {
+        return sho::launch_blocks_f32(E, p->d_tab32, u2, static_cast<float *>(psi_v), s);
+      });
+    return e;
+  }
   if (p->hp.flags & SHO_FLAG_STORED) {
     if (p->hp.expand_mode == sho::kExpandBlocks) {
       sho::EArgs E = make_eargs(p);
@@ -497,8 +532,18 @@ sho_status sho_plan_create(const sho_grid *grid, int32_t natoms,
                            int32_t nbands, uint32_t flags, sho_plan_t *out) {
   if (!out) return fail(SHO_E_INVALID, "out must not be NULL");
   *out = nullptr;
+  const bool f32 = (flags & SHO_FLAG_FP32) != 0;
+  if (f32) {
+    if (nbands <= 0 || nbands % 2)
+      return fail(SHO_E_INVALID, "FP32 plans need a positive, even number of bands");
+    if (flags & (SHO_FLAG_STORED | SHO_FLAG_PER_ATOM))
+      return fail(SHO_E_INVALID,
+                  "SHO_FLAG_FP32 does not combine with SHO_FLAG_STORED or SHO_FLAG_PER_ATOM");
+    nbands /= 2;  // the kernels work on band pairs
+  }
   sho_plan_s *p = new (std::nothrow) sho_plan_s();
   if (!p) return fail(SHO_E_NOMEM, "host allocation failed");
+  p->fp32 = f32;
   std::string msg;
   sho_status st = sho::build_host_plan(grid, natoms, pos, sigma, numax, rbox,
                                        nbands, flags, &p->hp, &msg);
@@ -506,9 +551,12 @@ sho_status sho_plan_create(const sho_grid *grid, int32_t natoms,
     delete p;
     return fail(st, msg);
   }
+  // FP32 plans keep the projection's coefficient tile in double for both
+  // bands of a pair: half the LDS budget per lane value
+  const size_t lds_div = f32 ? 2 : 1;
   if (flags & SHO_FLAG_HOST_ONLY) {
     // geometry and sizes only; work split as for a 64 KiB workgroup LDS
-    const int tbs = sho::choose_tb_shift(nbands, p->hp.nu_max, 65536 - 1024);
+    const int tbs = sho::choose_tb_shift(nbands, p->hp.nu_max, (65536 - 1024) / lds_div);
     if (tbs < 0) {
       delete p;
       return fail(SHO_E_BOX, "coefficient tile too large for the workgroup LDS");
@@ -531,7 +579,7 @@ sho_status sho_plan_create(const sho_grid *grid, int32_t natoms,
     delete p;
     return hip_fail(e, "hipDeviceGetAttribute");
   }
-  p->lds_limit = (size_t)std::max(shm - 1024, 0);  // static LDS of the kernels
+  p->lds_limit = (size_t)std::max(shm - 1024, 0) / lds_div;  // static LDS of the kernels
   const int tbs = sho::choose_tb_shift(nbands, p->hp.nu_max, p->lds_limit);
   if (tbs < 0) {
     delete p;
@@ -562,6 +610,14 @@ sho_status sho_plan_create(const sho_grid *grid, int32_t natoms,
   p->device_bytes += std::max<int64_t>(p->hp.table_doubles, 1) * sizeof(double);
   e = sho::launch_tables(p->d_atoms, p->hp.natoms, p->hp.grid.h, p->d_tab, p->hp.m_max,
                          nullptr);
+  if (e == hipSuccess && f32) {
+    const int64_t tb = std::max<int64_t>(p->hp.table_doubles, 1) * sizeof(float);
+    e = hipMalloc((void **)&p->d_tab32, tb);
+    if (e == hipSuccess) {
+      p->device_bytes += tb;
+      e = sho::launch_tables_f32(p->d_tab, p->d_tab32, p->hp.table_doubles, nullptr);
+    }
+  }
   if (e == hipSuccess && (flags & SHO_FLAG_STORED)) {
     sho::HostPlan &hp = p->hp;
     sho::build_stored(&hp, sho::kStoredChunk);
@@ -648,11 +704,12 @@ sho_status sho_plan_profile_read(sho_plan_t p, int64_t *counts, double *mean_ms)
 sho_status sho_plan_get_info(sho_plan_t p, sho_plan_info *info) {
   if (!p || !info) return fail(SHO_E_INVALID, "NULL plan or info");
   info->natoms = p->hp.natoms;
-  info->nbands = p->hp.nbands;
+  const int64_t per_lane = p->fp32 ? 2 : 1;  // bands per kernel lane
+  info->nbands = (int32_t)(p->hp.nbands * per_lane);
   info->nu_max = p->hp.nu_max;
   info->flags = (int32_t)p->hp.flags;
   info->coeff_rows = p->hp.coeff_rows;
-  info->coeff_doubles = p->hp.coeff_rows * p->hp.nbands;
+  info->coeff_doubles = p->hp.coeff_rows * p->hp.nbands * per_lane;
   info->support_points = p->hp.support_points;
   info->lines = (int64_t)p->hp.lines.size();
   info->planes = (int64_t)p->hp.planes.size();
@@ -676,6 +733,8 @@ sho_status sho_plan_coeff_offsets(sho_plan_t p, int64_t *off) {
   if (!p || !off) return fail(SHO_E_INVALID, "NULL plan or output");
   std::memcpy(off, p->hp.coeff_off.data(),
               p->hp.coeff_off.size() * sizeof(int64_t));
+  if (p->fp32)  // element offsets: two floats per band pair
+    for (size_t a = 0; a < p->hp.coeff_off.size(); ++a) off[a] *= 2;
   return SHO_OK;
 }
 
@@ -708,6 +767,8 @@ sho_status sho_plan_set_centres(sho_plan_t p, const double *pos, void *stream) {
   if (e == hipSuccess)
     e = sho::launch_tables(p->d_atoms, p->hp.natoms, p->hp.grid.h, p->d_tab,
                            p->hp.m_max, s);
+  if (e == hipSuccess && p->fp32)
+    e = sho::launch_tables_f32(p->d_tab, p->d_tab32, p->hp.table_doubles, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "centre upload");
   return SHO_OK;
@@ -732,9 +793,27 @@ sho_status sho_plan_expand(sho_plan_t p, const double *c, double *psi,
   return SHO_OK;
 }
 
+sho_status sho_plan_project_f32(sho_plan_t p, const float *psi, float *c, void *stream) {
+  sho_status st = check_project(p, psi, c, 1);
+  if (st != SHO_OK || p->hp.coeff_rows == 0) return st;
+  hipError_t e = run_project(p, psi, c, (hipStream_t)stream, p->prof_on);
+  if (e != hipSuccess) return hip_fail(e, "project launch");
+  return SHO_OK;
+}
+
+sho_status sho_plan_expand_f32(sho_plan_t p, const float *c, float *psi, void *stream) {
+  sho_status st = check_project(p, psi, c, 1);
+  if (st != SHO_OK || p->hp.coeff_rows == 0) return st;
+  if ((st = ensure_u2(p)) != SHO_OK) return st;
+  hipError_t e = run_expand(p, c, psi, (hipStream_t)stream, p->prof_on);
+  if (e != hipSuccess) return hip_fail(e, "expand launch");
+  return SHO_OK;
+}
+
 sho_status sho_plan_force(sho_plan_t p, const double *psi, const double *w,
                           double *grad, void *stream) {
   if (!p) return fail(SHO_E_INVALID, "NULL plan");
+  if (p->fp32) return fail(SHO_E_INVALID, "the derivative is FP64 only");
   if (p->hp.flags & SHO_FLAG_HOST_ONLY)
     return fail(SHO_E_INVALID, "host-only plan cannot run kernels");
   if (p->hp.natoms == 0) return SHO_OK;
@@ -775,7 +854,9 @@ sho_status sho_plan_set_schedule(sho_plan_t p, int32_t schedule, int32_t band_ti
     if ((1 << k) == band_tile) tbs = k;
   if (band_tile == 0) tbs = p->hp.tb_shift;
   if (tbs < 0) return fail(SHO_E_INVALID, "band_tile must be 0 or a power of two <= 64");
-  const size_t limit = (p->hp.flags & SHO_FLAG_HOST_ONLY) ? 65536 - 1024 : p->lds_limit;
+  const size_t limit = (p->hp.flags & SHO_FLAG_HOST_ONLY)
+                           ? (65536 - 1024) / (p->fp32 ? 2 : 1)
+                           : p->lds_limit;
   if (sho::lds_tile_bytes(p->hp.nu_max + 2, 1 << tbs) > limit)
     return fail(SHO_E_BOX, "band tile too wide for the workgroup LDS");
   if (!(p->hp.flags & SHO_FLAG_HOST_ONLY)) {
@@ -804,6 +885,8 @@ sho_status sho_plan_set_expand(sho_plan_t p, int32_t mode, int32_t block_rows,
   if (!p) return fail(SHO_E_INVALID, "NULL plan");
   if (mode != sho::kExpandRows && mode != sho::kExpandBlocks)
     return fail(SHO_E_INVALID, "unknown expansion form");
+  if (p->fp32 && mode != sho::kExpandBlocks)
+    return fail(SHO_E_INVALID, "FP32 plans expand in the block form only");
   if (mode == sho::kExpandBlocks) {
     int32_t R = block_rows, X = block_x;
     if (R == 0 && X == 0) sho::default_block_shape(p->hp, &R, &X);
@@ -833,9 +916,9 @@ sho_status sho_plan_get_expand(sho_plan_t p, int32_t *mode, int32_t *block_rows,
   return SHO_OK;
 }
 
-sho_status sho_plan_tune(sho_plan_t p, const double *psi, double *c, int32_t reps,
+sho_status sho_plan_tune(sho_plan_t p, const void *psi, void *c, int32_t reps,
                          void *stream, sho_tune_result *result) {
-  sho_status st = check_project(p, psi, c);
+  sho_status st = check_project(p, psi, c, -1);
   if (st != SHO_OK) return st;
   if (reps < 1 || reps > 1000) return fail(SHO_E_INVALID, "reps outside 1..1000");
   if (p->hp.flags & (SHO_FLAG_STORED | SHO_FLAG_PER_ATOM))
@@ -916,6 +999,7 @@ sho_status check_multiply(const sho_plan_s *p, const double *D, const double *c,
   if (!p) return fail(SHO_E_INVALID, "NULL plan");
   if (p->hp.flags & SHO_FLAG_HOST_ONLY)
     return fail(SHO_E_INVALID, "host-only plan cannot run kernels");
+  if (p->fp32) return fail(SHO_E_INVALID, "the atomic-matrix product is FP64 only");
   if (p->hp.coeff_rows == 0) return SHO_OK;
   const int64_t db = p->hp.dmat_off.back() * (int64_t)sizeof(double);
   if (!device_range_ok(D, db) || !device_range_ok(c, coeff_bytes(p)) ||

@@ -278,12 +278,18 @@ inline int expand_tile_shift(int nbands, int mode, bool stored = false) {
   return nbands > 8 ? 4 : 3;
 }
 
-// Whether an R x X block fits: the LDS tile (R X bands-per-tile doubles) and
+// Values (bands, or band pairs of SHO_FLAG_FP32 plans, which accumulate
+// both bands of a pair in double) that one block's LDS tile holds.
+inline int32_t block_tile_values(const HostPlan &P) {
+  return (P.flags & SHO_FLAG_FP32) ? kBlockTileDoubles / 2 : kBlockTileDoubles;
+}
+
+// Whether an R x X block fits: the LDS tile (R X values per band tile) and
 // the x-table staging of one wave (X rows of the widest table).
 inline bool block_shape_ok(const HostPlan &P, int32_t R, int32_t X) {
   const int tbe = 1 << expand_tile_shift(P.nbands, kExpandBlocks,
                                          (P.flags & SHO_FLAG_STORED) != 0);
-  return R >= 1 && X >= 1 && (int64_t)R * X * tbe <= kBlockTileDoubles &&
+  return R >= 1 && X >= 1 && (int64_t)R * X * tbe <= block_tile_values(P) &&
          X * table_nfp(P.nu_max) <= 256 && R * table_nfp(P.nu_max) <= 256;
 }
 
@@ -295,7 +301,7 @@ inline void default_block_shape(const HostPlan &P, int32_t *R, int32_t *X) {
                                          (P.flags & SHO_FLAG_STORED) != 0);
   const int nfp = table_nfp(P.nu_max);
   *X = std::min(256 / nfp, tbe == 64 ? 16 : 32);
-  *R = std::min(kBlockTileDoubles / (*X * tbe), 256 / nfp);
+  *R = std::min(block_tile_values(P) / (*X * tbe), 256 / nfp);
 }
 
 // Layout of the stored projector tables (SHO_FLAG_STORED plans): the points

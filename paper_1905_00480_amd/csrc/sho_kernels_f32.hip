@@ -1,0 +1,659 @@
+// sho_kernels_f32.hip -- single-precision projection and expansion.
+//
+// The paper measures its kernels in float as well as double (sec. 6,
+// table 4).  An FP32 plan holds an even number 2P of bands; each lane works
+// on one pair of adjacent bands (one aligned 8-byte float pair), so that
+// every record of the plan, every launch shape and scratch size is that of
+// an FP64 plan with P bands, and each load and store moves the same 8 bytes
+// per lane as in double precision.  Tables, the x and y passes and the plane
+// partials are FP32.  The sums that go through LDS atomics (the projection's
+// z pass and the expansion's accumulation into each grid value) are kept in
+// FP64 and rounded to float once at the end: on gfx950 a 32-bit float
+// atomic add in LDS is more than an order of magnitude slower than the
+// 64-bit one, and the wider sums only tighten the error.  Complex
+// single-precision bands are such pairs (real, imaginary): the SHO functions
+// are real, so both halves are projected and expanded alike.
+//
+// The passes are those of the FP64 kernels (x, y, z contractions with the
+// x table read through the scalar cache; expansion by plane partials and
+// owner-computes blocks).  They live in a translation unit of their own so
+// that the FP64 kernels are compiled exactly as they are without them.
+#include <hip/hip_runtime.h>
+
+#include "sho_launch.hpp"
+
+namespace sho {
+namespace f32 {
+
+constexpr int kBlock = 64 * kWaves;
+constexpr int kBatch = 8;  // loads in flight per lane and batch
+
+#define SHO_F32_NU_CASES(X) \
+  X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10)
+
+// waves per SIMD the register allocator must allow (a pair of floats takes
+// the registers of one double, so the FP64 budget carries over)
+constexpr int waves_per_eu(int nf) { return nf <= 6 ? 4 : 2; }
+
+// Two adjacent bands of one grid point (or one complex band).
+struct __attribute__((aligned(8))) Pair {
+  float a, b;
+};
+
+__device__ inline Pair fma2(float s, Pair v, Pair acc) {
+  return Pair{fmaf(s, v.a, acc.a), fmaf(s, v.b, acc.b)};
+}
+
+__device__ inline Pair zero2() { return Pair{0.f, 0.f}; }
+
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T *;
+
+template <typename T>
+__device__ inline cptr<T> as_const(const T *p) {
+  return (cptr<T>)p;
+}
+
+template <typename T>
+__device__ inline T load_uniform(const T *p) {
+  static_assert(sizeof(T) % 4 == 0, "record size");
+  T out;
+  const cptr<uint32_t> src = (cptr<uint32_t>)p;
+  uint32_t *dst = reinterpret_cast<uint32_t *>(&out);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) dst[i] = src[i];
+  return out;
+}
+
+// ---------------------------------------------------------------- tables --
+
+// The FP32 tables are the FP64 samples rounded once to nearest.
+__global__ void k_round_tables(const double *__restrict__ src, float *__restrict__ dst,
+                               int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = (float)src[i];
+}
+
+// ------------------------------------------------------------- lane state --
+
+struct Lanes {
+  int slot;  // run slot of this lane
+  int TB;    // band pairs per slot
+  int bl;    // pair within the tile
+  bool bok;  // pair exists
+  int bc;    // pair used for addressing (clamped into range)
+};
+
+__device__ inline Lanes lane_geometry(const KArgs &K, int tile) {
+  Lanes L;
+  const int lane = threadIdx.x & 63;
+  L.TB = 1 << K.tb_shift;
+  L.slot = lane >> K.tb_shift;
+  L.bl = lane & (L.TB - 1);
+  const int b = tile * L.TB + L.bl;
+  L.bok = b < K.B;
+  L.bc = L.bok ? b : K.B - 1;
+  return L;
+}
+
+__device__ inline int wave_id() {
+  return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+}
+
+struct RunState {
+  const Pair *base;  // psi at the run's first point, this lane's pair
+  int jx0;
+  int len;
+  int jy;
+  bool active;
+};
+
+__device__ inline RunState run_state(const KArgs &K, const Lanes &L, const Pair *psi,
+                                     const BundleRec &bd) {
+  const int s = min(L.slot, bd.nruns - 1);
+  const LineRec ln = K.lines[bd.run0 + s];
+  RunState r;
+  r.base = psi + ((int64_t)ln.row * K.nx + ln.x0m) * K.B + L.bc;
+  r.jx0 = ln.jx0;
+  r.len = ln.len;
+  r.jy = ln.jy;
+  r.active = L.slot < bd.nruns;
+  return r;
+}
+
+__device__ inline void load_batch(const KArgs &K, const RunState &r, int jb, Pair *v) {
+#pragma unroll
+  for (int u = 0; u < kBatch; ++u) {
+    const int k = min(max(jb + u - r.jx0, 0), r.len - 1);
+    v[u] = r.base[k * K.B];
+  }
+}
+
+// LDS tiles hold the two bands of a pair in separate rows of TB doubles
+// ([..][2][TB]), so that the lanes of one slot touch consecutive words.
+
+// z pass for one plane: fold the slots, then C[n] += phi_nz(z) T2[nx][ny]
+// into the LDS tile ([n][2][TB] doubles; float products are exact in double).
+template <int NU>
+__device__ inline void flush_plane(cptr<float> fz, Pair *T2, double *cacc, const Lanes &L) {
+  constexpr int NF = NU + 1;
+  constexpr int NP = NF * (NF + 1) / 2;
+  for (int s = 32; s >= L.TB; s >>= 1) {
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      T2[q].a += __shfl_xor(T2[q].a, s);
+      T2[q].b += __shfl_xor(T2[q].b, s);
+    }
+  }
+  if (L.slot == 0 && L.bok) {
+    // the lane's word offset is made opaque here so that the per-coefficient
+    // addresses are formed at the flush instead of being held live (and
+    // spilled) across the whole stream of bundles
+    int lane_off = L.bl;
+    asm volatile("" : "+v"(lane_off));
+    const int row = 2 * L.TB;
+    int idx = 0;
+#pragma unroll
+    for (int nz = 0; nz < NF; ++nz) {
+      const double f = fz[nz];
+      int q = 0;
+#pragma unroll
+      for (int ny = 0; ny < NF; ++ny) {
+#pragma unroll
+        for (int nx = 0; nx < NF - ny; ++nx, ++q) {
+          if (nx + ny + nz <= NU) {
+            double *dst = cacc + (idx * row + lane_off);
+            atomicAdd(dst, f * (double)T2[q].a);
+            atomicAdd(dst + L.TB, f * (double)T2[q].b);
+            ++idx;
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NP; ++q) T2[q] = zero2();
+}
+
+// ------------------------------------------------------- projection core --
+
+template <int NU>
+__device__ inline void project_bundles(const KArgs &K, const float *tab, const AtomRec &A,
+                                       const Lanes &L, int b0, int b1,
+                                       const Pair *__restrict__ psi, double *cacc) {
+  constexpr int NF = NU + 1;
+  constexpr int NP = NF * (NF + 1) / 2;
+  if (b0 >= b1) return;
+  const int nfp = A.tab_nfp;
+  const cptr<float> tx = as_const(tab) + A.tab_off;
+  const float *ty = tab + A.tab_off + (int64_t)A.mx * nfp;
+  const cptr<float> tz = tx + (int64_t)(A.mx + A.my) * nfp;
+
+  Pair T2[NP];
+#pragma unroll
+  for (int q = 0; q < NP; ++q) T2[q] = zero2();
+  int cur_jz = -1;
+  BundleRec bd = load_uniform(K.bundles + b0);
+  RunState rs = run_state(K, L, psi, bd);
+  Pair v[kBatch];
+  load_batch(K, rs, bd.jlo, v);
+  for (int bi = b0; bi < b1; ++bi) {
+    if (bd.jz != cur_jz) {
+      if (cur_jz >= 0) flush_plane<NU>(tz + cur_jz * nfp, T2, cacc, L);
+      cur_jz = bd.jz;
+    }
+    Pair T1[NF];
+#pragma unroll
+    for (int n = 0; n < NF; ++n) T1[n] = zero2();
+    BundleRec nbd = bd;
+    RunState nrs = rs;
+    for (int jb = bd.jlo; jb <= bd.jhi; jb += kBatch) {
+      Pair w[kBatch];
+      if (jb + kBatch <= bd.jhi) {
+        load_batch(K, rs, jb + kBatch, w);
+      } else if (bi + 1 < b1) {
+        nbd = load_uniform(K.bundles + bi + 1);
+        nrs = run_state(K, L, psi, nbd);
+        load_batch(K, nrs, nbd.jlo, w);
+      } else {
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) w[u] = zero2();
+      }
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        const int jx = jb + u;
+        if (jx <= bd.jhi) {
+          const int k = jx - rs.jx0;
+          const bool ok = rs.active && k >= 0 && k < rs.len;
+          const Pair xv = ok ? v[u] : zero2();
+          const cptr<float> f = tx + jx * nfp;
+#pragma unroll
+          for (int n = 0; n < NF; ++n) T1[n] = fma2(f[n], xv, T1[n]);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) v[u] = w[u];
+    }
+    const float *fy = ty + rs.jy * nfp;
+    int q = 0;
+#pragma unroll
+    for (int ny = 0; ny < NF; ++ny) {
+      const float fv = fy[ny];
+#pragma unroll
+      for (int nx = 0; nx < NF - ny; ++nx, ++q) T2[q] = fma2(fv, T1[nx], T2[q]);
+    }
+    bd = nbd;
+    rs = nrs;
+  }
+  flush_plane<NU>(tz + cur_jz * nfp, T2, cacc, L);
+}
+
+template <int NU>
+__device__ inline void project_item(const KArgs &K, const float *tab, cptr<WorkRec> W,
+                                    const AtomRec &A, const Pair *__restrict__ psi,
+                                    Pair *__restrict__ c, double *cacc) {
+  constexpr int NF = NU + 1;
+  constexpr int NS = NF * (NF + 1) * (NF + 2) / 6;
+  const int tile = blockIdx.y;
+  const int TB = 1 << K.tb_shift;
+  for (int t = threadIdx.x; t < 2 * NS * TB; t += blockDim.x) cacc[t] = 0.0;
+  __syncthreads();
+  const int w = wave_id();
+  const Lanes L = lane_geometry(K, tile);
+  project_bundles<NU>(K, tab, A, L, W->wb[w], W->wb[w + 1], psi, cacc);
+  __syncthreads();
+  const bool split = W->split != 0;
+  for (int t = threadIdx.x; t < NS * TB; t += blockDim.x) {
+    const int n = t >> K.tb_shift;
+    const int bb = tile * TB + (t & (TB - 1));
+    if (bb >= K.B) continue;
+    Pair *dst = c + (A.coeff_row + n) * K.B + bb;
+    const int ia = t + (t & ~(TB - 1));  // [n][2][TB]: first float of the pair
+    const Pair v{(float)(K.h3 * cacc[ia]), (float)(K.h3 * cacc[ia + TB])};
+    if (split) {
+      unsafeAtomicAdd(&dst->a, v.a);
+      unsafeAtomicAdd(&dst->b, v.b);
+    } else {
+      *dst = v;
+    }
+  }
+}
+
+template <int NU>
+__global__ __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(waves_per_eu(NU + 1)))) void k_project(
+    KArgs K, const float *__restrict__ tab, const Pair *__restrict__ psi,
+    Pair *__restrict__ c) {
+  extern __shared__ double cacc[];
+  const cptr<WorkRec> W = as_const(K.work) + blockIdx.x;
+  if (W->atom < 0) return;  // padding of an XCD-dealt launch
+  const AtomRec A = load_uniform(K.atoms + W->atom);
+  project_item<NU>(K, tab, W, A, psi, c, cacc);
+}
+
+template <int NUMAX>
+__global__ __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(waves_per_eu(NUMAX + 1)))) void k_project_any(
+    KArgs K, const float *__restrict__ tab, const Pair *__restrict__ psi,
+    Pair *__restrict__ c) {
+  extern __shared__ double cacc[];
+  const cptr<WorkRec> W = as_const(K.work) + blockIdx.x;
+  if (W->atom < 0) return;
+  const AtomRec A = load_uniform(K.atoms + W->atom);
+  switch (A.nu) {
+#define X(N)                                                                 \
+  case N:                                                                    \
+    if constexpr (N <= NUMAX) project_item<N>(K, tab, W, A, psi, c, cacc);   \
+    break;
+    SHO_F32_NU_CASES(X)
+#undef X
+  }
+}
+
+// ------------------------------------------------------------- expansion --
+
+constexpr int kU2Tile = 32;  // band pairs per plane-partial workgroup
+
+// Plane partials U2[jz][q][pair] = sum_nz phi_nz(z_jz) C[nx,ny,nz][pair].
+template <int NU>
+__global__ __launch_bounds__(256) void k_u2(EArgs E, const float *__restrict__ tab,
+                                            const Pair *__restrict__ c,
+                                            Pair *__restrict__ u2) {
+  constexpr int NF = NU + 1;
+  constexpr int NS = NF * (NF + 1) * (NF + 2) / 6;
+  constexpr int NP = NF * (NF + 1) / 2;
+  __shared__ Pair cs[NS * kU2Tile];
+  const int a = E.nu_atoms[E.nu_begin[NU] + blockIdx.x];
+  const AtomRec A = load_uniform(E.atoms + a);
+  const int b0 = blockIdx.y * kU2Tile;
+  {
+    constexpr int U = 8;
+    const int count = NS * kU2Tile;
+    for (int t0 = 0; t0 < count; t0 += U * (int)blockDim.x) {
+      Pair v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int t = t0 + u * (int)blockDim.x + (int)threadIdx.x;
+        const int n = t / kU2Tile, bl = t % kU2Tile;
+        v[u] = (t < count && b0 + bl < E.B) ? c[(A.coeff_row + n) * E.B + b0 + bl] : zero2();
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int t = t0 + u * (int)blockDim.x + (int)threadIdx.x;
+        if (t < count) cs[t] = v[u];
+      }
+    }
+  }
+  __syncthreads();
+  const float *tz = tab + A.tab_off + (int64_t)(A.mx + A.my) * A.tab_nfp;
+  Pair *dst = u2 + E.u2_off[a];
+  for (int t = threadIdx.x; t < A.mz * kU2Tile; t += blockDim.x) {
+    const int bl = t % kU2Tile;
+    const int jz = t / kU2Tile;
+    if (b0 + bl >= E.B) continue;
+    float fz[NF];
+#pragma unroll
+    for (int n = 0; n < NF; ++n) fz[n] = tz[(int64_t)jz * A.tab_nfp + n];
+    Pair *out = dst + (int64_t)jz * NP * E.B + b0 + bl;
+    int q = 0;
+#pragma unroll
+    for (int ny = 0; ny < NF; ++ny) {
+#pragma unroll
+      for (int nx = 0; nx < NF - ny; ++nx, ++q) {
+        Pair acc = zero2();
+#pragma unroll
+        for (int nz = 0; nz < NF; ++nz) {
+          if (nx + ny + nz <= NU) {
+            // coefficient order: nz-major, then ny, nx fastest
+            int base = 0;
+#pragma unroll
+            for (int k = 0; k < nz; ++k) base += (NU - k + 1) * (NU - k + 2) / 2;
+#pragma unroll
+            for (int j = 0; j < ny; ++j) base += NU - nz - j + 1;
+            acc = fma2(fz[nz], cs[(base + nx) * kU2Tile + bl], acc);
+          }
+        }
+        out[(int64_t)q * E.B] = acc;
+      }
+    }
+  }
+}
+
+constexpr int kBlkWaves = 4;
+constexpr int kBlkBlock = 64 * kBlkWaves;
+constexpr int kBlkXStage = 256;  // floats per wave: the x-table rows of a block
+
+constexpr int blk_group(int nu, int numax) { return (numax > 5 && nu <= 5) ? 4 : 2; }
+
+// Adds every run of one entry (one atom plane, one image) into the LDS tile
+// of the block ([row][x][2][TB] doubles).
+template <int NU, int NUMAX>
+__device__ inline void add_entry(const EArgs &E, const float *tab, const EntryRec &en,
+                                 const Pair *u2, int nxl, double *tile, float *xstage,
+                                 int TB, int slot, int bl, int bc) {
+  constexpr int NF = NU + 1;
+  constexpr int NP = NF * (NF + 1) / 2;
+  constexpr int G = blk_group(NU, NUMAX);
+  const int nfp = en.nfp;
+  const int lane = threadIdx.x & 63;
+  const int slots = 64 / TB;
+  const Pair *ub = u2 + en.u2 + bc;
+  Pair u2v[NP];
+#pragma unroll
+  for (int q = 0; q < NP; ++q) u2v[q] = ub[(int64_t)q * E.B];
+  const uint32_t mydesc = lane < en.nruns ? as_const(E.run_desc)[en.run_begin + lane] : 0u;
+  float tx[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int i = lane * 4 + k;
+    const int pt = i / nfp;
+    tx[k] = (pt >= en.x_lo && pt < en.x_hi) ? tab[en.tab_x + i] : 0.f;
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) xstage[lane * 4 + k] = tx[k];
+  for (int g0 = 0; g0 < en.nruns; g0 += G * slots) {
+    const int gend = min(g0 + G * slots, en.nruns);
+    int lo = 255, hi = 0;
+    for (int k = g0; k < gend; ++k) {
+      const uint32_t d = __builtin_amdgcn_readlane(mydesc, k);
+      lo = min(lo, (int)((d >> 8) & 0xff));
+      hi = max(hi, (int)((d >> 16) & 0xff));
+    }
+    int rr[G], xa[G], xb[G];
+    Pair U1[G][NF];
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+      const int i = g0 + j * slots + slot;
+      const uint32_t d = __shfl(mydesc, min(i, gend - 1));
+      rr[j] = d & 0xff;
+      xa[j] = i < gend ? (int)((d >> 8) & 0xff) : 0;
+      xb[j] = i < gend ? (int)((d >> 16) & 0xff) : 0;
+      const float *fy = tab + en.tab_y + rr[j] * nfp;
+#pragma unroll
+      for (int n = 0; n < NF; ++n) U1[j][n] = zero2();
+      int q = 0;
+#pragma unroll
+      for (int ny = 0; ny < NF; ++ny) {
+        const float fv = fy[ny];
+#pragma unroll
+        for (int nx = 0; nx < NF - ny; ++nx, ++q) U1[j][nx] = fma2(fv, u2v[q], U1[j][nx]);
+      }
+    }
+    for (int x = lo; x < hi; ++x) {
+      const float *f = xstage + x * nfp;
+      float fx[NF];
+#pragma unroll
+      for (int n = 0; n < NF; ++n) fx[n] = f[n];
+#pragma unroll
+      for (int j = 0; j < G; ++j) {
+        Pair val = zero2();
+#pragma unroll
+        for (int n = 0; n < NF; ++n) val = fma2(fx[n], U1[j][n], val);
+        if (x >= xa[j] && x < xb[j]) {
+          double *dst = tile + (((rr[j] * nxl + x) * TB) << 1) + bl;
+          atomicAdd(dst, (double)val.a);
+          atomicAdd(dst + TB, (double)val.b);
+        }
+      }
+    }
+  }
+}
+
+// One workgroup per (block, band-pair tile): the block's values of psi are
+// read into LDS once (as doubles), every entry adds its runs, and the block
+// is written back once, rounded to float.  A tile holds at most
+// kBlockTileDoubles / 2 pairs, the LDS bytes of the FP64 tile.
+template <int NUMAX>
+__global__ __launch_bounds__(kBlkBlock) void k_expand_blocks(EArgs E,
+                                                            const float *__restrict__ tab,
+                                                            const Pair *__restrict__ u2,
+                                                            Pair *psi) {
+  extern __shared__ double lds[];
+  const BlockRec bk = load_uniform(E.blocks + blockIdx.x);
+  if (bk.nentries < 0) return;
+  const int w = wave_id();
+  double *tile = lds;
+  const int TB = 1 << E.tbe_shift;
+  const int btile = blockIdx.y;
+  const int xe = min(bk.x0 + E.blk_x, E.nx);
+  const int nxl = xe - bk.x0;
+  const int nrow = min(bk.y0 + E.blk_rows, E.ny) - bk.y0;
+  const int rowbase = bk.z * E.ny + bk.y0;
+  const int per_row = nxl << E.tbe_shift;
+  const int nval = nrow * per_row;
+  auto gidx = [&](int t, int &b) -> int64_t {
+    const int r = t / per_row;
+    const int rem = t - r * per_row;
+    const int x = rem >> E.tbe_shift;
+    b = btile * TB + (rem & (TB - 1));
+    return ((int64_t)(rowbase + r) * E.nx + bk.x0 + x) * E.B + b;
+  };
+  constexpr int kPer = kBlockTileDoubles / 2 / kBlkBlock;
+  for (int t0 = 0; t0 < nval; t0 += kPer * kBlkBlock) {
+    Pair v[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int t = t0 + u * kBlkBlock + (int)threadIdx.x;
+      int bb = 0;
+      const int64_t g = t < nval ? gidx(t, bb) : 0;
+      v[u] = (t < nval && bb < E.B) ? psi[g] : zero2();
+    }
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int t = t0 + u * kBlkBlock + (int)threadIdx.x;
+      if (t < nval) {
+        const int ia = t + (t & ~(TB - 1));
+        tile[ia] = v[u].a;
+        tile[ia + TB] = v[u].b;
+      }
+    }
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int slot = lane >> E.tbe_shift;
+  const int bl = lane & (TB - 1);
+  const int b = btile * TB + bl;
+  const int bc = b < E.B ? b : E.B - 1;
+  float *xstage = reinterpret_cast<float *>(lds + kBlockTileDoubles) + w * kBlkXStage;
+  EntryRec en;
+  if (w < bk.nentries) en = load_uniform(E.entries + bk.entry_begin + w);
+  for (int i = w; i < bk.nentries; i += kBlkWaves) {
+    EntryRec nxt = en;
+    if (i + kBlkWaves < bk.nentries)
+      nxt = load_uniform(E.entries + bk.entry_begin + i + kBlkWaves);
+    switch (en.nu) {
+#define X(N)                                                                        \
+  case N:                                                                           \
+    if constexpr (N <= NUMAX)                                                       \
+      add_entry<N, NUMAX>(E, tab, en, u2, nxl, tile, xstage, TB, slot, bl, bc);     \
+    break;
+      SHO_F32_NU_CASES(X)
+#undef X
+    }
+    en = nxt;
+  }
+  __syncthreads();
+  for (int t0 = 0; t0 < nval; t0 += kPer * kBlkBlock) {
+    Pair v[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int t = t0 + u * kBlkBlock + (int)threadIdx.x;
+      const int ia = t + (t & ~(TB - 1));
+      v[u] = t < nval ? Pair{(float)tile[ia], (float)tile[ia + TB]} : zero2();
+    }
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int t = t0 + u * kBlkBlock + (int)threadIdx.x;
+      if (t < nval) {
+        int bb;
+        const int64_t g = gidx(t, bb);
+        if (bb < E.B) psi[g] = v[u];
+      }
+    }
+  }
+}
+
+static dim3 grid_of(const KArgs &K) { return dim3((unsigned)K.nwork, (unsigned)K.ntiles); }
+
+template <int NU>
+static hipError_t launch_project_nu(const KArgs &K, const float *tab, const Pair *psi,
+                                    Pair *c, hipStream_t s) {
+  const size_t shm = 2 * lds_tile_bytes(NU + 1, 1 << K.tb_shift);
+  hipLaunchKernelGGL(k_project<NU>, grid_of(K), dim3(kBlock), shm, s, K, tab, psi, c);
+  return hipGetLastError();
+}
+
+template <int NUMAX>
+static hipError_t launch_project_any_nu(const KArgs &K, const float *tab, const Pair *psi,
+                                        Pair *c, hipStream_t s) {
+  const size_t shm = 2 * lds_tile_bytes(NUMAX + 1, 1 << K.tb_shift);
+  hipLaunchKernelGGL(k_project_any<NUMAX>, grid_of(K), dim3(kBlock), shm, s, K, tab, psi,
+                     c);
+  return hipGetLastError();
+}
+
+}  // namespace f32
+
+using f32::Pair;
+
+hipError_t launch_tables_f32(const double *tab, float *tab32, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(f32::k_round_tables, dim3((unsigned)blocks), dim3(256), 0, s, tab,
+                     tab32, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_project_f32(int nu, const KArgs &K, const float *tab, const float *psi,
+                              float *c, hipStream_t s) {
+  if (K.nwork <= 0) return hipSuccess;
+  const Pair *pp = reinterpret_cast<const Pair *>(psi);
+  Pair *cp = reinterpret_cast<Pair *>(c);
+  switch (nu) {
+#define X(N) case N: return f32::launch_project_nu<N>(K, tab, pp, cp, s);
+    SHO_F32_NU_CASES(X)
+#undef X
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_project_any_f32(int nu_max, const KArgs &K, const float *tab,
+                                  const float *psi, float *c, hipStream_t s) {
+  if (K.nwork <= 0) return hipSuccess;
+  const Pair *pp = reinterpret_cast<const Pair *>(psi);
+  Pair *cp = reinterpret_cast<Pair *>(c);
+  switch (nu_max) {
+#define X(N) case N: return f32::launch_project_any_nu<N>(K, tab, pp, cp, s);
+    SHO_F32_NU_CASES(X)
+#undef X
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_expand_planes_f32(const EArgs &E, const float *tab, const float *c,
+                                    float *u2, hipStream_t s) {
+  const Pair *cp = reinterpret_cast<const Pair *>(c);
+  Pair *up = reinterpret_cast<Pair *>(u2);
+  for (int nu = 0; nu <= SHO_NU_MAX; ++nu) {
+    const int cnt = E.nu_begin[nu + 1] - E.nu_begin[nu];
+    if (cnt <= 0) continue;
+    const dim3 g((unsigned)cnt, (unsigned)E.ntiles_u2);
+    switch (nu) {
+#define X(N)                                                                  \
+  case N:                                                                     \
+    hipLaunchKernelGGL(f32::k_u2<N>, g, dim3(256), 0, s, E, tab, cp, up);     \
+    break;
+      SHO_F32_NU_CASES(X)
+#undef X
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_blocks_f32(const EArgs &E, const float *tab, const float *u2, float *psi,
+                             hipStream_t s) {
+  if (E.nblocks > 0) {
+    const Pair *up = reinterpret_cast<const Pair *>(u2);
+    Pair *pp = reinterpret_cast<Pair *>(psi);
+    const dim3 g((unsigned)E.nblocks, (unsigned)E.ntiles);
+    const size_t shm =
+        kBlockTileDoubles * sizeof(double) + f32::kBlkWaves * f32::kBlkXStage * sizeof(float);
+    switch (E.nu_max) {
+#define X(N)                                                                             \
+  case N:                                                                                \
+    hipLaunchKernelGGL((f32::k_expand_blocks<N>), g, dim3(f32::kBlkBlock), shm, s, E, tab, \
+                       up, pp);                                                          \
+    break;
+      SHO_F32_NU_CASES(X)
+#undef X
+      default:
+        return hipErrorInvalidValue;
+    }
+  }
+  return hipGetLastError();
+}
+
+}  // namespace sho

@@ -121,4 +121,16 @@ hipError_t launch_force(int nu, const KArgs &K, const double *psi,
                         const double *w, double *grad, hipStream_t s);
 hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s);
 
+// FP32 plans (an even number of bands, processed as pairs: K.B and E.B count
+// pairs).  tab: the plan's tables rounded to FP32.
+hipError_t launch_tables_f32(const double *tab, float *tab32, int64_t n, hipStream_t s);
+hipError_t launch_project_f32(int nu, const KArgs &K, const float *tab, const float *psi,
+                              float *c, hipStream_t s);
+hipError_t launch_project_any_f32(int nu_max, const KArgs &K, const float *tab,
+                                  const float *psi, float *c, hipStream_t s);
+hipError_t launch_expand_planes_f32(const EArgs &E, const float *tab, const float *c,
+                                    float *u2, hipStream_t s);
+hipError_t launch_blocks_f32(const EArgs &E, const float *tab, const float *u2, float *psi,
+                             hipStream_t s);
+
 }  // namespace sho

@@ -66,7 +66,8 @@ sho_status build_host_plan(const sho_grid *grid, int32_t natoms,
     return SHO_E_INVALID;
   }
   const uint32_t known =
-      SHO_FLAG_STORED | SHO_FLAG_ALLOW_UNDERSAMPLED | SHO_FLAG_HOST_ONLY | SHO_FLAG_PER_ATOM;
+      SHO_FLAG_STORED | SHO_FLAG_ALLOW_UNDERSAMPLED | SHO_FLAG_HOST_ONLY | SHO_FLAG_PER_ATOM |
+      SHO_FLAG_FP32;
   if (flags & ~known) {
     *msg = "unknown flag bits";
     return SHO_E_INVALID;

@@ -27,7 +27,7 @@ def _lib():
 def _declared():
     txt = open(HEADER).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(sho_[a-z_]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(sho_[a-z0-9_]+)\s*\(", txt)))
 
 
 def test_header_declarations_are_exported():
