@@ -270,6 +270,34 @@ def fp32_step(bd, wl, args, ms_fp64):
             "expand_xy_GB/s": xy_bytes / (xy_ms * 1e-3) / 1e9 if xy_ms > 0 else None}
 
 
+def setup_step(bd):
+    """Host-side set-up of the basis (once per SCF cycle, sec. 3.5): the
+    atomic matrix of 18 synthetic radial projectors (two each for s, p, d) in
+    the Cartesian SHO basis, on a 2001-point radial quadrature."""
+    r = np.linspace(0.0, 10.0, 2001)
+    w = np.full(r.size, r[1] - r[0])
+    w[1:-1:2] *= 4.0 / 3.0
+    w[2:-1:2] *= 2.0 / 3.0
+    w[[0, -1]] /= 3.0
+    ell = [0, 0, 1, 1, 2, 2]
+    P = np.array([r ** l * (1.0 + 0.3 * k * r) * np.exp(-r * r / 1.2)
+                  for k, l in enumerate(ell)])
+    D = np.eye(18)
+    out = {}
+    bd.setup_matrix(4, 0.6, ell, r, w, P, D)  # warm-up (library load)
+    for nu_max in (4, 5, 10):
+        t0 = time.perf_counter()
+        reps = 0
+        while True:
+            bd.setup_matrix(nu_max, 0.6, ell, r, w, P, D)
+            reps += 1
+            if time.perf_counter() - t0 > 0.2:
+                break
+        out["nu_max=%d ms" % nu_max] = (time.perf_counter() - t0) / reps * 1e3
+    return {"workload": "18 radial projectors (s, p, d x 2), 2001-point radial grid, "
+                        "script-D = U^T F^T D F U on the host", **out}
+
+
 def diff_step(bd, wl, args):
     """Differentiation workload (isolated 96^3, 256 atoms, nu 6, 16 bands):
     forward projection and the backward pair (expansion of h^3 dL/dc for
@@ -530,6 +558,7 @@ def main():
     _log("scale workload: %.3f ms per step" % ms_per_step)
     rec["apply"] = apply_step(bd, wl, plan, s, psi, args)
     _log("non-local application: %.3f ms per step" % rec["apply"]["ms_per_step"])
+    rec["setup"] = setup_step(bd)
     if not args.no_fp32:
         rec["fp32"] = fp32_step(bd, wl, args, ms_per_step)
         _log("fp32 scale step: %.3f ms" % rec["fp32"]["ms_per_step"])

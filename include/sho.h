@@ -433,6 +433,63 @@ sho_status sho_server_destroy(sho_server_t server);
 /* Drop every plan held by the stateless cache (waits for the device). */
 sho_status sho_cache_clear(void);
 
+/*
+ * Set-up side (host only, no device call; once per SCF cycle, sec. 3.5).
+ *
+ * Radial SHO states Psi_s = R_{nr l}(r) Y_lm (sec. 2.3) are ordered by nu
+ * ascending, then l = nu mod 2 .. nu in steps of 2, then m = -l..l, with
+ * nr = (nu - l)/2 ("radial order").  R_{nr l}(r) = N r~^l L_nr^(l+1/2)(r~^2)
+ * exp(-r~^2/2) sigma^(-3/2), r~ = r/sigma, normalised so that
+ * int R^2 r^2 dr = 1.  Y_lm are real spherical harmonics without the
+ * Condon-Shortley sign: m > 0 ~ cos(m phi), m < 0 ~ sin(|m| phi), so that
+ * Y_11 ~ +x/r and Y_1-1 ~ +y/r.  Cartesian states Phi_c = phi_nx phi_ny phi_nz
+ * are in the coefficient order of the projection (nz outer, ny, nx fastest).
+ */
+#define SHO_SETUP_NU_MAX 60   /* largest nu of the radial-only calls */
+
+/* U[c][s] = <Phi_c | Psi_s> (sec. 2.5, the unitary map between the two
+ * degenerate-shell bases; zero unless nx+ny+nz = l + 2 nr).  U: host
+ * [N_SHO(nu_max)][N_SHO(nu_max)] row-major, rows Cartesian, columns radial
+ * order; independent of sigma.  Errors: SHO_E_NU_RANGE (nu_max outside
+ * 0..SHO_NU_MAX), SHO_E_INVALID (NULL). */
+sho_status sho_setup_unitary(int32_t nu_max, double *U);
+
+/* R[k][i] = R_{nr l}(r[i]; sigma) for every (nr, l) with l + 2 nr <= nu_max,
+ * k in radial order without m (nu ascending, then l).  Host arrays:
+ * r[npts], R[count][npts].  Errors: SHO_E_NU_RANGE (outside
+ * 0..SHO_SETUP_NU_MAX), SHO_E_INVALID. */
+sho_status sho_setup_radial(int32_t nu_max, double sigma, int64_t npts,
+                            const double *r, double *R);
+
+/*
+ * The atomic matrix in the Cartesian SHO basis (sec. 3.5):
+ *   out = M^T D M,  M[j][c] = <p_j | Phi_c> = sum_s F[j][s] U[c][s],
+ *   F[j][s] = <p_j | Psi_s> = delta_{l l_j} delta_{m m_j} sum_i w_i r_i^2 P_k(r_i) R_s(r_i).
+ * Projectors p_j = P_k(r) Y_{l_k m}: radial function k = 0..nrad-1 with
+ * angular momentum ell[k], and m = -ell[k]..ell[k]; j runs over k, then m
+ * (nproj = sum_k (2 ell[k] + 1)).  Host arrays: ell[nrad]; a radial
+ * quadrature r[ngrid], w[ngrid] with sum_i w_i g(r_i) ~ int g(r) dr;
+ * P[nrad][ngrid] projector values; D[nproj][nproj] row-major; out
+ * [N_SHO(nu_max)][N_SHO(nu_max)] row-major in the coefficient order (the
+ * per-atom block that sho_plan_multiply / sho_plan_apply take).  Functions
+ * outside the basis (l_k > nu_max) contribute nothing.  Errors:
+ * SHO_E_NU_RANGE, SHO_E_INVALID (NULL, ngrid < 1, negative l, sigma <= 0).
+ */
+sho_status sho_setup_matrix(int32_t nu_max, double sigma, int32_t nrad,
+                            const int32_t *ell, int64_t ngrid, const double *r,
+                            const double *w, const double *P, const double *D,
+                            double *out);
+
+/* Representation quality of one radial projector P(r) of angular momentum
+ * ell in the radial SHO basis of spread sigma (sec. 4):
+ *   Q[nu] = sum_{nr <= (nu - ell)/2} <P | R_{nr ell}>^2 / <P | P>, nu = 0..nu_max
+ * (0 for nu < ell), inner products with weight r^2 on the caller's
+ * quadrature.  Q[nu_max + 1] host output.  Errors: SHO_E_NU_RANGE (outside
+ * 0..SHO_SETUP_NU_MAX), SHO_E_INVALID (NULL, zero norm, sigma <= 0). */
+sho_status sho_setup_quality(int32_t nu_max, double sigma, int32_t ell,
+                             int64_t ngrid, const double *r, const double *w,
+                             const double *P, double *Q);
+
 #ifdef __cplusplus
 }
 #endif

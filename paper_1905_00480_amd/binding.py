@@ -30,6 +30,7 @@ SHO_E_NOMEM = -5
 SHO_E_DEVICE = -6
 SHO_E_BUDGET = -7
 SHO_NU_MAX = 10
+SHO_SETUP_NU_MAX = 60
 FLAG_STORED = 0x1
 FLAG_ALLOW_UNDERSAMPLED = 0x2
 FLAG_HOST_ONLY = 0x4
@@ -61,6 +62,7 @@ EXPORTS = (
     "sho_server_drain", "sho_server_request_info", "sho_server_read",
     "sho_server_get_stats", "sho_server_system_info", "sho_server_inputs",
     "sho_server_clock", "sho_server_destroy", "sho_server_prefetch",
+    "sho_setup_unitary", "sho_setup_radial", "sho_setup_matrix", "sho_setup_quality",
 )
 JOB_PROJECT, JOB_EXPAND, JOB_FORCE = 0, 1, 2
 KERNEL_KINDS = ("project", "expand_z", "expand_xy", "force")
@@ -177,6 +179,12 @@ def load_library(path=None):
                                       ctypes.POINTER(_dp)]
     lib.sho_server_clock.argtypes = [P, _dp]
     lib.sho_server_destroy.argtypes = [P]
+    lib.sho_setup_unitary.argtypes = [ctypes.c_int32, _dp]
+    lib.sho_setup_radial.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_int64, _dp, _dp]
+    lib.sho_setup_matrix.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_int32, _i32p,
+                                     ctypes.c_int64, _dp, _dp, _dp, _dp, _dp]
+    lib.sho_setup_quality.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
+                                      ctypes.c_int64, _dp, _dp, _dp, _dp]
     for name in EXPORTS:
         if name not in ("sho_nsho", "sho_last_error"):
             getattr(lib, name).restype = ctypes.c_int32
@@ -602,3 +610,63 @@ def nsho(nu):
 
 def cache_clear():
     _check(load_library().sho_cache_clear())
+
+
+# ------------------------------------------------------------ set-up side --
+
+def _nsho(nu):
+    return (nu + 1) * (nu + 2) * (nu + 3) // 6
+
+
+def setup_unitary(nu_max):
+    """U[c][s] = <Phi_c | Psi_s> (rows: coefficient order, columns: radial order)."""
+    lib = load_library()
+    N = _nsho(int(nu_max))
+    U = np.empty((N, N))
+    _check(lib.sho_setup_unitary(int(nu_max), U.ctypes.data_as(_dp)))
+    return U
+
+
+def setup_radial(nu_max, sigma, r):
+    """R[k][i] = R_{nr l}(r_i; sigma), k over (nu ascending, l ascending)."""
+    lib = load_library()
+    r = _host_f64(r, (-1,))
+    count = sum(len(range(nu % 2, nu + 1, 2)) for nu in range(int(nu_max) + 1))
+    R = np.empty((count, r.size))
+    _check(lib.sho_setup_radial(int(nu_max), float(sigma), r.size, r.ctypes.data_as(_dp),
+                                R.ctypes.data_as(_dp)))
+    return R
+
+
+def setup_matrix(nu_max, sigma, ell, r, w, P, D):
+    """The atomic matrix D of projectors P_k(r) Y_lm in the Cartesian SHO basis."""
+    lib = load_library()
+    ell = _host_i32(ell, (-1,))
+    r = _host_f64(r, (-1,))
+    w = _host_f64(w, (r.size,))
+    P = _host_f64(P, (ell.size, r.size))
+    D = _host_f64(D, (-1,))
+    if np.all(ell >= 0):  # (a negative l is left to the library to refuse)
+        nproj = int(np.sum(2 * ell + 1))
+        if D.size != nproj * nproj:
+            raise ValueError("D must be [%d][%d]" % (nproj, nproj))
+    N = _nsho(int(nu_max))
+    out = np.empty((N, N))
+    _check(lib.sho_setup_matrix(int(nu_max), float(sigma), ell.size, ell.ctypes.data_as(_i32p),
+                                r.size, r.ctypes.data_as(_dp), w.ctypes.data_as(_dp),
+                                P.ctypes.data_as(_dp), D.ctypes.data_as(_dp),
+                                out.ctypes.data_as(_dp)))
+    return out
+
+
+def setup_quality(nu_max, sigma, ell, r, w, P):
+    """Q[nu], nu = 0..nu_max, of one radial projector (sec. 4)."""
+    lib = load_library()
+    r = _host_f64(r, (-1,))
+    w = _host_f64(w, (r.size,))
+    P = _host_f64(P, (r.size,))
+    Q = np.empty(int(nu_max) + 1)
+    _check(lib.sho_setup_quality(int(nu_max), float(sigma), int(ell), r.size,
+                                 r.ctypes.data_as(_dp), w.ctypes.data_as(_dp),
+                                 P.ctypes.data_as(_dp), Q.ctypes.data_as(_dp)))
+    return Q

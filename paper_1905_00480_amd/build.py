@@ -3,6 +3,7 @@
 Objects:
   sho_plan.cpp     host geometry, g++ -ffp-contract=off (the support membership
                    test must be evaluated in the documented operation order)
+  sho_setup.cpp    set-up side of the basis (host only), g++
   sho_api.cpp      C ABI layer (host HIP runtime calls)
   sho_server.cpp   request server: admission under a byte budget, streams
   sho_kernels.hip  gfx950 kernels
@@ -46,6 +47,10 @@ def build(verbose: bool = False, jobs: int = 3) -> str:
     cmd = ["g++"] + HOST_FLAGS + ["-c", os.path.join(CSRC, "sho_plan.cpp"), "-o", plan_o]
     procs.append((cmd, subprocess.Popen(cmd)))
     objs.append(plan_o)
+    setup_o = os.path.join(BUILD, "sho_setup.o")
+    cmd = ["g++"] + HOST_FLAGS + ["-c", os.path.join(CSRC, "sho_setup.cpp"), "-o", setup_o]
+    procs.append((cmd, subprocess.Popen(cmd)))
+    objs.append(setup_o)
     for src in ("sho_api.cpp", "sho_server.cpp", "sho_kernels.hip", "sho_kernels_f32.hip"):
         o = os.path.join(BUILD, src.rsplit(".", 1)[0] + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
