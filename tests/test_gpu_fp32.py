@@ -136,6 +136,40 @@ def test_fp32_band_counts(nbands):
     _run_fp32(bd, s, accumulate=nbands < 100)
 
 
+def test_fp32_boxes_wider_than_cell():
+    """Supports wider than a small periodic cell: every image contributes."""
+    _run_fp32(_bd(), wl.make_system("f32wide", (8, 9, 7), 0.2, (True,) * 3, 3, 0.6, 3, 4, 41))
+
+
+def test_fp32_isolated_edges_and_empty_support():
+    s = wl.make_system("f32edge", (20, 16, 12), 0.25, (False,) * 3, 6, 0.5, 4, 4, 42)
+    s.pos[0] = [-0.3, 1.0, 1.0]
+    s.pos[1] = [5.2, 4.1, 3.2]
+    s.pos[2] = [-9.0, 1.0, 1.0]   # no support point inside the grid
+    _run_fp32(_bd(), s)
+
+
+def test_fp32_all_nu_values():
+    """Every nu in 0..10 in one FP32 plan."""
+    s = wl.make_system("f32allnu", (30, 28, 26), 0.16, (True,) * 3, 11, None, 0, 6,
+                       60, sigma_range=(0.7, 0.9))
+    s.numax[:] = np.arange(11)
+    _run_fp32(_bd(), s, accumulate=False)
+
+
+def test_fp32_zero_atoms():
+    bd = _bd()
+    p = bd.Plan((8, 8, 8), 0.2, (True,) * 3, np.zeros((0, 3)), [], [], 4, flags=bd.FLAG_FP32)
+    psi = torch.randn(8 * 8 * 8 * 4, dtype=torch.float32, device="cuda")
+    keep = psi.clone()
+    c = torch.empty(0, dtype=torch.float32, device="cuda")
+    p.project(psi, c)
+    p.expand(c, psi)
+    torch.cuda.synchronize()
+    assert torch.equal(psi, keep)
+    p.close()
+
+
 def test_fp32_paper_geometry_sampled():
     """The paper's fcc geometry (11 projections per grid value) at 64 bands:
     sampled atoms and points against the oracle."""
