@@ -26,7 +26,7 @@ namespace sho {
 namespace f32 {
 
 constexpr int kBlock = 64 * kWaves;
-constexpr int kBatch = 8;  // loads in flight per lane and batch
+constexpr int kBatch = 6;  // loads in flight per lane and batch
 
 #define SHO_F32_NU_CASES(X) \
   X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10)
