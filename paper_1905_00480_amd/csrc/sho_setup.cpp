@@ -167,7 +167,8 @@ std::vector<CartState> cart_states(int nu_max) {
 }
 
 // U [N][N] row-major (rows Cartesian, columns radial), shell by shell.
-void build_unitary(int nu_max, double *U) {
+// False if a Gauss-Hermite rule did not come out with all its nodes.
+bool build_unitary(int nu_max, double *U) {
   const auto cart = cart_states(nu_max);
   const auto rad = radial_states(nu_max);
   const size_t N = cart.size();
@@ -182,6 +183,7 @@ void build_unitary(int nu_max, double *U) {
       if (rad[s].nu == nu) ss.push_back((int)s);
     gauss_hermite(nu + 1, &gx, &gw);
     const int nq = (int)gx.size();
+    if (nq != nu + 1) return false;
     std::vector<double> cv(cs.size()), rv(ss.size());
     for (int i = 0; i < nq; ++i) {
       hermite_on(nu, gx[i], hx.data());
@@ -208,6 +210,7 @@ void build_unitary(int nu_max, double *U) {
       }
     }
   }
+  return true;
 }
 
 bool sigma_ok(double s) { return std::isfinite(s) && s > 0.0; }
@@ -219,7 +222,7 @@ extern "C" {
 sho_status sho_setup_unitary(int32_t nu_max, double *U) {
   if (!U) return fail(SHO_E_INVALID, "U must not be NULL");
   if (nu_max < 0 || nu_max > SHO_NU_MAX) return fail(SHO_E_NU_RANGE, "nu_max out of range");
-  build_unitary(nu_max, U);
+  if (!build_unitary(nu_max, U)) return fail(SHO_E_INVALID, "Gauss-Hermite nodes not found");
   return SHO_OK;
 }
 
@@ -253,7 +256,8 @@ sho_status sho_setup_matrix(int32_t nu_max, double sigma, int32_t nrad, const in
   const auto rad = radial_states(nu_max);
   const int64_t N = (int64_t)rad.size();
   std::vector<double> U(N * N);
-  build_unitary(nu_max, U.data());
+  if (!build_unitary(nu_max, U.data()))
+    return fail(SHO_E_INVALID, "Gauss-Hermite nodes not found");
   // F[j][s]: only s with the projector's (l, m) are non-zero
   std::vector<double> F(nproj * N, 0.0);
   int64_t j0 = 0;
