@@ -284,12 +284,21 @@ inline int32_t block_tile_values(const HostPlan &P) {
   return (P.flags & SHO_FLAG_FP32) ? kBlockTileDoubles / 2 : kBlockTileDoubles;
 }
 
-// Whether an R x X block fits: the LDS tile (R X values per band tile) and
-// the x-table staging of one wave (X rows of the widest table).
+// Smallest power of two >= X.
+inline int32_t pow2_ceil(int32_t X) {
+  int32_t p = 1;
+  while (p < X) p <<= 1;
+  return p;
+}
+
+// Whether an R x X block fits: the LDS tile (R rows of pow2_ceil(X) points,
+// the row stride of the block kernel's tile, per band tile) and the x-table
+// staging of one wave (X rows of the widest table).
 inline bool block_shape_ok(const HostPlan &P, int32_t R, int32_t X) {
   const int tbe = 1 << expand_tile_shift(P.nbands, kExpandBlocks,
                                          (P.flags & SHO_FLAG_STORED) != 0);
-  return R >= 1 && X >= 1 && (int64_t)R * X * tbe <= block_tile_values(P) &&
+  return R >= 1 && X >= 1 && X <= 256 &&
+         (int64_t)R * pow2_ceil(X) * tbe <= block_tile_values(P) &&
          X * table_nfp(P.nu_max) <= 256 && R * table_nfp(P.nu_max) <= 256;
 }
 

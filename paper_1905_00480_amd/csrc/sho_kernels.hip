@@ -727,7 +727,7 @@ __device__ inline void add_entry(const EArgs &E, const EntryRec &en, const doubl
 #pragma unroll
         for (int n = 0; n < NF; ++n) val = fma(fx[n], U1[j][n], val);
         if (x >= xa[j] && x < xb[j])
-          atomicAdd(&tile[((int64_t)rr[j] * nxl + x) * TB + bl], val);
+          atomicAdd(&tile[(rr[j] * nxl + x) * TB + bl], val);
       }
     }
   }
@@ -735,7 +735,12 @@ __device__ inline void add_entry(const EArgs &E, const EntryRec &en, const doubl
 
 // One workgroup per (block, band tile): the block's values of psi are read
 // into LDS once, every entry adds its runs (waves take entries round robin),
-// and the block is written back once with plain stores.
+// and the block is written back once with plain stores.  The tile is laid
+// out as [row][X2][band] with X2 the block width rounded up to a power of
+// two, so that a tile slot splits into (row, x, band) with shifts and masks
+// instead of divisions (the index arithmetic of the fill and write-back is a
+// large share of the kernel's instructions); slots past the grid's last
+// column hold zeros and are not written back.
 template <int NUMAX>
 __global__ __launch_bounds__(kBlkBlock) void k_expand_blocks(EArgs E,
                                                             const double *__restrict__ u2,
@@ -750,25 +755,27 @@ __global__ __launch_bounds__(kBlkBlock) void k_expand_blocks(EArgs E,
   const int xe = min(bk.x0 + E.blk_x, E.nx);
   const int nxl = xe - bk.x0;
   const int nrow = min(bk.y0 + E.blk_rows, E.ny) - bk.y0;
-  const int rowbase = bk.z * E.ny + bk.y0;
-  const int per_row = nxl << E.tbe_shift;
-  const int nval = nrow * per_row;
-  // tile value t = (row r, x, band) <-> psi index; b >= B marks a padding band
-  auto gidx = [&](int t, int &b) -> int64_t {
-    const int r = t / per_row;
-    const int rem = t - r * per_row;
-    const int x = rem >> E.tbe_shift;
-    b = btile * TB + (rem & (TB - 1));
-    return ((int64_t)(rowbase + r) * E.nx + bk.x0 + x) * E.B + b;
+  const int x2s = E.blk_x <= 1 ? 0 : 32 - __clz(E.blk_x - 1);
+  const int rs = x2s + E.tbe_shift;
+  const int nval = nrow << rs;  // tile slots, padding columns included
+  const int64_t gbase = ((int64_t)(bk.z * E.ny + bk.y0) * E.nx + bk.x0) * E.B + btile * TB;
+  const int64_t grow = (int64_t)E.nx * E.B;
+  // slot t <-> psi index g; false past the grid's last column or for a
+  // padding band
+  auto slot = [&](int64_t base, int t, int64_t &g) -> bool {
+    const int r = t >> rs;
+    const int x = (t >> E.tbe_shift) & ((1 << x2s) - 1);
+    const int l = t & (TB - 1);
+    g = base + r * grow + (int64_t)__umul24(x, E.B) + l;
+    return x < nxl && btile * TB + l < E.B;
   };
   fill_lds<kBlockTileDoubles / kBlkBlock>(tile, nval, [&](int t) {
-    int bb;
-    const int64_t g = gidx(t, bb);
-    return bb < E.B ? psi[g] : 0.0;
+    int64_t g = 0;
+    return slot(gbase, t, g) ? psi[g] : 0.0;
   });
   __syncthreads();
   const int lane = threadIdx.x & 63;
-  const int slot = lane >> E.tbe_shift;
+  const int lslot = lane >> E.tbe_shift;
   const int bl = lane & (TB - 1);
   const int b = btile * TB + bl;
   const int bc = b < E.B ? b : E.B - 1;
@@ -785,7 +792,7 @@ __global__ __launch_bounds__(kBlkBlock) void k_expand_blocks(EArgs E,
 #define X(N)                                                                          \
   case N:                                                                             \
     if constexpr (N <= NUMAX)                                                         \
-      add_entry<N, NUMAX>(E, en, u2, nxl, tile, xstage, TB, slot, bl, bc);            \
+      add_entry<N, NUMAX>(E, en, u2, 1 << x2s, tile, xstage, TB, lslot, bl, bc);      \
     break;
       X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10)
 #undef X
@@ -793,6 +800,10 @@ __global__ __launch_bounds__(kBlkBlock) void k_expand_blocks(EArgs E,
     en = nxt;
   }
   __syncthreads();
+  // the write-back forms its addresses again (the base is made opaque)
+  // instead of holding them in registers across the entries
+  int64_t gb = gbase;
+  asm volatile("" : "+s"(gb));
   constexpr int kPer = kBlockTileDoubles / kBlkBlock;
   for (int t0 = 0; t0 < nval; t0 += kPer * kBlkBlock) {
     double v[kPer];
@@ -804,11 +815,8 @@ __global__ __launch_bounds__(kBlkBlock) void k_expand_blocks(EArgs E,
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
       const int t = t0 + u * kBlkBlock + (int)threadIdx.x;
-      if (t < nval) {
-        int bb;
-        const int64_t g = gidx(t, bb);
-        if (bb < E.B) psi[g] = v[u];
-      }
+      int64_t g = 0;
+      if (t < nval && slot(gb, t, g)) psi[g] = v[u];
     }
   }
 }
