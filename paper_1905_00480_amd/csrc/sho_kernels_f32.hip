@@ -463,7 +463,9 @@ __device__ inline void add_entry(const EArgs &E, const float *tab, const EntryRe
 // One workgroup per (block, band-pair tile): the block's values of psi are
 // read into LDS once (as doubles), every entry adds its runs, and the block
 // is written back once, rounded to float.  A tile holds at most
-// kBlockTileDoubles / 2 pairs, the LDS bytes of the FP64 tile.
+// kBlockTileDoubles / 2 pairs, the LDS bytes of the FP64 tile, laid out as
+// [row][X2][pair] (X2 the block width rounded up to a power of two) so that
+// the fill and write-back split a slot with shifts and masks.
 template <int NUMAX>
 __global__ __launch_bounds__(kBlkBlock) void k_expand_blocks(EArgs E,
                                                             const float *__restrict__ tab,
@@ -479,15 +481,19 @@ __global__ __launch_bounds__(kBlkBlock) void k_expand_blocks(EArgs E,
   const int xe = min(bk.x0 + E.blk_x, E.nx);
   const int nxl = xe - bk.x0;
   const int nrow = min(bk.y0 + E.blk_rows, E.ny) - bk.y0;
-  const int rowbase = bk.z * E.ny + bk.y0;
-  const int per_row = nxl << E.tbe_shift;
-  const int nval = nrow * per_row;
-  auto gidx = [&](int t, int &b) -> int64_t {
-    const int r = t / per_row;
-    const int rem = t - r * per_row;
-    const int x = rem >> E.tbe_shift;
-    b = btile * TB + (rem & (TB - 1));
-    return ((int64_t)(rowbase + r) * E.nx + bk.x0 + x) * E.B + b;
+  const int x2s = E.blk_x <= 1 ? 0 : 32 - __clz(E.blk_x - 1);
+  const int rs = x2s + E.tbe_shift;
+  const int nval = nrow << rs;  // pair slots, padding columns included
+  const int64_t gbase = ((int64_t)(bk.z * E.ny + bk.y0) * E.nx + bk.x0) * E.B + btile * TB;
+  const int64_t grow = (int64_t)E.nx * E.B;
+  // slot t <-> psi index g; false past the grid's last column or for a
+  // padding pair
+  auto slot = [&](int64_t base, int t, int64_t &g) -> bool {
+    const int r = t >> rs;
+    const int x = (t >> E.tbe_shift) & ((1 << x2s) - 1);
+    const int l = t & (TB - 1);
+    g = base + r * grow + (int64_t)__umul24(x, E.B) + l;
+    return x < nxl && btile * TB + l < E.B;
   };
   constexpr int kPer = kBlockTileDoubles / 2 / kBlkBlock;
   for (int t0 = 0; t0 < nval; t0 += kPer * kBlkBlock) {
@@ -495,9 +501,8 @@ __global__ __launch_bounds__(kBlkBlock) void k_expand_blocks(EArgs E,
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
       const int t = t0 + u * kBlkBlock + (int)threadIdx.x;
-      int bb = 0;
-      const int64_t g = t < nval ? gidx(t, bb) : 0;
-      v[u] = (t < nval && bb < E.B) ? psi[g] : zero2();
+      int64_t g = 0;
+      v[u] = (t < nval && slot(gbase, t, g)) ? psi[g] : zero2();
     }
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
@@ -511,7 +516,7 @@ __global__ __launch_bounds__(kBlkBlock) void k_expand_blocks(EArgs E,
   }
   __syncthreads();
   const int lane = threadIdx.x & 63;
-  const int slot = lane >> E.tbe_shift;
+  const int lslot = lane >> E.tbe_shift;
   const int bl = lane & (TB - 1);
   const int b = btile * TB + bl;
   const int bc = b < E.B ? b : E.B - 1;
@@ -526,7 +531,7 @@ __global__ __launch_bounds__(kBlkBlock) void k_expand_blocks(EArgs E,
 #define X(N)                                                                        \
   case N:                                                                           \
     if constexpr (N <= NUMAX)                                                       \
-      add_entry<N, NUMAX>(E, tab, en, u2, nxl, tile, xstage, TB, slot, bl, bc);     \
+      add_entry<N, NUMAX>(E, tab, en, u2, 1 << x2s, tile, xstage, TB, lslot, bl, bc); \
     break;
       SHO_F32_NU_CASES(X)
 #undef X
@@ -534,6 +539,9 @@ __global__ __launch_bounds__(kBlkBlock) void k_expand_blocks(EArgs E,
     en = nxt;
   }
   __syncthreads();
+  // the write-back forms its addresses again (the base is made opaque)
+  int64_t gb = gbase;
+  asm volatile("" : "+s"(gb));
   for (int t0 = 0; t0 < nval; t0 += kPer * kBlkBlock) {
     Pair v[kPer];
 #pragma unroll
@@ -545,11 +553,8 @@ __global__ __launch_bounds__(kBlkBlock) void k_expand_blocks(EArgs E,
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
       const int t = t0 + u * kBlkBlock + (int)threadIdx.x;
-      if (t < nval) {
-        int bb;
-        const int64_t g = gidx(t, bb);
-        if (bb < E.B) psi[g] = v[u];
-      }
+      int64_t g = 0;
+      if (t < nval && slot(gb, t, g)) psi[g] = v[u];
     }
   }
 }
