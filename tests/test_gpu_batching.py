@@ -167,10 +167,13 @@ def test_batching_config_sampled():
     plan.close()
 
 
-@pytest.mark.parametrize("form", [(0, 0, 0), (1, 0, 0), (1, 1, 1), (1, 2, 16), (1, 16, 8)])
+@pytest.mark.parametrize("form", [(0, 0, 0), (1, 0, 0), (1, 1, 1), (1, 2, 16), (1, 16, 8),
+                                  (1, 3, 12), (1, 5, 10), (1, 2, 7)])
 def test_expansion_forms_match_oracle(mixed, form):
     """Row form, block form at the default shape and at extreme shapes (one
-    point per block; wide and tall blocks), accumulating into random psi."""
+    point per block; wide and tall blocks), and widths that are not powers of
+    two (the tile row is padded to the next one; blocks at the grid's x edge
+    are partial), accumulating into random psi."""
     bd = _bd()
     s, psi, cin, _, (e_ref, e_abs), _ = mixed
     plan = bd.Plan.from_system(s)
@@ -189,7 +192,7 @@ def test_expansion_forms_wide_boxes():
     s = wl.make_system("wide", (8, 9, 7), 0.2, (True,) * 3, 3, 0.6, 3, 2, 41)
     c = wl.coeffs_for(s)
     e_ref, e_abs = oracle.expand(*s.geometry(), c, np.zeros(s.psi_shape), with_abs=True)
-    for form in ((0, 0, 0), (1, 0, 0), (1, 4, 4), (1, 1, 8)):
+    for form in ((0, 0, 0), (1, 0, 0), (1, 4, 4), (1, 1, 8), (1, 3, 5), (1, 2, 3)):
         plan = bd.Plan.from_system(s)
         plan.set_expand(*form)
         out = torch.zeros(s.psi_shape, dtype=torch.float64, device="cuda")

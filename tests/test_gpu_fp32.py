@@ -285,6 +285,25 @@ def test_complex_bands(precision):
     plan.close()
 
 
+@pytest.mark.parametrize("form", [(1, 3, 12), (1, 1, 5), (1, 8, 8)])
+def test_fp32_block_shapes(form):
+    """FP32 expansion with block widths that are not powers of two and with
+    partial blocks at the grid's x edge."""
+    bd = _bd()
+    s = wl.small_mixed()
+    c_in = wl.coeffs_for(s).astype(np.float32)
+    psi = wl.psi_for(s, dtype=np.float32)
+    plan = bd.Plan.from_system(s, flags=bd.FLAG_FP32)
+    plan.set_expand(*form)
+    d_acc = _dev(psi)
+    plan.expand(_dev(c_in), d_acc)
+    a_ref, a_abs = oracle.expand(*s.geometry(), c_in.astype(np.float64),
+                                 psi.astype(np.float64), with_abs=True)
+    k = np.repeat(3 * (int(s.numax.max()) + 1) + 4 + _overlaps(s), s.nbands)
+    _assert_close(_host(d_acc), a_ref, a_abs, k, "fp32 expand form %s" % (form,))
+    plan.close()
+
+
 def test_fp32_tune_keeps_results():
     """The schedule tuner runs on FP32 plans; results stay within the bound."""
     bd = _bd()
