@@ -310,12 +310,11 @@ def diff_step(bd, wl, args):
     c = torch.empty(plan.coeff_doubles, dtype=torch.float64, device="cuda")
     gpsi = torch.zeros_like(psi)
     grad = torch.empty((s.natoms, 3), dtype=torch.float64, device="cuda")
-    wh = w * s.h ** 3
 
     def step():
         plan.project(psi, c)
         gpsi.zero_()
-        plan.expand(wh, gpsi)
+        plan.expand(w, gpsi, alpha=s.h ** 3)
         plan.force(psi, w, grad)
 
     ms, _ = _time_steps(step, args.steps, args.warmup)

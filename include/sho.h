@@ -163,7 +163,12 @@ const char *sho_last_error(void);
 /*
  * Build a reusable plan: per-atom supports (the projection spheres of sec. 6)
  * cut into (z, y) lines, uploaded to the current device.  Host-side work plus
- * synchronous uploads; the plan may then be used from any stream.
+ * synchronous uploads; the plan may then be used from any stream.  Calls of
+ * one plan that use its device scratch (the expansion's plane partials) on
+ * different streams are ordered by the library: each waits for the previous
+ * one.  Work recorded into a captured graph is not ordered that way, so a
+ * graph must not be replayed while another call of its plan runs.  A plan
+ * must not be called from two host threads at once.
  *   rbox   optional host [natoms] support radii (NULL: default rule)
  *   flags  SHO_FLAG_* bits
  * Errors: SHO_E_INVALID, SHO_E_NU_RANGE, SHO_E_UNDERSAMPLED, SHO_E_BOX,
@@ -205,6 +210,17 @@ sho_status sho_plan_project(sho_plan_t plan, const double *psi, double *c,
  * add in an unspecified order.  psi and c must not overlap. */
 sho_status sho_plan_expand(sho_plan_t plan, const double *c, double *psi,
                            void *stream);
+
+/* psi (device) += alpha * expansion of c (device), i.e. the expansion of the
+ * coefficients scaled by alpha (the scaling is applied to c inside the
+ * kernels' z pass; c is not modified).  With alpha = h^3 this is the
+ * gradient of a loss L(c) with respect to psi, dL/dpsi = h^3 expand(dL/dc),
+ * since the projection carries the h^3 of the sampled integral (sec. 3.5).
+ * FP64 plans only.  Errors as sho_plan_expand, and SHO_E_INVALID for a
+ * non-finite alpha. */
+sho_status sho_plan_expand_scaled(sho_plan_t plan, double alpha, const double *c,
+                                  double *psi, void *stream);
+
 
 /*
  * Single precision (SHO_FLAG_FP32 plans), same layouts with float elements:

@@ -1,9 +1,9 @@
 """Differentiable projection: c = P(R) psi with hand-written backward.
 
 Forward:   c[a][n][b] = h^3 sum_{i in S_a} P_an(i; R_a) psi_b(i)   (sho_plan_project)
-Backward:  dL/dpsi    = h^3 sum_a sum_n (dL/dc)[a][n][b] P_an          (sho_plan_expand of
-                        h^3 dL/dc into a zeroed buffer: the expansion is the adjoint of
-                        the projection up to the grid-volume factor)
+Backward:  dL/dpsi    = h^3 sum_a sum_n (dL/dc)[a][n][b] P_an          (sho_plan_expand_scaled
+                        with alpha = h^3 into a zeroed buffer: the expansion is the
+                        adjoint of the projection up to the grid-volume factor)
            dL/dR_a    = sum_{n,b} (dL/dc)[a][n][b] dc[a][n][b]/dR_a    (sho_plan_force)
 
 Derivatives with respect to the atom centres are taken with every support S_a
@@ -21,9 +21,8 @@ from . import binding as bd
 
 def _use_centres(plan, p):
     """Make p the plan's function centres (supports stay as built)."""
-    if not np.array_equal(p, getattr(plan, "_centres", plan._pos)):
+    if not np.array_equal(p, plan.centres()):
         plan.set_centres(p)
-        plan._centres = p.copy()
 
 
 class SHOProject(torch.autograd.Function):
@@ -55,7 +54,7 @@ class SHOProject(torch.autograd.Function):
         grad_psi = grad_pos = None
         if ctx.needs_input_grad[0]:
             grad_psi = torch.zeros_like(psi)
-            plan.expand(g * plan.h ** 3, grad_psi)
+            plan.expand(g, grad_psi, alpha=plan.h ** 3)
         if ctx.needs_input_grad[1]:
             grad_pos = plan.force(psi.contiguous(), g).to(ctx.pos_device)
         return grad_psi, grad_pos, None

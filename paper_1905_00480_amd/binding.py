@@ -52,6 +52,7 @@ EXPORTS = (
     "sho_plan_set_centres", "sho_plan_project", "sho_plan_expand",
     "sho_plan_project_f32", "sho_plan_expand_f32",
     "sho_plan_force", "sho_project", "sho_expand", "sho_force",
+    "sho_plan_expand_scaled",
     "sho_cache_clear", "sho_plan_profile", "sho_plan_profile_read",
     "sho_plan_set_schedule", "sho_plan_get_schedule", "sho_plan_tune",
     "sho_plan_set_expand", "sho_plan_get_expand",
@@ -143,6 +144,7 @@ def load_library(path=None):
     lib.sho_plan_expand.argtypes = [P, _vp, _vp, _vp]
     lib.sho_plan_project_f32.argtypes = [P, _vp, _vp, _vp]
     lib.sho_plan_expand_f32.argtypes = [P, _vp, _vp, _vp]
+    lib.sho_plan_expand_scaled.argtypes = [P, ctypes.c_double, _vp, _vp, _vp]
     lib.sho_plan_force.argtypes = [P, _vp, _vp, _vp, _vp]
     geo = [G, ctypes.c_int32, _dp, _dp, _i32p, ctypes.c_int32]
     lib.sho_project.argtypes = geo + [_vp, _vp, ctypes.c_uint32, _vp]
@@ -249,6 +251,7 @@ class Plan:
         pos = _host_f64(pos, (-1, 3))
         self.natoms = pos.shape[0]
         self._pos = pos
+        self._centres = pos.copy()  # the function centres the plan holds now
         self._sigma = _host_f64(sigma, (self.natoms,))
         self._numax = _host_i32(numax, (self.natoms,))
         self._rbox = None if rbox is None else _host_f64(rbox, (self.natoms,))
@@ -292,6 +295,11 @@ class Plan:
         pos = _host_f64(pos, (self.natoms, 3))
         _check(self._lib.sho_plan_set_centres(self._h, pos.ctypes.data_as(_dp),
                                               _stream(stream)))
+        self._centres = pos.copy()
+
+    def centres(self):
+        """The function centres the plan holds (host copy)."""
+        return self._centres.copy()
 
     def project(self, psi, c=None, stream=None):
         import torch
@@ -304,8 +312,14 @@ class Plan:
                   _dev(c, self.coeff_doubles, "c", f32), _stream(stream)))
         return c
 
-    def expand(self, c, psi, stream=None):
+    def expand(self, c, psi, stream=None, alpha=None):
+        """psi += expansion of c (times alpha, if given: FP64 plans)."""
         f32 = self.fp32
+        if alpha is not None:
+            _check(self._lib.sho_plan_expand_scaled(
+                self._h, float(alpha), _dev(c, self.coeff_doubles, "c"),
+                _dev(psi, self.psi_numel, "psi"), _stream(stream)))
+            return psi
         fn = self._lib.sho_plan_expand_f32 if f32 else self._lib.sho_plan_expand
         _check(fn(self._h, _dev(c, self.coeff_doubles, "c", f32),
                   _dev(psi, self.psi_numel, "psi", f32), _stream(stream)))

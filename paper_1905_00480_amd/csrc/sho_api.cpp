@@ -88,6 +88,11 @@ struct sho_plan_s {
   int64_t blk_bytes = 0;
   bool prof_on = false;
   std::vector<ProfEvent> prof;
+  // Ordering of the plan's own scratch (plane partials) across streams: the
+  // event marks the end of the last call that used it, on scratch_stream.
+  hipEvent_t scratch_ev = nullptr;
+  hipStream_t scratch_stream = nullptr;
+  bool scratch_used = false;
   int64_t device_bytes = 0;
   int64_t stored_bytes = 0;
 };
@@ -106,6 +111,8 @@ hipError_t upload(T **dst, const std::vector<T> &src, int64_t *bytes) {
 }
 
 void free_plan_device(sho_plan_s *p) {
+  if (p->scratch_ev) (void)hipEventDestroy(p->scratch_ev);
+  p->scratch_ev = nullptr;
   if (p->d_atoms) (void)hipFree(p->d_atoms);
   if (p->d_lines) (void)hipFree(p->d_lines);
   if (p->d_bundles) (void)hipFree(p->d_bundles);
@@ -211,6 +218,7 @@ sho::SArgs make_sargs(const sho_plan_s *p, const Group &g) {
   S.B = p->hp.nbands;
   const double h = p->hp.grid.h;
   S.h3 = h * h * h;
+  S.alpha = 1.0;
   return S;
 }
 
@@ -231,6 +239,7 @@ sho::KArgs make_args(const sho_plan_s *p, const Group &g) {
   K.pad = 0;
   const double h = p->hp.grid.h;
   K.h3 = h * h * h;
+  K.alpha = 1.0;
   return K;
 }
 
@@ -285,6 +294,7 @@ sho::EArgs make_eargs(const sho_plan_s *p) {
   E.blk_rows = p->hp.blk_rows;
   E.blk_x = p->hp.blk_x;
   E.ny = p->hp.grid.n[1];
+  E.alpha = 1.0;
   for (int nu = 0; nu <= SHO_NU_MAX + 1; ++nu) E.nu_begin[nu] = 0;
   {
     int nu = 0;
@@ -461,15 +471,44 @@ hipError_t run_project(sho_plan_s *p, const void *psi_v, void *c_v, hipStream_t 
   });
 }
 
-// The expansion's launches on s (arguments checked, scratch allocated).
+// True if s is capturing a graph (no cross-stream ordering is recorded then).
+bool capturing(hipStream_t s) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &st) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return st != hipStreamCaptureStatusNone;
+}
+
+// Calls that use the plan's scratch on different streams are ordered: the
+// call on s waits for the end of the previous one (outside graph capture).
+hipError_t scratch_acquire(sho_plan_s *p, hipStream_t s) {
+  if (!p->scratch_used || p->scratch_stream == s || capturing(s)) return hipSuccess;
+  return hipStreamWaitEvent(s, p->scratch_ev, 0);
+}
+
+hipError_t scratch_release(sho_plan_s *p, hipStream_t s) {
+  if (capturing(s)) return hipSuccess;
+  hipError_t e = hipEventRecord(p->scratch_ev, s);
+  if (e == hipSuccess) {
+    p->scratch_stream = s;
+    p->scratch_used = true;
+  }
+  return e;
+}
+
+// The expansion's launches on s (arguments checked, scratch allocated):
+// psi += alpha * expansion of c, with the plane partials in u2 (the plan's
+// own scratch or the static one; unused by stored and per-atom plans).
 hipError_t run_expand(sho_plan_s *p, const void *c_v, void *psi_v, hipStream_t s,
-                      bool prof) {
+                      bool prof, double *u2_buf, double alpha = 1.0) {
   const double *c = static_cast<const double *>(c_v);
   double *psi = static_cast<double *>(psi_v);
   if (p->fp32) {
     // FP32 plans: plane partials and the block form only
     sho::EArgs E = make_eargs(p);
-    float *u2 = reinterpret_cast<float *>(p->d_u2);
+    float *u2 = reinterpret_cast<float *>(u2_buf);
     hipError_t e = timed(p, prof, SHO_KERNEL_EXPAND_Z, s, [&]() {
       return sho::launch_expand_planes_f32(E, p->d_tab32, static_cast<const float *>(c_v),
                                            u2, s);
@@ -483,12 +522,15 @@ hipError_t run_expand(sho_plan_s *p, const void *c_v, void *psi_v, hipStream_t s
   if (p->hp.flags & SHO_FLAG_STORED) {
     if (p->hp.expand_mode == sho::kExpandBlocks) {
       sho::EArgs E = make_eargs(p);
+      E.alpha = alpha;
       return timed(p, prof, SHO_KERNEL_EXPAND_XY, s,
                    [&]() { return sho::launch_blocks_stored(E, c, psi, s); });
     }
     return timed(p, prof, SHO_KERNEL_EXPAND_XY, s, [&]() {
       for (const Group &g : p->sgroups) {
-        hipError_t e1 = sho::launch_expand_stored(g.nu, make_sargs(p, g), c, psi, s);
+        sho::SArgs S = make_sargs(p, g);
+        S.alpha = alpha;
+        hipError_t e1 = sho::launch_expand_stored(g.nu, S, c, psi, s);
         if (e1 != hipSuccess) return e1;
       }
       return hipSuccess;
@@ -499,20 +541,32 @@ hipError_t run_expand(sho_plan_s *p, const void *c_v, void *psi_v, hipStream_t s
       for (int32_t a = 0; a < p->hp.natoms; ++a) {
         const Group g = atom_group(p, a);
         if (!g.count) continue;
-        hipError_t e1 = sho::launch_expand_atomic(g.nu, make_args(p, g), c, psi, s);
+        sho::KArgs K = make_args(p, g);
+        K.alpha = alpha;
+        hipError_t e1 = sho::launch_expand_atomic(g.nu, K, c, psi, s);
         if (e1 != hipSuccess) return e1;
       }
       return hipSuccess;
     });
   }
   sho::EArgs E = make_eargs(p);
+  E.alpha = alpha;
   hipError_t e = timed(p, prof, SHO_KERNEL_EXPAND_Z, s,
-                       [&]() { return sho::launch_expand_planes(E, c, p->d_u2, s); });
+                       [&]() { return sho::launch_expand_planes(E, c, u2_buf, s); });
   if (e == hipSuccess)
     e = timed(p, prof, SHO_KERNEL_EXPAND_XY, s, [&]() {
-      return p->hp.expand_mode == sho::kExpandBlocks ? sho::launch_blocks(E, p->d_u2, psi, s)
-                                                     : sho::launch_rows(E, p->d_u2, psi, s);
+      return p->hp.expand_mode == sho::kExpandBlocks ? sho::launch_blocks(E, u2_buf, psi, s)
+                                                     : sho::launch_rows(E, u2_buf, psi, s);
     });
+  return e;
+}
+
+// run_expand on the plan's own scratch, ordered against its other users.
+hipError_t run_expand_own(sho_plan_s *p, const void *c, void *psi, hipStream_t s, bool prof,
+                          double alpha = 1.0) {
+  hipError_t e = scratch_acquire(p, s);
+  if (e == hipSuccess) e = run_expand(p, c, psi, s, prof, p->d_u2, alpha);
+  if (e == hipSuccess) e = scratch_release(p, s);
   return e;
 }
 
@@ -647,6 +701,7 @@ sho_status sho_plan_create(const sho_grid *grid, int32_t natoms,
                             nullptr);
     }
   }
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&p->scratch_ev, hipEventDisableTiming);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     free_plan_device(p);
@@ -788,7 +843,18 @@ sho_status sho_plan_expand(sho_plan_t p, const double *c, double *psi,
   sho_status st = check_project(p, psi, c);
   if (st != SHO_OK || p->hp.coeff_rows == 0) return st;
   if ((st = ensure_u2(p)) != SHO_OK) return st;
-  hipError_t e = run_expand(p, c, psi, (hipStream_t)stream, p->prof_on);
+  hipError_t e = run_expand_own(p, c, psi, (hipStream_t)stream, p->prof_on);
+  if (e != hipSuccess) return hip_fail(e, "expand launch");
+  return SHO_OK;
+}
+
+sho_status sho_plan_expand_scaled(sho_plan_t p, double alpha, const double *c, double *psi,
+                                  void *stream) {
+  if (!std::isfinite(alpha)) return fail(SHO_E_INVALID, "alpha must be finite");
+  sho_status st = check_project(p, psi, c);
+  if (st != SHO_OK || p->hp.coeff_rows == 0) return st;
+  if ((st = ensure_u2(p)) != SHO_OK) return st;
+  hipError_t e = run_expand_own(p, c, psi, (hipStream_t)stream, p->prof_on, alpha);
   if (e != hipSuccess) return hip_fail(e, "expand launch");
   return SHO_OK;
 }
@@ -805,7 +871,7 @@ sho_status sho_plan_expand_f32(sho_plan_t p, const float *c, float *psi, void *s
   sho_status st = check_project(p, psi, c, 1);
   if (st != SHO_OK || p->hp.coeff_rows == 0) return st;
   if ((st = ensure_u2(p)) != SHO_OK) return st;
-  hipError_t e = run_expand(p, c, psi, (hipStream_t)stream, p->prof_on);
+  hipError_t e = run_expand_own(p, c, psi, (hipStream_t)stream, p->prof_on);
   if (e != hipSuccess) return hip_fail(e, "expand launch");
   return SHO_OK;
 }
@@ -1037,7 +1103,7 @@ sho_status sho_plan_apply(sho_plan_t p, const double *psi, const double *D, doub
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = run_project(p, psi, c, s, p->prof_on);
   if (e == hipSuccess) e = run_multiply(p, D, c, d, s);
-  if (e == hipSuccess) e = run_expand(p, d, out, s, p->prof_on);
+  if (e == hipSuccess) e = run_expand_own(p, d, out, s, p->prof_on);
   if (e != hipSuccess) return hip_fail(e, "apply launch");
   return SHO_OK;
 }
@@ -1100,7 +1166,7 @@ sho_status sho_graph_create(sho_plan_t p, const double *psi, double *c, double *
   if ((st = ensure_u2(p)) != SHO_OK) return st;
   return capture(p, [&](hipStream_t cs) {
     hipError_t e1 = run_project(p, psi, c, cs, false);
-    if (e1 == hipSuccess) e1 = run_expand(p, c, out, cs, false);
+    if (e1 == hipSuccess) e1 = run_expand(p, c, out, cs, false, p->d_u2);
     return e1;
   }, g);
 }
@@ -1117,7 +1183,7 @@ sho_status sho_graph_create_apply(sho_plan_t p, const double *psi, const double 
   return capture(p, [&](hipStream_t cs) {
     hipError_t e1 = run_project(p, psi, c, cs, false);
     if (e1 == hipSuccess) e1 = run_multiply(p, D, c, d, cs);
-    if (e1 == hipSuccess) e1 = run_expand(p, d, out, cs, false);
+    if (e1 == hipSuccess) e1 = run_expand(p, d, out, cs, false, p->d_u2);
     return e1;
   }, g);
 }
@@ -1169,9 +1235,13 @@ std::string cache_key(const sho_grid *grid, int32_t natoms, const double *pos,
   return k;
 }
 
-sho_status cached_plan(const sho_grid *grid, int32_t natoms, const double *pos,
-                       const double *sigma, const int32_t *numax,
-                       int32_t nbands, uint32_t flags, sho_plan_t *out) {
+// Runs f(plan) with the plan for this geometry, built or reused from the
+// cache.  The cache lock is held until f returns (f only queues work), so
+// that no other thread can evict and destroy the plan while it is in use.
+template <typename F>
+sho_status with_cached_plan(const sho_grid *grid, int32_t natoms, const double *pos,
+                            const double *sigma, const int32_t *numax, int32_t nbands,
+                            uint32_t flags, F &&f) {
   if (!grid || natoms < 0 || (natoms > 0 && (!pos || !sigma || !numax)))
     return fail(SHO_E_INVALID, "NULL geometry arguments");
   int dev = 0;
@@ -1181,8 +1251,7 @@ sho_status cached_plan(const sho_grid *grid, int32_t natoms, const double *pos,
   for (auto it = g_cache.begin(); it != g_cache.end(); ++it) {
     if (it->first == key) {
       g_cache.splice(g_cache.begin(), g_cache, it);
-      *out = g_cache.front().second;
-      return SHO_OK;
+      return f(g_cache.front().second);
     }
   }
   sho_plan_t p = nullptr;
@@ -1194,8 +1263,7 @@ sho_status cached_plan(const sho_grid *grid, int32_t natoms, const double *pos,
     sho_plan_destroy(g_cache.back().second);
     g_cache.pop_back();
   }
-  *out = p;
-  return SHO_OK;
+  return f(p);
 }
 
 }  // namespace
@@ -1206,30 +1274,25 @@ sho_status sho_project(const sho_grid *grid, int32_t natoms, const double *pos,
                        const double *sigma, const int32_t *numax,
                        int32_t nbands, const double *psi, double *c,
                        uint32_t flags, void *stream) {
-  sho_plan_t p = nullptr;
-  sho_status st = cached_plan(grid, natoms, pos, sigma, numax, nbands, flags, &p);
-  if (st != SHO_OK) return st;
-  return sho_plan_project(p, psi, c, stream);
+  return with_cached_plan(grid, natoms, pos, sigma, numax, nbands, flags,
+                          [&](sho_plan_t p) { return sho_plan_project(p, psi, c, stream); });
 }
 
 sho_status sho_expand(const sho_grid *grid, int32_t natoms, const double *pos,
                       const double *sigma, const int32_t *numax,
                       int32_t nbands, const double *c, double *psi,
                       uint32_t flags, void *stream) {
-  sho_plan_t p = nullptr;
-  sho_status st = cached_plan(grid, natoms, pos, sigma, numax, nbands, flags, &p);
-  if (st != SHO_OK) return st;
-  return sho_plan_expand(p, c, psi, stream);
+  return with_cached_plan(grid, natoms, pos, sigma, numax, nbands, flags,
+                          [&](sho_plan_t p) { return sho_plan_expand(p, c, psi, stream); });
 }
 
 sho_status sho_force(const sho_grid *grid, int32_t natoms, const double *pos,
                      const double *sigma, const int32_t *numax, int32_t nbands,
                      const double *psi, const double *w, double *grad,
                      uint32_t flags, void *stream) {
-  sho_plan_t p = nullptr;
-  sho_status st = cached_plan(grid, natoms, pos, sigma, numax, nbands, flags, &p);
-  if (st != SHO_OK) return st;
-  return sho_plan_force(p, psi, w, grad, stream);
+  return with_cached_plan(grid, natoms, pos, sigma, numax, nbands, flags, [&](sho_plan_t p) {
+    return sho_plan_force(p, psi, w, grad, stream);
+  });
 }
 
 sho_status sho_cache_clear(void) {

@@ -372,7 +372,7 @@ __attribute__((amdgpu_waves_per_eu(waves_per_eu(NU + 1)))) void k_expand_atomic(
   fill_lds<4>(cin, NS * TB, [&](int t) {
     const int n = t >> K.tb_shift;
     const int bb = tile * TB + (t & (TB - 1));
-    return bb < K.B ? c[(A.coeff_row + n) * K.B + bb] : 0.0;
+    return bb < K.B ? K.alpha * c[(A.coeff_row + n) * K.B + bb] : 0.0;
   });
   __syncthreads();
   const int w = wave_id();
@@ -461,7 +461,7 @@ __global__ __launch_bounds__(256) void k_u2(EArgs E, const double *__restrict__ 
   const int b0 = blockIdx.y * kU2Tile;
   fill_lds<8>(cs, NS * kU2Tile, [&](int t) {
     const int n = t / kU2Tile, bl = t % kU2Tile;
-    return (b0 + bl < E.B) ? c[(A.coeff_row + n) * E.B + b0 + bl] : 0.0;
+    return (b0 + bl < E.B) ? E.alpha * c[(A.coeff_row + n) * E.B + b0 + bl] : 0.0;
   });
   __syncthreads();
   const double *tz = E.tab + A.tab_off + (int64_t)(A.mx + A.my) * A.tab_nfp;
@@ -482,8 +482,6 @@ __global__ __launch_bounds__(256) void k_u2(EArgs E, const double *__restrict__ 
       for (int nx = 0; nx < NF - ny; ++nx, ++q) {
         double acc = 0.0;
         // C index of (nx, ny, nz): nz-major, then ny, nx fastest
-        int idx = nx;
-        int rowcnt = 0;
 #pragma unroll
         for (int nz = 0; nz < NF; ++nz) {
           if (nx + ny + nz <= NU) {
@@ -496,8 +494,6 @@ __global__ __launch_bounds__(256) void k_u2(EArgs E, const double *__restrict__ 
             acc = fma(fz[nz], cs[(base + nx) * kU2Tile + bl], acc);
           }
         }
-        (void)idx;
-        (void)rowcnt;
         out[(int64_t)q * E.B] = acc;
       }
     }
@@ -964,8 +960,8 @@ __global__ __launch_bounds__(kStoredBlock) void k_expand_stored(
 #pragma unroll
   for (int m = 0; m < NK; ++m) {
     const int n = q * NK + m;
-    cA[m] = (n < NS && okA) ? c[(row0 + n) * S.B + bA] : 0.0;
-    cB[m] = (n < NS && okB) ? c[(row0 + n) * S.B + bB] : 0.0;
+    cA[m] = (n < NS && okA) ? S.alpha * c[(row0 + n) * S.B + bA] : 0.0;
+    cB[m] = (n < NS && okB) ? S.alpha * c[(row0 + n) * S.B + bB] : 0.0;
   }
   for (int k = it.k0 + 16 * w; k < it.k1; k += 16 * 4) {
     const int kp = k + col;
@@ -1022,8 +1018,8 @@ __device__ inline void add_entry_stored(const EArgs &E, const EntryRec &en,
 #pragma unroll
   for (int m = 0; m < NK; ++m) {
     const int n = q * NK + m;
-    cA[m] = (n < NS && okA) ? c[(row0 + n) * E.B + bA] : 0.0;
-    cB[m] = (n < NS && okB) ? c[(row0 + n) * E.B + bB] : 0.0;
+    cA[m] = (n < NS && okA) ? E.alpha * c[(row0 + n) * E.B + bA] : 0.0;
+    cB[m] = (n < NS && okB) ? E.alpha * c[(row0 + n) * E.B + bB] : 0.0;
   }
   const uint32_t mydesc = lane < en.nruns ? as_const(E.run_desc)[en.run_begin + lane] : 0u;
   const int64_t mybase = lane < en.nruns ? E.desc_pbase[en.run_begin + lane] : 0;

@@ -1,7 +1,7 @@
 // sho_kernels_f32.hip -- single-precision projection and expansion.
 //
 // The paper measures its kernels in float as well as double (sec. 6,
-// table 4).  An FP32 plan holds an even number 2P of bands; each lane works
+// table 2).  An FP32 plan holds an even number 2P of bands; each lane works
 // on one pair of adjacent bands (one aligned 8-byte float pair), so that
 // every record of the plan, every launch shape and scratch size is that of
 // an FP64 plan with P bands, and each load and store moves the same 8 bytes

@@ -30,6 +30,7 @@ struct KArgs {
   int32_t ntiles;            // band tiles per atom
   int32_t pad;
   double h3;
+  double alpha;              // expansion: psi += alpha * sum_n c P_n
 };
 
 // Argument block of the row-owner expansion.
@@ -61,6 +62,7 @@ struct EArgs {
   int32_t blk_rows;     // R
   int32_t blk_x;        // X
   int32_t ny;
+  double alpha;         // psi += alpha * sum_n c P_n (applied to c in the z pass)
 };
 
 // Argument block of the stored-projector kernels.
@@ -74,6 +76,7 @@ struct SArgs {
   int32_t nitems;
   int32_t B;
   double h3;
+  double alpha;              // expansion: psi += alpha * sum_n c P_n
 };
 
 // Samples the 1D tables of every atom (rows padded with zeros).

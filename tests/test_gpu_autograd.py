@@ -83,3 +83,22 @@ def test_gradcheck_small():
     assert torch.autograd.gradcheck(f, (psi, pos), eps=1e-6, atol=1e-7, rtol=1e-6,
                                     nondet_tol=1e-12)
     plan.close()
+
+
+def test_direct_set_centres_between_autograd_calls():
+    """A direct Plan.set_centres between two autograd projections at the same
+    positions: the second must move the centres back (the plan tracks the
+    centres it holds), so both equal the oracle at those positions."""
+    bd, ag = _mods()
+    s = wl.make_system("setc", (24, 22, 20), 0.2, (True,) * 3, 3, 0.6, 4, 4, 83)
+    psi_h = wl.psi_for(s)
+    plan = bd.Plan.from_system(s)
+    psi = torch.from_numpy(psi_h).cuda()
+    pos = torch.from_numpy(s.pos.copy())
+    c0 = ag.project(psi, pos, plan).cpu().numpy()
+    plan.set_centres(s.pos + 0.05)
+    c1 = ag.project(psi, pos, plan).cpu().numpy()
+    ref, ab = oracle.project(*s.geometry(), psi_h, with_abs=True)
+    for c in (c0, c1):
+        assert np.all(np.abs(c - ref) <= 1e-12 * ab + 1e-300)
+    plan.close()

@@ -78,6 +78,24 @@ def run_all(bd, s, psi_in=True, force=True):
     plan.close()
 
 
+def test_scaled_expansion():
+    """sho_plan_expand_scaled: psi += alpha * expansion of c, against the
+    oracle's expansion of alpha * c."""
+    bd = _bd()
+    s = wl.small_periodic()
+    plan = bd.Plan.from_system(s)
+    c_in = wl.coeffs_for(s)
+    psi = wl.psi_for(s)
+    alpha = 0.2 ** 3 * 1.7
+    d_out = _dev(psi)
+    plan.expand(_dev(c_in), d_out, alpha=alpha)
+    ref, ab = oracle.expand(*s.geometry(), alpha * c_in, psi, with_abs=True)
+    assert_parity(_host(d_out), ref, ab, "expand_scaled")
+    with pytest.raises(bd.ShoError):
+        plan.expand(_dev(c_in), d_out, alpha=float("nan"))
+    plan.close()
+
+
 def test_tiny_config():
     bd = _bd()
     run_all(bd, wl.tiny())
