@@ -111,6 +111,27 @@ typedef int32_t sho_status;
                                              entry points, the derivative, the
                                              atomic-matrix product and graphs
                                              refuse such a plan. */
+#define SHO_FLAG_DETERMINISTIC 0x20u      /* bitwise reproducible results:
+                                             every sum (over a support, over
+                                             overlapping atoms, over band
+                                             tiles) is taken in an order fixed
+                                             by the plan, never through
+                                             atomics.  The projection and the
+                                             derivative keep one coefficient
+                                             tile per wave, added in wave
+                                             order, and one work item per
+                                             atom; the expansion takes the
+                                             owner form (SHO_EXPAND_OWNER).
+                                             Repeated calls on the same inputs
+                                             give identical bits.  FP64 only;
+                                             not with SHO_FLAG_STORED,
+                                             SHO_FLAG_PER_ATOM or
+                                             SHO_FLAG_FP32 (SHO_E_INVALID). */
+
+/* Expansion forms (sho_plan_set_expand) */
+#define SHO_EXPAND_ROWS 0
+#define SHO_EXPAND_BLOCKS 1
+#define SHO_EXPAND_OWNER 2
 
 /* Projection launch schedules (sho_plan_set_schedule, sho_plan_tune) */
 #define SHO_SCHED_BY_NU 0      /* one launch per cut-off nu */
@@ -318,8 +339,15 @@ sho_status sho_plan_get_schedule(sho_plan_t plan, int32_t *schedule,
  *              row loads its atom plane's partial sums;
  *   1  blocks: one workgroup per block of block_rows rows x block_x points of
  *              one plane; the partial sums of an atom plane are loaded once
- *              for all its runs in the block (default).
- * Both read and write every touched value of psi once with plain loads and
+ *              for all its runs in the block (default);
+ *   2  owner:  one wavefront per strip of R rows x block_x points (16 or 32)
+ *              of one plane and one tile of T bands (T = 16, or 8 for plans
+ *              of at most 8 bands; R = 64 / T, block_rows must be 0 or R):
+ *              each lane keeps its row's values in registers and adds the
+ *              atoms touching the strip in the plan's order, without
+ *              atomics, so the result is bitwise reproducible (the form of
+ *              SHO_FLAG_DETERMINISTIC plans, which accept no other).
+ * All read and write every touched value of psi once with plain loads and
  * stores.  For SHO_FLAG_STORED plans the forms are: 0 the atom-owner form
  * (global atomics, default for nu_max > 2), 1 the block form with the
  * products on matrix cores (default for nu_max <= 2).  block_rows = block_x = 0 picks the default shape; a shape whose

@@ -36,12 +36,14 @@ FLAG_ALLOW_UNDERSAMPLED = 0x2
 FLAG_HOST_ONLY = 0x4
 FLAG_PER_ATOM = 0x8
 FLAG_FP32 = 0x10
+FLAG_DETERMINISTIC = 0x20
 SCHED_BY_NU = 0
 SCHED_SINGLE = 1
 SCHED_SINGLE_LPT = 2
 SCHED_XCD = 4
 EXPAND_ROWS = 0
 EXPAND_BLOCKS = 1
+EXPAND_OWNER = 2
 SCHEDULES = (SCHED_BY_NU, SCHED_SINGLE, SCHED_SINGLE_LPT,
              SCHED_BY_NU | SCHED_XCD, SCHED_SINGLE | SCHED_XCD, SCHED_SINGLE_LPT | SCHED_XCD)
 
@@ -382,7 +384,8 @@ class Plan:
         return sc.value, bt.value, tp.value
 
     def set_expand(self, mode, block_rows=0, block_x=0):
-        """Expansion form: EXPAND_ROWS or EXPAND_BLOCKS (with block shape)."""
+        """Expansion form: EXPAND_ROWS, EXPAND_BLOCKS or EXPAND_OWNER (with
+        block shape; 0 picks the default)."""
         _check(self._lib.sho_plan_set_expand(self._h, int(mode), int(block_rows),
                                              int(block_x)))
 

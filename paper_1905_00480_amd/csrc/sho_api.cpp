@@ -80,6 +80,7 @@ struct sho_plan_s {
   sho::WorkRec *d_work_proj = nullptr;  // the projection's launch order
   int64_t sched_version = 0;      // bumped whenever the work items change
   int64_t sched_bytes = 0;        // device bytes of the schedule tables
+  double *d_gpart = nullptr;           // deterministic derivative: per-tile sums
   int64_t *d_doff = nullptr;           // per-atom offsets of the atomic matrices
   int64_t *d_desc_pbase = nullptr;     // stored plans: block descriptors -> P
   sho::BlockRec *d_blocks = nullptr;   // block form of the expansion
@@ -137,6 +138,8 @@ void free_plan_device(sho_plan_s *p) {
   p->d_u2 = nullptr;
   if (p->d_doff) (void)hipFree(p->d_doff);
   p->d_doff = nullptr;
+  if (p->d_gpart) (void)hipFree(p->d_gpart);
+  p->d_gpart = nullptr;
   if (p->d_desc_pbase) (void)hipFree(p->d_desc_pbase);
   p->d_desc_pbase = nullptr;
   for (void *q : {(void *)p->d_stored, (void *)p->d_run_poff, (void *)p->d_atom_poff,
@@ -236,7 +239,7 @@ sho::KArgs make_args(const sho_plan_s *p, const Group &g) {
   K.B = p->hp.nbands;
   K.tb_shift = p->hp.tb_shift;
   K.ntiles = (p->hp.nbands + (1 << K.tb_shift) - 1) >> K.tb_shift;
-  K.pad = 0;
+  K.det = (p->hp.flags & SHO_FLAG_DETERMINISTIC) ? 1 : 0;
   const double h = p->hp.grid.h;
   K.h3 = h * h * h;
   K.alpha = 1.0;
@@ -361,6 +364,11 @@ int64_t estimate_device_bytes(const sho::HostPlan &hp) {
 }
 
 void build_default_blocks(sho::HostPlan *hp) {
+  if (hp->flags & SHO_FLAG_DETERMINISTIC) {
+    hp->expand_mode = sho::kExpandOwner;
+    sho::build_blocks(hp, sho::owner_rows(*hp), 32);
+    return;
+  }
   int32_t R = 0, X = 0;
   sho::default_block_shape(*hp, &R, &X);
   sho::build_blocks(hp, R, X);
@@ -555,8 +563,14 @@ hipError_t run_expand(sho_plan_s *p, const void *c_v, void *psi_v, hipStream_t s
                        [&]() { return sho::launch_expand_planes(E, c, u2_buf, s); });
   if (e == hipSuccess)
     e = timed(p, prof, SHO_KERNEL_EXPAND_XY, s, [&]() {
-      return p->hp.expand_mode == sho::kExpandBlocks ? sho::launch_blocks(E, u2_buf, psi, s)
-                                                     : sho::launch_rows(E, u2_buf, psi, s);
+      switch (p->hp.expand_mode) {
+        case sho::kExpandBlocks:
+          return sho::launch_blocks(E, u2_buf, psi, s);
+        case sho::kExpandOwner:
+          return sho::launch_owner(E, u2_buf, psi, s);
+        default:
+          return sho::launch_rows(E, u2_buf, psi, s);
+      }
     });
   return e;
 }
@@ -595,6 +609,11 @@ sho_status sho_plan_create(const sho_grid *grid, int32_t natoms,
                   "SHO_FLAG_FP32 does not combine with SHO_FLAG_STORED or SHO_FLAG_PER_ATOM");
     nbands /= 2;  // the kernels work on band pairs
   }
+  if ((flags & SHO_FLAG_DETERMINISTIC) &&
+      (flags & (SHO_FLAG_STORED | SHO_FLAG_PER_ATOM | SHO_FLAG_FP32)))
+    return fail(SHO_E_INVALID,
+                "SHO_FLAG_DETERMINISTIC does not combine with SHO_FLAG_STORED, "
+                "SHO_FLAG_PER_ATOM or SHO_FLAG_FP32");
   sho_plan_s *p = new (std::nothrow) sho_plan_s();
   if (!p) return fail(SHO_E_NOMEM, "host allocation failed");
   p->fp32 = f32;
@@ -606,8 +625,9 @@ sho_status sho_plan_create(const sho_grid *grid, int32_t natoms,
     return fail(st, msg);
   }
   // FP32 plans keep the projection's coefficient tile in double for both
-  // bands of a pair: half the LDS budget per lane value
-  const size_t lds_div = f32 ? 2 : 1;
+  // bands of a pair: half the LDS budget per lane value; deterministic plans
+  // keep one tile per wave
+  const size_t lds_div = f32 ? 2 : (flags & SHO_FLAG_DETERMINISTIC) ? sho::kWaves : 1;
   if (flags & SHO_FLAG_HOST_ONLY) {
     // geometry and sizes only; work split as for a 64 KiB workgroup LDS
     const int tbs = sho::choose_tb_shift(nbands, p->hp.nu_max, (65536 - 1024) / lds_div);
@@ -701,6 +721,12 @@ sho_status sho_plan_create(const sho_grid *grid, int32_t natoms,
                             nullptr);
     }
   }
+  if (e == hipSuccess && (flags & SHO_FLAG_DETERMINISTIC)) {
+    // per-(atom, band tile) derivative sums, for any band tile down to one
+    const int64_t gb = std::max<int64_t>((int64_t)p->hp.natoms * nbands * 3, 1) * sizeof(double);
+    e = hipMalloc((void **)&p->d_gpart, gb);
+    if (e == hipSuccess) p->device_bytes += gb;
+  }
   if (e == hipSuccess) e = hipEventCreateWithFlags(&p->scratch_ev, hipEventDisableTiming);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
@@ -777,7 +803,7 @@ sho_status sho_plan_get_info(sho_plan_t p, sho_plan_info *info) {
   info->union_points = p->hp.union_points;
   // the row kernel moves whole chunks of touched rows: with 32 or 64 bands
   // per tile a chunk spans 64 or 32 points (2048 doubles)
-  info->expand_points = p->hp.expand_mode == sho::kExpandBlocks
+  info->expand_points = p->hp.expand_mode != sho::kExpandRows
                             ? p->hp.block_points
                             : p->hp.rows_touched * (int64_t)p->hp.grid.n[0];
   info->expand_scratch_doubles = p->hp.u2_doubles;
@@ -887,7 +913,12 @@ sho_status sho_plan_force(sho_plan_t p, const double *psi, const double *w,
       !device_range_ok(grad, 3 * (int64_t)p->hp.natoms * (int64_t)sizeof(double)))
     return fail(SHO_E_INVALID, "psi, w and grad must be device buffers of the plan's sizes");
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e = sho::launch_fill(grad, 3 * (int64_t)p->hp.natoms, 0.0, s);
+  const bool det = (p->hp.flags & SHO_FLAG_DETERMINISTIC) != 0;
+  // deterministic plans write every (atom, band tile) sum, then add them in
+  // tile order; the others add into a zeroed grad with atomics
+  hipError_t e = det ? hipSuccess : sho::launch_fill(grad, 3 * (int64_t)p->hp.natoms, 0.0, s);
+  if (e == hipSuccess && det) e = sho::launch_fill(p->d_gpart, 3 * (int64_t)p->hp.natoms *
+                                                                   p->hp.nbands, 0.0, s);
   if (e != hipSuccess) return hip_fail(e, "fill");
   e = timed(p, p->prof_on, SHO_KERNEL_FORCE, s, [&]() {
     if (p->hp.flags & SHO_FLAG_PER_ATOM) {
@@ -899,11 +930,14 @@ sho_status sho_plan_force(sho_plan_t p, const double *psi, const double *w,
       }
       return hipSuccess;
     }
+    sho::KArgs K0 = make_args(p, Group{0, 0, 0});
     for (const Group &g : p->groups) {
-      hipError_t e1 = sho::launch_force(g.nu, make_args(p, g), psi, w, grad, s);
+      hipError_t e1 = sho::launch_force(g.nu, make_args(p, g), psi, w, grad, s,
+                                        det ? p->d_gpart : nullptr);
       if (e1 != hipSuccess) return e1;
     }
-    return hipSuccess;
+    return det ? sho::launch_force_sum(p->d_gpart, p->hp.natoms, K0.ntiles, grad, s)
+               : hipSuccess;
   });
   if (e != hipSuccess) return hip_fail(e, "force launch");
   return SHO_OK;
@@ -921,7 +955,9 @@ sho_status sho_plan_set_schedule(sho_plan_t p, int32_t schedule, int32_t band_ti
   if (band_tile == 0) tbs = p->hp.tb_shift;
   if (tbs < 0) return fail(SHO_E_INVALID, "band_tile must be 0 or a power of two <= 64");
   const size_t limit = (p->hp.flags & SHO_FLAG_HOST_ONLY)
-                           ? (65536 - 1024) / (p->fp32 ? 2 : 1)
+                           ? (65536 - 1024) / (p->fp32 ? 2
+                                               : (p->hp.flags & SHO_FLAG_DETERMINISTIC) ? sho::kWaves
+                                                                                        : 1)
                            : p->lds_limit;
   if (sho::lds_tile_bytes(p->hp.nu_max + 2, 1 << tbs) > limit)
     return fail(SHO_E_BOX, "band tile too wide for the workgroup LDS");
@@ -949,10 +985,30 @@ sho_status sho_plan_get_schedule(sho_plan_t p, int32_t *schedule, int32_t *band_
 sho_status sho_plan_set_expand(sho_plan_t p, int32_t mode, int32_t block_rows,
                                int32_t block_x) {
   if (!p) return fail(SHO_E_INVALID, "NULL plan");
-  if (mode != sho::kExpandRows && mode != sho::kExpandBlocks)
+  if (mode != sho::kExpandRows && mode != sho::kExpandBlocks && mode != sho::kExpandOwner)
     return fail(SHO_E_INVALID, "unknown expansion form");
   if (p->fp32 && mode != sho::kExpandBlocks)
     return fail(SHO_E_INVALID, "FP32 plans expand in the block form only");
+  if ((p->hp.flags & SHO_FLAG_STORED) && mode == sho::kExpandOwner)
+    return fail(SHO_E_INVALID, "stored plans expand in the row or block form");
+  if ((p->hp.flags & SHO_FLAG_DETERMINISTIC) && mode != sho::kExpandOwner)
+    return fail(SHO_E_INVALID, "deterministic plans expand in the owner form only");
+  if (mode == sho::kExpandOwner) {
+    const int32_t R = sho::owner_rows(p->hp);
+    const int32_t X = block_x ? block_x : 32;
+    if ((block_rows && block_rows != R) || !sho::owner_width_ok(X))
+      return fail(SHO_E_INVALID, "owner form: block_rows must be 0 or 64 / band tile, "
+                                 "block_x 0, 16 or 32");
+    if (!(p->hp.flags & SHO_FLAG_HOST_ONLY)) {
+      hipError_t e = hipDeviceSynchronize();
+      if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+    }
+    sho::build_blocks(&p->hp, R, X);
+    if (!(p->hp.flags & SHO_FLAG_HOST_ONLY)) {
+      hipError_t e = upload_blocks(p);
+      if (e != hipSuccess) return hip_fail(e, "block upload");
+    }
+  }
   if (mode == sho::kExpandBlocks) {
     int32_t R = block_rows, X = block_x;
     if (R == 0 && X == 0) sho::default_block_shape(p->hp, &R, &X);

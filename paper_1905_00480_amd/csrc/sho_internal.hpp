@@ -141,6 +141,7 @@ inline uint32_t pack_run(int r, int xa, int xb) {
 // Expansion forms.
 constexpr int32_t kExpandRows = 0;
 constexpr int32_t kExpandBlocks = 1;
+constexpr int32_t kExpandOwner = 2;  // one wave per strip, values in registers
 constexpr int kBlockTileDoubles = 4096;  // LDS tile of a block workgroup
 
 // Rows handled by one expansion workgroup.
@@ -273,6 +274,7 @@ void build_blocks(HostPlan *P, int32_t R, int32_t X);
 // the wave with run slots.
 inline int expand_tile_shift(int nbands, int mode, bool stored = false) {
   if (stored) return nbands > 16 ? 5 : 4;  // 16-band matrix-core blocks, <= 2
+  if (mode == kExpandOwner) return nbands > 8 ? 4 : 3;
   if (nbands > 32) return 6;
   if (mode == kExpandRows || nbands > 16) return 5;
   return nbands > 8 ? 4 : 3;
@@ -301,6 +303,13 @@ inline bool block_shape_ok(const HostPlan &P, int32_t R, int32_t X) {
          (int64_t)R * pow2_ceil(X) * tbe <= block_tile_values(P) &&
          X * table_nfp(P.nu_max) <= 256 && R * table_nfp(P.nu_max) <= 256;
 }
+
+// Owner form: a strip is 64 / (bands per tile) rows (one per lane group of a
+// wave) by X points, X one of the widths the kernel is built for.
+inline int32_t owner_rows(const HostPlan &P) {
+  return 64 >> expand_tile_shift(P.nbands, kExpandOwner);
+}
+inline bool owner_width_ok(int32_t X) { return X == 16 || X == 32; }
 
 // Default block shape: as wide in x as the staging allows (at most 32 points,
 // 16 for 64-band tiles), then as many rows as the tile holds and the y

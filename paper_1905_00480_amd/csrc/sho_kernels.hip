@@ -186,7 +186,7 @@ __device__ inline void load_batch(const KArgs &K, const RunState &r, int jb,
 // different runs of the plane), then C[n] += phi_nz(z) T2[nx][ny].
 template <int NU>
 __device__ inline void flush_plane(cptr<double> fz, double *T2, double *cacc,
-                                   const Lanes &L) {
+                                   const Lanes &L, bool det) {
   constexpr int NF = NU + 1;
   constexpr int NP = NF * (NF + 1) / 2;
   for (int s = 32; s >= L.TB; s >>= 1) {
@@ -204,7 +204,11 @@ __device__ inline void flush_plane(cptr<double> fz, double *T2, double *cacc,
 #pragma unroll
         for (int nx = 0; nx < NF - ny; ++nx, ++q) {
           if (nx + ny + nz <= NU) {
-            atomicAdd(&cacc[idx * L.TB + L.bl], f * T2[q]);
+            // deterministic plans: the wave's own tile, one lane per value
+            if (det)
+              cacc[idx * L.TB + L.bl] += f * T2[q];
+            else
+              atomicAdd(&cacc[idx * L.TB + L.bl], f * T2[q]);
             ++idx;
           }
         }
@@ -243,7 +247,7 @@ __device__ inline void project_bundles(const KArgs &K, const AtomRec &A,
   load_batch(K, rs, bd.jlo, v);
   for (int bi = b0; bi < b1; ++bi) {
     if (bd.jz != cur_jz) {
-      if (cur_jz >= 0) flush_plane<NU>(tz + cur_jz * nfp, T2, cacc, L);
+      if (cur_jz >= 0) flush_plane<NU>(tz + cur_jz * nfp, T2, cacc, L, K.det != 0);
       cur_jz = bd.jz;
     }
     double T1[NF];
@@ -290,7 +294,7 @@ __device__ inline void project_bundles(const KArgs &K, const AtomRec &A,
     bd = nbd;
     rs = nrs;
   }
-  flush_plane<NU>(tz + cur_jz * nfp, T2, cacc, L);
+  flush_plane<NU>(tz + cur_jz * nfp, T2, cacc, L, K.det != 0);
 }
 
 // One work item of the projection: zero the LDS tile, stream the item's
@@ -303,22 +307,26 @@ __device__ inline void project_item(const KArgs &K, cptr<WorkRec> W, const AtomR
   constexpr int NS = NF * (NF + 1) * (NF + 2) / 6;
   const int tile = blockIdx.y;
   const int TB = 1 << K.tb_shift;
-  for (int t = threadIdx.x; t < NS * TB; t += blockDim.x) cacc[t] = 0.0;
+  const int nt = NS * TB;  // one coefficient tile
+  const int tiles = K.det ? kWaves : 1;
+  for (int t = threadIdx.x; t < nt * tiles; t += blockDim.x) cacc[t] = 0.0;
   __syncthreads();
   const int w = wave_id();
   const Lanes L = lane_geometry(K, tile);
-  project_bundles<NU>(K, A, L, W->wb[w], W->wb[w + 1], psi, cacc);
+  project_bundles<NU>(K, A, L, W->wb[w], W->wb[w + 1], psi, K.det ? cacc + w * nt : cacc);
   __syncthreads();
   const bool split = W->split != 0;
-  for (int t = threadIdx.x; t < NS * TB; t += blockDim.x) {
+  for (int t = threadIdx.x; t < nt; t += blockDim.x) {
     const int n = t >> K.tb_shift;
     const int bb = tile * TB + (t & (TB - 1));
     if (bb >= K.B) continue;
+    double v = cacc[t];
+    for (int k = 1; k < tiles; ++k) v += cacc[k * nt + t];  // waves in order
     double *dst = c + (A.coeff_row + n) * K.B + bb;
     if (split)
-      unsafeAtomicAdd(dst, K.h3 * cacc[t]);
+      unsafeAtomicAdd(dst, K.h3 * v);
     else
-      *dst = K.h3 * cacc[t];
+      *dst = K.h3 * v;
   }
 }
 
@@ -817,6 +825,99 @@ __global__ __launch_bounds__(kBlkBlock) void k_expand_blocks(EArgs E,
   }
 }
 
+// ------------------------------------------------ expansion by owners --
+
+// Owner form of the expansion's y and x passes.  One wave owns a strip of R
+// rows x X points of one plane for one tile of TB bands (R = 64 / TB): lane
+// (r, b) keeps the X values psi(z, y0 + r, x0 .. x0 + X - 1)[b] in
+// registers, reads them once, adds the contribution of every entry (atom
+// plane and image) that touches the strip, in the plan's fixed entry order,
+// and writes them once.  No value is shared between lanes, so there are no
+// atomics and the sum over atoms is taken in the same order on every run.
+// Per entry a lane forms U1[nx] = sum_ny phi_ny(y) U2[nx][ny] for its row
+// from the plane partials, then the x pass adds sum_nx phi_nx(x) U1[nx] to
+// the points of its row's run; phi_x is wave-uniform (scalar loads).
+template <int NU, int X>
+__device__ inline void owner_entry(const EArgs &E, const EntryRec &en, const double *u2,
+                                   double (&acc)[X], int r, int bc) {
+  constexpr int NF = NU + 1;
+  const int nfp = en.nfp;
+  // this lane's run (at most one per row) and the union of the entry's runs
+  const cptr<uint32_t> desc = as_const(E.run_desc) + en.run_begin;
+  int xa = 0, xb = 0, lo = X, hi = 0, rr = -1;
+  for (int k = 0; k < en.nruns; ++k) {
+    const uint32_t d = desc[k];
+    const int dr = d & 0xff, da = (d >> 8) & 0xff, db = (d >> 16) & 0xff;
+    lo = min(lo, da);
+    hi = max(hi, db);
+    if (rr < 0) rr = dr;  // a row of the entry, for the lanes without a run
+    if (dr == r) {
+      xa = da;
+      xb = db;
+    }
+  }
+  const int ry = xa < xb ? r : rr;
+  // y pass of this lane's row
+  const double *fy = E.tab + en.tab_y + ry * nfp;
+  const double *ub = u2 + en.u2 + bc;
+  double U1[NF];
+#pragma unroll
+  for (int n = 0; n < NF; ++n) U1[n] = 0.0;
+  int q = 0;
+#pragma unroll
+  for (int ny = 0; ny < NF; ++ny) {
+    const double fv = fy[ny];
+#pragma unroll
+    for (int nx = 0; nx < NF - ny; ++nx, ++q) U1[nx] = fma(fv, ub[(int64_t)q * E.B], U1[nx]);
+  }
+  // x pass over the union of the runs (a wave-uniform range)
+  const cptr<double> tx = as_const(E.tab) + en.tab_x;
+#pragma unroll
+  for (int x = 0; x < X; ++x) {
+    if (x >= lo && x < hi) {
+      const cptr<double> f = tx + x * nfp;
+      double v = 0.0;
+#pragma unroll
+      for (int n = 0; n < NF; ++n) v = fma(f[n], U1[n], v);
+      if (x >= xa && x < xb) acc[x] += v;
+    }
+  }
+}
+
+template <int NUMAX, int X>
+__global__ __launch_bounds__(64) void k_expand_owner(EArgs E, const double *__restrict__ u2,
+                                                      double *psi) {
+  if ((int)blockIdx.x >= E.nblocks) return;  // launch rounded up to 8 XCDs
+  const BlockRec bk = load_uniform(E.blocks + blockIdx.x);
+  if (bk.nentries < 0) return;
+  const int lane = threadIdx.x;
+  const int TB = 1 << E.tbe_shift;
+  const int r = lane >> E.tbe_shift;
+  const int b = (int)blockIdx.y * TB + (lane & (TB - 1));
+  const bool live = b < E.B && bk.y0 + r < E.ny;
+  const int bc = b < E.B ? b : E.B - 1;
+  const int nxl = min(X, E.nx - bk.x0);
+  double *base = psi + ((int64_t)(bk.z * E.ny + (live ? bk.y0 + r : bk.y0)) * E.nx + bk.x0) *
+                           E.B + bc;
+  double acc[X];
+#pragma unroll
+  for (int x = 0; x < X; ++x) acc[x] = (live && x < nxl) ? base[(int64_t)x * E.B] : 0.0;
+  for (int i = 0; i < bk.nentries; ++i) {
+    const EntryRec en = load_uniform(E.entries + bk.entry_begin + i);
+    switch (en.nu) {
+#define X_(N)                                                      \
+  case N:                                                          \
+    if constexpr (N <= NUMAX) owner_entry<N, X>(E, en, u2, acc, r, bc); \
+    break;
+      X_(0) X_(1) X_(2) X_(3) X_(4) X_(5) X_(6) X_(7) X_(8) X_(9) X_(10)
+#undef X_
+    }
+  }
+#pragma unroll
+  for (int x = 0; x < X; ++x)
+    if (live && x < nxl) base[(int64_t)x * E.B] = acc[x];
+}
+
 // ------------------------------------------------- stored projectors --
 
 // P[run][k][n] = phi_nx(x) phi_ny(y) phi_nz(z) at point k of the run, for all
@@ -1197,7 +1298,7 @@ template <int NU1>
 __global__ __launch_bounds__(kBlock)
 __attribute__((amdgpu_waves_per_eu(waves_per_eu(NU1 + 1)))) void k_force(
     KArgs K, const double *__restrict__ psi, const double *__restrict__ w,
-    double *grad) {
+    double *grad, double *gpart) {
   constexpr int NF = NU1 + 1;
   constexpr int NS1 = NF * (NF + 1) * (NF + 2) / 6;
   constexpr int NU = NU1 - 1;
@@ -1209,12 +1310,22 @@ __attribute__((amdgpu_waves_per_eu(waves_per_eu(NU1 + 1)))) void k_force(
   const int a = W->atom;
   const AtomRec A = load_uniform(K.atoms + a);
   const int TB = 1 << K.tb_shift;
-  for (int t = threadIdx.x; t < NS1 * TB; t += blockDim.x) cacc[t] = 0.0;
+  const int nt = NS1 * TB;
+  const int tiles = K.det ? kWaves : 1;
+  for (int t = threadIdx.x; t < nt * tiles; t += blockDim.x) cacc[t] = 0.0;
   __syncthreads();
   const int wv = wave_id();
   const Lanes L = lane_geometry(K, tile);
-  project_bundles<NU1>(K, A, L, W->wb[wv], W->wb[wv + 1], psi, cacc);
+  project_bundles<NU1>(K, A, L, W->wb[wv], W->wb[wv + 1], psi, K.det ? cacc + wv * nt : cacc);
   __syncthreads();
+  if (K.det) {  // the waves' tiles, added in wave order into the first
+    for (int t = threadIdx.x; t < nt; t += blockDim.x) {
+      double v = cacc[t];
+      for (int k = 1; k < tiles; ++k) v += cacc[k * nt + t];
+      cacc[t] = v;
+    }
+    __syncthreads();
+  }
 
   double g[3] = {0.0, 0.0, 0.0};
   for (int t = threadIdx.x; t < NS * TB; t += blockDim.x) {
@@ -1249,8 +1360,23 @@ __attribute__((amdgpu_waves_per_eu(waves_per_eu(NU1 + 1)))) void k_force(
   if (threadIdx.x < 3) {
     double s = 0.0;
     for (int k = 0; k < kWaves; ++k) s += red[threadIdx.x][k];
-    unsafeAtomicAdd(&grad[3 * a + threadIdx.x], -K.h3 / A.sigma * s);
+    if (gpart)
+      gpart[((int64_t)a * K.ntiles + tile) * 3 + threadIdx.x] = -K.h3 / A.sigma * s;
+    else
+      unsafeAtomicAdd(&grad[3 * a + threadIdx.x], -K.h3 / A.sigma * s);
   }
+}
+
+// grad[a][d] = sum over band tiles, in tile order, of the deterministic
+// derivative's per-tile sums.
+__global__ void k_force_sum(const double *__restrict__ gpart, int32_t natoms, int32_t ntiles,
+                            double *__restrict__ grad) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;  // (atom, direction)
+  if (i >= 3 * natoms) return;
+  const int a = i / 3, d = i % 3;
+  double v = 0.0;
+  for (int t = 0; t < ntiles; ++t) v += gpart[((int64_t)a * ntiles + t) * 3 + d];
+  grad[i] = v;
 }
 
 __global__ void k_fill(double *p, int64_t n, double v) {
@@ -1265,10 +1391,16 @@ static dim3 grid_of(const KArgs &K) {
   return dim3((unsigned)K.nwork, (unsigned)K.ntiles);
 }
 
+// LDS of a projection workgroup: one coefficient tile, or one per wave for
+// deterministic sums.
+static size_t proj_lds(const KArgs &K, int nf) {
+  return lds_tile_bytes(nf, 1 << K.tb_shift) * (K.det ? kWaves : 1);
+}
+
 template <int NU>
 static hipError_t launch_project_nu(const KArgs &K, const double *psi,
                                     double *c, hipStream_t s) {
-  const size_t shm = lds_tile_bytes(NU + 1, 1 << K.tb_shift);
+  const size_t shm = proj_lds(K, NU + 1);
   hipLaunchKernelGGL(k_project<NU>, grid_of(K), dim3(kBlock), shm, s, K, psi, c);
   return hipGetLastError();
 }
@@ -1276,9 +1408,9 @@ static hipError_t launch_project_nu(const KArgs &K, const double *psi,
 template <int NU1>
 static hipError_t launch_force_nu(const KArgs &K, const double *psi,
                                   const double *w, double *grad,
-                                  hipStream_t s) {
-  const size_t shm = lds_tile_bytes(NU1 + 1, 1 << K.tb_shift);
-  hipLaunchKernelGGL(k_force<NU1>, grid_of(K), dim3(kBlock), shm, s, K, psi, w, grad);
+                                  hipStream_t s, double *gpart) {
+  const size_t shm = proj_lds(K, NU1 + 1);
+  hipLaunchKernelGGL(k_force<NU1>, grid_of(K), dim3(kBlock), shm, s, K, psi, w, grad, gpart);
   return hipGetLastError();
 }
 
@@ -1286,7 +1418,7 @@ static hipError_t launch_force_nu(const KArgs &K, const double *psi,
 template <int NUMAX>
 static hipError_t launch_project_any_nu(const KArgs &K, const double *psi,
                                         double *c, hipStream_t s) {
-  const size_t shm = lds_tile_bytes(NUMAX + 1, 1 << K.tb_shift);
+  const size_t shm = proj_lds(K, NUMAX + 1);
   hipLaunchKernelGGL(k_project_any<NUMAX>, grid_of(K), dim3(kBlock), shm, s, K, psi, c);
   return hipGetLastError();
 }
@@ -1332,9 +1464,10 @@ hipError_t launch_project(int nu, const KArgs &K, const double *psi, double *c,
 }
 
 hipError_t launch_force(int nu, const KArgs &K, const double *psi,
-                        const double *w, double *grad, hipStream_t s) {
+                        const double *w, double *grad, hipStream_t s, double *gpart) {
+  if (K.nwork <= 0) return hipSuccess;
   switch (nu) {
-#define X(N) case N: return launch_force_nu<N + 1>(K, psi, w, grad, s);
+#define X(N) case N: return launch_force_nu<N + 1>(K, psi, w, grad, s, gpart);
     SHO_NU_CASES(X)
 #undef X
   }
@@ -1400,6 +1533,28 @@ hipError_t launch_blocks(const EArgs &E, const double *u2, double *psi,
       default:
         return hipErrorInvalidValue;
     }
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_owner(const EArgs &E, const double *u2, double *psi, hipStream_t s) {
+  if (E.nblocks <= 0) return hipSuccess;
+  // whole groups of 8 workgroups, so that block g runs on XCD g mod 8 for
+  // every band tile (the plan deals the planes' strips to the XCDs that way)
+  const unsigned gx = (unsigned)((E.nblocks + 7) / 8 * 8);
+  const dim3 g(gx, (unsigned)E.ntiles);
+  switch (E.nu_max * 64 + E.blk_x) {
+#define X_(N)                                                                         \
+  case N * 64 + 16:                                                                   \
+    hipLaunchKernelGGL((k_expand_owner<N, 16>), g, dim3(64), 0, s, E, u2, psi);      \
+    break;                                                                            \
+  case N * 64 + 32:                                                                   \
+    hipLaunchKernelGGL((k_expand_owner<N, 32>), g, dim3(64), 0, s, E, u2, psi);      \
+    break;
+    SHO_NU_CASES(X_)
+#undef X_
+    default:
+      return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
@@ -1487,6 +1642,14 @@ hipError_t launch_tables(const AtomRec *atoms, int32_t natoms, double h,
   (void)mmax;
   if (natoms <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_tables, dim3((unsigned)natoms), dim3(256), 0, s, atoms, h, tab);
+  return hipGetLastError();
+}
+
+hipError_t launch_force_sum(const double *gpart, int32_t natoms, int32_t ntiles, double *grad,
+                            hipStream_t s) {
+  if (natoms <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_force_sum, dim3((unsigned)((3 * natoms + 255) / 256)), dim3(256), 0, s,
+                     gpart, natoms, ntiles, grad);
   return hipGetLastError();
 }
 

@@ -28,7 +28,8 @@ struct KArgs {
   int32_t B;                 // bands: stride of one grid point
   int32_t tb_shift;          // log2(bands per lane slot)
   int32_t ntiles;            // band tiles per atom
-  int32_t pad;
+  int32_t det;               // 1: deterministic sums (per-wave LDS tiles
+                             // added in wave order; no atomics)
   double h3;
   double alpha;              // expansion: psi += alpha * sum_n c P_n
 };
@@ -102,6 +103,9 @@ hipError_t launch_rows(const EArgs &E, const double *u2, double *psi,
 // Block form of the second half (blocks of R rows x X points).
 hipError_t launch_blocks(const EArgs &E, const double *u2, double *psi,
                          hipStream_t s);
+// Owner form of the second half: one wave per strip of 64/TB rows x X points
+// (X = E.blk_x, 16 or 32), values in registers, entries in plan order.
+hipError_t launch_owner(const EArgs &E, const double *u2, double *psi, hipStream_t s);
 // Stored plans: the whole expansion in the block form, P_an read from the
 // tables (per-block products on FP64 matrix cores); nu_max <= 5.
 hipError_t launch_blocks_stored(const EArgs &E, const double *c, double *psi,
@@ -119,9 +123,14 @@ hipError_t launch_expand_stored(int nu, const SArgs &S, const double *c,
 hipError_t launch_multiply(const AtomRec *atoms, int32_t natoms, const int64_t *doff,
                            const double *D, const double *c, double *d, int32_t B,
                            hipStream_t s);
-// grad must be zeroed first (launch_fill)
+// grad must be zeroed first (launch_fill).  With K.det, every (atom, band
+// tile) writes its three sums to gpart[(atom * ntiles + tile) * 3 + d]
+// instead, and launch_force_sum adds them in tile order into grad.
 hipError_t launch_force(int nu, const KArgs &K, const double *psi,
-                        const double *w, double *grad, hipStream_t s);
+                        const double *w, double *grad, hipStream_t s,
+                        double *gpart = nullptr);
+hipError_t launch_force_sum(const double *gpart, int32_t natoms, int32_t ntiles, double *grad,
+                            hipStream_t s);
 hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s);
 
 // FP32 plans (an even number of bands, processed as pairs: K.B and E.B count

@@ -67,7 +67,7 @@ sho_status build_host_plan(const sho_grid *grid, int32_t natoms,
   }
   const uint32_t known =
       SHO_FLAG_STORED | SHO_FLAG_ALLOW_UNDERSAMPLED | SHO_FLAG_HOST_ONLY | SHO_FLAG_PER_ATOM |
-      SHO_FLAG_FP32;
+      SHO_FLAG_FP32 | SHO_FLAG_DETERMINISTIC;
   if (flags & ~known) {
     *msg = "unknown flag bits";
     return SHO_E_INVALID;
@@ -337,7 +337,9 @@ void build_work(HostPlan *P, int tb_shift, int64_t target_points, int32_t sched)
       if (A.nu != nu || A.npoints == 0) continue;
       const int32_t bb = atom_bundle_begin[a], be = atom_bundle_begin[a + 1];
       const int64_t parts =
-          std::max<int64_t>(1, (A.npoints + target_points - 1) / target_points);
+          (P->flags & SHO_FLAG_DETERMINISTIC)  // one item per atom: no atomics into c
+              ? 1
+              : std::max<int64_t>(1, (A.npoints + target_points - 1) / target_points);
       std::vector<int64_t> cum(be - bb + 1, 0);
       for (int32_t i = bb; i < be; ++i) cum[i - bb + 1] = cum[i - bb] + cost[i];
       const int64_t total = cum.back();

@@ -78,6 +78,10 @@ def test_argument_errors():
                                           [[200.0, 0.8, 0.8]], [0.6], [3], 1,
                                           rbox=[120.0], flags=bd.FLAG_HOST_ONLY))
     _expect(bd.SHO_E_INVALID, lambda: mk(rbox=[1.0, -1.0]))
+    # deterministic sums are FP64, on-the-fly, batched only
+    for other in (bd.FLAG_STORED, bd.FLAG_PER_ATOM, bd.FLAG_FP32):
+        _expect(bd.SHO_E_INVALID,
+                lambda: mk(flags=bd.FLAG_HOST_ONLY | bd.FLAG_DETERMINISTIC | other))
     # stored projector tables are offered up to nu = 5 only
     _expect(bd.SHO_E_NU_RANGE, lambda: mk(numax=[5, 6],
                                           flags=bd.FLAG_HOST_ONLY | bd.FLAG_STORED))
@@ -119,7 +123,7 @@ def test_expand_form_arguments_host_only():
     assert p.expand_form()[0] == bd.EXPAND_ROWS
     p.set_expand(bd.EXPAND_BLOCKS, 8, 16)
     assert p.expand_form() == (bd.EXPAND_BLOCKS, 8, 16)
-    _expect(bd.SHO_E_INVALID, lambda: p.set_expand(2))
+    _expect(bd.SHO_E_INVALID, lambda: p.set_expand(3))
     _expect(bd.SHO_E_INVALID, lambda: p.set_expand(bd.EXPAND_BLOCKS, 16, 16))   # 8192 doubles
     _expect(bd.SHO_E_INVALID, lambda: p.set_expand(bd.EXPAND_BLOCKS, 1, 64))    # staging
     _expect(bd.SHO_E_INVALID, lambda: p.set_expand(bd.EXPAND_BLOCKS, 0, 4))
@@ -204,3 +208,25 @@ def test_device_plan_without_gpu_reports_device_error():
     _lib()
     s = wl.small_periodic(natoms=2)
     _expect(bd.SHO_E_DEVICE, lambda: bd.Plan.from_system(s))
+
+
+def test_deterministic_host_plan_tables():
+    """A deterministic plan takes the owner form of the expansion (strips of
+    64 / T rows, T = 16 bands, or 8 for at most 8 bands), one work item per
+    atom, and refuses the other expansion forms."""
+    _lib()
+    s = wl.small_mixed()
+    p = _host_plan(s, flags=bd.FLAG_DETERMINISTIC)
+    mode, rows, width = p.expand_form()
+    assert mode == bd.EXPAND_OWNER and rows == (4 if s.nbands > 8 else 8) and width == 32
+    p.set_expand(bd.EXPAND_OWNER, 0, 16)
+    assert p.expand_form() == (bd.EXPAND_OWNER, rows, 16)
+    _expect(bd.SHO_E_INVALID, lambda: p.set_expand(bd.EXPAND_BLOCKS))
+    _expect(bd.SHO_E_INVALID, lambda: p.set_expand(bd.EXPAND_OWNER, 0, 24))
+    p.set_schedule(bd.SCHED_SINGLE, 0, 256)   # would split large atoms
+    p.close()
+    q = _host_plan(s)
+    q.set_expand(bd.EXPAND_OWNER)
+    assert q.expand_form()[0] == bd.EXPAND_OWNER
+    _expect(bd.SHO_E_INVALID, lambda: q.set_expand(bd.EXPAND_OWNER, 3, 32))
+    q.close()
