@@ -58,6 +58,9 @@ def _load():
     lib.oracle_expand_at.restype = ctypes.c_int
     lib.oracle_force.argtypes = geo + [_dp, ctypes.c_int, _dp, _dp, _dp, _dp, _dp]
     lib.oracle_force.restype = ctypes.c_int
+    for f in (lib.oracle_project_k, lib.oracle_expand_k):
+        f.argtypes = geo + [_dp, ctypes.c_int, _dp, _dp, _dp]
+        f.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -265,3 +268,59 @@ def apply(n, h, periodic, pos, sigma, numax, psi, D, psi_in, rbox=None, with_abs
     _, out_abs = expand(n, h, periodic, pos, sigma, numax, d_abs, np.abs(psi_in), rbox=rbox,
                         with_abs=True)
     return out, out_abs
+
+
+def _as_pairs(a):
+    """Complex array -> float64 interleaved (re, im) pairs (a view if already
+    float pairs)."""
+    a = np.asarray(a)
+    if np.iscomplexobj(a):
+        return np.ascontiguousarray(np.stack([a.real, a.imag], axis=-1), dtype=np.float64)
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def project_k(n, h, periodic, pos, sigma, numax, psi, kvec, rbox=None, with_abs=False):
+    """Complex bands at wave vector ``kvec`` (Bohr^-1): c[a][n][b] =
+    h^3 sum_{i in S_a} P_an(i) e^{i k.T_i} psi_b(i mod N).  ``psi`` complex
+    (nz, ny, nx, B); returns complex c (flat per-atom blocks [N][B]) and, with
+    ``with_abs``, the abs-sum h^3 sum |P| (|Re psi| + |Im psi|) (real)."""
+    na, pos, sigma, numax, rbox, _ = _atoms(pos, sigma, numax, rbox)
+    pp_ = _as_pairs(psi)
+    B = pp_.shape[-2]
+    total = int(coeff_offsets(numax, B)[-1])
+    c = np.zeros(2 * total)
+    ca = np.zeros(2 * total) if with_abs else None
+    k = _f64(kvec, (3,))
+    nn, hh, pp = _grid(n, h, periodic)
+    rc = _load().oracle_project_k(nn, hh, pp, na, _d(pos), _d(sigma),
+                                  numax.ctypes.data_as(_ip), _d(rbox), _d(k), B,
+                                  _d(pp_), _d(c), _d(ca))
+    if rc:
+        raise ValueError("oracle_project_k: bad arguments")
+    cz = c[0::2] + 1j * c[1::2]
+    return (cz, ca[0::2]) if with_abs else cz
+
+
+def expand_k(n, h, periodic, pos, sigma, numax, c, psi_in, kvec, rbox=None, with_abs=False):
+    """psi_out = psi_in + sum_a sum_{images} e^{-i k.T} sum_n c P_an, complex
+    arrays (psi (nz, ny, nx, B), c flat per-atom blocks); returns psi_out and,
+    with ``with_abs``, |Re psi_in| + |Im psi_in| + sum |P| (|Re c| + |Im c|)."""
+    na, pos, sigma, numax, rbox, _ = _atoms(pos, sigma, numax, rbox)
+    out = _as_pairs(np.asarray(psi_in, dtype=np.complex128)).copy()
+    B = out.shape[-2]
+    cc = _as_pairs(np.asarray(c, dtype=np.complex128))
+    assert cc.size == 2 * int(coeff_offsets(numax, B)[-1])
+    pab = None
+    if with_abs:
+        pin = np.asarray(psi_in, dtype=np.complex128)
+        s = np.abs(pin.real) + np.abs(pin.imag)
+        pab = np.ascontiguousarray(np.stack([s, s], axis=-1))
+    k = _f64(kvec, (3,))
+    nn, hh, pp = _grid(n, h, periodic)
+    rc = _load().oracle_expand_k(nn, hh, pp, na, _d(pos), _d(sigma),
+                                 numax.ctypes.data_as(_ip), _d(rbox), _d(k), B,
+                                 _d(cc), _d(out), _d(pab))
+    if rc:
+        raise ValueError("oracle_expand_k: bad arguments")
+    z = out[..., 0] + 1j * out[..., 1]
+    return (z, pab[..., 0]) if with_abs else z

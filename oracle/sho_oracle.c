@@ -27,6 +27,10 @@
  *   derivative        g[a][d] = sum_{n,b} w[a][n][b] dc[a][n][b]/dR_{a,d},
  *                     support S_a frozen; d/du of the sampled functions taken
  *                     from the monic polynomial directly (H'_n = n H_{n-1}).
+ *   complex bands     Bloch bands at a wave vector k (sec. 2.5: the basis
+ *   at k              spans functions R^3 -> C): every periodic image of a
+ *                     support point carries the phase e^{+-i k.T} of its
+ *                     lattice translation T (oracle_project_k / _expand_k).
  *
  * Sums are accumulated in long double so that the oracle's own rounding error
  * stays far below the comparison tolerance.  Membership in the support is
@@ -543,6 +547,165 @@ int oracle_force(const int n[3], double h, const int periodic[3], int natoms,
     }
     free(acc);
     free(ab);
+  }
+  return 0;
+}
+
+/* ------------------------------------------------- complex bands at k -- */
+
+/*
+ * Bloch bands (the SHO basis spans functions R^3 -> C, sec. 2.5): complex
+ * psi with psi(r + T) = e^{i k.T} psi(r) for every lattice vector T of the
+ * periodic axes.  Bands are interleaved (re, im) pairs: psi[mem][b][2],
+ * c[off_a + n][b][2] with B complex bands.  An unwrapped support point i
+ * lies at r_i = r_j + T_i, j = i mod N, T_i = (i - j) h, so that
+ *   projection  c[a][n][b] = h^3 sum_{i in S_a} P_an(i) e^{+i k.T_i} psi_b(j)
+ *   expansion   psi_b(j)  += sum_a sum_{i in S_a, i = j mod N}
+ *                            e^{-i k.T_i} sum_n c[a][n][b] P_an(i)
+ * The expansion builds the Bloch sum of the projectors with wave vector k,
+ * and is the adjoint of the projection (up to h^3) in the complex inner
+ * product.  Isolated axes have no images (T = 0 there).
+ */
+static double bloch_angle(const ogrid *g, const int i[3], const double k[3]) {
+  double th = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    const int j = wrap(i[d], g->n[d]);
+    th += k[d] * ((double)(i[d] - j) * g->h);
+  }
+  return th;
+}
+
+typedef struct {
+  const ogrid *g;
+  const double *fc;
+  double sigma;
+  int nu, B;
+  const double *k;
+  const double *psi; /* [mem][B][2] */
+  long double *acc;  /* [N][B][2] */
+  long double *abs;  /* [N][B][2] */
+} prjk_ctx;
+
+static void prjk_fn(void *p, const int i[3], int64_t mem) {
+  prjk_ctx *c = (prjk_ctx *)p;
+  double fx[ORACLE_NU_MAX + 1], fy[ORACLE_NU_MAX + 1], fz[ORACLE_NU_MAX + 1];
+  phi_all(c->nu, c->sigma, (double)i[0] * c->g->h - c->fc[0], fx);
+  phi_all(c->nu, c->sigma, (double)i[1] * c->g->h - c->fc[1], fy);
+  phi_all(c->nu, c->sigma, (double)i[2] * c->g->h - c->fc[2], fz);
+  const double th = bloch_angle(c->g, i, c->k);
+  const long double cs = cosl((long double)th), sn = sinl((long double)th);
+  const double *ps = c->psi + mem * 2 * c->B;
+  int idx = 0;
+  for (int nz = 0; nz <= c->nu; ++nz)
+    for (int ny = 0; ny <= c->nu - nz; ++ny)
+      for (int nx = 0; nx <= c->nu - nz - ny; ++nx, ++idx) {
+        const long double P = (long double)fx[nx] * fy[ny] * fz[nz];
+        long double *acc = c->acc + (int64_t)idx * 2 * c->B;
+        long double *ab = c->abs + (int64_t)idx * 2 * c->B;
+        for (int b = 0; b < c->B; ++b) {
+          const long double re = ps[2 * b], im = ps[2 * b + 1];
+          acc[2 * b] += P * (cs * re - sn * im);
+          acc[2 * b + 1] += P * (sn * re + cs * im);
+          const long double m = fabsl(P) * (fabsl(re) + fabsl(im));
+          ab[2 * b] += m;
+          ab[2 * b + 1] += m;
+        }
+      }
+}
+
+int oracle_project_k(const int n[3], double h, const int periodic[3], int natoms,
+                     const double *pos, const double *sigma, const int *numax,
+                     const double *rbox, const double *kvec, int B, const double *psi,
+                     double *c, double *cabs) {
+  ogrid g;
+  if (check_grid(n, h, periodic, &g) || B <= 0 || !kvec ||
+      check_atoms(natoms, sigma, numax, 0))
+    return -1;
+  const double h3 = h * h * h;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int a = 0; a < natoms; ++a) {
+    int nu = numax[a], N = oracle_nsho(nu);
+    long double *acc = calloc((size_t)N * 2 * B, sizeof(long double));
+    long double *ab = calloc((size_t)N * 2 * B, sizeof(long double));
+    prjk_ctx ctx = {&g, pos + 3 * a, sigma[a], nu, B, kvec, psi, acc, ab};
+    double R = rbox ? rbox[a] : box_radius(sigma[a], nu, h);
+    visit_support(&g, pos + 3 * a, R, prjk_fn, &ctx);
+    int64_t off = 2 * coeff_offset(numax, a, B);
+    for (int64_t k = 0; k < (int64_t)N * 2 * B; ++k) {
+      c[off + k] = (double)(h3 * acc[k]);
+      if (cabs) cabs[off + k] = (double)(h3 * ab[k]);
+    }
+    free(acc);
+    free(ab);
+  }
+  return 0;
+}
+
+typedef struct {
+  const ogrid *g;
+  const double *fc;
+  double sigma;
+  int nu, B, b0, b1;
+  const double *k;
+  const double *cc; /* this atom's [N][B][2] */
+  double *psi;      /* [mem][B][2] */
+  double *pabs;
+} addk_ctx;
+
+static void addk_fn(void *p, const int i[3], int64_t mem) {
+  addk_ctx *c = (addk_ctx *)p;
+  double fx[ORACLE_NU_MAX + 1], fy[ORACLE_NU_MAX + 1], fz[ORACLE_NU_MAX + 1];
+  phi_all(c->nu, c->sigma, (double)i[0] * c->g->h - c->fc[0], fx);
+  phi_all(c->nu, c->sigma, (double)i[1] * c->g->h - c->fc[1], fy);
+  phi_all(c->nu, c->sigma, (double)i[2] * c->g->h - c->fc[2], fz);
+  const double th = bloch_angle(c->g, i, c->k);
+  const long double cs = cosl((long double)th), sn = sinl((long double)th);
+  for (int b = c->b0; b < c->b1; ++b) {
+    long double sr = 0, si = 0, sa = 0;
+    int idx = 0;
+    for (int nz = 0; nz <= c->nu; ++nz)
+      for (int ny = 0; ny <= c->nu - nz; ++ny)
+        for (int nx = 0; nx <= c->nu - nz - ny; ++nx, ++idx) {
+          const long double P = (long double)fx[nx] * fy[ny] * fz[nz];
+          const long double re = c->cc[((int64_t)idx * c->B + b) * 2];
+          const long double im = c->cc[((int64_t)idx * c->B + b) * 2 + 1];
+          sr += P * re;
+          si += P * im;
+          sa += fabsl(P) * (fabsl(re) + fabsl(im));
+        }
+    /* times e^{-i theta} */
+    c->psi[(mem * c->B + b) * 2] += (double)(cs * sr + sn * si);
+    c->psi[(mem * c->B + b) * 2 + 1] += (double)(cs * si - sn * sr);
+    if (c->pabs) {
+      c->pabs[(mem * c->B + b) * 2] += (double)sa;
+      c->pabs[(mem * c->B + b) * 2 + 1] += (double)sa;
+    }
+  }
+}
+
+int oracle_expand_k(const int n[3], double h, const int periodic[3], int natoms,
+                    const double *pos, const double *sigma, const int *numax,
+                    const double *rbox, const double *kvec, int B, const double *c,
+                    double *psi, double *pabs) {
+  ogrid g;
+  if (check_grid(n, h, periodic, &g) || B <= 0 || !kvec ||
+      check_atoms(natoms, sigma, numax, 0))
+    return -1;
+#pragma omp parallel
+  {
+    int nt = 1, t = 0;
+#ifdef _OPENMP
+    nt = omp_get_num_threads();
+    t = omp_get_thread_num();
+#endif
+    int b0 = (int)((int64_t)B * t / nt), b1 = (int)((int64_t)B * (t + 1) / nt);
+    if (b1 > b0)
+      for (int a = 0; a < natoms; ++a) {
+        addk_ctx ctx = {&g,   pos + 3 * a, sigma[a], numax[a], B, b0, b1, kvec,
+                        c + 2 * coeff_offset(numax, a, B), psi, pabs};
+        double R = rbox ? rbox[a] : box_radius(sigma[a], numax[a], h);
+        visit_support(&g, pos + 3 * a, R, addk_fn, &ctx);
+      }
   }
   return 0;
 }

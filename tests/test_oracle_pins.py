@@ -434,3 +434,101 @@ def test_apply_self_adjoint_for_symmetric_matrices():
     lhs = np.sum(phi * oracle.apply(*s.geometry(), psi, D, z))
     rhs = np.sum(oracle.apply(*s.geometry(), phi, D, z) * psi)
     assert abs(lhs - rhs) <= 1e-12 * (abs(lhs) + abs(rhs))
+
+
+# ------------------------------------------------ complex bands at k ----
+
+def _bloch_setup():
+    """Periodic cell smaller than the enlarged support box (every point is
+    reached by many periodic images), sigma / h = 4."""
+    n = (24, 20, 22)
+    h = 0.125
+    per = (True, True, True)
+    sigma, nu = 0.5, 5
+    R = np.array([[1.013, 1.281, 0.94]])
+    return n, h, per, sigma, nu, R
+
+
+def test_project_k_bloch_plane_wave_closed_form():
+    """A Bloch band psi = e^{i(k+G).r} (G a reciprocal lattice vector, so psi
+    has wave vector k) projected with the phases e^{ik.T} of the periodic
+    images is the continuum integral of P_an against e^{iq.r}, q = k + G:
+    c_n = e^{iq.R} prod_d sigma^{1/2} sqrt(2 pi) i^{n_d} phi_{n_d}(q_d sigma; 1)
+    (Fourier eigenfunctions, sec. 3.6).  A wrong phase sign, a phase taken
+    from the position instead of the lattice translation, or a missing image
+    breaks the equality."""
+    n, h, per, sigma, nu, R = _bloch_setup()
+    L = np.array(n) * h
+    cases = [(np.array([0.7, -0.4, 0.9]), np.array([1, 0, -1])),
+             (np.array([-1.1, 0.3, 0.2]), np.array([0, -1, 1])),
+             (np.array([0.05, 1.3, -0.6]), np.array([0, 0, 0]))]
+    x = [np.arange(n[d]) * h for d in range(3)]
+    Z, Y, X = np.meshgrid(x[2], x[1], x[0], indexing="ij")
+    trip = [(x_, y_, z_) for z_ in range(nu + 1) for y_ in range(nu + 1 - z_)
+            for x_ in range(nu + 1 - z_ - y_)]
+    for k, m in cases:
+        q = k + 2 * np.pi * m / L
+        psi = np.exp(1j * (q[0] * X + q[1] * Y + q[2] * Z))[..., None]
+        c = oracle.project_k(n, h, per, R, [sigma], [nu], psi, k, rbox=[10 * sigma])
+        f1 = [np.sqrt(sigma) * np.sqrt(2 * np.pi) * (1j) ** np.arange(nu + 1)
+              * oracle.phi(nu, 1.0, [q[d] * sigma])[:, 0] for d in range(3)]
+        ref = np.exp(1j * np.dot(q, R[0])) * np.array(
+            [f1[0][a] * f1[1][b] * f1[2][cc] for a, b, cc in trip])
+        assert np.max(np.abs(c - ref)) < 1e-12, (k, m)
+
+
+def test_k_adjoint_identity():
+    """<project_k psi, w> = h^3 <psi, expand_k w> in the complex inner product
+    (sum of conj(a) b), overlapping atoms on a small cell with one isolated
+    axis: the expansion carries the conjugate phase of the projection."""
+    s = wl.make_system("adjk", (12, 11, 9), 0.25, (True, False, True), 3, None, None, 3, 23,
+                       sigma_range=(0.5, 0.9), numax_range=(1, 5))
+    rng = np.random.default_rng(3)
+    psi = rng.standard_normal(s.psi_shape) + 1j * rng.standard_normal(s.psi_shape)
+    nc = int(oracle.coeff_offsets(s.numax, s.nbands)[-1])
+    w = rng.standard_normal(nc) + 1j * rng.standard_normal(nc)
+    k = np.array([0.83, -0.41, 1.7])
+    c = oracle.project_k(*s.geometry(), psi, k)
+    e = oracle.expand_k(*s.geometry(), w, np.zeros(s.psi_shape, complex), k)
+    lhs = np.vdot(c, w)
+    rhs = s.h ** 3 * np.vdot(psi, e)
+    assert abs(lhs - rhs) < 1e-13 * (np.abs(c).sum() + 1)
+    # the phase matters: with the conjugate convention on one side only the
+    # identity fails (guards against a test that cannot fail)
+    e_wrong = oracle.expand_k(*s.geometry(), w, np.zeros(s.psi_shape, complex), -k)
+    assert abs(lhs - s.h ** 3 * np.vdot(psi, e_wrong)) > 1e-6
+
+
+def test_k_zero_is_real_bands_in_pairs():
+    """At k = 0 every image has phase 1: the complex projection and expansion
+    are those of the real and imaginary parts separately."""
+    s = wl.make_system("k0", (14, 12, 10), 0.25, (True, True, True), 3, None, None, 2, 24,
+                       sigma_range=(0.5, 0.9), numax_range=(2, 4))
+    rng = np.random.default_rng(4)
+    psi = rng.standard_normal(s.psi_shape) + 1j * rng.standard_normal(s.psi_shape)
+    nc = int(oracle.coeff_offsets(s.numax, s.nbands)[-1])
+    w = rng.standard_normal(nc) + 1j * rng.standard_normal(nc)
+    k0 = np.zeros(3)
+    c = oracle.project_k(*s.geometry(), psi, k0)
+    ref = oracle.project(*s.geometry(), psi.real) + 1j * oracle.project(*s.geometry(), psi.imag)
+    assert np.max(np.abs(c - ref)) < 1e-14 * np.abs(ref).max()
+    e = oracle.expand_k(*s.geometry(), w, psi, k0)
+    ref = (oracle.expand(*s.geometry(), w.real, psi.real)
+           + 1j * oracle.expand(*s.geometry(), w.imag, psi.imag))
+    assert np.max(np.abs(e - ref)) < 1e-14 * np.abs(ref).max()
+
+
+def test_k_shift_by_reciprocal_vector():
+    """k and k + G (G = 2 pi m / L) give the same phases e^{ik.T} on every
+    lattice translation T, hence identical results: the phase depends on the
+    image's lattice vector only, not on the position."""
+    s = wl.make_system("kg", (10, 12, 9), 0.25, (True, True, True), 2, 0.7, 3, 2, 25)
+    rng = np.random.default_rng(6)
+    psi = rng.standard_normal(s.psi_shape) + 1j * rng.standard_normal(s.psi_shape)
+    k = np.array([0.3, 0.9, -0.5])
+    G = 2 * np.pi * np.array([2, -1, 1]) / s.cell
+    a = oracle.project_k(*s.geometry(), psi, k)
+    b = oracle.project_k(*s.geometry(), psi, k + G)
+    assert np.max(np.abs(a - b)) < 1e-12 * np.abs(a).max()
+    c = oracle.project_k(*s.geometry(), psi, k + 0.5 * G)
+    assert np.max(np.abs(a - c)) > 1e-3 * np.abs(a).max()
