@@ -92,8 +92,11 @@ def measured_traffic(kernel):
 
 
 def cpu_baseline(s, psi, c, target_s):
-    """Oracle projection + expansion timed on a sample of atoms (all bands,
-    the full grid), scaled to gridpoint*bands per second."""
+    """CPU reference points on the host cores of this machine:
+    * the oracle (plain triple sums, long double) timed on a sample of atoms
+      (all bands, the full grid), scaled to gridpoint*bands per second;
+    * the factorised CPU path (x, y, z passes, double, OpenMP), the whole
+      step on the whole workload, median of 3 runs."""
     import oracle
     from paper_1905_00480_amd import workloads as wl
     off = wl.coeff_offsets(s)
@@ -118,11 +121,29 @@ def cpu_baseline(s, psi, c, target_s):
     pts = sum(len(oracle.support(s.n, s.h, s.periodic, s.pos[a],
                                  oracle.box_radius(s.sigma[a], s.numax[a], s.h))[1])
               for a in atoms)
-    cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
-    return {"value": pts * s.nbands / t, "unit": "gridpoint*bands/s", "cores": cores,
-            "kind": "oracle",
-            "sample": "%d of %d atoms (all %d bands, full grid), projection + expansion, "
-                      "%.1f s" % (len(atoms), s.natoms, s.nbands, t)}
+    threads = oracle.threads()
+    rec = {"value": pts * s.nbands / t, "unit": "gridpoint*bands/s", "cores": threads,
+           "kind": "oracle",
+           "sample": "%d of %d atoms (all %d bands, full grid), projection + expansion, "
+                     "%.1f s" % (len(atoms), s.natoms, s.nbands, t)}
+    all_pts = sum(len(oracle.support(s.n, s.h, s.periodic, s.pos[a],
+                                     oracle.box_radius(s.sigma[a], s.numax[a], s.h))[1])
+                  for a in range(s.natoms))
+    out = np.zeros_like(psi)
+    times = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        oracle.factorised_project(*s.geometry(), psi)
+        oracle.factorised_expand(*s.geometry(), c, out)
+        times.append(time.perf_counter() - t0)
+    tf = float(np.median(times))
+    rec["factorised"] = {"value": all_pts * s.nbands / tf, "unit": "gridpoint*bands/s",
+                         "cores": threads, "s_per_step": tf,
+                         "sample": "the whole step (all %d atoms, %d bands), median of 3"
+                                   % (s.natoms, s.nbands),
+                         "nproc": os.cpu_count(),
+                         "OMP_NUM_THREADS": os.environ.get("OMP_NUM_THREADS")}
+    return rec
 
 
 def _best_stored_form(plan, c, out, reps=3):
@@ -192,6 +213,29 @@ def _time_steps(step, steps, warmup):
     torch.cuda.synchronize()
     per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
     return ev[0].elapsed_time(ev[-1]) / steps, per
+
+
+def _paper_protocol(step, runs=15, reps=10):
+    """The paper's timing protocol (sec. 6): one warm-up, then `runs` runs of
+    `reps` back-to-back steps each; median and p10/p90 of the per-step time
+    of the runs."""
+    import torch
+    step()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    per_run = []
+    for _ in range(runs):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            step()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        per_run.append(e0.elapsed_time(e1) / reps)
+    return {"runs": runs, "reps": reps,
+            "ms_per_step_median": float(np.median(per_run)),
+            "ms_per_step_p10_p90": [float(np.percentile(per_run, q)) for q in (10, 90)]}
 
 
 def ceilings():
@@ -501,25 +545,35 @@ def main():
 
     coeff_bytes = plan.coeff_doubles * 8
     u2_bytes = info["expand_scratch_doubles"] * 8
+    # per-atom box accounting (every atom's support counted once per atom,
+    # as the paper counts each grid value once per projection it enters)
     kbytes = {
         "project": S * B * 8 + coeff_bytes,
         "expand_z": coeff_bytes + u2_bytes,
-        "expand_xy": 2 * info["union_points"] * B * 8 + u2_bytes,
+        "expand_xy": 2 * S * B * 8 + u2_bytes,
     }
     kernels = {}
     for k, nbytes in kbytes.items():
         n, ms = prof[k]
-        kernels[k] = {"launches": n, "ms": ms, "bytes": nbytes,
-                      "GB/s": nbytes / (ms * 1e-3) / 1e9 if ms > 0 else None}
+        gbs = nbytes / (ms * 1e-3) / 1e9 if ms > 0 else None
+        hbm = measured_traffic(k)
+        kernels[k] = {"launches": n, "ms": ms, "bytes_per_atom_accounting": nbytes,
+                      "GB/s": gbs, "frac_per_atom": gbs / HBM_PEAK_GBS if gbs else None,
+                      "hbm_bytes_counters": hbm,
+                      "frac_counters": (hbm / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS
+                                        if hbm and ms > 0 else None)}
+    # the expansion writes each covered value once: its unique bytes
+    kernels["expand_xy"]["bytes_unique_points"] = (2 * info["union_points"] * B * 8
+                                                   + u2_bytes)
     dom = max(kernels, key=lambda k: kernels[k]["ms"])
-    d = kernels[dom]
-    traffic = measured_traffic(dom)
+    d = kernels["project"]
     ceil = ceilings()
     # unique-psi floor of the step: every covered value read once by the
     # projection and read + written once by the expansion, or the x-pass flops
     union_bytes = info["union_points"] * B * 8
     xflops = 2 * 6 * S * B * 2  # x passes of projection and expansion, nu = 5
     floor_ms = max(3 * union_bytes / (HBM_PEAK_GBS * 1e9), xflops / 78.6e12) * 1e3
+    protocol = _paper_protocol(step)
 
     rec = {
         "metric": "projected gridpoint*bands/s",
@@ -539,11 +593,15 @@ def main():
                                "step = projection + expansion",
                    "bands": B, "support_points": S,
                    "union_points": info["union_points"], "grid": list(s.n)},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": d["GB/s"],
+        "roofline": {"bound": "hbm", "kernel": "project", "achieved": d["GB/s"],
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": d["GB/s"] / HBM_PEAK_GBS, "traffic": traffic,
-                     "algorithmic_bytes_per_launch": d["bytes"], "launch_ms": d["ms"],
-                     "frac_of_copy_ceiling": d["GB/s"] / ceil["copy_GB/s"]},
+                     "frac": d["frac_per_atom"], "traffic": d["hbm_bytes_counters"],
+                     "frac_counters": d["frac_counters"],
+                     "algorithmic_bytes_per_launch": d["bytes_per_atom_accounting"],
+                     "launch_ms": d["ms"],
+                     "frac_of_read_ceiling": d["GB/s"] / ceil["read_GB/s"],
+                     "dominant_kernel": dom,
+                     "dominant_frac_per_atom": kernels[dom]["frac_per_atom"]},
         "ceilings": ceil,
         "unique_psi_floor_ms_per_step": floor_ms,
         "kernels": kernels,
@@ -553,6 +611,7 @@ def main():
         "schedule": plan.schedule(),
         "wall_s_incl_warmup": wall,
         "step_ms_p10_p50_p90": [float(np.percentile(per_step, q)) for q in (10, 50, 90)],
+        "paper_protocol": protocol,
     }
     _log("scale workload: %.3f ms per step" % ms_per_step)
     rec["apply"] = apply_step(bd, wl, plan, s, psi, args)

@@ -138,6 +138,12 @@ typedef int32_t sho_status;
 #define SHO_SCHED_SINGLE 1     /* one launch over all work items, atoms in
                                   Morton order of their centres */
 #define SHO_SCHED_SINGLE_LPT 2 /* one launch, work items by falling cost */
+#define SHO_SCHED_SWEEP 3      /* one launch, work items (plane ranges of
+                                  atoms) by the memory plane z they start at,
+                                  then (x, y) Morton order: the workgroups
+                                  resident at one time read a few consecutive
+                                  planes, so overlapping supports are read
+                                  close in time (cache reuse) */
 #define SHO_SCHED_XCD 4        /* flag for any of the above: consecutive items
                                   of the order run on the same XCD (shared
                                   L2), each XCD taking one eighth */
@@ -320,7 +326,7 @@ sho_status sho_plan_profile_read(sho_plan_t plan, int64_t *counts,
 /*
  * Work decomposition of the projection (sec. 6 measures prj and add over
  * many atoms of one system; these calls batch them).  schedule is one of
- * SHO_SCHED_BY_NU, _SINGLE, _SINGLE_LPT, optionally | SHO_SCHED_XCD.  A work item is one
+ * SHO_SCHED_BY_NU, _SINGLE, _SINGLE_LPT, _SWEEP, optionally | SHO_SCHED_XCD.  A work item is one
  * atom, or a share of an atom of more than target_points support points;
  * band_tile bands share a lane slot (power of two <= 64, 0 keeps the current
  * tile).  Plans with several cut-offs start with SHO_SCHED_SINGLE, others
@@ -376,7 +382,7 @@ typedef struct sho_tune_result {
  * Autotuner: times the projection of psi into c (both device buffers of the
  * plan's sizes; c is overwritten) under every schedule (with and without
  * SHO_SCHED_XCD) x work item size
- * {8192, 16384, 32768} x band tile {current, half}, reps launches each after
+ * {4096, 8192, 16384, 32768} x band tile {current, half}, reps launches each after
  * one warm-up, on stream, and keeps the fastest.  Synchronous.  result may
  * be NULL.  psi and c hold the plan's element type (double, or float for
  * SHO_FLAG_FP32 plans).  Refused (SHO_E_INVALID) on stored and per-atom

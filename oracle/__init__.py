@@ -61,6 +61,11 @@ def _load():
     for f in (lib.oracle_project_k, lib.oracle_expand_k):
         f.argtypes = geo + [_dp, ctypes.c_int, _dp, _dp, _dp]
         f.restype = ctypes.c_int
+    lib.fact_threads.argtypes = []
+    lib.fact_threads.restype = ctypes.c_int
+    for f in (lib.fact_project, lib.fact_expand):
+        f.argtypes = geo + [ctypes.c_int, _dp, _dp]
+        f.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -170,6 +175,42 @@ def project(n, h, periodic, pos, sigma, numax, psi, rbox=None, spos=None,
     if rc:
         raise ValueError("oracle_project: bad arguments")
     return (c, ca) if with_abs else c
+
+
+def threads():
+    """OpenMP threads the CPU paths run with."""
+    return int(_load().fact_threads())
+
+
+def factorised_project(n, h, periodic, pos, sigma, numax, psi, rbox=None):
+    """The factorised CPU path (sho_factorised.c): x, y and z passes per atom,
+    double sums, OpenMP over atoms.  Same result as ``project`` up to
+    rounding; the benchmark's CPU reference point, not the checker."""
+    na, pos, sigma, numax, rbox, _ = _atoms(pos, sigma, numax, rbox, None)
+    psi = _f64(psi)
+    B = psi.shape[-1]
+    assert psi.size == int(n[0]) * int(n[1]) * int(n[2]) * B
+    c = np.zeros(int(coeff_offsets(numax, B)[-1]))
+    nn, hh, pp = _grid(n, h, periodic)
+    if _load().fact_project(nn, hh, pp, na, _d(pos), _d(sigma), numax.ctypes.data_as(_ip),
+                            _d(rbox), B, _d(psi), _d(c)):
+        raise ValueError("fact_project: bad arguments")
+    return c
+
+
+def factorised_expand(n, h, periodic, pos, sigma, numax, c, psi, rbox=None):
+    """psi += expansion of c by the factorised CPU path, in place (psi must be
+    a C-contiguous float64 array); returns psi."""
+    na, pos, sigma, numax, rbox, _ = _atoms(pos, sigma, numax, rbox, None)
+    assert psi.dtype == np.float64 and psi.flags.c_contiguous
+    B = psi.shape[-1]
+    c = _f64(c)
+    assert c.size == int(coeff_offsets(numax, B)[-1])
+    nn, hh, pp = _grid(n, h, periodic)
+    if _load().fact_expand(nn, hh, pp, na, _d(pos), _d(sigma), numax.ctypes.data_as(_ip),
+                           _d(rbox), B, _d(c), _d(psi)):
+        raise ValueError("fact_expand: bad arguments")
+    return psi
 
 
 def expand(n, h, periodic, pos, sigma, numax, c, psi_in, rbox=None, spos=None,

@@ -40,12 +40,14 @@ FLAG_DETERMINISTIC = 0x20
 SCHED_BY_NU = 0
 SCHED_SINGLE = 1
 SCHED_SINGLE_LPT = 2
+SCHED_SWEEP = 3
 SCHED_XCD = 4
 EXPAND_ROWS = 0
 EXPAND_BLOCKS = 1
 EXPAND_OWNER = 2
-SCHEDULES = (SCHED_BY_NU, SCHED_SINGLE, SCHED_SINGLE_LPT,
-             SCHED_BY_NU | SCHED_XCD, SCHED_SINGLE | SCHED_XCD, SCHED_SINGLE_LPT | SCHED_XCD)
+SCHEDULES = (SCHED_BY_NU, SCHED_SINGLE, SCHED_SINGLE_LPT, SCHED_SWEEP,
+             SCHED_BY_NU | SCHED_XCD, SCHED_SINGLE | SCHED_XCD, SCHED_SINGLE_LPT | SCHED_XCD,
+             SCHED_SWEEP | SCHED_XCD)
 
 # every symbol include/sho.h declares
 EXPORTS = (

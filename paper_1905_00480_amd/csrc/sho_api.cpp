@@ -1052,8 +1052,8 @@ sho_status sho_plan_tune(sho_plan_t p, const void *psi, void *c, int32_t reps,
   };
   std::vector<Cand> cands;
   const int32_t tb0 = p->hp.tb_shift;
-  for (int32_t sc : {0, 1, 2, 4, 5, 6})
-    for (int64_t tp : {(int64_t)8192, (int64_t)16384, (int64_t)32768})
+  for (int32_t sc : {0, 1, 2, 3, 4, 5, 6, 7})
+    for (int64_t tp : {(int64_t)4096, (int64_t)8192, (int64_t)16384, (int64_t)32768})
       for (int32_t tb = tb0; tb >= std::max(0, tb0 - 1); --tb) cands.push_back({sc, tb, tp});
   const Cand before{p->hp.sched, tb0, p->hp.target_points};
   hipEvent_t ea = nullptr, eb = nullptr;

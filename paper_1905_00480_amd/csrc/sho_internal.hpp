@@ -242,9 +242,11 @@ int choose_tb_shift(int nbands, int nu_max, size_t lds_limit);
 constexpr int32_t kSchedByNu = 0;       // one launch per cut-off
 constexpr int32_t kSchedSingle = 1;     // one launch, items in space order
 constexpr int32_t kSchedSingleLpt = 2;  // one launch, items by falling cost
+constexpr int32_t kSchedSweep = 3;      // one launch, items by first plane z,
+                                        // then (x, y) Morton order
 constexpr int32_t kSchedXcd = 4;        // flag: deal items to the 8 XCDs in
                                         // contiguous blocks of the order
-constexpr int32_t kSchedCount = 3;      // base schedules
+constexpr int32_t kSchedCount = 4;      // base schedules
 constexpr int32_t kXcds = 8;            // dispatch interleaves workgroups
                                         // over the XCDs by linear id
 

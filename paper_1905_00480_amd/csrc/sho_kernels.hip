@@ -184,9 +184,9 @@ __device__ inline void load_batch(const KArgs &K, const RunState &r, int jb,
 
 // z pass of the projection for one plane: fold the slots (same band,
 // different runs of the plane), then C[n] += phi_nz(z) T2[nx][ny].
-template <int NU>
+template <int NU, bool DET>
 __device__ inline void flush_plane(cptr<double> fz, double *T2, double *cacc,
-                                   const Lanes &L, bool det) {
+                                   const Lanes &L) {
   constexpr int NF = NU + 1;
   constexpr int NP = NF * (NF + 1) / 2;
   for (int s = 32; s >= L.TB; s >>= 1) {
@@ -205,7 +205,7 @@ __device__ inline void flush_plane(cptr<double> fz, double *T2, double *cacc,
         for (int nx = 0; nx < NF - ny; ++nx, ++q) {
           if (nx + ny + nz <= NU) {
             // deterministic plans: the wave's own tile, one lane per value
-            if (det)
+            if constexpr (DET)
               cacc[idx * L.TB + L.bl] += f * T2[q];
             else
               atomicAdd(&cacc[idx * L.TB + L.bl], f * T2[q]);
@@ -224,7 +224,7 @@ __device__ inline void flush_plane(cptr<double> fz, double *T2, double *cacc,
 // Adds sum over the runs of bundles [b0,b1) of P_n(i) psi(i) (no h^3), for
 // the workgroup's band tile, into cacc[n*TB + bl] (LDS).  One batch of loads
 // is always in flight while the previous one is contracted.
-template <int NU>
+template <int NU, bool DET>
 __device__ inline void project_bundles(const KArgs &K, const AtomRec &A,
                                        const Lanes &L, int b0, int b1,
                                        const double *__restrict__ psi,
@@ -247,7 +247,7 @@ __device__ inline void project_bundles(const KArgs &K, const AtomRec &A,
   load_batch(K, rs, bd.jlo, v);
   for (int bi = b0; bi < b1; ++bi) {
     if (bd.jz != cur_jz) {
-      if (cur_jz >= 0) flush_plane<NU>(tz + cur_jz * nfp, T2, cacc, L, K.det != 0);
+      if (cur_jz >= 0) flush_plane<NU, DET>(tz + cur_jz * nfp, T2, cacc, L);
       cur_jz = bd.jz;
     }
     double T1[NF];
@@ -294,12 +294,12 @@ __device__ inline void project_bundles(const KArgs &K, const AtomRec &A,
     bd = nbd;
     rs = nrs;
   }
-  flush_plane<NU>(tz + cur_jz * nfp, T2, cacc, L, K.det != 0);
+  flush_plane<NU, DET>(tz + cur_jz * nfp, T2, cacc, L);
 }
 
 // One work item of the projection: zero the LDS tile, stream the item's
 // bundles, write (or, for a shared atom, add) h^3 C into c.
-template <int NU>
+template <int NU, bool DET>
 __device__ inline void project_item(const KArgs &K, cptr<WorkRec> W, const AtomRec &A,
                                     const double *__restrict__ psi,
                                     double *__restrict__ c, double *cacc) {
@@ -308,12 +308,12 @@ __device__ inline void project_item(const KArgs &K, cptr<WorkRec> W, const AtomR
   const int tile = blockIdx.y;
   const int TB = 1 << K.tb_shift;
   const int nt = NS * TB;  // one coefficient tile
-  const int tiles = K.det ? kWaves : 1;
+  constexpr int tiles = DET ? kWaves : 1;
   for (int t = threadIdx.x; t < nt * tiles; t += blockDim.x) cacc[t] = 0.0;
   __syncthreads();
   const int w = wave_id();
   const Lanes L = lane_geometry(K, tile);
-  project_bundles<NU>(K, A, L, W->wb[w], W->wb[w + 1], psi, K.det ? cacc + w * nt : cacc);
+  project_bundles<NU, DET>(K, A, L, W->wb[w], W->wb[w + 1], psi, DET ? cacc + w * nt : cacc);
   __syncthreads();
   const bool split = W->split != 0;
   for (int t = threadIdx.x; t < nt; t += blockDim.x) {
@@ -330,7 +330,7 @@ __device__ inline void project_item(const KArgs &K, cptr<WorkRec> W, const AtomR
   }
 }
 
-template <int NU>
+template <int NU, bool DET>
 __global__ __launch_bounds__(kBlock)
 __attribute__((amdgpu_waves_per_eu(waves_per_eu(NU + 1)))) void k_project(
     KArgs K, const double *__restrict__ psi, double *__restrict__ c) {
@@ -338,13 +338,13 @@ __attribute__((amdgpu_waves_per_eu(waves_per_eu(NU + 1)))) void k_project(
   const cptr<WorkRec> W = as_const(K.work) + blockIdx.x;
   if (W->atom < 0) return;  // padding of an XCD-dealt launch
   const AtomRec A = load_uniform(K.atoms + W->atom);
-  project_item<NU>(K, W, A, psi, c, cacc);
+  project_item<NU, DET>(K, W, A, psi, c, cacc);
 }
 
 // All cut-offs in one launch: the item's atom selects the instantiation
 // (a wave-uniform branch).  Registers are those of the largest case, so the
 // single launch serves plans whose cut-offs differ.
-template <int NUMAX>
+template <int NUMAX, bool DET>
 __global__ __launch_bounds__(kBlock)
 __attribute__((amdgpu_waves_per_eu(waves_per_eu(NUMAX + 1)))) void k_project_any(
     KArgs K, const double *__restrict__ psi, double *__restrict__ c) {
@@ -355,7 +355,7 @@ __attribute__((amdgpu_waves_per_eu(waves_per_eu(NUMAX + 1)))) void k_project_any
   switch (A.nu) {
 #define X(N)                                                  \
   case N:                                                     \
-    if constexpr (N <= NUMAX) project_item<N>(K, W, A, psi, c, cacc); \
+    if constexpr (N <= NUMAX) project_item<N, DET>(K, W, A, psi, c, cacc); \
     break;
     SHO_NU_CASES(X)
 #undef X
@@ -1294,7 +1294,7 @@ __device__ inline void coeff_decode(int n, int nu, int &nx, int &ny, int &nz) {
 // (phi_n' = (1/sigma)[sqrt(n/2) phi_{n-1} - sqrt((n+1)/2) phi_{n+1}]) and the
 // contraction grad[a][d] += sum_{n,b} w[n][b] dC[n][b]/dR_d.
 // grad must be zero before the launch (work items and band tiles add).
-template <int NU1>
+template <int NU1, bool DET>
 __global__ __launch_bounds__(kBlock)
 __attribute__((amdgpu_waves_per_eu(waves_per_eu(NU1 + 1)))) void k_force(
     KArgs K, const double *__restrict__ psi, const double *__restrict__ w,
@@ -1311,14 +1311,14 @@ __attribute__((amdgpu_waves_per_eu(waves_per_eu(NU1 + 1)))) void k_force(
   const AtomRec A = load_uniform(K.atoms + a);
   const int TB = 1 << K.tb_shift;
   const int nt = NS1 * TB;
-  const int tiles = K.det ? kWaves : 1;
+  constexpr int tiles = DET ? kWaves : 1;
   for (int t = threadIdx.x; t < nt * tiles; t += blockDim.x) cacc[t] = 0.0;
   __syncthreads();
   const int wv = wave_id();
   const Lanes L = lane_geometry(K, tile);
-  project_bundles<NU1>(K, A, L, W->wb[wv], W->wb[wv + 1], psi, K.det ? cacc + wv * nt : cacc);
+  project_bundles<NU1, DET>(K, A, L, W->wb[wv], W->wb[wv + 1], psi, DET ? cacc + wv * nt : cacc);
   __syncthreads();
-  if (K.det) {  // the waves' tiles, added in wave order into the first
+  if constexpr (DET) {  // the waves' tiles, added in wave order into the first
     for (int t = threadIdx.x; t < nt; t += blockDim.x) {
       double v = cacc[t];
       for (int k = 1; k < tiles; ++k) v += cacc[k * nt + t];
@@ -1360,7 +1360,7 @@ __attribute__((amdgpu_waves_per_eu(waves_per_eu(NU1 + 1)))) void k_force(
   if (threadIdx.x < 3) {
     double s = 0.0;
     for (int k = 0; k < kWaves; ++k) s += red[threadIdx.x][k];
-    if (gpart)
+    if constexpr (DET)
       gpart[((int64_t)a * K.ntiles + tile) * 3 + threadIdx.x] = -K.h3 / A.sigma * s;
     else
       unsafeAtomicAdd(&grad[3 * a + threadIdx.x], -K.h3 / A.sigma * s);
@@ -1401,7 +1401,10 @@ template <int NU>
 static hipError_t launch_project_nu(const KArgs &K, const double *psi,
                                     double *c, hipStream_t s) {
   const size_t shm = proj_lds(K, NU + 1);
-  hipLaunchKernelGGL(k_project<NU>, grid_of(K), dim3(kBlock), shm, s, K, psi, c);
+  if (K.det)
+    hipLaunchKernelGGL((k_project<NU, true>), grid_of(K), dim3(kBlock), shm, s, K, psi, c);
+  else
+    hipLaunchKernelGGL((k_project<NU, false>), grid_of(K), dim3(kBlock), shm, s, K, psi, c);
   return hipGetLastError();
 }
 
@@ -1410,7 +1413,14 @@ static hipError_t launch_force_nu(const KArgs &K, const double *psi,
                                   const double *w, double *grad,
                                   hipStream_t s, double *gpart) {
   const size_t shm = proj_lds(K, NU1 + 1);
-  hipLaunchKernelGGL(k_force<NU1>, grid_of(K), dim3(kBlock), shm, s, K, psi, w, grad, gpart);
+  if (K.det) {
+    if (!gpart) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_force<NU1, true>), grid_of(K), dim3(kBlock), shm, s, K, psi, w, grad,
+                       gpart);
+  } else {
+    hipLaunchKernelGGL((k_force<NU1, false>), grid_of(K), dim3(kBlock), shm, s, K, psi, w, grad,
+                       gpart);
+  }
   return hipGetLastError();
 }
 
@@ -1419,7 +1429,12 @@ template <int NUMAX>
 static hipError_t launch_project_any_nu(const KArgs &K, const double *psi,
                                         double *c, hipStream_t s) {
   const size_t shm = proj_lds(K, NUMAX + 1);
-  hipLaunchKernelGGL(k_project_any<NUMAX>, grid_of(K), dim3(kBlock), shm, s, K, psi, c);
+  if (K.det)
+    hipLaunchKernelGGL((k_project_any<NUMAX, true>), grid_of(K), dim3(kBlock), shm, s, K, psi,
+                       c);
+  else
+    hipLaunchKernelGGL((k_project_any<NUMAX, false>), grid_of(K), dim3(kBlock), shm, s, K, psi,
+                       c);
   return hipGetLastError();
 }
 

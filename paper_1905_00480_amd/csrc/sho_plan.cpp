@@ -272,6 +272,22 @@ uint64_t morton_key(const HostPlan *P, int32_t a) {
   return key;
 }
 
+// 2D Morton key of the (x, y) position of a centre, cells of four points.
+uint64_t morton_xy(const HostPlan *P, int32_t a) {
+  uint64_t key = 0;
+  uint32_t q[2];
+  for (int d = 0; d < 2; ++d) {
+    const int32_t n = P->grid.n[d];
+    int64_t i = (int64_t)std::floor(P->support_centre[3 * a + d] / P->grid.h);
+    if (P->grid.periodic[d]) i = ((i % n) + n) % n;
+    i = std::min<int64_t>(std::max<int64_t>(i, 0), n - 1);
+    q[d] = (uint32_t)(i >> 2);
+  }
+  for (int bit = 0; bit < 16; ++bit)
+    for (int d = 0; d < 2; ++d) key |= (uint64_t)((q[d] >> bit) & 1u) << (2 * bit + (1 - d));
+  return key;
+}
+
 }  // namespace
 
 void build_work(HostPlan *P, int tb_shift, int64_t target_points, int32_t sched) {
@@ -392,6 +408,29 @@ void build_work(HostPlan *P, int tb_shift, int64_t target_points, int32_t sched)
                        [&](int32_t x, int32_t y) { return item_cost[x] > item_cost[y]; });
       order_items.clear();
       for (int32_t i : idx) order_items.push_back(P->work[i]);
+    }
+    if (base == kSchedSweep) {
+      // plane sweep: items by the memory plane of their first bundle, then
+      // by the (x, y) Morton key of their atom, so that the workgroups
+      // resident at one time cover a few consecutive planes of psi and the
+      // overlapping supports of neighbouring atoms are read close in time
+      const int32_t nz = P->grid.n[2];
+      std::vector<std::pair<uint64_t, int32_t>> keyed(order_items.size());
+      for (size_t i = 0; i < order_items.size(); ++i) {
+        const WorkRec &W = order_items[i];
+        const AtomRec &A = P->atoms[W.atom];
+        int64_t z = (int64_t)A.iz0 + P->bundles[W.wb[0]].jz;
+        if (P->grid.periodic[2]) z = ((z % nz) + nz) % nz;
+        z = std::min<int64_t>(std::max<int64_t>(z, 0), nz - 1);
+        keyed[i] = {((uint64_t)z << 40) | morton_xy(P, W.atom), (int32_t)i};
+      }
+      std::stable_sort(keyed.begin(), keyed.end(),
+                       [](const std::pair<uint64_t, int32_t> &x,
+                          const std::pair<uint64_t, int32_t> &y) { return x.first < y.first; });
+      std::vector<WorkRec> sorted;
+      sorted.reserve(order_items.size());
+      for (const auto &k : keyed) sorted.push_back(order_items[k.second]);
+      order_items.swap(sorted);
     }
     if (!order_items.empty()) groups.push_back(ProjGroup{-1, 0, (int32_t)order_items.size()});
   }

@@ -51,7 +51,7 @@ def mixed():
     return s, psi, cin, c_ref, e_ref, g_ref
 
 
-@pytest.mark.parametrize("sched", [0, 1, 2, 4, 5, 6])
+@pytest.mark.parametrize("sched", [0, 1, 2, 3, 4, 5, 6, 7])
 @pytest.mark.parametrize("tile_half", [False, True])
 @pytest.mark.parametrize("target", [256, 16384])
 def test_schedules_match_oracle(mixed, sched, tile_half, target):
