@@ -281,6 +281,24 @@ sho_status sho_plan_force(sho_plan_t plan, const double *psi,
 sho_status sho_plan_matrix_offsets(sho_plan_t plan, int64_t *off);
 sho_status sho_plan_multiply(sho_plan_t plan, const double *D, const double *c,
                              double *d, void *stream);
+/*
+ * Allocation-free expansion, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): psi (device) += expansion of c (device), as sho_plan_expand,
+ * but the plane partials live in a static device array of the library
+ * (SHO_STATIC_SCRATCH_DOUBLES doubles, 32 MiB, one copy per device, held
+ * until the process ends) instead of the plan's lazily allocated scratch.
+ * The call allocates nothing and records no profiling events.  Every call on
+ * one device shares that device's array and overwrites it: calls that
+ * overlap in time on one device (other streams, other threads, other plans)
+ * race and give wrong results; the caller must order them.  FP64 plans only.
+ * Errors as sho_plan_expand, and SHO_E_INVALID when the plan's plane
+ * partials (sho_plan_info.expand_scratch_doubles) exceed the array.
+ */
+#define SHO_STATIC_SCRATCH_DOUBLES 4194304
+sho_status sho_plan_expand_noalloc(sho_plan_t plan, const double *c, double *psi,
+                                   void *stream);
+
 sho_status sho_plan_apply(sho_plan_t plan, const double *psi, const double *D,
                           double *c, double *d, double *out, void *stream);
 

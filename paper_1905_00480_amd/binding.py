@@ -56,7 +56,7 @@ EXPORTS = (
     "sho_plan_set_centres", "sho_plan_project", "sho_plan_expand",
     "sho_plan_project_f32", "sho_plan_expand_f32",
     "sho_plan_force", "sho_project", "sho_expand", "sho_force",
-    "sho_plan_expand_scaled",
+    "sho_plan_expand_scaled", "sho_plan_expand_noalloc",
     "sho_cache_clear", "sho_plan_profile", "sho_plan_profile_read",
     "sho_plan_set_schedule", "sho_plan_get_schedule", "sho_plan_tune",
     "sho_plan_set_expand", "sho_plan_get_expand",
@@ -152,6 +152,7 @@ def load_library(path=None):
     lib.sho_plan_force.argtypes = [P, _vp, _vp, _vp, _vp]
     geo = [G, ctypes.c_int32, _dp, _dp, _i32p, ctypes.c_int32]
     lib.sho_project.argtypes = geo + [_vp, _vp, ctypes.c_uint32, _vp]
+    lib.sho_plan_expand_noalloc.argtypes = [P, _vp, _vp, _vp]
     lib.sho_expand.argtypes = geo + [_vp, _vp, ctypes.c_uint32, _vp]
     lib.sho_force.argtypes = geo + [_vp, _vp, _vp, ctypes.c_uint32, _vp]
     lib.sho_cache_clear.argtypes = []
@@ -364,6 +365,14 @@ class Plan:
         if d is None:
             d = torch.empty_like(c)
         nD = int(self.matrix_offsets()[-1])
+    def expand_noalloc(self, c, psi, stream=None):
+        """psi += expansion of c with the library's static scratch (FP64 plans;
+        allocates nothing; calls overlapping on one device race)."""
+        _check(self._lib.sho_plan_expand_noalloc(
+            self._h, _dev(c, self.coeff_doubles, "c"), _dev(psi, self.psi_numel, "psi"),
+            _stream(stream)))
+        return psi
+
         _check(self._lib.sho_plan_apply(
             self._h, _dev(psi, self.psi_numel, "psi"), _dev(D, nD, "D"),
             _dev(c, self.coeff_doubles, "c"), _dev(d, self.coeff_doubles, "d"),

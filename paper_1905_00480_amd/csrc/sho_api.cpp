@@ -985,6 +985,25 @@ sho_status sho_plan_get_schedule(sho_plan_t p, int32_t *schedule, int32_t *band_
 sho_status sho_plan_set_expand(sho_plan_t p, int32_t mode, int32_t block_rows,
                                int32_t block_x) {
   if (!p) return fail(SHO_E_INVALID, "NULL plan");
+sho_status sho_plan_expand_noalloc(sho_plan_t p, const double *c, double *psi, void *stream) {
+  sho_status st = check_project(p, psi, c);
+  if (st != SHO_OK || p->hp.coeff_rows == 0) return st;
+  const bool uses_u2 = !(p->hp.flags & (SHO_FLAG_STORED | SHO_FLAG_PER_ATOM));
+  if (uses_u2 && p->hp.u2_doubles > sho::kStaticScratchDoubles)
+    return fail(SHO_E_INVALID,
+                "plane partials need " + std::to_string(p->hp.u2_doubles) +
+                    " doubles, the static scratch holds " +
+                    std::to_string(sho::kStaticScratchDoubles));
+  double *u2 = nullptr;
+  hipError_t e = hipSuccess;
+  if (uses_u2 && (e = sho::static_scratch(&u2)) != hipSuccess)
+    return hip_fail(e, "static scratch address");
+  // no profiling events: nothing is created or allocated on this path
+  e = run_expand(p, c, psi, (hipStream_t)stream, false, u2);
+  if (e != hipSuccess) return hip_fail(e, "expand launch");
+  return SHO_OK;
+}
+
   if (mode != sho::kExpandRows && mode != sho::kExpandBlocks && mode != sho::kExpandOwner)
     return fail(SHO_E_INVALID, "unknown expansion form");
   if (p->fp32 && mode != sho::kExpandBlocks)

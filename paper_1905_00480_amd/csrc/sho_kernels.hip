@@ -26,6 +26,8 @@
 // rescaled so that every phi_n has unit L2 norm).
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "sho_launch.hpp"
 
 namespace sho {
@@ -1677,3 +1679,31 @@ hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s) {
 }
 
 }  // namespace sho
+// ------------------------------------------------- static expansion scratch --
+
+// Plane partials of the allocation-free expansion: one copy per device,
+// loaded with the code object and held until the process ends.  Host code
+// must not pass this name to a kernel (on the host it is only a stand-in);
+// static_scratch() returns the device address.
+__device__ __align__(256) double scratch[kStaticScratchDoubles];
+
+hipError_t static_scratch(double **ptr) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static double *addr[kMaxDevices] = {};
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    addr[dev] = static_cast<double *>(p);
+  }
+  *ptr = addr[dev];
+  return hipSuccess;
+}
+

@@ -146,3 +146,10 @@ hipError_t launch_blocks_f32(const EArgs &E, const float *tab, const float *u2, 
                              hipStream_t s);
 
 }  // namespace sho
+// Capacity of the static scratch of the allocation-free expansion (32 MiB).
+constexpr int64_t kStaticScratchDoubles = (int64_t)1 << 22;
+static_assert(kStaticScratchDoubles == SHO_STATIC_SCRATCH_DOUBLES, "static scratch size");
+// Device address of the current device's static scratch (looked up once per
+// device; no allocation).
+hipError_t static_scratch(double **ptr);
+
