@@ -99,9 +99,9 @@ def test_schedule_arguments_host_only():
     for sched in bd.SCHEDULES:
         p.set_schedule(sched, tile // 2, 4096)
         assert p.schedule() == (sched, tile // 2, 4096)
-    _expect(bd.SHO_E_INVALID, lambda: p.set_schedule(3, 0, 4096))
-    _expect(bd.SHO_E_INVALID, lambda: p.set_schedule(7, 0, 4096))
+    _expect(bd.SHO_E_INVALID, lambda: p.set_schedule(-1, 0, 4096))
     _expect(bd.SHO_E_INVALID, lambda: p.set_schedule(8, 0, 4096))
+    _expect(bd.SHO_E_INVALID, lambda: p.set_schedule(12, 0, 4096))
     _expect(bd.SHO_E_INVALID, lambda: p.set_schedule(0, 3, 4096))
     _expect(bd.SHO_E_INVALID, lambda: p.set_schedule(0, 0, 10))
     # nu_max + 1 = 11 coefficients tile (364 functions) at twice the widest
