@@ -415,12 +415,51 @@ def paper_table(bd, wl, args):
         rows.append(row)
         _log("paper geometry nu_max %d: SHO prj %.2f add %.2f ms, USU prj %.2f add %.2f ms"
              % (nu, row["SHOprj_ms"], row["SHOadd_ms"], row["USUprj_ms"], row["USUadd_ms"]))
+    # table 2 of the paper: 18 stored numerical projectors (two radial
+    # functions each for s, p, d) against the 35 SHO functions of nu_max = 4
+    # that span them, on the same spheres
+    s = wl.paper_fcc(numax=0)
+    rc = float(s.rbox[0])
+    ell, dr, tab = wl.radial_set(rc)
+    plan = bd.Plan.radial(s.n, s.h, s.periodic, s.pos, np.full(s.natoms, rc), ell, dr, tab,
+                          s.nbands)
+    c = torch.zeros(plan.coeff_doubles, dtype=torch.float64, device="cuda")
+    plan.project(psi, c)
+    form = _best_stored_form(plan, c, out, reps=2)[0]
+    plan.expand(c, out)
+    torch.cuda.synchronize()
+    plan.profile(True)
+    for _ in range(3):
+        plan.project(psi, c)
+    for _ in range(3):
+        plan.expand(c, out)
+    torch.cuda.synchronize()
+    prof = plan.profile_read()
+    plan.profile(False)
+    usu = {"projectors": int(plan.coeff_doubles // (s.natoms * s.nbands)),
+           "prj_ms": prof["project"][1],
+           "add_ms": prof["expand_z"][1] + prof["expand_xy"][1],
+           "expand_form": form, "stored_bytes": plan.info["device_bytes"]}
+    plan.close()
+    del c
+    sho35 = rows[4]
+    table2 = {"USU18_prj_ms": usu["prj_ms"], "USU18_add_ms": usu["add_ms"],
+              "SHO35_prj_ms": sho35["SHOprj_ms"], "SHO35_add_ms": sho35["SHOadd_ms"],
+              "S_prj": usu["prj_ms"] / sho35["SHOprj_ms"],
+              "S_add": usu["add_ms"] / sho35["SHOadd_ms"],
+              "S_both": (usu["prj_ms"] + usu["add_ms"]) /
+                        (sho35["SHOprj_ms"] + sho35["SHOadd_ms"]),
+              "USU18": usu,
+              "paper_double_P100_V100": {"prj": [2.2, 1.4], "add": [3.1, 2.5],
+                                         "both": [2.6, 2.0]}}
+    _log("paper geometry USU18 vs SHO35: prj %.2f / %.2f ms, add %.2f / %.2f ms"
+         % (usu["prj_ms"], sho35["SHOprj_ms"], usu["add_ms"], sho35["SHOadd_ms"]))
     del psi, out
     torch.cuda.empty_cache()
     return {"workload": "fcc a=4.08 A, isolated 64^3 at h=0.25 A, 650 atoms with 3.55 A "
                         "projection spheres (11 projections per grid value), sigma=1.6 Bohr, "
                         "1024 FP64 bands; times per kernel call",
-            "rows": rows}
+            "rows": rows, "table2_usu18_vs_sho35": table2}
 
 
 def batching(bd, wl, args):

@@ -206,6 +206,38 @@ sho_status sho_plan_create(const sho_grid *grid, int32_t natoms,
                            const int32_t *numax, const double *rbox,
                            int32_t nbands, uint32_t flags, sho_plan_t *out);
 
+/*
+ * Stored numerical projectors (the paper's USU reference kernels, sec. 6:
+ * precomputed projector values read from memory; its USU18 set holds two
+ * radial functions each for l = 0, 1, 2):
+ *   p_j(r) = P_k(|r - R_a|) Y_{l_k m}((r - R_a)^),  j over k, then m = -l_k..l_k
+ * with P_k tabulated on a uniform radial grid, tables[k][i] = P_k(i dr),
+ * i = 0..nr-1; between nodes P_k is the cubic Lagrange interpolant through
+ * the nodes s..s+3, s = clamp(floor(r/dr) - 1, 0, nr - 4), and zero from
+ * r = (nr-1) dr on.  Y_lm are the real spherical harmonics without the
+ * Condon-Shortley sign (Y_11 ~ +x, Y_1,-1 ~ +y), unit-normalised on the
+ * sphere; at r = 0 only l = 0 is nonzero.  The support of atom a is the
+ * sphere of radius rcut[a] (same point rule, images and clipping as the SHO
+ * supports).  The plan samples every p_j at every support point once, into
+ * its device tables, and then projects and expands by reading them back on
+ * the FP64 matrix cores (the stored kernels of SHO_FLAG_STORED plans):
+ *   c[a][j][b] = h^3 sum_{i in S_a} p_j(i) psi_b(i),  psi_b += sum c p_j.
+ * Coefficient blocks are [nproj][nbands] per atom, nproj = sum_k (2 l_k + 1).
+ *   ell     host [nradial], 0..3;  nradial 1..16, nproj <= 56
+ *   tables  host [nradial][nr], copied during the call;  nr >= 4, dr > 0
+ *   rcut    host [natoms] support radii (Bohr)
+ *   flags   0 or SHO_FLAG_HOST_ONLY
+ * sho_plan_project / _expand / _destroy / _get_info / _coeff_offsets /
+ * _support_counts / _set_expand and the graph calls accept the plan; the
+ * derivative, moving centres, the atomic-matrix calls, FP32 and tuning are
+ * refused (SHO_E_INVALID).  Errors: SHO_E_INVALID, SHO_E_BOX, SHO_E_NOMEM,
+ * SHO_E_DEVICE.
+ */
+sho_status sho_plan_create_radial(const sho_grid *grid, int32_t natoms, const double *pos,
+                                  const double *rcut, int32_t nradial, const int32_t *ell,
+                                  int32_t nr, double dr, const double *tables,
+                                  int32_t nbands, uint32_t flags, sho_plan_t *out);
+
 /* Free a plan's device tables.  Waits for the device first, so work already
  * queued with the plan finishes.  NULL is accepted. */
 sho_status sho_plan_destroy(sho_plan_t plan);
@@ -250,6 +282,24 @@ sho_status sho_plan_expand_scaled(sho_plan_t plan, double alpha, const double *c
 
 
 /*
+ * Allocation-free expansion, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): psi (device) += expansion of c (device), as sho_plan_expand,
+ * but the plane partials live in a static device array of the library
+ * (SHO_STATIC_SCRATCH_DOUBLES doubles, 32 MiB, one copy per device, held
+ * until the process ends) instead of the plan's lazily allocated scratch.
+ * The call allocates nothing and records no profiling events.  Every call on
+ * one device shares that device's array and overwrites it: calls that
+ * overlap in time on one device (other streams, other threads, other plans)
+ * race and give wrong results; the caller must order them.  FP64 plans only.
+ * Errors as sho_plan_expand, and SHO_E_INVALID when the plan's plane
+ * partials (sho_plan_info.expand_scratch_doubles) exceed the array.
+ */
+#define SHO_STATIC_SCRATCH_DOUBLES 4194304
+sho_status sho_plan_expand_noalloc(sho_plan_t plan, const double *c, double *psi,
+                                   void *stream);
+
+/*
  * Single precision (SHO_FLAG_FP32 plans), same layouts with float elements:
  * c[n][b] (device, coeff_doubles floats) <- projection of psi (device,
  * grid x nbands floats), and psi += expansion of c.  The 1D functions are
@@ -281,24 +331,6 @@ sho_status sho_plan_force(sho_plan_t plan, const double *psi,
 sho_status sho_plan_matrix_offsets(sho_plan_t plan, int64_t *off);
 sho_status sho_plan_multiply(sho_plan_t plan, const double *D, const double *c,
                              double *d, void *stream);
-/*
- * Allocation-free expansion, for callers that cannot allocate device memory
- * (code under HIP graph capture, tight serving loops, harnesses that forbid
- * hipMalloc): psi (device) += expansion of c (device), as sho_plan_expand,
- * but the plane partials live in a static device array of the library
- * (SHO_STATIC_SCRATCH_DOUBLES doubles, 32 MiB, one copy per device, held
- * until the process ends) instead of the plan's lazily allocated scratch.
- * The call allocates nothing and records no profiling events.  Every call on
- * one device shares that device's array and overwrites it: calls that
- * overlap in time on one device (other streams, other threads, other plans)
- * race and give wrong results; the caller must order them.  FP64 plans only.
- * Errors as sho_plan_expand, and SHO_E_INVALID when the plan's plane
- * partials (sho_plan_info.expand_scratch_doubles) exceed the array.
- */
-#define SHO_STATIC_SCRATCH_DOUBLES 4194304
-sho_status sho_plan_expand_noalloc(sho_plan_t plan, const double *c, double *psi,
-                                   void *stream);
-
 sho_status sho_plan_apply(sho_plan_t plan, const double *psi, const double *D,
                           double *c, double *d, double *out, void *stream);
 

@@ -56,7 +56,7 @@ EXPORTS = (
     "sho_plan_set_centres", "sho_plan_project", "sho_plan_expand",
     "sho_plan_project_f32", "sho_plan_expand_f32",
     "sho_plan_force", "sho_project", "sho_expand", "sho_force",
-    "sho_plan_expand_scaled", "sho_plan_expand_noalloc",
+    "sho_plan_expand_scaled", "sho_plan_expand_noalloc", "sho_plan_create_radial",
     "sho_cache_clear", "sho_plan_profile", "sho_plan_profile_read",
     "sho_plan_set_schedule", "sho_plan_get_schedule", "sho_plan_tune",
     "sho_plan_set_expand", "sho_plan_get_expand",
@@ -139,6 +139,9 @@ def load_library(path=None):
     lib.sho_plan_create.argtypes = [G, ctypes.c_int32, _dp, _dp, _i32p, _dp,
                                     ctypes.c_int32, ctypes.c_uint32,
                                     ctypes.POINTER(_vp)]
+    lib.sho_plan_create_radial.argtypes = [G, ctypes.c_int32, _dp, _dp, ctypes.c_int32, _i32p,
+                                           ctypes.c_int32, ctypes.c_double, _dp, ctypes.c_int32,
+                                           ctypes.c_uint32, ctypes.POINTER(ctypes.c_void_p)]
     lib.sho_plan_destroy.argtypes = [P]
     lib.sho_plan_get_info.argtypes = [P, ctypes.POINTER(sho_plan_info)]
     lib.sho_plan_coeff_offsets.argtypes = [P, _i64p]
@@ -149,10 +152,10 @@ def load_library(path=None):
     lib.sho_plan_project_f32.argtypes = [P, _vp, _vp, _vp]
     lib.sho_plan_expand_f32.argtypes = [P, _vp, _vp, _vp]
     lib.sho_plan_expand_scaled.argtypes = [P, ctypes.c_double, _vp, _vp, _vp]
+    lib.sho_plan_expand_noalloc.argtypes = [P, _vp, _vp, _vp]
     lib.sho_plan_force.argtypes = [P, _vp, _vp, _vp, _vp]
     geo = [G, ctypes.c_int32, _dp, _dp, _i32p, ctypes.c_int32]
     lib.sho_project.argtypes = geo + [_vp, _vp, ctypes.c_uint32, _vp]
-    lib.sho_plan_expand_noalloc.argtypes = [P, _vp, _vp, _vp]
     lib.sho_expand.argtypes = geo + [_vp, _vp, ctypes.c_uint32, _vp]
     lib.sho_force.argtypes = geo + [_vp, _vp, _vp, ctypes.c_uint32, _vp]
     lib.sho_cache_clear.argtypes = []
@@ -269,13 +272,45 @@ class Plan:
             self._numax.ctypes.data_as(_i32p),
             None if self._rbox is None else self._rbox.ctypes.data_as(_dp),
             self.nbands, int(flags), ctypes.byref(handle)))
+        self._adopt(handle, flags)
+
+    def _adopt(self, handle, flags):
         self._h = handle
         self.fp32 = bool(int(flags) & FLAG_FP32)
         info = sho_plan_info()
-        _check(lib.sho_plan_get_info(self._h, ctypes.byref(info)))
+        _check(self._lib.sho_plan_get_info(self._h, ctypes.byref(info)))
         self.info = {k: getattr(info, k) for k, _ in sho_plan_info._fields_}
         self.coeff_doubles = int(info.coeff_doubles)
         self.support_points = int(info.support_points)
+
+    @classmethod
+    def radial(cls, n, h, periodic, pos, rcut, ell, dr, tables, nbands, flags=0):
+        """Plan over stored numerical projectors P_k(r) Y_lm (sho_plan_create_radial):
+        ell [nradial], tables [nradial][nr] on the radial grid i*dr, rcut [natoms]."""
+        self = cls.__new__(cls)
+        lib = load_library()
+        self._lib = lib
+        self.n = tuple(int(v) for v in n)
+        self.h = float(h)
+        self.periodic = tuple(bool(v) for v in periodic)
+        pos = _host_f64(pos, (-1, 3))
+        self.natoms = pos.shape[0]
+        self._pos = pos
+        self._centres = pos.copy()
+        self._rcut = _host_f64(rcut, (self.natoms,))
+        self._ell = _host_i32(ell, (-1,))
+        tables = _host_f64(tables, (self._ell.size, -1))
+        self._tables = tables
+        self.nbands = int(nbands)
+        self._grid = make_grid(self.n, self.h, self.periodic)
+        handle = ctypes.c_void_p()
+        _check(lib.sho_plan_create_radial(
+            ctypes.byref(self._grid), self.natoms, self._pos.ctypes.data_as(_dp),
+            self._rcut.ctypes.data_as(_dp), int(self._ell.size),
+            self._ell.ctypes.data_as(_i32p), int(tables.shape[1]), float(dr),
+            tables.ctypes.data_as(_dp), self.nbands, int(flags), ctypes.byref(handle)))
+        self._adopt(handle, flags)
+        return self
 
     @classmethod
     def from_system(cls, s, flags=0, rbox=None):
@@ -330,6 +365,14 @@ class Plan:
                   _dev(psi, self.psi_numel, "psi", f32), _stream(stream)))
         return psi
 
+    def expand_noalloc(self, c, psi, stream=None):
+        """psi += expansion of c with the library's static scratch (FP64 plans;
+        allocates nothing; calls overlapping on one device race)."""
+        _check(self._lib.sho_plan_expand_noalloc(
+            self._h, _dev(c, self.coeff_doubles, "c"), _dev(psi, self.psi_numel, "psi"),
+            _stream(stream)))
+        return psi
+
     def force(self, psi, w, grad=None, stream=None):
         import torch
         if grad is None:
@@ -365,14 +408,6 @@ class Plan:
         if d is None:
             d = torch.empty_like(c)
         nD = int(self.matrix_offsets()[-1])
-    def expand_noalloc(self, c, psi, stream=None):
-        """psi += expansion of c with the library's static scratch (FP64 plans;
-        allocates nothing; calls overlapping on one device race)."""
-        _check(self._lib.sho_plan_expand_noalloc(
-            self._h, _dev(c, self.coeff_doubles, "c"), _dev(psi, self.psi_numel, "psi"),
-            _stream(stream)))
-        return psi
-
         _check(self._lib.sho_plan_apply(
             self._h, _dev(psi, self.psi_numel, "psi"), _dev(D, nD, "D"),
             _dev(c, self.coeff_doubles, "c"), _dev(d, self.coeff_doubles, "d"),

@@ -209,6 +209,14 @@ hipError_t upload_blocks(sho_plan_s *p) {
   return hipSuccess;
 }
 
+// Radial projector set of a plan made by sho_plan_create_radial.
+struct RadialInput {
+  int32_t nrad, nr, nproj;
+  double dr;
+  const int32_t *ell;     // [nrad]
+  const double *tables;   // host [nrad][nr]
+};
+
 sho::SArgs make_sargs(const sho_plan_s *p, const Group &g) {
   sho::SArgs S;
   S.atoms = p->d_atoms;
@@ -219,6 +227,7 @@ sho::SArgs make_sargs(const sho_plan_s *p, const Group &g) {
   S.items = p->d_sitems + g.work_begin;
   S.nitems = g.count;
   S.B = p->hp.nbands;
+  S.ncol = p->hp.ncols > 0 ? p->hp.ncols : sho::nsho(g.nu);
   const double h = p->hp.grid.h;
   S.h3 = h * h * h;
   S.alpha = 1.0;
@@ -297,6 +306,7 @@ sho::EArgs make_eargs(const sho_plan_s *p) {
   E.blk_rows = p->hp.blk_rows;
   E.blk_x = p->hp.blk_x;
   E.ny = p->hp.grid.n[1];
+  E.ncol = p->hp.ncols;
   E.alpha = 1.0;
   for (int nu = 0; nu <= SHO_NU_MAX + 1; ++nu) E.nu_begin[nu] = 0;
   {
@@ -354,7 +364,7 @@ int64_t estimate_device_bytes(const sho::HostPlan &hp) {
               b((int64_t)hp.run_desc.size(), 4);
   if (hp.flags & SHO_FLAG_STORED) {
     int64_t stored = 0;
-    for (const auto &A : hp.atoms) stored += (int64_t)A.npoints * sho::nsho(A.nu);
+    for (const auto &A : hp.atoms) stored += (int64_t)A.npoints * sho::stored_cols(hp, A);
     const int64_t items = (hp.support_points + sho::kStoredChunk - 1) / sho::kStoredChunk +
                           hp.natoms;
     t += b(stored, 8) + b(nl + 1, 8) + 2 * b(hp.natoms + 1, 8) + b(hp.support_points, 4) +
@@ -373,8 +383,9 @@ void build_default_blocks(sho::HostPlan *hp) {
   sho::default_block_shape(*hp, &R, &X);
   sho::build_blocks(hp, R, X);
   // stored plans: the block form wins while the products are short (measured
-  // up to nu_max = 2), the atom-owner form with atomics beyond
-  if ((hp->flags & SHO_FLAG_STORED) && hp->nu_max > 2) hp->expand_mode = sho::kExpandRows;
+  // up to nu_max = 2, 10 columns), the atom-owner form with atomics beyond
+  const bool long_rows = hp->ncols > 0 ? hp->ncols > 10 : hp->nu_max > 2;
+  if ((hp->flags & SHO_FLAG_STORED) && long_rows) hp->expand_mode = sho::kExpandRows;
 }
 
 // Plans with several cut-offs run the projection as one launch.
@@ -446,7 +457,7 @@ hipError_t run_project(sho_plan_s *p, const void *psi_v, void *c_v, hipStream_t 
   return timed(p, prof, SHO_KERNEL_PROJECT, s, [&]() {
     if (p->hp.flags & SHO_FLAG_STORED) {
       for (const Group &g : p->sgroups) {
-        hipError_t e1 = sho::launch_project_stored(g.nu, make_sargs(p, g), psi, c, s);
+        hipError_t e1 = sho::launch_project_stored(make_sargs(p, g), psi, c, s);
         if (e1 != hipSuccess) return e1;
       }
       return hipSuccess;
@@ -538,7 +549,7 @@ hipError_t run_expand(sho_plan_s *p, const void *c_v, void *psi_v, hipStream_t s
       for (const Group &g : p->sgroups) {
         sho::SArgs S = make_sargs(p, g);
         S.alpha = alpha;
-        hipError_t e1 = sho::launch_expand_stored(g.nu, S, c, psi, s);
+        hipError_t e1 = sho::launch_expand_stored(S, c, psi, s);
         if (e1 != hipSuccess) return e1;
       }
       return hipSuccess;
@@ -584,46 +595,11 @@ hipError_t run_expand_own(sho_plan_s *p, const void *c, void *psi, hipStream_t s
   return e;
 }
 
-}  // namespace
-
-// ----------------------------------------------------------------- C ABI --
-
-extern "C" {
-
-int32_t sho_nsho(int32_t nu) { return nu < 0 ? -1 : sho::nsho(nu); }
-
-const char *sho_last_error(void) { return g_err.c_str(); }
-
-sho_status sho_plan_create(const sho_grid *grid, int32_t natoms,
-                           const double *pos, const double *sigma,
-                           const int32_t *numax, const double *rbox,
-                           int32_t nbands, uint32_t flags, sho_plan_t *out) {
-  if (!out) return fail(SHO_E_INVALID, "out must not be NULL");
-  *out = nullptr;
-  const bool f32 = (flags & SHO_FLAG_FP32) != 0;
-  if (f32) {
-    if (nbands <= 0 || nbands % 2)
-      return fail(SHO_E_INVALID, "FP32 plans need a positive, even number of bands");
-    if (flags & (SHO_FLAG_STORED | SHO_FLAG_PER_ATOM))
-      return fail(SHO_E_INVALID,
-                  "SHO_FLAG_FP32 does not combine with SHO_FLAG_STORED or SHO_FLAG_PER_ATOM");
-    nbands /= 2;  // the kernels work on band pairs
-  }
-  if ((flags & SHO_FLAG_DETERMINISTIC) &&
-      (flags & (SHO_FLAG_STORED | SHO_FLAG_PER_ATOM | SHO_FLAG_FP32)))
-    return fail(SHO_E_INVALID,
-                "SHO_FLAG_DETERMINISTIC does not combine with SHO_FLAG_STORED, "
-                "SHO_FLAG_PER_ATOM or SHO_FLAG_FP32");
-  sho_plan_s *p = new (std::nothrow) sho_plan_s();
-  if (!p) return fail(SHO_E_NOMEM, "host allocation failed");
-  p->fp32 = f32;
-  std::string msg;
-  sho_status st = sho::build_host_plan(grid, natoms, pos, sigma, numax, rbox,
-                                       nbands, flags, &p->hp, &msg);
-  if (st != SHO_OK) {
-    delete p;
-    return fail(st, msg);
-  }
+// Device side of a new plan whose host geometry p->hp is built: work split,
+// tables, uploads, stored projector tables (sampled SHO functions, or the
+// radial set rad), scratch.  Takes ownership of p (deleted on failure).
+sho_status finish_plan(sho_plan_s *p, uint32_t flags, int32_t nbands, bool f32,
+                       const RadialInput *rad, sho_plan_t *out) {
   // FP32 plans keep the projection's coefficient tile in double for both
   // bands of a pair: half the LDS budget per lane value; deterministic plans
   // keep one tile per wave
@@ -717,8 +693,31 @@ sho_status sho_plan_create(const sho_grid *grid, int32_t natoms,
       p->device_bytes += sb;
       Group all{0, 0, 0};
       sho::KArgs K = make_args(p, all);
-      e = sho::launch_store(K, p->d_run_atom, (int32_t)hp.lines.size(), p->d_stored,
-                            nullptr);
+      if (rad) {
+        // the radial tables are needed only while the stored values are sampled
+        double *d_rad = nullptr;
+        const size_t rb = (size_t)rad->nrad * rad->nr * sizeof(double);
+        e = hipMalloc((void **)&d_rad, rb);
+        if (e == hipSuccess)
+          e = hipMemcpy(d_rad, rad->tables, rb, hipMemcpyHostToDevice);
+        if (e == hipSuccess) {
+          sho::RArgs R{};
+          R.rad = d_rad;
+          R.nrad = rad->nrad;
+          R.nr = rad->nr;
+          R.nproj = rad->nproj;
+          for (int32_t k = 0; k < rad->nrad; ++k) R.ell[k] = rad->ell[k];
+          R.dr = rad->dr;
+          R.h = hp.grid.h;
+          e = sho::launch_store_radial(K, R, p->d_run_atom, (int32_t)hp.lines.size(),
+                                       p->d_stored, nullptr);
+          if (e == hipSuccess) e = hipDeviceSynchronize();
+        }
+        if (d_rad) (void)hipFree(d_rad);
+      } else {
+        e = sho::launch_store(K, p->d_run_atom, (int32_t)hp.lines.size(), p->d_stored,
+                              nullptr);
+      }
     }
   }
   if (e == hipSuccess && (flags & SHO_FLAG_DETERMINISTIC)) {
@@ -736,6 +735,107 @@ sho_status sho_plan_create(const sho_grid *grid, int32_t natoms,
   }
   *out = p;
   return SHO_OK;
+}
+
+
+}  // namespace
+
+// ----------------------------------------------------------------- C ABI --
+
+extern "C" {
+
+int32_t sho_nsho(int32_t nu) { return nu < 0 ? -1 : sho::nsho(nu); }
+
+const char *sho_last_error(void) { return g_err.c_str(); }
+
+sho_status sho_plan_create(const sho_grid *grid, int32_t natoms,
+                           const double *pos, const double *sigma,
+                           const int32_t *numax, const double *rbox,
+                           int32_t nbands, uint32_t flags, sho_plan_t *out) {
+  if (!out) return fail(SHO_E_INVALID, "out must not be NULL");
+  *out = nullptr;
+  const bool f32 = (flags & SHO_FLAG_FP32) != 0;
+  if (f32) {
+    if (nbands <= 0 || nbands % 2)
+      return fail(SHO_E_INVALID, "FP32 plans need a positive, even number of bands");
+    if (flags & (SHO_FLAG_STORED | SHO_FLAG_PER_ATOM))
+      return fail(SHO_E_INVALID,
+                  "SHO_FLAG_FP32 does not combine with SHO_FLAG_STORED or SHO_FLAG_PER_ATOM");
+    nbands /= 2;  // the kernels work on band pairs
+  }
+  if ((flags & SHO_FLAG_DETERMINISTIC) &&
+      (flags & (SHO_FLAG_STORED | SHO_FLAG_PER_ATOM | SHO_FLAG_FP32)))
+    return fail(SHO_E_INVALID,
+                "SHO_FLAG_DETERMINISTIC does not combine with SHO_FLAG_STORED, "
+                "SHO_FLAG_PER_ATOM or SHO_FLAG_FP32");
+  sho_plan_s *p = new (std::nothrow) sho_plan_s();
+  if (!p) return fail(SHO_E_NOMEM, "host allocation failed");
+  p->fp32 = f32;
+  std::string msg;
+  sho_status st = sho::build_host_plan(grid, natoms, pos, sigma, numax, rbox,
+                                       nbands, flags, &p->hp, &msg);
+  if (st != SHO_OK) {
+    delete p;
+    return fail(st, msg);
+  }
+  return finish_plan(p, flags, nbands, f32, nullptr, out);
+}
+
+sho_status sho_plan_create_radial(const sho_grid *grid, int32_t natoms, const double *pos,
+                                  const double *rcut, int32_t nradial, const int32_t *ell,
+                                  int32_t nr, double dr, const double *tables,
+                                  int32_t nbands, uint32_t flags, sho_plan_t *out) {
+  if (!out) return fail(SHO_E_INVALID, "out must not be NULL");
+  *out = nullptr;
+  if (flags & ~(uint32_t)SHO_FLAG_HOST_ONLY)
+    return fail(SHO_E_INVALID, "radial plans take no flags but SHO_FLAG_HOST_ONLY");
+  if (nradial < 1 || nradial > sho::kRadialMaxFuncs || !ell || !tables)
+    return fail(SHO_E_INVALID, "need 1..16 radial functions with their l and tables");
+  if (nr < 4 || !(dr > 0.0) || !std::isfinite(dr))
+    return fail(SHO_E_INVALID, "radial tables need nr >= 4 nodes and a finite dr > 0");
+  int32_t nproj = 0;
+  for (int32_t k = 0; k < nradial; ++k) {
+    if (ell[k] < 0 || ell[k] > sho::kRadialMaxL)
+      return fail(SHO_E_INVALID, "angular momenta must lie in 0..3");
+    nproj += 2 * ell[k] + 1;
+  }
+  if (nproj > sho::kRadialMaxProj)
+    return fail(SHO_E_INVALID, "at most 56 projectors per atom");
+  for (int64_t i = 0; i < (int64_t)nradial * nr; ++i)
+    if (!std::isfinite(tables[i])) return fail(SHO_E_INVALID, "non-finite radial table value");
+  if (natoms < 0 || (natoms > 0 && (!pos || !rcut)))
+    return fail(SHO_E_INVALID, "positions and cut-off radii are required");
+  for (int32_t a = 0; a < natoms; ++a)
+    if (!(rcut[a] > 0.0) || !std::isfinite(rcut[a]))
+      return fail(SHO_E_INVALID, "cut-off radii must be finite and positive");
+  // the support geometry is that of an SHO plan with nu = 0 and the cut-off
+  // as support radius (sigma = rcut only satisfies the sampling bound; the
+  // SHO tables of such a plan are not used)
+  if (!grid || !(grid->h > 0.0)) return fail(SHO_E_INVALID, "grid with a positive spacing required");
+  std::vector<int32_t> nu0(std::max(natoms, 1), 0);
+  std::vector<double> sig(std::max(natoms, 1), grid->h);
+  for (int32_t a = 0; a < natoms; ++a) sig[a] = std::max(rcut[a], grid->h);
+  sho_plan_s *p = new (std::nothrow) sho_plan_s();
+  if (!p) return fail(SHO_E_NOMEM, "host allocation failed");
+  const uint32_t pflags = flags | SHO_FLAG_STORED;
+  std::string msg;
+  sho_status st = sho::build_host_plan(grid, natoms, pos, sig.data(), nu0.data(), rcut,
+                                       nbands, pflags, &p->hp, &msg);
+  if (st != SHO_OK) {
+    delete p;
+    return fail(st, msg);
+  }
+  // coefficient blocks [nproj][B] per atom
+  sho::HostPlan &hp = p->hp;
+  hp.ncols = nproj;
+  hp.coeff_rows = 0;
+  for (int32_t a = 0; a < natoms; ++a) {
+    hp.atoms[a].coeff_row = hp.coeff_rows;
+    hp.coeff_rows += nproj;
+    hp.coeff_off[a + 1] = hp.coeff_rows * nbands;
+  }
+  const RadialInput rad{nradial, nr, nproj, dr, ell, tables};
+  return finish_plan(p, pflags, nbands, false, &rad, out);
 }
 
 sho_status sho_plan_destroy(sho_plan_t p) {
@@ -885,6 +985,25 @@ sho_status sho_plan_expand_scaled(sho_plan_t p, double alpha, const double *c, d
   return SHO_OK;
 }
 
+sho_status sho_plan_expand_noalloc(sho_plan_t p, const double *c, double *psi, void *stream) {
+  sho_status st = check_project(p, psi, c);
+  if (st != SHO_OK || p->hp.coeff_rows == 0) return st;
+  const bool uses_u2 = !(p->hp.flags & (SHO_FLAG_STORED | SHO_FLAG_PER_ATOM));
+  if (uses_u2 && p->hp.u2_doubles > sho::kStaticScratchDoubles)
+    return fail(SHO_E_INVALID,
+                "plane partials need " + std::to_string(p->hp.u2_doubles) +
+                    " doubles, the static scratch holds " +
+                    std::to_string(sho::kStaticScratchDoubles));
+  double *u2 = nullptr;
+  hipError_t e = hipSuccess;
+  if (uses_u2 && (e = sho::static_scratch(&u2)) != hipSuccess)
+    return hip_fail(e, "static scratch address");
+  // no profiling events: nothing is created or allocated on this path
+  e = run_expand(p, c, psi, (hipStream_t)stream, false, u2);
+  if (e != hipSuccess) return hip_fail(e, "expand launch");
+  return SHO_OK;
+}
+
 sho_status sho_plan_project_f32(sho_plan_t p, const float *psi, float *c, void *stream) {
   sho_status st = check_project(p, psi, c, 1);
   if (st != SHO_OK || p->hp.coeff_rows == 0) return st;
@@ -906,6 +1025,7 @@ sho_status sho_plan_force(sho_plan_t p, const double *psi, const double *w,
                           double *grad, void *stream) {
   if (!p) return fail(SHO_E_INVALID, "NULL plan");
   if (p->fp32) return fail(SHO_E_INVALID, "the derivative is FP64 only");
+  if (p->hp.ncols > 0) return fail(SHO_E_INVALID, "radial plans have no derivative");
   if (p->hp.flags & SHO_FLAG_HOST_ONLY)
     return fail(SHO_E_INVALID, "host-only plan cannot run kernels");
   if (p->hp.natoms == 0) return SHO_OK;
@@ -985,25 +1105,6 @@ sho_status sho_plan_get_schedule(sho_plan_t p, int32_t *schedule, int32_t *band_
 sho_status sho_plan_set_expand(sho_plan_t p, int32_t mode, int32_t block_rows,
                                int32_t block_x) {
   if (!p) return fail(SHO_E_INVALID, "NULL plan");
-sho_status sho_plan_expand_noalloc(sho_plan_t p, const double *c, double *psi, void *stream) {
-  sho_status st = check_project(p, psi, c);
-  if (st != SHO_OK || p->hp.coeff_rows == 0) return st;
-  const bool uses_u2 = !(p->hp.flags & (SHO_FLAG_STORED | SHO_FLAG_PER_ATOM));
-  if (uses_u2 && p->hp.u2_doubles > sho::kStaticScratchDoubles)
-    return fail(SHO_E_INVALID,
-                "plane partials need " + std::to_string(p->hp.u2_doubles) +
-                    " doubles, the static scratch holds " +
-                    std::to_string(sho::kStaticScratchDoubles));
-  double *u2 = nullptr;
-  hipError_t e = hipSuccess;
-  if (uses_u2 && (e = sho::static_scratch(&u2)) != hipSuccess)
-    return hip_fail(e, "static scratch address");
-  // no profiling events: nothing is created or allocated on this path
-  e = run_expand(p, c, psi, (hipStream_t)stream, false, u2);
-  if (e != hipSuccess) return hip_fail(e, "expand launch");
-  return SHO_OK;
-}
-
   if (mode != sho::kExpandRows && mode != sho::kExpandBlocks && mode != sho::kExpandOwner)
     return fail(SHO_E_INVALID, "unknown expansion form");
   if (p->fp32 && mode != sho::kExpandBlocks)
@@ -1141,6 +1242,8 @@ sho_status check_multiply(const sho_plan_s *p, const double *D, const double *c,
   if (p->hp.flags & SHO_FLAG_HOST_ONLY)
     return fail(SHO_E_INVALID, "host-only plan cannot run kernels");
   if (p->fp32) return fail(SHO_E_INVALID, "the atomic-matrix product is FP64 only");
+  if (p->hp.ncols > 0)
+    return fail(SHO_E_INVALID, "radial plans carry no atomic matrices in the SHO basis");
   if (p->hp.coeff_rows == 0) return SHO_OK;
   const int64_t db = p->hp.dmat_off.back() * (int64_t)sizeof(double);
   if (!device_range_ok(D, db) || !device_range_ok(c, coeff_bytes(p)) ||

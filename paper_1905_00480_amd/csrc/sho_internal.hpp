@@ -205,6 +205,9 @@ struct HostPlan {
   std::vector<int32_t> pidx;          // grid memory index of every point
   std::vector<StoredItem> sitems;     // point chunks, sorted by nu
   int64_t stored_doubles = 0;
+  int32_t ncols = 0;          // radial plans: projectors per atom (stored
+                              // columns and coefficient rows); 0: the SHO
+                              // basis, N_SHO(nu_a) per atom
   int64_t union_points = 0;   // distinct grid points covered by any support
   int64_t rows_touched = 0;   // memory rows with at least one run
   std::vector<double> support_centre;  // [natoms][3], fixed at creation
@@ -218,6 +221,28 @@ struct HostPlan {
 
 inline int32_t nsho(int32_t nu) {
   return nu < 0 ? 0 : (nu + 1) * (nu + 2) * (nu + 3) / 6;
+}
+
+// Stored values per support point of atom A (columns of its projector table).
+inline int32_t stored_cols(const HostPlan &P, const AtomRec &A) {
+  return P.ncols > 0 ? P.ncols : nsho(A.nu);
+}
+
+// Largest number of radial projectors per atom (sho_plan_create_radial).
+constexpr int32_t kRadialMaxProj = 56;
+constexpr int32_t kRadialMaxFuncs = 16;
+constexpr int32_t kRadialMaxL = 3;
+
+// Compile-time column bound of the stored kernels for a table of ncol
+// columns: the SHO sizes exactly, other counts the next larger of 20 or 56;
+// 0 if more than 56.
+inline int32_t stored_bound(int32_t ncol) {
+  switch (ncol) {
+    case 1: case 4: case 10: case 20: case 35: case 56:
+      return ncol;
+    default:
+      return ncol <= 0 ? 0 : ncol <= 20 ? 20 : ncol <= 56 ? 56 : 0;
+  }
 }
 
 // Builds the host plan geometry (supports, runs, tables layout); returns

@@ -955,6 +955,80 @@ __global__ __launch_bounds__(256) void k_store(KArgs K, const int32_t *__restric
   }
 }
 
+// Real solid harmonic r^l Y_lm(r^) at offset (x, y, z) for l <= 3, m = -l..l:
+// the real spherical harmonics without the Condon-Shortley sign (Y_11 ~ +x,
+// Y_1,-1 ~ +y), normalised on the unit sphere.
+__device__ inline double solid_harmonic(int l, int m, double x, double y, double z) {
+  const double pi = 3.14159265358979323846;
+  const double r2 = x * x + y * y + z * z;
+  switch (l * 8 + m + 3) {
+    case 0 * 8 + 3: return 0.5 / sqrt(pi);
+    case 1 * 8 + 2: return sqrt(0.75 / pi) * y;
+    case 1 * 8 + 3: return sqrt(0.75 / pi) * z;
+    case 1 * 8 + 4: return sqrt(0.75 / pi) * x;
+    case 2 * 8 + 1: return 0.5 * sqrt(15.0 / pi) * x * y;
+    case 2 * 8 + 2: return 0.5 * sqrt(15.0 / pi) * y * z;
+    case 2 * 8 + 3: return 0.25 * sqrt(5.0 / pi) * (3.0 * z * z - r2);
+    case 2 * 8 + 4: return 0.5 * sqrt(15.0 / pi) * x * z;
+    case 2 * 8 + 5: return 0.25 * sqrt(15.0 / pi) * (x * x - y * y);
+    case 3 * 8 + 0: return 0.25 * sqrt(17.5 / pi) * y * (3.0 * x * x - y * y);
+    case 3 * 8 + 1: return 0.5 * sqrt(105.0 / pi) * x * y * z;
+    case 3 * 8 + 2: return 0.25 * sqrt(10.5 / pi) * y * (5.0 * z * z - r2);
+    case 3 * 8 + 3: return 0.25 * sqrt(7.0 / pi) * z * (5.0 * z * z - 3.0 * r2);
+    case 3 * 8 + 4: return 0.25 * sqrt(10.5 / pi) * x * (5.0 * z * z - r2);
+    case 3 * 8 + 5: return 0.25 * sqrt(105.0 / pi) * z * (x * x - y * y);
+    case 3 * 8 + 6: return 0.25 * sqrt(17.5 / pi) * x * (x * x - 3.0 * y * y);
+    default: return 0.0;
+  }
+}
+
+// Radial plans: P[run][k][j] = P_kr(r) Y_lm(r^) at point k of the run, r the
+// offset from the atom, for every projector j (radial function kr, then m).
+// P_kr between the table nodes is the cubic Lagrange interpolant through the
+// nodes s .. s+3, s = clamp(floor(r/dr) - 1, 0, nr - 4); zero from the last
+// node on.  One workgroup per run, thread = (point, projector).
+__global__ __launch_bounds__(256) void k_store_radial(KArgs K, RArgs R,
+                                                      const int32_t *__restrict__ run_atom,
+                                                      double *__restrict__ stored) {
+  const int run = blockIdx.x;
+  const LineRec ln = K.lines[run];
+  const AtomRec A = K.atoms[run_atom[run]];
+  const int np = R.nproj;
+  double *out = stored + K.run_poff[run];
+  const double y = (double)(A.iy0 + ln.jy) * R.h - A.cy;
+  const double z = (double)(A.iz0 + ln.jz) * R.h - A.cz;
+  for (int t = threadIdx.x; t < ln.len * np; t += blockDim.x) {
+    const int k = t / np;
+    int j = t - k * np;
+    int kr = 0;
+    while (j >= 2 * R.ell[kr] + 1) {  // projector j -> (radial function, m)
+      j -= 2 * R.ell[kr] + 1;
+      ++kr;
+    }
+    const int l = R.ell[kr], m = j - l;
+    const double x = (double)(A.ix0 + ln.jx0 + k) * R.h - A.cx;
+    const double r = sqrt(x * x + y * y + z * z);
+    const double tt = r / R.dr;
+    double rad = 0.0;
+    if (tt < (double)(R.nr - 1)) {
+      const int s0 = min(max((int)floor(tt) - 1, 0), R.nr - 4);
+      const double u = tt - (double)s0;
+      const double *row = R.rad + (int64_t)kr * R.nr + s0;
+      rad = -(u - 1.0) * (u - 2.0) * (u - 3.0) / 6.0 * row[0] +
+            u * (u - 2.0) * (u - 3.0) / 2.0 * row[1] -
+            u * (u - 1.0) * (u - 3.0) / 2.0 * row[2] + u * (u - 1.0) * (u - 2.0) / 6.0 * row[3];
+    }
+    double ang;
+    if (l == 0)
+      ang = solid_harmonic(0, 0, x, y, z);
+    else if (r > 0.0)
+      ang = solid_harmonic(l, m, x, y, z) / (l == 1 ? r : l == 2 ? r * r : r * r * r);
+    else
+      ang = 0.0;
+    out[t] = rad * ang;
+  }
+}
+
 // The stored forms are dense contractions per atom, run on FP64 MFMA
 // (v_mfma_f64_16x16x4f64, D[16][16] += A[16][4] B[4][16]).  Lane l supplies
 // A[l % 16][l / 16] and B[l / 16][l % 16]; it receives D[4 r + l / 16][l % 16]
@@ -971,12 +1045,12 @@ constexpr int kStoredTile = 32;    // bands per workgroup (two 16-band MFMA colu
 // c[n][b] += h^3 sum_k P[k][n] psi(k)[b] over the item's points k: MFMA with
 // i = n (16 per block), j = b, and four points per step along the sum.  Each
 // wave takes every fourth step; the waves meet in LDS, then one atomic add
-// per coefficient and band goes to c.
-template <int NU>
+// per coefficient and band goes to c.  The table has S.ncol <= NS columns.
+template <int NS>
 __global__ __launch_bounds__(kStoredBlock) void k_project_stored(
     SArgs S, const double *__restrict__ psi, double *__restrict__ c) {
-  constexpr int NS = (NU + 1) * (NU + 2) * (NU + 3) / 6;
   constexpr int NBN = (NS + 15) / 16;
+  const int ncol = S.ncol;
   constexpr int U = 2;  // steps in flight per wave
   __shared__ double red[NBN * 16 * kStoredTile];
   const StoredItem it = load_uniform(S.items + blockIdx.x);
@@ -1000,12 +1074,12 @@ __global__ __launch_bounds__(kStoredBlock) void k_project_stored(
       const int kp = k + 16 * u + q;
       const bool ok = kp < it.k1;
       const int kc = ok ? kp : it.k1 - 1;
-      const double *prow = P + (int64_t)kc * NS;
+      const double *prow = P + (int64_t)kc * ncol;
       const double *vrow = psi + (int64_t)pidx[kc] * S.B;
 #pragma unroll
       for (int nb = 0; nb < NBN; ++nb) {
         const int n = nb * 16 + col;
-        av[u][nb] = (ok && n < NS) ? prow[n] : 0.0;
+        av[u][nb] = (ok && n < ncol) ? prow[n] : 0.0;
       }
       vA[u] = (ok && okA) ? vrow[bA] : 0.0;
       vB[u] = (ok && okB) ? vrow[bB] : 0.0;
@@ -1031,7 +1105,7 @@ __global__ __launch_bounds__(kStoredBlock) void k_project_stored(
   }
   __syncthreads();
   const int64_t row0 = S.atoms[a].coeff_row;
-  for (int t = threadIdx.x; t < NS * kStoredTile; t += kStoredBlock) {
+  for (int t = threadIdx.x; t < ncol * kStoredTile; t += kStoredBlock) {
     const int n = t / kStoredTile;
     const int b = b0 + (t % kStoredTile);
     if (b < S.B) unsafeAtomicAdd(c + (row0 + n) * S.B + b, S.h3 * red[t]);
@@ -1041,12 +1115,12 @@ __global__ __launch_bounds__(kStoredBlock) void k_project_stored(
 // psi(k)[b] += sum_n P[k][n] c[n][b]: MFMA with i = point (16 per tile),
 // j = band and four coefficients per step along the sum; the atom's
 // coefficients stay in registers.  Overlapping atoms meet in global FP64
-// atomics.
-template <int NU>
+// atomics.  The table has S.ncol <= NS columns.
+template <int NS>
 __global__ __launch_bounds__(kStoredBlock) void k_expand_stored(
     SArgs S, const double *__restrict__ c, double *psi) {
-  constexpr int NS = (NU + 1) * (NU + 2) * (NU + 3) / 6;
   constexpr int NK = (NS + 3) / 4;
+  const int ncol = S.ncol;
   const StoredItem it = load_uniform(S.items + blockIdx.x);
   const int a = it.atom;
   const int lane = threadIdx.x & 63;
@@ -1063,18 +1137,18 @@ __global__ __launch_bounds__(kStoredBlock) void k_expand_stored(
 #pragma unroll
   for (int m = 0; m < NK; ++m) {
     const int n = q * NK + m;
-    cA[m] = (n < NS && okA) ? S.alpha * c[(row0 + n) * S.B + bA] : 0.0;
-    cB[m] = (n < NS && okB) ? S.alpha * c[(row0 + n) * S.B + bB] : 0.0;
+    cA[m] = (n < ncol && okA) ? S.alpha * c[(row0 + n) * S.B + bA] : 0.0;
+    cB[m] = (n < ncol && okB) ? S.alpha * c[(row0 + n) * S.B + bB] : 0.0;
   }
   for (int k = it.k0 + 16 * w; k < it.k1; k += 16 * 4) {
     const int kp = k + col;
     const bool ok = kp < it.k1;
-    const double *prow = P + (int64_t)(ok ? kp : it.k1 - 1) * NS;
+    const double *prow = P + (int64_t)(ok ? kp : it.k1 - 1) * ncol;
     double av[NK];
 #pragma unroll
     for (int m = 0; m < NK; ++m) {
       const int n = q * NK + m;
-      av[m] = (ok && n < NS) ? prow[n] : 0.0;
+      av[m] = (ok && n < ncol) ? prow[n] : 0.0;
     }
     int32_t mi[4];
 #pragma unroll
@@ -1104,11 +1178,11 @@ __global__ __launch_bounds__(kStoredBlock) void k_expand_stored(
 // at a time, D[point][band] = sum_n P[point][n] c[n][band] on FP64 MFMA
 // (i = point, j = band, four n per step; the atom's coefficients of this
 // lane's bands stay in registers), then LDS atomic adds into the block tile.
-template <int NU>
+// The atom's table has ncol <= NS columns.
+template <int NS>
 __device__ inline void add_entry_stored(const EArgs &E, const EntryRec &en,
                                         const double *__restrict__ c, int nxl, double *tile,
-                                        int TB, int btile) {
-  constexpr int NS = (NU + 1) * (NU + 2) * (NU + 3) / 6;
+                                        int TB, int btile, int ncol) {
   constexpr int NK = (NS + 3) / 4;
   const int lane = threadIdx.x & 63;
   const int q = lane >> 4, col = lane & 15;
@@ -1121,8 +1195,8 @@ __device__ inline void add_entry_stored(const EArgs &E, const EntryRec &en,
 #pragma unroll
   for (int m = 0; m < NK; ++m) {
     const int n = q * NK + m;
-    cA[m] = (n < NS && okA) ? E.alpha * c[(row0 + n) * E.B + bA] : 0.0;
-    cB[m] = (n < NS && okB) ? E.alpha * c[(row0 + n) * E.B + bB] : 0.0;
+    cA[m] = (n < ncol && okA) ? E.alpha * c[(row0 + n) * E.B + bA] : 0.0;
+    cB[m] = (n < ncol && okB) ? E.alpha * c[(row0 + n) * E.B + bB] : 0.0;
   }
   const uint32_t mydesc = lane < en.nruns ? as_const(E.run_desc)[en.run_begin + lane] : 0u;
   const int64_t mybase = lane < en.nruns ? E.desc_pbase[en.run_begin + lane] : 0;
@@ -1135,12 +1209,12 @@ __device__ inline void add_entry_stored(const EArgs &E, const EntryRec &en,
     for (int p0 = xa; p0 < xb; p0 += 16) {
       const int pt = p0 + col;  // A row of this lane
       const bool ok = pt < xb;
-      const double *prow = E.P + pb + (int64_t)(ok ? pt : xb - 1) * NS;
+      const double *prow = E.P + pb + (int64_t)(ok ? pt : xb - 1) * ncol;
       dx4 dA = {0.0, 0.0, 0.0, 0.0}, dB = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int m = 0; m < NK; ++m) {
         const int n = q * NK + m;
-        const double av = (ok && n < NS) ? prow[n] : 0.0;
+        const double av = (ok && n < ncol) ? prow[n] : 0.0;
         dA = mfma_f64(av, cA[m], dA);
         dB = mfma_f64(av, cB[m], dB);
       }
@@ -1156,7 +1230,9 @@ __device__ inline void add_entry_stored(const EArgs &E, const EntryRec &en,
   }
 }
 
-template <int NUMAX>
+// NUMAX: the largest cut-off of an SHO plan; RNS > 0: radial plan, the
+// column bound of its E.ncol projectors.
+template <int NUMAX, int RNS>
 __global__ __launch_bounds__(kBlkBlock) void k_expand_blocks_stored(
     EArgs E, const double *__restrict__ c, double *psi) {
   extern __shared__ double lds[];
@@ -1187,13 +1263,19 @@ __global__ __launch_bounds__(kBlkBlock) void k_expand_blocks_stored(
   __syncthreads();
   for (int i = w; i < bk.nentries; i += kBlkWaves) {
     const EntryRec en = load_uniform(E.entries + bk.entry_begin + i);
-    switch (en.nu) {
-#define X(N)                                                                  \
-  case N:                                                                     \
-    if constexpr (N <= NUMAX) add_entry_stored<N>(E, en, c, nxl, tile, TB, btile); \
+    if constexpr (RNS > 0) {
+      add_entry_stored<RNS>(E, en, c, nxl, tile, TB, btile, E.ncol);
+    } else {
+      switch (en.nu) {
+#define X(N)                                                                         \
+  case N:                                                                            \
+    if constexpr (N <= NUMAX)                                                        \
+      add_entry_stored<(N + 1) * (N + 2) * (N + 3) / 6>(E, en, c, nxl, tile, TB, btile, \
+                                                        (N + 1) * (N + 2) * (N + 3) / 6); \
     break;
-      X(0) X(1) X(2) X(3) X(4) X(5)
+        X(0) X(1) X(2) X(3) X(4) X(5)
 #undef X
+      }
     }
   }
   __syncthreads();
@@ -1581,10 +1663,25 @@ hipError_t launch_blocks_stored(const EArgs &E, const double *c, double *psi,
   if (E.nblocks > 0) {
     const dim3 g((unsigned)E.nblocks, (unsigned)E.ntiles);
     const size_t shm = kBlockTileDoubles * sizeof(double);
+    if (E.ncol > 0) {
+      switch (stored_bound(E.ncol)) {
+#define X(N)                                                                         \
+  case N:                                                                            \
+    hipLaunchKernelGGL((k_expand_blocks_stored<0, N>), g, dim3(kBlkBlock), shm, s, E, c, \
+                       psi);                                                         \
+    break;
+        X(1) X(4) X(10) X(20) X(35) X(56)
+#undef X
+        default:
+          return hipErrorInvalidValue;
+      }
+      return hipGetLastError();
+    }
     switch (E.nu_max) {
 #define X(N)                                                                        \
   case N:                                                                           \
-    hipLaunchKernelGGL((k_expand_blocks_stored<N>), g, dim3(kBlkBlock), shm, s, E, c, psi); \
+    hipLaunchKernelGGL((k_expand_blocks_stored<N, 0>), g, dim3(kBlkBlock), shm, s, E, c, \
+                       psi);                                                        \
     break;
       X(0) X(1) X(2) X(3) X(4) X(5)
 #undef X
@@ -1602,7 +1699,6 @@ hipError_t launch_expand_rows(const EArgs &E, const double *c, double *u2,
   return launch_rows(E, u2, psi, s);
 }
 
-#define SHO_STORED_NU_CASES(X) X(0) X(1) X(2) X(3) X(4) X(5)
 
 hipError_t launch_store(const KArgs &K, const int32_t *run_atom, int32_t nruns,
                         double *stored, hipStream_t s) {
@@ -1611,35 +1707,45 @@ hipError_t launch_store(const KArgs &K, const int32_t *run_atom, int32_t nruns,
   return hipGetLastError();
 }
 
+hipError_t launch_store_radial(const KArgs &K, const RArgs &R, const int32_t *run_atom,
+                               int32_t nruns, double *stored, hipStream_t s) {
+  if (nruns <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_store_radial, dim3((unsigned)nruns), dim3(256), 0, s, K, R, run_atom,
+                     stored);
+  return hipGetLastError();
+}
+
 static dim3 stored_grid(const SArgs &S) {
   return dim3((unsigned)S.nitems, (unsigned)((S.B + kStoredTile - 1) / kStoredTile));
 }
 
-hipError_t launch_project_stored(int nu, const SArgs &S, const double *psi,
-                                 double *c, hipStream_t s) {
+#define SHO_STORED_BOUNDS(X) X(1) X(4) X(10) X(20) X(35) X(56)
+
+hipError_t launch_project_stored(const SArgs &S, const double *psi, double *c,
+                                 hipStream_t s) {
   if (S.nitems <= 0) return hipSuccess;
-  switch (nu) {
+  switch (stored_bound(S.ncol)) {
 #define X(N)                                                                   \
   case N:                                                                      \
     hipLaunchKernelGGL(k_project_stored<N>, stored_grid(S), dim3(kStoredBlock), 0, s, S, \
                        psi, c);                                                \
     return hipGetLastError();
-    SHO_STORED_NU_CASES(X)
+    SHO_STORED_BOUNDS(X)
 #undef X
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_expand_stored(int nu, const SArgs &S, const double *c,
-                                double *psi, hipStream_t s) {
+hipError_t launch_expand_stored(const SArgs &S, const double *c, double *psi,
+                                hipStream_t s) {
   if (S.nitems <= 0) return hipSuccess;
-  switch (nu) {
+  switch (stored_bound(S.ncol)) {
 #define X(N)                                                                  \
   case N:                                                                     \
     hipLaunchKernelGGL(k_expand_stored<N>, stored_grid(S), dim3(kStoredBlock), 0, s, S, \
                        c, psi);                                               \
     return hipGetLastError();
-    SHO_STORED_NU_CASES(X)
+    SHO_STORED_BOUNDS(X)
 #undef X
   }
   return hipErrorInvalidValue;
@@ -1678,7 +1784,6 @@ hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s) {
   return hipGetLastError();
 }
 
-}  // namespace sho
 // ------------------------------------------------- static expansion scratch --
 
 // Plane partials of the allocation-free expansion: one copy per device,
@@ -1707,3 +1812,4 @@ hipError_t static_scratch(double **ptr) {
   return hipSuccess;
 }
 
+}  // namespace sho

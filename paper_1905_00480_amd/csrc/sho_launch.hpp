@@ -63,6 +63,7 @@ struct EArgs {
   int32_t blk_rows;     // R
   int32_t blk_x;        // X
   int32_t ny;
+  int32_t ncol;         // stored plans: 0, or the radial projectors per atom
   double alpha;         // psi += alpha * sum_n c P_n (applied to c in the z pass)
 };
 
@@ -76,8 +77,20 @@ struct SArgs {
   const StoredItem *items;   // work items of this launch (one nu)
   int32_t nitems;
   int32_t B;
+  int32_t ncol;              // stored values per point (= coefficient rows
+                             // per atom) of the launch's atoms
   double h3;
   double alpha;              // expansion: psi += alpha * sum_n c P_n
+};
+
+// Radial projector sets (sho_plan_create_radial): p_j(r) = P_k(|r|) Y_lm(r^)
+// with P_k tabulated on a uniform radial grid.
+struct RArgs {
+  const double *rad;         // [nrad][nr] table values P_k(m dr)
+  int32_t nrad, nr, nproj;
+  int32_t ell[kRadialMaxFuncs];
+  double dr;
+  double h;
 };
 
 // Samples the 1D tables of every atom (rows padded with zeros).
@@ -114,11 +127,15 @@ hipError_t launch_blocks_stored(const EArgs &E, const double *c, double *psi,
 // project / expand by reading them back (nu <= 5).
 hipError_t launch_store(const KArgs &K, const int32_t *run_atom, int32_t nruns,
                         double *stored, hipStream_t s);
+// Radial plans: p_j at every support point into the stored tables.
+hipError_t launch_store_radial(const KArgs &K, const RArgs &R, const int32_t *run_atom,
+                               int32_t nruns, double *stored, hipStream_t s);
 // c must be zeroed first (launch_fill): every item adds its chunk's share.
-hipError_t launch_project_stored(int nu, const SArgs &S, const double *psi,
-                                 double *c, hipStream_t s);
-hipError_t launch_expand_stored(int nu, const SArgs &S, const double *c,
-                                double *psi, hipStream_t s);
+// S.ncol selects the table width (N_SHO(nu) or the radial projector count).
+hipError_t launch_project_stored(const SArgs &S, const double *psi, double *c,
+                                 hipStream_t s);
+hipError_t launch_expand_stored(const SArgs &S, const double *c, double *psi,
+                                hipStream_t s);
 // d = D c per atom (D: per-atom N x N row-major blocks at doff[a]).
 hipError_t launch_multiply(const AtomRec *atoms, int32_t natoms, const int64_t *doff,
                            const double *D, const double *c, double *d, int32_t B,
@@ -133,6 +150,13 @@ hipError_t launch_force_sum(const double *gpart, int32_t natoms, int32_t ntiles,
                             hipStream_t s);
 hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s);
 
+// Capacity of the static scratch of the allocation-free expansion (32 MiB).
+constexpr int64_t kStaticScratchDoubles = (int64_t)1 << 22;
+static_assert(kStaticScratchDoubles == SHO_STATIC_SCRATCH_DOUBLES, "static scratch size");
+// Device address of the current device's static scratch (looked up once per
+// device; no allocation).
+hipError_t static_scratch(double **ptr);
+
 // FP32 plans (an even number of bands, processed as pairs: K.B and E.B count
 // pairs).  tab: the plan's tables rounded to FP32.
 hipError_t launch_tables_f32(const double *tab, float *tab32, int64_t n, hipStream_t s);
@@ -146,10 +170,3 @@ hipError_t launch_blocks_f32(const EArgs &E, const float *tab, const float *u2, 
                              hipStream_t s);
 
 }  // namespace sho
-// Capacity of the static scratch of the allocation-free expansion (32 MiB).
-constexpr int64_t kStaticScratchDoubles = (int64_t)1 << 22;
-static_assert(kStaticScratchDoubles == SHO_STATIC_SCRATCH_DOUBLES, "static scratch size");
-// Device address of the current device's static scratch (looked up once per
-// device; no allocation).
-hipError_t static_scratch(double **ptr);
-

@@ -462,7 +462,7 @@ void build_stored(HostPlan *P, int32_t chunk) {
   int64_t off = 0;
   for (int32_t a = 0; a < P->natoms; ++a) {
     const AtomRec &A = P->atoms[a];
-    const int64_t ns = nsho(A.nu);
+    const int64_t ns = stored_cols(*P, A);
     P->atom_poff[a] = off;
     P->atom_pbeg[a] = (int64_t)P->pidx.size();
     for (int32_t r = A.line_begin; r < A.line_begin + A.nlines; ++r) {
@@ -673,8 +673,9 @@ void build_desc_pbase(HostPlan *P) {
     if (B.nentries < 0) continue;
     for (int32_t e = B.entry_begin; e < B.entry_begin + B.nentries; ++e) {
       EntryRec &E = P->entries[e];
-      const int64_t ns = nsho(E.nu);
-      E.u2 = P->atoms[P->run_atom[P->run_desc_run[E.run_begin]]].coeff_row;
+      const AtomRec &A = P->atoms[P->run_atom[P->run_desc_run[E.run_begin]]];
+      const int64_t ns = stored_cols(*P, A);
+      E.u2 = A.coeff_row;
       for (int32_t k = E.run_begin; k < E.run_begin + E.nruns; ++k) {
         const LineRec &L = P->lines[P->run_desc_run[k]];
         P->desc_pbase[k] = P->run_poff[P->run_desc_run[k]] + (int64_t)(B.x0 - L.x0m) * ns;

@@ -231,6 +231,34 @@ def coeff_offsets(system: System):
     return np.concatenate([[0], np.cumsum(cnt)]).astype(np.int64)
 
 
+# ------------------------------------------------- numerical projectors ----
+
+def radial_set(rcut, ell=(0, 0, 1, 1, 2, 2), nr=512, seed=7):
+    """Synthetic radial projector tables for a stored-projector (USU) plan:
+    P_k(r) = r^l (1 + c1 r + c2 r^2) exp(-r^2 / (2 a^2)) (1 - (r/rcut)^2)^2 on
+    the uniform grid r_i = i dr, i = 0..nr-1, dr = rcut / (nr - 1), with
+    c1, c2 ~ U[-0.3, 0.3] and a ~ U[0.3, 0.5] rcut per function.  The default
+    ell is the paper's USU18 set: two functions each for s, p and d (18
+    projectors).  Returns (ell, dr, tables[nradial][nr])."""
+    rng = np.random.default_rng(np.random.SeedSequence(seed).spawn(1)[0])
+    ell = np.asarray(ell, dtype=np.int32)
+    dr = float(rcut) / (nr - 1)
+    r = np.arange(nr) * dr
+    tab = np.empty((ell.size, nr))
+    for k, l in enumerate(ell):
+        c1, c2 = rng.uniform(-0.3, 0.3, size=2)
+        a = rng.uniform(0.3, 0.5) * rcut
+        tab[k] = (r ** int(l) * (1 + c1 * r + c2 * r * r) * np.exp(-r * r / (2 * a * a))
+                  * (1 - (r / rcut) ** 2) ** 2)
+    return ell, dr, tab
+
+
+def radial_coeffs_for(system: System, nproj: int, seed: Optional[int] = None):
+    """Coefficients ~ N(0, 1) for a stored-projector plan, blocks [nproj][B]."""
+    g = _streams(system.seed if seed is None else seed)[3]
+    return g.standard_normal(size=system.natoms * int(nproj) * system.nbands)
+
+
 # --------------------------------------------------------------- serving ----
 
 def serving_pool(seed=4, nsystems=32, hbm_cap_bytes=None):
