@@ -60,6 +60,8 @@ def parse():
                     help="skip the differentiation (forward + backward) workload")
     ap.add_argument("--no-fp32", action="store_true",
                     help="skip the single-precision scale step")
+    ap.add_argument("--no-bloch", action="store_true",
+                    help="skip the complex Bloch-band scale step")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the plan's default schedule (no autotuning)")
     ap.add_argument("--serve-requests", type=int, default=2000)
@@ -312,6 +314,48 @@ def fp32_step(bd, wl, args, ms_fp64):
             "speedup_vs_fp64": ms_fp64 / ms, "tune": tune,
             "kernel_ms": {k: round(v[1], 4) for k, v in prof.items() if v[0]},
             "expand_xy_GB/s": xy_bytes / (xy_ms * 1e-3) / 1e9 if xy_ms > 0 else None}
+
+
+def bloch_step(bd, wl, args, ms_fp64):
+    """The scale workload with 32 complex Bloch bands at k = (0.31, -0.17,
+    0.52) Bohr^-1 (SHO_FLAG_BLOCH, sec. 2.5: every periodic image carries its
+    phase), FP64, tuned; step = projection + expansion.  Twice the bytes of
+    the 32 real bands of the headline step."""
+    import torch
+    s = wl.scale()
+    rng = np.random.default_rng(21)
+    psi_h = rng.standard_normal(s.psi_shape + (2,))
+    psi = torch.view_as_complex(torch.from_numpy(psi_h).cuda())
+    plan = bd.Plan.from_system(s, flags=bd.FLAG_BLOCH)
+    plan.set_kpoint((0.31, -0.17, 0.52))
+    c = torch.empty(plan.coeff_doubles // 2, dtype=torch.complex128, device="cuda")
+    out = torch.zeros_like(psi)
+    tune = None if args.no_tune else plan.tune(psi, c, reps=3)
+
+    def step():
+        plan.project(psi, c)
+        plan.expand(c, out)
+
+    ms, _ = _time_steps(step, args.steps, args.warmup)
+    plan.profile(True)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    prof = plan.profile_read()
+    plan.profile(False)
+    S = plan.support_points
+    prj_ms = prof["project"][1]
+    units = S * s.nbands
+    plan.close()
+    return {"workload": "scale: periodic 128^3, h=0.2 Bohr, 512 atoms, sigma=0.6, nu_max=5, "
+                        "32 complex FP64 bands at k = (0.31, -0.17, 0.52) Bohr^-1; "
+                        "step = projection + expansion",
+            "dtype": "c128", "ms_per_step": ms,
+            "gridpoint*complex_bands/s": units / (ms * 1e-3),
+            "ms_vs_real_32_bands": ms / ms_fp64, "tune": tune,
+            "kernel_ms": {k: round(v[1], 4) for k, v in prof.items() if v[0]},
+            "project_per_atom_GB/s": S * s.nbands * 16 / (prj_ms * 1e-3) / 1e9
+            if prj_ms > 0 else None}
 
 
 def setup_step(bd):
@@ -659,6 +703,9 @@ def main():
     if not args.no_fp32:
         rec["fp32"] = fp32_step(bd, wl, args, ms_per_step)
         _log("fp32 scale step: %.3f ms" % rec["fp32"]["ms_per_step"])
+    if not args.no_bloch:
+        rec["bloch"] = bloch_step(bd, wl, args, ms_per_step)
+        _log("bloch scale step: %.3f ms" % rec["bloch"]["ms_per_step"])
     if not args.no_stored:
         rec["stored_baseline"] = stored_baseline(bd, s, psi, c, out, args)
     if not args.no_stored:

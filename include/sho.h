@@ -127,6 +127,25 @@ typedef int32_t sho_status;
                                              not with SHO_FLAG_STORED,
                                              SHO_FLAG_PER_ATOM or
                                              SHO_FLAG_FP32 (SHO_E_INVALID). */
+#define SHO_FLAG_BLOCH 0x40u              /* complex Bloch bands at a wave
+                                             vector k (sec. 2.5: the basis
+                                             spans functions R^3 -> C; set by
+                                             sho_plan_set_kpoint, default 0).
+                                             nbands counts complex bands;
+                                             psi is [z][y][x][nbands][2] and c
+                                             [N_SHO][nbands][2] (real,
+                                             imaginary interleaved: complex128,
+                                             or complex64 with SHO_FLAG_FP32).
+                                             A support point reached through
+                                             the periodic image translated by
+                                             T contributes e^{+i k.T} psi to
+                                             the projection and receives
+                                             e^{-i k.T} sum_n c P_n from the
+                                             expansion.  Single-launch
+                                             schedules and the block form of
+                                             the expansion only; not with
+                                             SHO_FLAG_STORED, _PER_ATOM or
+                                             _DETERMINISTIC; no derivative. */
 
 /* Expansion forms (sho_plan_set_expand) */
 #define SHO_EXPAND_ROWS 0
@@ -237,6 +256,16 @@ sho_status sho_plan_create_radial(const sho_grid *grid, int32_t natoms, const do
                                   const double *rcut, int32_t nradial, const int32_t *ell,
                                   int32_t nr, double dr, const double *tables,
                                   int32_t nbands, uint32_t flags, sho_plan_t *out);
+
+/*
+ * Bloch wave vector of a SHO_FLAG_BLOCH plan, k[3] in Bohr^-1 (host).  Later
+ * calls use it; work already queued keeps the previous one.  The phase of
+ * an image is e^{i k.T}, T = (m_x n_x h, m_y n_y h, m_z n_z h) with the
+ * image counts m_d; a support reaching more than 127 images along an axis is
+ * refused at plan creation (SHO_E_BOX).  Errors: SHO_E_INVALID (not a Bloch
+ * plan, non-finite k).
+ */
+sho_status sho_plan_set_kpoint(sho_plan_t plan, const double *k);
 
 /* Free a plan's device tables.  Waits for the device first, so work already
  * queued with the plan finishes.  NULL is accepted. */

@@ -37,6 +37,7 @@ FLAG_HOST_ONLY = 0x4
 FLAG_PER_ATOM = 0x8
 FLAG_FP32 = 0x10
 FLAG_DETERMINISTIC = 0x20
+FLAG_BLOCH = 0x40
 SCHED_BY_NU = 0
 SCHED_SINGLE = 1
 SCHED_SINGLE_LPT = 2
@@ -57,6 +58,7 @@ EXPORTS = (
     "sho_plan_project_f32", "sho_plan_expand_f32",
     "sho_plan_force", "sho_project", "sho_expand", "sho_force",
     "sho_plan_expand_scaled", "sho_plan_expand_noalloc", "sho_plan_create_radial",
+    "sho_plan_set_kpoint",
     "sho_cache_clear", "sho_plan_profile", "sho_plan_profile_read",
     "sho_plan_set_schedule", "sho_plan_get_schedule", "sho_plan_tune",
     "sho_plan_set_expand", "sho_plan_get_expand",
@@ -147,6 +149,7 @@ def load_library(path=None):
     lib.sho_plan_coeff_offsets.argtypes = [P, _i64p]
     lib.sho_plan_support_counts.argtypes = [P, _i64p]
     lib.sho_plan_set_centres.argtypes = [P, _dp, _vp]
+    lib.sho_plan_set_kpoint.argtypes = [P, _dp]
     lib.sho_plan_project.argtypes = [P, _vp, _vp, _vp]
     lib.sho_plan_expand.argtypes = [P, _vp, _vp, _vp]
     lib.sho_plan_project_f32.argtypes = [P, _vp, _vp, _vp]
@@ -233,9 +236,15 @@ def _stream(stream):
 
 
 def _dev(t, numel, name, f32=False):
+    """Device pointer of a contiguous GPU tensor of `numel` real elements
+    (complex tensors count their real and imaginary parts)."""
     import torch
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
         raise TypeError("%s must be a GPU tensor" % name)
+    if t.is_complex():
+        if not t.is_contiguous():
+            raise ValueError("%s must be contiguous" % name)
+        t = torch.view_as_real(t)
     want = torch.float32 if f32 else torch.float64
     if t.dtype != want:
         raise TypeError("%s must be %s" % (name, str(want).split(".")[-1]))
@@ -277,6 +286,7 @@ class Plan:
     def _adopt(self, handle, flags):
         self._h = handle
         self.fp32 = bool(int(flags) & FLAG_FP32)
+        self.bloch = bool(int(flags) & FLAG_BLOCH)
         info = sho_plan_info()
         _check(self._lib.sho_plan_get_info(self._h, ctypes.byref(info)))
         self.info = {k: getattr(info, k) for k, _ in sho_plan_info._fields_}
@@ -319,7 +329,13 @@ class Plan:
 
     @property
     def psi_numel(self):
-        return self.n[0] * self.n[1] * self.n[2] * self.nbands
+        """Real elements of psi (complex bands of Bloch plans count twice)."""
+        return self.n[0] * self.n[1] * self.n[2] * self.nbands * (2 if self.bloch else 1)
+
+    def set_kpoint(self, k):
+        """Bloch wave vector (Bohr^-1) of a FLAG_BLOCH plan."""
+        k = _host_f64(k, (3,))
+        _check(self._lib.sho_plan_set_kpoint(self._h, k.ctypes.data_as(_dp)))
 
     def coeff_offsets(self):
         off = np.empty(self.natoms + 1, dtype=np.int64)
@@ -345,8 +361,13 @@ class Plan:
         import torch
         f32 = self.fp32
         if c is None:
-            c = torch.empty(self.coeff_doubles,
-                            dtype=torch.float32 if f32 else torch.float64, device=psi.device)
+            if self.bloch:
+                c = torch.empty(self.coeff_doubles // 2,
+                                dtype=torch.complex64 if f32 else torch.complex128,
+                                device=psi.device)
+            else:
+                c = torch.empty(self.coeff_doubles,
+                                dtype=torch.float32 if f32 else torch.float64, device=psi.device)
         fn = self._lib.sho_plan_project_f32 if f32 else self._lib.sho_plan_project
         _check(fn(self._h, _dev(psi, self.psi_numel, "psi", f32),
                   _dev(c, self.coeff_doubles, "c", f32), _stream(stream)))

@@ -63,6 +63,9 @@ struct sho_plan_s {
   sho::WorkRec *d_work = nullptr;
   double *d_tab = nullptr;
   bool fp32 = false;          // SHO_FLAG_FP32: hp.nbands counts band pairs
+  bool bloch = false;         // SHO_FLAG_BLOCH: complex bands, hp.nbands counts
+                              // real lanes (FP64: 2 per band; FP32: 1 pair)
+  double kvec[3] = {0.0, 0.0, 0.0};  // Bloch wave vector (Bohr^-1)
   float *d_tab32 = nullptr;   // FP32 plans: the tables rounded to float
   int32_t *d_run_atom = nullptr;
   int32_t *d_row_runs = nullptr;
@@ -249,9 +252,14 @@ sho::KArgs make_args(const sho_plan_s *p, const Group &g) {
   K.tb_shift = p->hp.tb_shift;
   K.ntiles = (p->hp.nbands + (1 << K.tb_shift) - 1) >> K.tb_shift;
   K.det = (p->hp.flags & SHO_FLAG_DETERMINISTIC) ? 1 : 0;
+  K.ny = p->hp.grid.n[1];
+  K.nz = p->hp.grid.n[2];
+  K.bloch = p->bloch ? 1 : 0;
   const double h = p->hp.grid.h;
   K.h3 = h * h * h;
   K.alpha = 1.0;
+  K.h = h;
+  for (int d = 0; d < 3; ++d) K.k[d] = p->kvec[d];
   return K;
 }
 
@@ -307,7 +315,11 @@ sho::EArgs make_eargs(const sho_plan_s *p) {
   E.blk_x = p->hp.blk_x;
   E.ny = p->hp.grid.n[1];
   E.ncol = p->hp.ncols;
+  E.nz = p->hp.grid.n[2];
+  E.bloch = p->bloch ? 1 : 0;
   E.alpha = 1.0;
+  E.h = p->hp.grid.h;
+  for (int d = 0; d < 3; ++d) E.k[d] = p->kvec[d];
   for (int nu = 0; nu <= SHO_NU_MAX + 1; ++nu) E.nu_begin[nu] = 0;
   {
     int nu = 0;
@@ -390,6 +402,7 @@ void build_default_blocks(sho::HostPlan *hp) {
 
 // Plans with several cut-offs run the projection as one launch.
 int32_t default_schedule(const sho::HostPlan &hp) {
+  if (hp.flags & SHO_FLAG_BLOCH) return sho::kSchedSingle;  // one kernel family
   for (const auto &A : hp.atoms)
     if (A.npoints > 0 && A.nu != hp.atoms[0].nu) return sho::kSchedSingle;
   return sho::kSchedByNu;
@@ -607,7 +620,7 @@ sho_status finish_plan(sho_plan_s *p, uint32_t flags, int32_t nbands, bool f32,
   if (flags & SHO_FLAG_HOST_ONLY) {
     // geometry and sizes only; work split as for a 64 KiB workgroup LDS
     const int tbs = sho::choose_tb_shift(nbands, p->hp.nu_max, (65536 - 1024) / lds_div);
-    if (tbs < 0) {
+    if (tbs < 0 || (p->bloch && !f32 && tbs < 1)) {
       delete p;
       return fail(SHO_E_BOX, "coefficient tile too large for the workgroup LDS");
     }
@@ -631,7 +644,7 @@ sho_status finish_plan(sho_plan_s *p, uint32_t flags, int32_t nbands, bool f32,
   }
   p->lds_limit = (size_t)std::max(shm - 1024, 0) / lds_div;  // static LDS of the kernels
   const int tbs = sho::choose_tb_shift(nbands, p->hp.nu_max, p->lds_limit);
-  if (tbs < 0) {
+  if (tbs < 0 || (p->bloch && !f32 && tbs < 1)) {
     delete p;
     return fail(SHO_E_BOX, "coefficient tile too large for the workgroup LDS");
   }
@@ -755,6 +768,15 @@ sho_status sho_plan_create(const sho_grid *grid, int32_t natoms,
   if (!out) return fail(SHO_E_INVALID, "out must not be NULL");
   *out = nullptr;
   const bool f32 = (flags & SHO_FLAG_FP32) != 0;
+  const bool bloch = (flags & SHO_FLAG_BLOCH) != 0;
+  if (bloch) {
+    if (nbands <= 0 || nbands > (1 << 29))
+      return fail(SHO_E_INVALID, "Bloch plans need a positive number of complex bands");
+    if (flags & (SHO_FLAG_STORED | SHO_FLAG_PER_ATOM | SHO_FLAG_DETERMINISTIC))
+      return fail(SHO_E_INVALID, "SHO_FLAG_BLOCH does not combine with SHO_FLAG_STORED, "
+                                 "SHO_FLAG_PER_ATOM or SHO_FLAG_DETERMINISTIC");
+    nbands *= 2;  // real and imaginary parts
+  }
   if (f32) {
     if (nbands <= 0 || nbands % 2)
       return fail(SHO_E_INVALID, "FP32 plans need a positive, even number of bands");
@@ -771,12 +793,28 @@ sho_status sho_plan_create(const sho_grid *grid, int32_t natoms,
   sho_plan_s *p = new (std::nothrow) sho_plan_s();
   if (!p) return fail(SHO_E_NOMEM, "host allocation failed");
   p->fp32 = f32;
+  p->bloch = bloch;
   std::string msg;
   sho_status st = sho::build_host_plan(grid, natoms, pos, sigma, numax, rbox,
                                        nbands, flags, &p->hp, &msg);
   if (st != SHO_OK) {
     delete p;
     return fail(st, msg);
+  }
+  if (bloch) {
+    // image counts along each axis must fit the entry records (|m| <= 127)
+    for (const auto &A : p->hp.atoms) {
+      if (A.npoints == 0) continue;
+      const int32_t i0[3] = {A.ix0, A.iy0, A.iz0}, m[3] = {A.mx, A.my, A.mz};
+      for (int d = 0; d < 3; ++d) {
+        const int64_t n = p->hp.grid.n[d];
+        auto img = [&](int64_t i) { return i >= 0 ? i / n : -((-i + n - 1) / n); };
+        if (std::llabs(img(i0[d])) > 127 || std::llabs(img((int64_t)i0[d] + m[d] - 1)) > 127) {
+          delete p;
+          return fail(SHO_E_BOX, "a support reaches more than 127 periodic images");
+        }
+      }
+    }
   }
   return finish_plan(p, flags, nbands, f32, nullptr, out);
 }
@@ -886,7 +924,8 @@ sho_status sho_plan_get_info(sho_plan_t p, sho_plan_info *info) {
   if (!p || !info) return fail(SHO_E_INVALID, "NULL plan or info");
   info->natoms = p->hp.natoms;
   const int64_t per_lane = p->fp32 ? 2 : 1;  // bands per kernel lane
-  info->nbands = (int32_t)(p->hp.nbands * per_lane);
+  // Bloch plans: complex bands (two reals each)
+  info->nbands = (int32_t)(p->hp.nbands * per_lane / (p->bloch ? 2 : 1));
   info->nu_max = p->hp.nu_max;
   info->flags = (int32_t)p->hp.flags;
   info->coeff_rows = p->hp.coeff_rows;
@@ -922,6 +961,16 @@ sho_status sho_plan_coeff_offsets(sho_plan_t p, int64_t *off) {
 sho_status sho_plan_support_counts(sho_plan_t p, int64_t *counts) {
   if (!p || !counts) return fail(SHO_E_INVALID, "NULL plan or output");
   for (int32_t a = 0; a < p->hp.natoms; ++a) counts[a] = p->hp.atoms[a].npoints;
+  return SHO_OK;
+}
+
+sho_status sho_plan_set_kpoint(sho_plan_t p, const double *k) {
+  if (!p || !k) return fail(SHO_E_INVALID, "NULL plan or k");
+  if (!p->bloch) return fail(SHO_E_INVALID, "not a Bloch plan (SHO_FLAG_BLOCH)");
+  for (int d = 0; d < 3; ++d)
+    if (!std::isfinite(k[d])) return fail(SHO_E_INVALID, "k must be finite");
+  for (int d = 0; d < 3; ++d) p->kvec[d] = k[d];
+  p->sched_version++;  // graphs captured with the previous k are refused
   return SHO_OK;
 }
 
@@ -1026,6 +1075,7 @@ sho_status sho_plan_force(sho_plan_t p, const double *psi, const double *w,
   if (!p) return fail(SHO_E_INVALID, "NULL plan");
   if (p->fp32) return fail(SHO_E_INVALID, "the derivative is FP64 only");
   if (p->hp.ncols > 0) return fail(SHO_E_INVALID, "radial plans have no derivative");
+  if (p->bloch) return fail(SHO_E_INVALID, "Bloch plans have no derivative");
   if (p->hp.flags & SHO_FLAG_HOST_ONLY)
     return fail(SHO_E_INVALID, "host-only plan cannot run kernels");
   if (p->hp.natoms == 0) return SHO_OK;
@@ -1074,6 +1124,10 @@ sho_status sho_plan_set_schedule(sho_plan_t p, int32_t schedule, int32_t band_ti
     if ((1 << k) == band_tile) tbs = k;
   if (band_tile == 0) tbs = p->hp.tb_shift;
   if (tbs < 0) return fail(SHO_E_INVALID, "band_tile must be 0 or a power of two <= 64");
+  if (p->bloch && (schedule & ~sho::kSchedXcd) == sho::kSchedByNu)
+    return fail(SHO_E_INVALID, "Bloch plans run single-launch schedules");
+  if (p->bloch && !p->fp32 && tbs < 1)
+    return fail(SHO_E_INVALID, "Bloch plans keep the real and imaginary lanes in one tile");
   const size_t limit = (p->hp.flags & SHO_FLAG_HOST_ONLY)
                            ? (65536 - 1024) / (p->fp32 ? 2
                                                : (p->hp.flags & SHO_FLAG_DETERMINISTIC) ? sho::kWaves
@@ -1109,6 +1163,8 @@ sho_status sho_plan_set_expand(sho_plan_t p, int32_t mode, int32_t block_rows,
     return fail(SHO_E_INVALID, "unknown expansion form");
   if (p->fp32 && mode != sho::kExpandBlocks)
     return fail(SHO_E_INVALID, "FP32 plans expand in the block form only");
+  if (p->bloch && mode != sho::kExpandBlocks)
+    return fail(SHO_E_INVALID, "Bloch plans expand in the block form only");
   if ((p->hp.flags & SHO_FLAG_STORED) && mode == sho::kExpandOwner)
     return fail(SHO_E_INVALID, "stored plans expand in the row or block form");
   if ((p->hp.flags & SHO_FLAG_DETERMINISTIC) && mode != sho::kExpandOwner)
@@ -1172,9 +1228,12 @@ sho_status sho_plan_tune(sho_plan_t p, const void *psi, void *c, int32_t reps,
   };
   std::vector<Cand> cands;
   const int32_t tb0 = p->hp.tb_shift;
-  for (int32_t sc : {0, 1, 2, 3, 4, 5, 6, 7})
+  const int32_t tb_min = (p->bloch && !p->fp32) ? 1 : 0;  // Bloch: re, im in one tile
+  for (int32_t sc : {0, 1, 2, 3, 4, 5, 6, 7}) {
+    if (p->bloch && (sc & ~sho::kSchedXcd) == sho::kSchedByNu) continue;
     for (int64_t tp : {(int64_t)4096, (int64_t)8192, (int64_t)16384, (int64_t)32768})
-      for (int32_t tb = tb0; tb >= std::max(0, tb0 - 1); --tb) cands.push_back({sc, tb, tp});
+      for (int32_t tb = tb0; tb >= std::max(tb_min, tb0 - 1); --tb) cands.push_back({sc, tb, tp});
+  }
   const Cand before{p->hp.sched, tb0, p->hp.target_points};
   hipEvent_t ea = nullptr, eb = nullptr;
   hipError_t e = hipEventCreate(&ea);

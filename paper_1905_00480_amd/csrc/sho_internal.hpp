@@ -129,6 +129,9 @@ struct EntryRec {
   int16_t y_lo, y_hi;  // staged y rows that exist, relative to y0
   int32_t run_begin;   // into run_desc
   int32_t nruns;
+  int8_t img[3];       // periodic image of the entry's runs: unwrapped minus
+                       // memory position is img[d] * n[d] points per axis
+  int8_t pad;
 };
 static_assert(sizeof(EntryRec) == 40, "EntryRec layout");
 

@@ -158,10 +158,23 @@ struct RunState {
   int len;
   int jy;
   bool active;
+  double pc, ps;       // Bloch plans: cos, sin of k.T for the run's image T
 };
 
+// Phase angle k.T of a run of atom A: T = unwrapped minus memory position
+// of its points (a lattice translation), per axis (i - (i mod n)) h.
+__device__ inline double run_angle(const KArgs &K, const AtomRec &A, const LineRec &ln) {
+  const int ym = ln.row % K.ny, zm = ln.row / K.ny;
+  double th = K.k[0] * ((double)(A.ix0 + ln.jx0 - ln.x0m) * K.h);
+  th += K.k[1] * ((double)(A.iy0 + ln.jy - ym) * K.h);
+  th += K.k[2] * ((double)(A.iz0 + ln.jz - zm) * K.h);
+  return th;
+}
+
+template <bool CPLX = false>
 __device__ inline RunState run_state(const KArgs &K, const Lanes &L,
-                                     const double *psi, const BundleRec &bd) {
+                                     const double *psi, const BundleRec &bd,
+                                     const AtomRec *A = nullptr) {
   const int s = min(L.slot, bd.nruns - 1);
   const LineRec ln = K.lines[bd.run0 + s];
   RunState r;
@@ -170,7 +183,17 @@ __device__ inline RunState run_state(const KArgs &K, const Lanes &L,
   r.len = ln.len;
   r.jy = ln.jy;
   r.active = L.slot < bd.nruns;
+  if constexpr (CPLX) sincos(run_angle(K, *A, ln), &r.ps, &r.pc);
   return r;
+}
+
+// Complex bands: lanes hold the real (even band) and imaginary (odd band)
+// part of one band, in neighbouring lanes.  v <- e^{+-i th} v for the pair:
+// sgn_s = -s on real lanes and +s on imaginary lanes multiplies by e^{+i th};
+// the opposite signs by e^{-i th}.
+__device__ inline double rotate_pair(double v, double c, double sgn_s) {
+  const double p = __shfl_xor(v, 1);
+  return fma(sgn_s, p, c * v);
 }
 
 // Issues kBatch loads: table indices jb .. jb+kBatch-1 of the lane's run,
@@ -226,7 +249,7 @@ __device__ inline void flush_plane(cptr<double> fz, double *T2, double *cacc,
 // Adds sum over the runs of bundles [b0,b1) of P_n(i) psi(i) (no h^3), for
 // the workgroup's band tile, into cacc[n*TB + bl] (LDS).  One batch of loads
 // is always in flight while the previous one is contracted.
-template <int NU, bool DET>
+template <int NU, bool DET, bool CPLX = false>
 __device__ inline void project_bundles(const KArgs &K, const AtomRec &A,
                                        const Lanes &L, int b0, int b1,
                                        const double *__restrict__ psi,
@@ -244,7 +267,7 @@ __device__ inline void project_bundles(const KArgs &K, const AtomRec &A,
   for (int q = 0; q < NP; ++q) T2[q] = 0.0;
   int cur_jz = -1;
   BundleRec bd = load_uniform(K.bundles + b0);
-  RunState rs = run_state(K, L, psi, bd);
+  RunState rs = run_state<CPLX>(K, L, psi, bd, &A);
   double v[kBatch];
   load_batch(K, rs, bd.jlo, v);
   for (int bi = b0; bi < b1; ++bi) {
@@ -263,7 +286,7 @@ __device__ inline void project_bundles(const KArgs &K, const AtomRec &A,
         load_batch(K, rs, jb + kBatch, w);
       } else if (bi + 1 < b1) {
         nbd = load_uniform(K.bundles + bi + 1);
-        nrs = run_state(K, L, psi, nbd);
+        nrs = run_state<CPLX>(K, L, psi, nbd, &A);
         load_batch(K, nrs, nbd.jlo, w);
       } else {
 #pragma unroll
@@ -284,6 +307,12 @@ __device__ inline void project_bundles(const KArgs &K, const AtomRec &A,
 #pragma unroll
       for (int u = 0; u < kBatch; ++u) v[u] = w[u];
     }
+    if constexpr (CPLX) {
+      // the run's image carries e^{+i k.T}
+      const double sg = (L.bl & 1) ? rs.ps : -rs.ps;
+#pragma unroll
+      for (int n = 0; n < NF; ++n) T1[n] = rotate_pair(T1[n], rs.pc, sg);
+    }
     // y pass with this lane's run
     const double *fy = ty + rs.jy * nfp;
     int q = 0;
@@ -301,7 +330,7 @@ __device__ inline void project_bundles(const KArgs &K, const AtomRec &A,
 
 // One work item of the projection: zero the LDS tile, stream the item's
 // bundles, write (or, for a shared atom, add) h^3 C into c.
-template <int NU, bool DET>
+template <int NU, bool DET, bool CPLX = false>
 __device__ inline void project_item(const KArgs &K, cptr<WorkRec> W, const AtomRec &A,
                                     const double *__restrict__ psi,
                                     double *__restrict__ c, double *cacc) {
@@ -315,7 +344,8 @@ __device__ inline void project_item(const KArgs &K, cptr<WorkRec> W, const AtomR
   __syncthreads();
   const int w = wave_id();
   const Lanes L = lane_geometry(K, tile);
-  project_bundles<NU, DET>(K, A, L, W->wb[w], W->wb[w + 1], psi, DET ? cacc + w * nt : cacc);
+  project_bundles<NU, DET, CPLX>(K, A, L, W->wb[w], W->wb[w + 1], psi,
+                                 DET ? cacc + w * nt : cacc);
   __syncthreads();
   const bool split = W->split != 0;
   for (int t = threadIdx.x; t < nt; t += blockDim.x) {
@@ -346,7 +376,7 @@ __attribute__((amdgpu_waves_per_eu(waves_per_eu(NU + 1)))) void k_project(
 // All cut-offs in one launch: the item's atom selects the instantiation
 // (a wave-uniform branch).  Registers are those of the largest case, so the
 // single launch serves plans whose cut-offs differ.
-template <int NUMAX, bool DET>
+template <int NUMAX, bool DET, bool CPLX = false>
 __global__ __launch_bounds__(kBlock)
 __attribute__((amdgpu_waves_per_eu(waves_per_eu(NUMAX + 1)))) void k_project_any(
     KArgs K, const double *__restrict__ psi, double *__restrict__ c) {
@@ -357,7 +387,7 @@ __attribute__((amdgpu_waves_per_eu(waves_per_eu(NUMAX + 1)))) void k_project_any
   switch (A.nu) {
 #define X(N)                                                  \
   case N:                                                     \
-    if constexpr (N <= NUMAX) project_item<N, DET>(K, W, A, psi, c, cacc); \
+    if constexpr (N <= NUMAX) project_item<N, DET, CPLX>(K, W, A, psi, c, cacc); \
     break;
     SHO_NU_CASES(X)
 #undef X
@@ -666,7 +696,7 @@ constexpr int kBlkXStage = 256;  // doubles per wave: the x-table rows of a bloc
 // cut-off anyway, else two.
 constexpr int blk_group(int nu, int numax) { return (numax > 5 && nu <= 5) ? 4 : 2; }
 
-template <int NU, int NUMAX>
+template <int NU, int NUMAX, bool CPLX>
 __device__ inline void add_entry(const EArgs &E, const EntryRec &en, const double *u2,
                                  int nxl, double *tile, double *xstage, int TB, int slot,
                                  int bl, int bc) {
@@ -682,6 +712,17 @@ __device__ inline void add_entry(const EArgs &E, const EntryRec &en, const doubl
   double u2v[NP];
 #pragma unroll
   for (int q = 0; q < NP; ++q) u2v[q] = ub[(int64_t)q * E.B];
+  if constexpr (CPLX) {
+    // the entry's image T receives e^{-i k.T} times the plane partials
+    double th = E.k[0] * ((double)(en.img[0] * E.nx) * E.h);
+    th += E.k[1] * ((double)(en.img[1] * E.ny) * E.h);
+    th += E.k[2] * ((double)(en.img[2] * E.nz) * E.h);
+    double sn, cs;
+    sincos(th, &sn, &cs);
+    const double sg = (bl & 1) ? -sn : sn;
+#pragma unroll
+    for (int q = 0; q < NP; ++q) u2v[q] = rotate_pair(u2v[q], cs, sg);
+  }
   const uint32_t mydesc = lane < en.nruns ? as_const(E.run_desc)[en.run_begin + lane] : 0u;
   double tx[4];
 #pragma unroll
@@ -747,7 +788,7 @@ __device__ inline void add_entry(const EArgs &E, const EntryRec &en, const doubl
 // instead of divisions (the index arithmetic of the fill and write-back is a
 // large share of the kernel's instructions); slots past the grid's last
 // column hold zeros and are not written back.
-template <int NUMAX>
+template <int NUMAX, bool CPLX>
 __global__ __launch_bounds__(kBlkBlock) void k_expand_blocks(EArgs E,
                                                             const double *__restrict__ u2,
                                                             double *psi) {
@@ -798,7 +839,7 @@ __global__ __launch_bounds__(kBlkBlock) void k_expand_blocks(EArgs E,
 #define X(N)                                                                          \
   case N:                                                                             \
     if constexpr (N <= NUMAX)                                                         \
-      add_entry<N, NUMAX>(E, en, u2, 1 << x2s, tile, xstage, TB, lslot, bl, bc);      \
+      add_entry<N, NUMAX, CPLX>(E, en, u2, 1 << x2s, tile, xstage, TB, lslot, bl, bc); \
     break;
       X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10)
 #undef X
@@ -1516,6 +1557,9 @@ static hipError_t launch_project_any_nu(const KArgs &K, const double *psi,
   if (K.det)
     hipLaunchKernelGGL((k_project_any<NUMAX, true>), grid_of(K), dim3(kBlock), shm, s, K, psi,
                        c);
+  else if (K.bloch)
+    hipLaunchKernelGGL((k_project_any<NUMAX, false, true>), grid_of(K), dim3(kBlock), shm, s, K,
+                       psi, c);
   else
     hipLaunchKernelGGL((k_project_any<NUMAX, false>), grid_of(K), dim3(kBlock), shm, s, K, psi,
                        c);
@@ -1554,6 +1598,7 @@ hipError_t launch_expand_atomic(int nu, const KArgs &K, const double *c,
 
 hipError_t launch_project(int nu, const KArgs &K, const double *psi, double *c,
                           hipStream_t s) {
+  if (K.bloch) return hipErrorInvalidValue;  // Bloch plans run k_project_any
   switch (nu) {
 #define X(N) case N: return launch_project_nu<N>(K, psi, c, s);
     SHO_NU_CASES(X)
@@ -1595,6 +1640,7 @@ hipError_t launch_expand_planes(const EArgs &E, const double *c, double *u2,
 
 hipError_t launch_rows(const EArgs &E, const double *u2, double *psi,
                        hipStream_t s) {
+  if (E.bloch) return hipErrorInvalidValue;  // Bloch plans expand in the block form
   if (E.nrows > 0) {
     const int xchunk = kRowChunkDoubles >> E.tbe_shift;
     const dim3 g((unsigned)E.nrows, (unsigned)((E.nx + xchunk - 1) / xchunk),
@@ -1623,9 +1669,14 @@ hipError_t launch_blocks(const EArgs &E, const double *u2, double *psi,
     const dim3 g((unsigned)E.nblocks, (unsigned)E.ntiles);
     const size_t shm = (kBlockTileDoubles + kBlkWaves * kBlkXStage) * sizeof(double);
     switch (E.nu_max) {
-#define X(N)                                                                        \
-  case N:                                                                           \
-    hipLaunchKernelGGL((k_expand_blocks<N>), g, dim3(kBlkBlock), shm, s, E, u2, psi); \
+#define X(N)                                                                          \
+  case N:                                                                             \
+    if (E.bloch)                                                                      \
+      hipLaunchKernelGGL((k_expand_blocks<N, true>), g, dim3(kBlkBlock), shm, s, E, u2, \
+                         psi);                                                        \
+    else                                                                              \
+      hipLaunchKernelGGL((k_expand_blocks<N, false>), g, dim3(kBlkBlock), shm, s, E, u2, \
+                         psi);                                                        \
     break;
       SHO_NU_CASES(X)
 #undef X
@@ -1637,6 +1688,7 @@ hipError_t launch_blocks(const EArgs &E, const double *u2, double *psi,
 }
 
 hipError_t launch_owner(const EArgs &E, const double *u2, double *psi, hipStream_t s) {
+  if (E.bloch) return hipErrorInvalidValue;  // Bloch plans expand in the block form
   if (E.nblocks <= 0) return hipSuccess;
   // whole groups of 8 workgroups, so that block g runs on XCD g mod 8 for
   // every band tile (the plan deals the planes' strips to the XCDs that way)

@@ -107,10 +107,12 @@ struct RunState {
   int len;
   int jy;
   bool active;
+  float pc, ps;      // Bloch plans: cos, sin of k.T for the run's image T
 };
 
+template <bool CPLX = false>
 __device__ inline RunState run_state(const KArgs &K, const Lanes &L, const Pair *psi,
-                                     const BundleRec &bd) {
+                                     const BundleRec &bd, const AtomRec *A = nullptr) {
   const int s = min(L.slot, bd.nruns - 1);
   const LineRec ln = K.lines[bd.run0 + s];
   RunState r;
@@ -119,7 +121,25 @@ __device__ inline RunState run_state(const KArgs &K, const Lanes &L, const Pair 
   r.len = ln.len;
   r.jy = ln.jy;
   r.active = L.slot < bd.nruns;
+  if constexpr (CPLX) {
+    // k.T, T = unwrapped minus memory position of the run's points; the
+    // angle and its sine and cosine in double, rounded once to float
+    const int ym = ln.row % K.ny, zm = ln.row / K.ny;
+    double th = K.k[0] * ((double)(A->ix0 + ln.jx0 - ln.x0m) * K.h);
+    th += K.k[1] * ((double)(A->iy0 + ln.jy - ym) * K.h);
+    th += K.k[2] * ((double)(A->iz0 + ln.jz - zm) * K.h);
+    double sn, cs;
+    sincos(th, &sn, &cs);
+    r.pc = (float)cs;
+    r.ps = (float)sn;
+  }
   return r;
+}
+
+// A complex band as one pair (a = real, b = imaginary part): v e^{i th} for
+// sn = sin th, or v e^{-i th} for sn = -sin th.
+__device__ inline Pair rotate(Pair v, float cs, float sn) {
+  return Pair{fmaf(-sn, v.b, cs * v.a), fmaf(sn, v.a, cs * v.b)};
 }
 
 __device__ inline void load_batch(const KArgs &K, const RunState &r, int jb, Pair *v) {
@@ -178,7 +198,7 @@ __device__ inline void flush_plane(cptr<float> fz, Pair *T2, double *cacc, const
 
 // ------------------------------------------------------- projection core --
 
-template <int NU>
+template <int NU, bool CPLX = false>
 __device__ inline void project_bundles(const KArgs &K, const float *tab, const AtomRec &A,
                                        const Lanes &L, int b0, int b1,
                                        const Pair *__restrict__ psi, double *cacc) {
@@ -195,7 +215,7 @@ __device__ inline void project_bundles(const KArgs &K, const float *tab, const A
   for (int q = 0; q < NP; ++q) T2[q] = zero2();
   int cur_jz = -1;
   BundleRec bd = load_uniform(K.bundles + b0);
-  RunState rs = run_state(K, L, psi, bd);
+  RunState rs = run_state<CPLX>(K, L, psi, bd, &A);
   Pair v[kBatch];
   load_batch(K, rs, bd.jlo, v);
   for (int bi = b0; bi < b1; ++bi) {
@@ -214,7 +234,7 @@ __device__ inline void project_bundles(const KArgs &K, const float *tab, const A
         load_batch(K, rs, jb + kBatch, w);
       } else if (bi + 1 < b1) {
         nbd = load_uniform(K.bundles + bi + 1);
-        nrs = run_state(K, L, psi, nbd);
+        nrs = run_state<CPLX>(K, L, psi, nbd, &A);
         load_batch(K, nrs, nbd.jlo, w);
       } else {
 #pragma unroll
@@ -235,6 +255,11 @@ __device__ inline void project_bundles(const KArgs &K, const float *tab, const A
 #pragma unroll
       for (int u = 0; u < kBatch; ++u) v[u] = w[u];
     }
+    if constexpr (CPLX) {
+      // the run's image carries e^{+i k.T}
+#pragma unroll
+      for (int n = 0; n < NF; ++n) T1[n] = rotate(T1[n], rs.pc, rs.ps);
+    }
     const float *fy = ty + rs.jy * nfp;
     int q = 0;
 #pragma unroll
@@ -249,7 +274,7 @@ __device__ inline void project_bundles(const KArgs &K, const float *tab, const A
   flush_plane<NU>(tz + cur_jz * nfp, T2, cacc, L);
 }
 
-template <int NU>
+template <int NU, bool CPLX = false>
 __device__ inline void project_item(const KArgs &K, const float *tab, cptr<WorkRec> W,
                                     const AtomRec &A, const Pair *__restrict__ psi,
                                     Pair *__restrict__ c, double *cacc) {
@@ -261,7 +286,7 @@ __device__ inline void project_item(const KArgs &K, const float *tab, cptr<WorkR
   __syncthreads();
   const int w = wave_id();
   const Lanes L = lane_geometry(K, tile);
-  project_bundles<NU>(K, tab, A, L, W->wb[w], W->wb[w + 1], psi, cacc);
+  project_bundles<NU, CPLX>(K, tab, A, L, W->wb[w], W->wb[w + 1], psi, cacc);
   __syncthreads();
   const bool split = W->split != 0;
   for (int t = threadIdx.x; t < NS * TB; t += blockDim.x) {
@@ -292,7 +317,7 @@ __attribute__((amdgpu_waves_per_eu(waves_per_eu(NU + 1)))) void k_project(
   project_item<NU>(K, tab, W, A, psi, c, cacc);
 }
 
-template <int NUMAX>
+template <int NUMAX, bool CPLX = false>
 __global__ __launch_bounds__(kBlock)
 __attribute__((amdgpu_waves_per_eu(waves_per_eu(NUMAX + 1)))) void k_project_any(
     KArgs K, const float *__restrict__ tab, const Pair *__restrict__ psi,
@@ -304,7 +329,7 @@ __attribute__((amdgpu_waves_per_eu(waves_per_eu(NUMAX + 1)))) void k_project_any
   switch (A.nu) {
 #define X(N)                                                                 \
   case N:                                                                    \
-    if constexpr (N <= NUMAX) project_item<N>(K, tab, W, A, psi, c, cacc);   \
+    if constexpr (N <= NUMAX) project_item<N, CPLX>(K, tab, W, A, psi, c, cacc); \
     break;
     SHO_F32_NU_CASES(X)
 #undef X
@@ -388,7 +413,7 @@ constexpr int blk_group(int nu, int numax) { return (numax > 5 && nu <= 5) ? 4 :
 
 // Adds every run of one entry (one atom plane, one image) into the LDS tile
 // of the block ([row][x][2][TB] doubles).
-template <int NU, int NUMAX>
+template <int NU, int NUMAX, bool CPLX = false>
 __device__ inline void add_entry(const EArgs &E, const float *tab, const EntryRec &en,
                                  const Pair *u2, int nxl, double *tile, float *xstage,
                                  int TB, int slot, int bl, int bc) {
@@ -402,6 +427,16 @@ __device__ inline void add_entry(const EArgs &E, const float *tab, const EntryRe
   Pair u2v[NP];
 #pragma unroll
   for (int q = 0; q < NP; ++q) u2v[q] = ub[(int64_t)q * E.B];
+  if constexpr (CPLX) {
+    // the entry's image T receives e^{-i k.T} times the plane partials
+    double th = E.k[0] * ((double)(en.img[0] * E.nx) * E.h);
+    th += E.k[1] * ((double)(en.img[1] * E.ny) * E.h);
+    th += E.k[2] * ((double)(en.img[2] * E.nz) * E.h);
+    double sn, cs;
+    sincos(th, &sn, &cs);
+#pragma unroll
+    for (int q = 0; q < NP; ++q) u2v[q] = rotate(u2v[q], (float)cs, -(float)sn);
+  }
   const uint32_t mydesc = lane < en.nruns ? as_const(E.run_desc)[en.run_begin + lane] : 0u;
   float tx[4];
 #pragma unroll
@@ -466,7 +501,7 @@ __device__ inline void add_entry(const EArgs &E, const float *tab, const EntryRe
 // kBlockTileDoubles / 2 pairs, the LDS bytes of the FP64 tile, laid out as
 // [row][X2][pair] (X2 the block width rounded up to a power of two) so that
 // the fill and write-back split a slot with shifts and masks.
-template <int NUMAX>
+template <int NUMAX, bool CPLX = false>
 __global__ __launch_bounds__(kBlkBlock) void k_expand_blocks(EArgs E,
                                                             const float *__restrict__ tab,
                                                             const Pair *__restrict__ u2,
@@ -531,7 +566,7 @@ __global__ __launch_bounds__(kBlkBlock) void k_expand_blocks(EArgs E,
 #define X(N)                                                                        \
   case N:                                                                           \
     if constexpr (N <= NUMAX)                                                       \
-      add_entry<N, NUMAX>(E, tab, en, u2, 1 << x2s, tile, xstage, TB, lslot, bl, bc); \
+      add_entry<N, NUMAX, CPLX>(E, tab, en, u2, 1 << x2s, tile, xstage, TB, lslot, bl, bc); \
     break;
       SHO_F32_NU_CASES(X)
 #undef X
@@ -573,8 +608,12 @@ template <int NUMAX>
 static hipError_t launch_project_any_nu(const KArgs &K, const float *tab, const Pair *psi,
                                         Pair *c, hipStream_t s) {
   const size_t shm = 2 * lds_tile_bytes(NUMAX + 1, 1 << K.tb_shift);
-  hipLaunchKernelGGL(k_project_any<NUMAX>, grid_of(K), dim3(kBlock), shm, s, K, tab, psi,
-                     c);
+  if (K.bloch)
+    hipLaunchKernelGGL((k_project_any<NUMAX, true>), grid_of(K), dim3(kBlock), shm, s, K, tab,
+                       psi, c);
+  else
+    hipLaunchKernelGGL((k_project_any<NUMAX, false>), grid_of(K), dim3(kBlock), shm, s, K, tab,
+                       psi, c);
   return hipGetLastError();
 }
 
@@ -593,6 +632,7 @@ hipError_t launch_tables_f32(const double *tab, float *tab32, int64_t n, hipStre
 hipError_t launch_project_f32(int nu, const KArgs &K, const float *tab, const float *psi,
                               float *c, hipStream_t s) {
   if (K.nwork <= 0) return hipSuccess;
+  if (K.bloch) return hipErrorInvalidValue;  // Bloch plans run k_project_any
   const Pair *pp = reinterpret_cast<const Pair *>(psi);
   Pair *cp = reinterpret_cast<Pair *>(c);
   switch (nu) {
@@ -649,8 +689,12 @@ hipError_t launch_blocks_f32(const EArgs &E, const float *tab, const float *u2, 
     switch (E.nu_max) {
 #define X(N)                                                                             \
   case N:                                                                                \
-    hipLaunchKernelGGL((f32::k_expand_blocks<N>), g, dim3(f32::kBlkBlock), shm, s, E, tab, \
-                       up, pp);                                                          \
+    if (E.bloch)                                                                         \
+      hipLaunchKernelGGL((f32::k_expand_blocks<N, true>), g, dim3(f32::kBlkBlock), shm, s, E, \
+                         tab, up, pp);                                                   \
+    else                                                                                 \
+      hipLaunchKernelGGL((f32::k_expand_blocks<N, false>), g, dim3(f32::kBlkBlock), shm, s, E, \
+                         tab, up, pp);                                                   \
     break;
       SHO_F32_NU_CASES(X)
 #undef X

@@ -30,8 +30,12 @@ struct KArgs {
   int32_t ntiles;            // band tiles per atom
   int32_t det;               // 1: deterministic sums (per-wave LDS tiles
                              // added in wave order; no atomics)
+  int32_t ny, nz;            // grid points along y, z
+  int32_t bloch;             // 1: complex bands (re, im) at wave vector k
   double h3;
   double alpha;              // expansion: psi += alpha * sum_n c P_n
+  double h;                  // grid spacing
+  double k[3];               // Bloch wave vector (Bohr^-1)
 };
 
 // Argument block of the row-owner expansion.
@@ -64,7 +68,11 @@ struct EArgs {
   int32_t blk_x;        // X
   int32_t ny;
   int32_t ncol;         // stored plans: 0, or the radial projectors per atom
+  int32_t nz;
+  int32_t bloch;        // 1: complex bands (re, im) at wave vector k
   double alpha;         // psi += alpha * sum_n c P_n (applied to c in the z pass)
+  double h;             // grid spacing
+  double k[3];          // Bloch wave vector (Bohr^-1)
 };
 
 // Argument block of the stored-projector kernels.

@@ -67,7 +67,7 @@ sho_status build_host_plan(const sho_grid *grid, int32_t natoms,
   }
   const uint32_t known =
       SHO_FLAG_STORED | SHO_FLAG_ALLOW_UNDERSAMPLED | SHO_FLAG_HOST_ONLY | SHO_FLAG_PER_ATOM |
-      SHO_FLAG_FP32 | SHO_FLAG_DETERMINISTIC;
+      SHO_FLAG_FP32 | SHO_FLAG_DETERMINISTIC | SHO_FLAG_BLOCH;
   if (flags & ~known) {
     *msg = "unknown flag bits";
     return SHO_E_INVALID;
@@ -628,6 +628,18 @@ void build_blocks(HostPlan *P, int32_t R, int32_t X) {
       E.y_hi = (int16_t)std::min(R, A.my - jy0);
       E.run_begin = (int32_t)P->run_desc.size();
       E.nruns = 0;
+      // image counts (clamped; Bloch plans refuse supports beyond 127 images)
+      {
+        const int32_t nz = P->grid.n[2];
+        const int64_t dxyz[3] = {(int64_t)A.ix0 + it.jshift, (int64_t)A.iy0 + it.yshift,
+                                 (int64_t)A.iz0 + it.jz - B.z};
+        const int32_t nd[3] = {nx, ny, nz};
+        for (int d = 0; d < 3; ++d) {
+          const int64_t m = dxyz[d] / nd[d];
+          E.img[d] = (int8_t)std::min<int64_t>(std::max<int64_t>(m, -127), 127);
+        }
+        E.pad = 0;
+      }
       // at most 64 runs per entry (one descriptor per lane)
       while (i < items.size() && E.nruns < 64 && items[i].block == blk &&
              items[i].atom == it.atom && items[i].jz == it.jz &&
