@@ -60,6 +60,8 @@ def parse():
                     help="skip the differentiation (forward + backward) workload")
     ap.add_argument("--no-fp32", action="store_true",
                     help="skip the single-precision scale step")
+    ap.add_argument("--no-per-atom", action="store_true",
+                    help="batching workload: skip timing the per-atom launch reference")
     ap.add_argument("--no-bloch", action="store_true",
                     help="skip the complex Bloch-band scale step")
     ap.add_argument("--no-tune", action="store_true",
@@ -68,6 +70,9 @@ def parse():
     ap.add_argument("--serve-warmup", type=int, default=200)
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample")
+    ap.add_argument("--digest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="turn two rocprofv3 --pmc counter files (FETCH_SIZE, WRITE_SIZE) "
+                         "into profiles/traffic.json and exit")
     ap.add_argument("--copy-calib", action="store_true",
                     help="first run a plain 1 GiB elementwise copy kernel (reads 1 GiB, "
                          "writes 1 GiB) so that profiler byte counters can be scaled")
@@ -79,18 +84,96 @@ def kernel_source_sha():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from committed counter runs, if they
-    were taken with the current kernel source."""
+def measured_traffic(kind, workload="scale"):
+    """HBM bytes per launch of kernel kind `kind` (project, expand_z,
+    expand_xy) of `workload` from the committed counter runs, if they were
+    taken with the current kernel source."""
     try:
         with open(TRAFFIC) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    rec = t.get("kernels", {}).get(kernel)
-    if not rec or t.get("kernel_source_sha") != kernel_source_sha():
+    if t.get("kernel_source_sha") != kernel_source_sha():
         return None
-    return rec.get("hbm_bytes_per_launch")
+    rec = t.get("kinds", {}).get(workload, {}).get(kind)
+    return rec.get("hbm_bytes_per_launch") if rec else None
+
+
+# Kernel kinds of the counter runs: (workload, kind) -> regexes of the
+# kernels that make up one launch of the kind; the first names the main
+# kernel, whose dispatch count is the number of launches.
+COUNTER_KINDS = {
+    "scale": {"project": [r"k_project(_any|_blocks)?<5\b", r"k_zpass<5>"],
+              "expand_z": [r"k_u2<5>"],
+              "expand_xy": [r"k_expand_blocks<5, false>"]},
+    "batching": {"project": [r"k_project(_any|_blocks)?<9\b", r"k_zpass<[0-9]>"],
+                 "expand_z": [r"k_u2<9>", r"k_u2<[0-8]>"],
+                 "expand_xy": [r"k_expand_blocks<9, false>"]},
+}
+
+
+def digest_counters(fetch_csv, write_csv, out=TRAFFIC):
+    """HBM bytes per launch from two rocprofv3 --pmc runs (FETCH_SIZE, then
+    WRITE_SIZE, KiB per dispatch) of `bench.py --copy-calib`: each counter is
+    scaled by what it reads for the plain 1 GiB elementwise copy kernel
+    (reads 1 GiB, writes 1 GiB) of the same run.  Dispatches from the first
+    kernel of cut-off 9 on belong to the batching workload (which runs after
+    the scale step).  Writes `out`."""
+    import csv
+    import re
+
+    def per_kernel(path, counter):
+        rows = []
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] == counter:
+                    rows.append((int(r["Dispatch_Id"]), r["Kernel_Name"],
+                                 float(r["Counter_Value"]) * 1024.0))
+        first9 = min([d for d, k, _ in rows if re.search(r"k_(project\w*|expand_blocks)<9", k)]
+                     or [1 << 62])
+        tot, cnt = {}, {}
+        for d, k, v in rows:
+            key = ("batching" if d >= first9 else "scale", k.split("(")[0])
+            tot[key] = tot.get(key, 0.0) + v
+            cnt[key] = cnt.get(key, 0) + 1
+        return tot, cnt
+
+    ft, fc = per_kernel(fetch_csv, "FETCH_SIZE")
+    wt, wc = per_kernel(write_csv, "WRITE_SIZE")
+    copy = [k for k in ft if "elementwise_kernel" in k[1] and "AUnaryFunctor" in k[1]]
+    if not copy:
+        raise SystemExit("no copy-calibration kernel in the counter runs (--copy-calib)")
+    gib = float(1 << 30)
+    fscale = gib / (ft[copy[0]] / fc[copy[0]])
+    wscale = gib / (wt[copy[0]] / wc[copy[0]])
+    kernels = {}
+    for (ph, k) in ft:
+        if "sho::" not in k:
+            continue
+        fb = ft[(ph, k)] / fc[(ph, k)] * fscale
+        wb = wt.get((ph, k), 0.0) / max(wc.get((ph, k), 1), 1) * wscale
+        kernels.setdefault(ph, {})[k] = {"dispatches": fc[(ph, k)], "fetch_bytes": fb,
+                                        "write_bytes": wb, "hbm_bytes_per_launch": fb + wb}
+    kinds = {}
+    for wname, ks in COUNTER_KINDS.items():
+        kk = kernels.get(wname, {})
+        for kind, pats in ks.items():
+            main = [k for k in kk if re.search(pats[0], k)]
+            if not main:
+                continue
+            n = sum(kk[k]["dispatches"] for k in main)
+            names = [k for k in kk if any(re.search(p, k) for p in pats)]
+            fb = sum(kk[k]["fetch_bytes"] * kk[k]["dispatches"] for k in names) / n
+            wb = sum(kk[k]["write_bytes"] * kk[k]["dispatches"] for k in names) / n
+            kinds.setdefault(wname, {})[kind] = {"kernels": sorted(names), "launches": n,
+                                                 "fetch_bytes": fb, "write_bytes": wb,
+                                                 "hbm_bytes_per_launch": fb + wb}
+    rec = {"workload": "scale and batching steps of bench.py (default schedules, --no-tune)",
+           "kernel_source_sha": kernel_source_sha(), "fetch_scale": fscale,
+           "write_scale": wscale, "kinds": kinds, "kernels": kernels}
+    with open(out, "w") as f:
+        json.dump(rec, f, indent=1)
+    return rec
 
 
 def cpu_baseline(s, psi, c, target_s):
@@ -532,7 +615,7 @@ def batching(bd, wl, args):
     ms, _ = _time_steps(step, steps, 1)
     res["default"] = {"schedule": plan.schedule(), "ms_per_step": ms,
                       "value": units / (ms * 1e-3)}
-    tune = plan.tune(psi, c, reps=2)
+    tune = None if args.no_tune else plan.tune(psi, c, reps=2)
     ms, per = _time_steps(step, steps, 1)
     plan.profile(True)
     step()
@@ -551,6 +634,10 @@ def batching(bd, wl, args):
     res["graph"] = {"ms_per_step": ms, "value": units / (ms * 1e-3)}
     g.close()
     plan.close()
+    if args.no_per_atom:
+        del psi, out, c
+        torch.cuda.empty_cache()
+        return res
     ref = bd.Plan.from_system(s, flags=bd.FLAG_PER_ATOM)
 
     def ref_step():
@@ -572,6 +659,10 @@ def batching(bd, wl, args):
 
 def main():
     args = parse()
+    if args.digest_counters:
+        rec = digest_counters(*args.digest_counters)
+        print(json.dumps(rec["kinds"], indent=1))
+        return
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (--gpus 1); the path "
               "shards over bands or z-slabs as described in DESIGN.md", file=sys.stderr)

@@ -258,12 +258,14 @@ sho_status sho_plan_create_radial(const sho_grid *grid, int32_t natoms, const do
                                   int32_t nbands, uint32_t flags, sho_plan_t *out);
 
 /*
- * Bloch wave vector of a SHO_FLAG_BLOCH plan, k[3] in Bohr^-1 (host).  Later
- * calls use it; work already queued keeps the previous one.  The phase of
- * an image is e^{i k.T}, T = (m_x n_x h, m_y n_y h, m_z n_z h) with the
- * image counts m_d; a support reaching more than 127 images along an axis is
- * refused at plan creation (SHO_E_BOX).  Errors: SHO_E_INVALID (not a Bloch
- * plan, non-finite k).
+ * Bloch wave vector of a SHO_FLAG_BLOCH plan, k[3] in Bohr^-1 (host).  Waits
+ * for the device (queued work reads the plan's phase tables), then stores
+ * (cos, sin) of k.T for every run bundle and block entry of the plan on the
+ * device; later calls use it.  The phase of an image is e^{i k.T},
+ * T = (m_x n_x h, m_y n_y h, m_z n_z h) with the image counts m_d; a support
+ * reaching more than 127 images along an axis is refused at plan creation
+ * (SHO_E_BOX).  Graphs captured before are refused.  Errors: SHO_E_INVALID
+ * (not a Bloch plan, non-finite k), SHO_E_DEVICE.
  */
 sho_status sho_plan_set_kpoint(sho_plan_t plan, const double *k);
 
@@ -419,6 +421,31 @@ sho_status sho_plan_get_schedule(sho_plan_t plan, int32_t *schedule,
                                  int32_t *band_tile, int64_t *target_points);
 
 /*
+ * Form of the projection (sec. 3.2 step 1):
+ *   SHO_PROJECT_ITEMS   work items of atoms (sho_plan_set_schedule): each
+ *                       workgroup streams the psi box of one atom (or a share
+ *                       of it), so a value held by k supports is read k times
+ *                       (default);
+ *   SHO_PROJECT_BLOCKS  one workgroup per block of block_rows x block_x points
+ *                       of one plane and band_tile bands (8, 16, 32 or 64):
+ *                       the block is read once and every atom plane touching
+ *                       it adds its plane sums into the plan's plane-partial
+ *                       scratch (atomics); a z pass writes c.  For heavily
+ *                       overlapping supports (many atoms per grid value).
+ * block_rows, block_x, band_tile = 0 pick 32 points, 16 bands and as many rows
+ * as 8192 values allow; rows and points at most 255.  The block form is for
+ * FP64 plans of real bands that are not stored, per-atom or deterministic
+ * (SHO_E_INVALID otherwise); the derivative always uses work items.
+ * set_project waits for the device; graphs made before it are refused.
+ */
+#define SHO_PROJECT_ITEMS 0
+#define SHO_PROJECT_BLOCKS 1
+sho_status sho_plan_set_project(sho_plan_t plan, int32_t form, int32_t block_rows,
+                                int32_t block_x, int32_t band_tile);
+sho_status sho_plan_get_project(sho_plan_t plan, int32_t *form, int32_t *block_rows,
+                                int32_t *block_x, int32_t *band_tile);
+
+/*
  * Form of the expansion's second half (sec. 3.2 step 3 after the z pass):
  *   0  rows:   one workgroup per chunk of one memory row; every run of the
  *              row loads its atom plane's partial sums;
@@ -447,6 +474,41 @@ sho_status sho_plan_set_expand(sho_plan_t plan, int32_t mode, int32_t block_rows
 sho_status sho_plan_get_expand(sho_plan_t plan, int32_t *mode, int32_t *block_rows,
                                int32_t *block_x);
 
+/*
+ * Band tile of the expansion's block form (bands per lane slot: 8, 16, 32 or
+ * 64; 0 restores the default rule: the power of two covering nbands, at most
+ * 64).  Narrower tiles run more band tiles over larger blocks, so that the
+ * plane partials of an atom plane are loaded for fewer blocks.  Rebuilds the
+ * blocks in the default shape for the tile.  Not for SHO_FLAG_STORED plans.
+ * Waits for the device; graphs made before it are refused.
+ */
+sho_status sho_plan_set_expand_tile(sho_plan_t plan, int32_t band_tile);
+sho_status sho_plan_get_expand_tile(sho_plan_t plan, int32_t *band_tile);
+
+typedef struct sho_tune_expand_result {
+  int32_t mode;          /* chosen SHO_EXPAND_* */
+  int32_t band_tile;     /* bands per lane slot of that form */
+  int32_t block_rows;    /* block shape (block form) */
+  int32_t block_x;
+  double ms;             /* mean expansion time of the choice */
+  double ms_before;      /* of the form the plan had before */
+  int32_t candidates;    /* forms timed */
+  int32_t pad;
+} sho_tune_expand_result;
+
+/*
+ * Expansion tuner: times the expansion of c into psi (device buffers of the
+ * plan's sizes; psi is used as scratch: it accumulates reps + 2 expansions
+ * per candidate) under the block form with every band tile from 8 to the
+ * one covering nbands and a few block shapes per tile (the default, half the
+ * rows, half the width, twice the rows at half the width), and the row form
+ * (FP64 plans of real bands), reps launches each after one warm-up, on
+ * stream, and keeps the fastest.  Synchronous.  Refused (SHO_E_INVALID) on
+ * stored, per-atom and deterministic plans.  result may be NULL.
+ */
+sho_status sho_plan_tune_expand(sho_plan_t plan, const void *c, void *psi, int32_t reps,
+                                void *stream, sho_tune_expand_result *result);
+
 typedef struct sho_tune_result {
   int32_t schedule;      /* chosen SHO_SCHED_* */
   int32_t band_tile;     /* chosen bands per lane slot */
@@ -454,16 +516,18 @@ typedef struct sho_tune_result {
   double ms;             /* mean projection time of the choice */
   double ms_before;      /* of the schedule the plan had before */
   int32_t candidates;    /* schedules timed */
-  int32_t pad;
+  int32_t project_form;  /* chosen SHO_PROJECT_* */
 } sho_tune_result;
 
 /*
  * Autotuner: times the projection of psi into c (both device buffers of the
  * plan's sizes; c is overwritten) under every schedule (with and without
  * SHO_SCHED_XCD) x work item size
- * {4096, 8192, 16384, 32768} x band tile {current, half}, reps launches each after
- * one warm-up, on stream, and keeps the fastest.  Synchronous.  result may
- * be NULL.  psi and c hold the plan's element type (double, or float for
+ * {4096, 8192, 16384, 32768} x band tile {current, half}, and (FP64 plans of
+ * real bands, not deterministic) the block form of the projection with band
+ * tiles 8..32 and blocks 16..64 points wide, reps launches each after one
+ * warm-up, on stream, and keeps the fastest (the item schedule is kept for
+ * the derivative either way).  Synchronous.  result may be NULL.  psi and c hold the plan's element type (double, or float for
  * SHO_FLAG_FP32 plans).  Refused (SHO_E_INVALID) on stored and per-atom
  * plans.
  */

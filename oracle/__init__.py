@@ -32,10 +32,13 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB_PATH):
+    # SHO_ORACLE_LIBRARY names another build of the oracle (the sanitized
+    # libsho_oracle_asan.so of `build.py --sanitize`)
+    path = os.environ.get("SHO_ORACLE_LIBRARY") or _LIB_PATH
+    if not os.path.exists(path):
         from . import build as _b
         _b.build()
-    lib = ctypes.CDLL(_LIB_PATH)
+    lib = ctypes.CDLL(path)
     lib.oracle_nsho.argtypes = [ctypes.c_int]
     lib.oracle_nsho.restype = ctypes.c_int
     lib.oracle_coeff_index.argtypes = [ctypes.c_int] * 4

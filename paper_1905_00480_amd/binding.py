@@ -42,6 +42,7 @@ SCHED_BY_NU = 0
 SCHED_SINGLE = 1
 SCHED_SINGLE_LPT = 2
 SCHED_SWEEP = 3
+PROJECT_ITEMS, PROJECT_BLOCKS = 0, 1
 SCHED_XCD = 4
 EXPAND_ROWS = 0
 EXPAND_BLOCKS = 1
@@ -58,7 +59,8 @@ EXPORTS = (
     "sho_plan_project_f32", "sho_plan_expand_f32",
     "sho_plan_force", "sho_project", "sho_expand", "sho_force",
     "sho_plan_expand_scaled", "sho_plan_expand_noalloc", "sho_plan_create_radial",
-    "sho_plan_set_kpoint",
+    "sho_plan_set_kpoint", "sho_plan_set_project", "sho_plan_get_project",
+    "sho_plan_set_expand_tile", "sho_plan_get_expand_tile", "sho_plan_tune_expand",
     "sho_cache_clear", "sho_plan_profile", "sho_plan_profile_read",
     "sho_plan_set_schedule", "sho_plan_get_schedule", "sho_plan_tune",
     "sho_plan_set_expand", "sho_plan_get_expand",
@@ -102,7 +104,14 @@ class sho_tune_result(ctypes.Structure):
     _fields_ = [("schedule", ctypes.c_int32), ("band_tile", ctypes.c_int32),
                 ("target_points", ctypes.c_int64), ("ms", ctypes.c_double),
                 ("ms_before", ctypes.c_double), ("candidates", ctypes.c_int32),
-                ("pad", ctypes.c_int32)]
+                ("project_form", ctypes.c_int32)]
+
+
+class sho_tune_expand_result(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("band_tile", ctypes.c_int32),
+                ("block_rows", ctypes.c_int32), ("block_x", ctypes.c_int32),
+                ("ms", ctypes.c_double), ("ms_before", ctypes.c_double),
+                ("candidates", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 class sho_server_stats(ctypes.Structure):
@@ -126,7 +135,9 @@ def load_library(path=None):
     if _lib is not None and path is None:
         return _lib
     import torch  # noqa: F401  -- torch's HIP runtime must be the one in use
-    p = path or LIB_PATH
+    # SHO_LIBRARY names another build of the same library (the host-sanitized
+    # libsho_asan.so of `build.py --sanitize`, run with its runtime preloaded)
+    p = path or os.environ.get("SHO_LIBRARY") or LIB_PATH
     if not os.path.exists(p):
         raise RuntimeError(
             "libsho.so not built: run `python -m paper_1905_00480_amd.build` "
@@ -150,6 +161,13 @@ def load_library(path=None):
     lib.sho_plan_support_counts.argtypes = [P, _i64p]
     lib.sho_plan_set_centres.argtypes = [P, _dp, _vp]
     lib.sho_plan_set_kpoint.argtypes = [P, _dp]
+    lib.sho_plan_set_project.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_int32]
+    lib.sho_plan_get_project.argtypes = [P, _i32p, _i32p, _i32p, _i32p]
+    lib.sho_plan_set_expand_tile.argtypes = [P, ctypes.c_int32]
+    lib.sho_plan_get_expand_tile.argtypes = [P, _i32p]
+    lib.sho_plan_tune_expand.argtypes = [P, _vp, _vp, ctypes.c_int32, _vp,
+                                         ctypes.POINTER(sho_tune_expand_result)]
     lib.sho_plan_project.argtypes = [P, _vp, _vp, _vp]
     lib.sho_plan_expand.argtypes = [P, _vp, _vp, _vp]
     lib.sho_plan_project_f32.argtypes = [P, _vp, _vp, _vp]
@@ -450,6 +468,18 @@ class Plan:
                                                ctypes.byref(tp)))
         return sc.value, bt.value, tp.value
 
+    def set_project(self, form, block_rows=0, block_x=0, band_tile=0):
+        """Projection form: PROJECT_ITEMS or PROJECT_BLOCKS (with block shape and
+        band tile; 0 picks the default)."""
+        _check(self._lib.sho_plan_set_project(self._h, int(form), int(block_rows),
+                                              int(block_x), int(band_tile)))
+
+    def project_form(self):
+        """(form, block_rows, block_x, band_tile) of the projection."""
+        v = [ctypes.c_int32() for _ in range(4)]
+        _check(self._lib.sho_plan_get_project(self._h, *[ctypes.byref(x) for x in v]))
+        return tuple(x.value for x in v)
+
     def set_expand(self, mode, block_rows=0, block_x=0):
         """Expansion form: EXPAND_ROWS, EXPAND_BLOCKS or EXPAND_OWNER (with
         block shape; 0 picks the default)."""
@@ -463,6 +493,25 @@ class Plan:
                                              ctypes.byref(x)))
         return m.value, r.value, x.value
 
+    def set_expand_tile(self, band_tile):
+        """Band tile of the expansion's block form (8..64, 0: default)."""
+        _check(self._lib.sho_plan_set_expand_tile(self._h, int(band_tile)))
+
+    def expand_tile(self):
+        v = ctypes.c_int32()
+        _check(self._lib.sho_plan_get_expand_tile(self._h, ctypes.byref(v)))
+        return v.value
+
+    def tune_expand(self, c, psi_scratch, reps=3, stream=None):
+        """Time the expansion forms on c -> psi_scratch (its contents are
+        overwritten by accumulations) and keep the fastest."""
+        r = sho_tune_expand_result()
+        _check(self._lib.sho_plan_tune_expand(
+            self._h, _dev(c, self.coeff_doubles, "c", self.fp32),
+            _dev(psi_scratch, self.psi_numel, "psi", self.fp32),
+            int(reps), _stream(stream), ctypes.byref(r)))
+        return {k: getattr(r, k) for k, _ in sho_tune_expand_result._fields_ if k != "pad"}
+
     def tune(self, psi, c, reps=3, stream=None):
         """Time the projection schedules on psi -> c and keep the fastest."""
         r = sho_tune_result()
@@ -470,7 +519,7 @@ class Plan:
             self._h, _dev(psi, self.psi_numel, "psi", self.fp32),
             _dev(c, self.coeff_doubles, "c", self.fp32),
             int(reps), _stream(stream), ctypes.byref(r)))
-        return {k: getattr(r, k) for k, _ in sho_tune_result._fields_ if k != "pad"}
+        return {k: getattr(r, k) for k, _ in sho_tune_result._fields_}
 
     def graph(self, psi, c, out):
         """A replayable graph of project(psi -> c) then expand(c -> out)."""

@@ -37,24 +37,39 @@ def _run(cmd, verbose):
     subprocess.run(cmd, check=True)
 
 
-def build(verbose: bool = False, jobs: int = 3) -> str:
-    """Compile every source and link libsho.so (always rebuilds)."""
-    os.makedirs(BUILD, exist_ok=True)
+# Host-code sanitizer build (libsho_asan.so, for the CPU test suite): the
+# host sources with clang's AddressSanitizer and UndefinedBehaviorSanitizer,
+# the HIP sources with the same on their host side only (-Xarch_host), linked
+# against clang's shared sanitizer runtime, which the test process preloads.
+CLANGXX = "/opt/rocm/llvm/bin/clang++"
+SAN = ["-fsanitize=address", "-fsanitize=undefined", "-fno-sanitize-recover=undefined"]
+LIB_ASAN = os.path.join(PKG, "libsho_asan.so")
+
+
+def build(verbose: bool = False, jobs: int = 3, sanitize: bool = False) -> str:
+    """Compile every source and link libsho.so (always rebuilds); with
+    sanitize, the host-sanitized libsho_asan.so instead."""
+    bdir = os.path.join(BUILD, "asan") if sanitize else BUILD
+    os.makedirs(bdir, exist_ok=True)
     t0 = time.time()
     objs = []
     procs = []
-    plan_o = os.path.join(BUILD, "sho_plan.o")
-    cmd = ["g++"] + HOST_FLAGS + ["-c", os.path.join(CSRC, "sho_plan.cpp"), "-o", plan_o]
-    procs.append((cmd, subprocess.Popen(cmd)))
-    objs.append(plan_o)
-    setup_o = os.path.join(BUILD, "sho_setup.o")
-    cmd = ["g++"] + HOST_FLAGS + ["-c", os.path.join(CSRC, "sho_setup.cpp"), "-o", setup_o]
-    procs.append((cmd, subprocess.Popen(cmd)))
-    objs.append(setup_o)
+    for src in ("sho_plan.cpp", "sho_setup.cpp"):
+        o = os.path.join(bdir, src.rsplit(".", 1)[0] + ".o")
+        if sanitize:
+            cmd = [CLANGXX] + HOST_FLAGS + SAN + ["-g", "-fno-omit-frame-pointer", "-c",
+                                                  os.path.join(CSRC, src), "-o", o]
+        else:
+            cmd = ["g++"] + HOST_FLAGS + ["-c", os.path.join(CSRC, src), "-o", o]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((cmd, subprocess.Popen(cmd)))
+        objs.append(o)
+    san_host = [f for x in SAN for f in ("-Xarch_host", x)] if sanitize else []
     for src in ("sho_api.cpp", "sho_server.cpp", "sho_kernels.hip", "sho_kernels_f32.hip"):
-        o = os.path.join(BUILD, src.rsplit(".", 1)[0] + ".o")
+        o = os.path.join(bdir, src.rsplit(".", 1)[0] + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
-        cmd = [HIPCC] + HIP_FLAGS + lang + ["-c", os.path.join(CSRC, src), "-o", o]
+        cmd = [HIPCC] + HIP_FLAGS + san_host + lang + ["-c", os.path.join(CSRC, src), "-o", o]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((cmd, subprocess.Popen(cmd)))
@@ -62,14 +77,16 @@ def build(verbose: bool = False, jobs: int = 3) -> str:
     bad = [c for c, p in procs if p.wait() != 0]
     if bad:
         raise RuntimeError("compile failed: " + " ".join(bad[0]))
-    tmp = LIB + ".tmp"
-    _run([HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs
+    lib = LIB_ASAN if sanitize else LIB
+    tmp = lib + ".tmp"
+    link_san = (SAN + ["-shared-libsan"]) if sanitize else []
+    _run([HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + link_san + objs
          + ["-Wl,-rpath,/opt/rocm/lib"], verbose)
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
     if verbose:
-        print("built %s in %.1fs" % (LIB, time.time() - t0), flush=True)
-    return LIB
+        print("built %s in %.1fs" % (lib, time.time() - t0), flush=True)
+    return lib
 
 
 if __name__ == "__main__":
-    build(verbose="-v" in sys.argv)
+    build(verbose="-v" in sys.argv, sanitize="--sanitize" in sys.argv)

@@ -66,6 +66,8 @@ struct sho_plan_s {
   bool bloch = false;         // SHO_FLAG_BLOCH: complex bands, hp.nbands counts
                               // real lanes (FP64: 2 per band; FP32: 1 pair)
   double kvec[3] = {0.0, 0.0, 0.0};  // Bloch wave vector (Bohr^-1)
+  double *d_bundle_phase = nullptr;  // Bloch plans: (cos, sin) of k.T per bundle
+  double *d_entry_phase = nullptr;   //   and per expansion block entry
   float *d_tab32 = nullptr;   // FP32 plans: the tables rounded to float
   int32_t *d_run_atom = nullptr;
   int32_t *d_row_runs = nullptr;
@@ -87,6 +89,10 @@ struct sho_plan_s {
   int64_t *d_doff = nullptr;           // per-atom offsets of the atomic matrices
   int64_t *d_desc_pbase = nullptr;     // stored plans: block descriptors -> P
   sho::BlockRec *d_blocks = nullptr;   // block form of the expansion
+  sho::BlockRec *d_pblocks = nullptr;  // block form of the projection
+  sho::EntryRec *d_pentries = nullptr;
+  uint32_t *d_prun_desc = nullptr;
+  int64_t pblk_bytes = 0;
   sho::EntryRec *d_entries = nullptr;
   uint32_t *d_run_desc = nullptr;
   int64_t blk_bytes = 0;
@@ -115,6 +121,10 @@ hipError_t upload(T **dst, const std::vector<T> &src, int64_t *bytes) {
 }
 
 void free_plan_device(sho_plan_s *p) {
+  for (double **q : {&p->d_bundle_phase, &p->d_entry_phase}) {
+    if (*q) (void)hipFree(*q);
+    *q = nullptr;
+  }
   if (p->scratch_ev) (void)hipEventDestroy(p->scratch_ev);
   p->scratch_ev = nullptr;
   if (p->d_atoms) (void)hipFree(p->d_atoms);
@@ -123,7 +133,8 @@ void free_plan_device(sho_plan_s *p) {
   if (p->d_work) (void)hipFree(p->d_work);
   if (p->d_work_proj) (void)hipFree(p->d_work_proj);
   p->d_work_proj = nullptr;
-  for (void **q : {(void **)&p->d_blocks, (void **)&p->d_entries, (void **)&p->d_run_desc}) {
+  for (void **q : {(void **)&p->d_blocks, (void **)&p->d_entries, (void **)&p->d_run_desc,
+                   (void **)&p->d_pblocks, (void **)&p->d_pentries, (void **)&p->d_prun_desc}) {
     if (*q) (void)hipFree(*q);
     *q = nullptr;
   }
@@ -163,6 +174,46 @@ void free_plan_device(sho_plan_s *p) {
 
 // (Re)uploads the schedule-dependent tables: bundles and both work-item
 // orders; regroups the items by nu.
+// Bloch plans: (cos, sin) of the phase angle k.T, T = (m_x n_x, m_y n_y,
+// m_z n_z) h for image counts m, per bundle of the projection (the image of
+// its runs) and per block entry of the expansion.
+void phase_of(const sho_plan_s *p, int64_t mx, int64_t my, int64_t mz, double *cs) {
+  const sho_grid &g = p->hp.grid;
+  double th = p->kvec[0] * ((double)(mx * g.n[0]) * g.h);
+  th += p->kvec[1] * ((double)(my * g.n[1]) * g.h);
+  th += p->kvec[2] * ((double)(mz * g.n[2]) * g.h);
+  cs[0] = std::cos(th);
+  cs[1] = std::sin(th);
+}
+
+hipError_t upload_phases(sho_plan_s *p) {
+  if (!p->bloch || (p->hp.flags & SHO_FLAG_HOST_ONLY)) return hipSuccess;
+  const sho::HostPlan &hp = p->hp;
+  std::vector<double> bph(2 * std::max<size_t>(hp.bundles.size(), 1), 0.0);
+  std::vector<int32_t> run_atom(hp.lines.size(), 0);
+  for (int32_t a = 0; a < hp.natoms; ++a)
+    for (int32_t r = hp.atoms[a].line_begin; r < hp.atoms[a].line_begin + hp.atoms[a].nlines; ++r)
+      run_atom[r] = a;
+  for (size_t b = 0; b < hp.bundles.size(); ++b) {
+    const sho::LineRec &L = hp.lines[hp.bundles[b].run0];
+    const sho::AtomRec &A = hp.atoms[run_atom[hp.bundles[b].run0]];
+    const int32_t ny = hp.grid.n[1];
+    phase_of(p, (A.ix0 + L.jx0 - L.x0m) / hp.grid.n[0], (A.iy0 + L.jy - L.row % ny) / ny,
+             (A.iz0 + L.jz - L.row / ny) / hp.grid.n[2], &bph[2 * b]);
+  }
+  std::vector<double> eph(2 * std::max<size_t>(hp.entries.size(), 1), 0.0);
+  for (size_t i = 0; i < hp.entries.size(); ++i)
+    phase_of(p, hp.entries[i].img[0], hp.entries[i].img[1], hp.entries[i].img[2], &eph[2 * i]);
+  int64_t bytes = 0;
+  for (double **q : {&p->d_bundle_phase, &p->d_entry_phase}) {
+    if (*q) (void)hipFree(*q);
+    *q = nullptr;
+  }
+  hipError_t e = upload(&p->d_bundle_phase, bph, &bytes);
+  if (e == hipSuccess) e = upload(&p->d_entry_phase, eph, &bytes);
+  return e;
+}
+
 hipError_t upload_schedule(sho_plan_s *p) {
   for (void **q : {(void **)&p->d_bundles, (void **)&p->d_work, (void **)&p->d_work_proj}) {
     if (*q) (void)hipFree(*q);
@@ -187,7 +238,7 @@ hipError_t upload_schedule(sho_plan_s *p) {
     p->groups.push_back(g);
   }
   p->sched_version++;
-  return hipSuccess;
+  return upload_phases(p);
 }
 
 // (Re)uploads the block tables of the expansion.
@@ -208,6 +259,22 @@ hipError_t upload_blocks(sho_plan_s *p) {
       (e = upload(&p->d_run_desc, p->hp.run_desc, &bytes)) != hipSuccess)
     return e;
   if (stored && (e = upload(&p->d_desc_pbase, p->hp.desc_pbase, &bytes)) != hipSuccess)
+    return e;
+  return upload_phases(p);
+}
+
+// (Re)uploads the block tables of the projection's block form.
+hipError_t upload_pblocks(sho_plan_s *p) {
+  for (void **q : {(void **)&p->d_pblocks, (void **)&p->d_pentries, (void **)&p->d_prun_desc}) {
+    if (*q) (void)hipFree(*q);
+    *q = nullptr;
+  }
+  int64_t &bytes = p->pblk_bytes;
+  bytes = 0;
+  hipError_t e;
+  if ((e = upload(&p->d_pblocks, p->hp.pblk.blocks, &bytes)) != hipSuccess ||
+      (e = upload(&p->d_pentries, p->hp.pblk.entries, &bytes)) != hipSuccess ||
+      (e = upload(&p->d_prun_desc, p->hp.pblk.run_desc, &bytes)) != hipSuccess)
     return e;
   return hipSuccess;
 }
@@ -252,14 +319,11 @@ sho::KArgs make_args(const sho_plan_s *p, const Group &g) {
   K.tb_shift = p->hp.tb_shift;
   K.ntiles = (p->hp.nbands + (1 << K.tb_shift) - 1) >> K.tb_shift;
   K.det = (p->hp.flags & SHO_FLAG_DETERMINISTIC) ? 1 : 0;
-  K.ny = p->hp.grid.n[1];
-  K.nz = p->hp.grid.n[2];
   K.bloch = p->bloch ? 1 : 0;
   const double h = p->hp.grid.h;
   K.h3 = h * h * h;
   K.alpha = 1.0;
-  K.h = h;
-  for (int d = 0; d < 3; ++d) K.k[d] = p->kvec[d];
+  K.bundle_phase = p->d_bundle_phase;
   return K;
 }
 
@@ -300,8 +364,7 @@ sho::EArgs make_eargs(const sho_plan_s *p) {
   E.natoms_u2 = (int32_t)p->hp.nu_atoms.size();
   E.nx = p->hp.grid.n[0];
   E.B = p->hp.nbands;
-  E.tbe_shift = sho::expand_tile_shift(p->hp.nbands, p->hp.expand_mode,
-                                       (p->hp.flags & SHO_FLAG_STORED) != 0);
+  E.tbe_shift = sho::plan_expand_shift(p->hp);
   E.desc_pbase = p->d_desc_pbase;
   E.P = p->d_stored;
   E.ntiles = (p->hp.nbands + (1 << E.tbe_shift) - 1) >> E.tbe_shift;
@@ -315,11 +378,9 @@ sho::EArgs make_eargs(const sho_plan_s *p) {
   E.blk_x = p->hp.blk_x;
   E.ny = p->hp.grid.n[1];
   E.ncol = p->hp.ncols;
-  E.nz = p->hp.grid.n[2];
   E.bloch = p->bloch ? 1 : 0;
   E.alpha = 1.0;
-  E.h = p->hp.grid.h;
-  for (int d = 0; d < 3; ++d) E.k[d] = p->kvec[d];
+  E.entry_phase = p->d_entry_phase;
   for (int nu = 0; nu <= SHO_NU_MAX + 1; ++nu) E.nu_begin[nu] = 0;
   {
     int nu = 0;
@@ -329,6 +390,21 @@ sho::EArgs make_eargs(const sho_plan_s *p) {
       while (nu <= cur && nu <= SHO_NU_MAX + 1) E.nu_begin[nu++] = (int32_t)i;
     }
   }
+  return E;
+}
+
+// Arguments of the projection's block form: the expansion's, with the
+// projection's block tables and band tile.
+sho::EArgs make_peargs(const sho_plan_s *p) {
+  sho::EArgs E = make_eargs(p);
+  E.blocks = p->d_pblocks;
+  E.entries = p->d_pentries;
+  E.run_desc = p->d_prun_desc;
+  E.nblocks = (int32_t)p->hp.pblk.blocks.size();
+  E.blk_rows = p->hp.pblk.rows;
+  E.blk_x = p->hp.pblk.x;
+  E.tbe_shift = p->hp.pblk_tb_shift;
+  E.ntiles = (p->hp.nbands + (1 << E.tbe_shift) - 1) >> E.tbe_shift;
   return E;
 }
 
@@ -461,11 +537,23 @@ hipError_t run_project(sho_plan_s *p, const void *psi_v, void *c_v, hipStream_t 
   // atoms whose support missed the grid entirely keep zero coefficients;
   // atoms shared by several work items (and every stored point chunk) are
   // summed into zeroed coefficients
-  bool zero = p->hp.any_split || (p->hp.flags & SHO_FLAG_STORED);
+  const bool blocks = p->hp.proj_form == sho::kProjectBlocks;
+  bool zero = (p->hp.any_split && !blocks) || (p->hp.flags & SHO_FLAG_STORED);
   for (const auto &A : p->hp.atoms) zero |= (A.npoints == 0);
   if (zero) {
     hipError_t e = sho::launch_fill(c, p->hp.coeff_rows * p->hp.nbands, 0.0, s);
     if (e != hipSuccess) return e;
+  }
+  if (blocks) {
+    // the plane sums go through the plan's plane-partial scratch
+    return timed(p, prof, SHO_KERNEL_PROJECT, s, [&]() {
+      const sho::EArgs E = make_peargs(p);
+      hipError_t e1 = sho::launch_fill(p->d_u2, p->hp.u2_doubles, 0.0, s);
+      if (e1 == hipSuccess) e1 = sho::launch_project_blocks(E, psi, p->d_u2, s);
+      const double h = p->hp.grid.h;
+      if (e1 == hipSuccess) e1 = sho::launch_zpass(E, p->d_u2, c, h * h * h, s);
+      return e1;
+    });
   }
   return timed(p, prof, SHO_KERNEL_PROJECT, s, [&]() {
     if (p->hp.flags & SHO_FLAG_STORED) {
@@ -596,6 +684,16 @@ hipError_t run_expand(sho_plan_s *p, const void *c_v, void *psi_v, hipStream_t s
           return sho::launch_rows(E, u2_buf, psi, s);
       }
     });
+  return e;
+}
+
+// run_project with the block form's plane sums in the plan's own scratch,
+// ordered against the scratch's other users (the item form uses none).
+hipError_t run_project_own(sho_plan_s *p, const void *psi, void *c, hipStream_t s, bool prof) {
+  if (p->hp.proj_form != sho::kProjectBlocks) return run_project(p, psi, c, s, prof);
+  hipError_t e = scratch_acquire(p, s);
+  if (e == hipSuccess) e = run_project(p, psi, c, s, prof);
+  if (e == hipSuccess) e = scratch_release(p, s);
   return e;
 }
 
@@ -969,7 +1067,13 @@ sho_status sho_plan_set_kpoint(sho_plan_t p, const double *k) {
   if (!p->bloch) return fail(SHO_E_INVALID, "not a Bloch plan (SHO_FLAG_BLOCH)");
   for (int d = 0; d < 3; ++d)
     if (!std::isfinite(k[d])) return fail(SHO_E_INVALID, "k must be finite");
+  if (!(p->hp.flags & SHO_FLAG_HOST_ONLY)) {
+    hipError_t e = hipDeviceSynchronize();  // queued work reads the phase tables
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+  }
   for (int d = 0; d < 3; ++d) p->kvec[d] = k[d];
+  hipError_t e = upload_phases(p);
+  if (e != hipSuccess) return hip_fail(e, "phase upload");
   p->sched_version++;  // graphs captured with the previous k are refused
   return SHO_OK;
 }
@@ -1008,7 +1112,7 @@ sho_status sho_plan_project(sho_plan_t p, const double *psi, double *c,
                             void *stream) {
   sho_status st = check_project(p, psi, c);
   if (st != SHO_OK || p->hp.coeff_rows == 0) return st;
-  hipError_t e = run_project(p, psi, c, (hipStream_t)stream, p->prof_on);
+  hipError_t e = run_project_own(p, psi, c, (hipStream_t)stream, p->prof_on);
   if (e != hipSuccess) return hip_fail(e, "project launch");
   return SHO_OK;
 }
@@ -1156,6 +1260,62 @@ sho_status sho_plan_get_schedule(sho_plan_t p, int32_t *schedule, int32_t *band_
   return SHO_OK;
 }
 
+sho_status sho_plan_set_project(sho_plan_t p, int32_t form, int32_t block_rows,
+                                int32_t block_x, int32_t band_tile) {
+  if (!p) return fail(SHO_E_INVALID, "NULL plan");
+  if (form != sho::kProjectItems && form != sho::kProjectBlocks)
+    return fail(SHO_E_INVALID, "unknown projection form");
+  if (form == sho::kProjectBlocks &&
+      ((p->hp.flags & (SHO_FLAG_STORED | SHO_FLAG_PER_ATOM | SHO_FLAG_DETERMINISTIC)) ||
+       p->fp32 || p->bloch))
+    return fail(SHO_E_INVALID, "the block form of the projection is for FP64 plans of real "
+                               "bands without SHO_FLAG_STORED, _PER_ATOM, _DETERMINISTIC");
+  const bool dev = !(p->hp.flags & SHO_FLAG_HOST_ONLY);
+  if (form == sho::kProjectItems) {
+    p->hp.proj_form = form;
+    p->sched_version++;
+    return SHO_OK;
+  }
+  int tbs = -1;
+  const int tb = band_tile ? band_tile : 16;
+  for (int k = 3; k <= 6; ++k)
+    if ((1 << k) == tb) tbs = k;
+  if (tbs < 0) return fail(SHO_E_INVALID, "band_tile must be 0, 8, 16, 32 or 64");
+  const int32_t X = block_x ? block_x : 32;
+  if (X < 1 || X > 255) return fail(SHO_E_INVALID, "block_x outside 1..255");
+  const int64_t per_row = (int64_t)sho::pow2_ceil(X) << tbs;
+  const int32_t R = block_rows ? block_rows
+                               : (int32_t)std::min<int64_t>(255, sho::kProjTileDoubles / per_row);
+  if (R < 1 || R > 255 || R * per_row > sho::kProjTileDoubles)
+    return fail(SHO_E_INVALID, "block of rows x points x band tile exceeds 8192 values");
+  if (dev) {
+    hipError_t e = hipDeviceSynchronize();  // the old tables may be in use
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+  }
+  sho::build_block_set(&p->hp, R, X, &p->hp.pblk);
+  p->hp.pblk_tb_shift = tbs;
+  if (dev) {
+    hipError_t e = upload_pblocks(p);
+    if (e != hipSuccess) return hip_fail(e, "block upload");
+    sho_status st = ensure_u2(p);
+    if (st != SHO_OK) return st;
+  }
+  p->hp.proj_form = form;
+  p->sched_version++;
+  return SHO_OK;
+}
+
+sho_status sho_plan_get_project(sho_plan_t p, int32_t *form, int32_t *block_rows,
+                                int32_t *block_x, int32_t *band_tile) {
+  if (!p || !form || !block_rows || !block_x || !band_tile)
+    return fail(SHO_E_INVALID, "NULL argument");
+  *form = p->hp.proj_form;
+  *block_rows = p->hp.pblk.rows;
+  *block_x = p->hp.pblk.x;
+  *band_tile = p->hp.pblk.rows ? 1 << p->hp.pblk_tb_shift : 0;
+  return SHO_OK;
+}
+
 sho_status sho_plan_set_expand(sho_plan_t p, int32_t mode, int32_t block_rows,
                                int32_t block_x) {
   if (!p) return fail(SHO_E_INVALID, "NULL plan");
@@ -1214,6 +1374,129 @@ sho_status sho_plan_get_expand(sho_plan_t p, int32_t *mode, int32_t *block_rows,
   return SHO_OK;
 }
 
+sho_status sho_plan_set_expand_tile(sho_plan_t p, int32_t band_tile) {
+  if (!p) return fail(SHO_E_INVALID, "NULL plan");
+  if (p->hp.flags & SHO_FLAG_STORED)
+    return fail(SHO_E_INVALID, "stored plans keep their matrix-core band tile");
+  int tbs = -1;
+  for (int k = 3; k <= 6; ++k)
+    if ((1 << k) == band_tile) tbs = k;
+  if (band_tile != 0 && tbs < 0)
+    return fail(SHO_E_INVALID, "band_tile must be 0, 8, 16, 32 or 64");
+  const bool dev = !(p->hp.flags & SHO_FLAG_HOST_ONLY);
+  if (dev) {
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+  }
+  p->hp.expand_tbe_shift = tbs;
+  if (p->hp.expand_mode == sho::kExpandBlocks) {
+    int32_t R = 0, X = 0;
+    sho::default_block_shape(p->hp, &R, &X);
+    sho::build_blocks(&p->hp, R, X);
+    if (dev) {
+      hipError_t e = upload_blocks(p);
+      if (e != hipSuccess) return hip_fail(e, "block upload");
+    }
+  }
+  p->sched_version++;
+  return SHO_OK;
+}
+
+sho_status sho_plan_get_expand_tile(sho_plan_t p, int32_t *band_tile) {
+  if (!p || !band_tile) return fail(SHO_E_INVALID, "NULL argument");
+  *band_tile = 1 << sho::block_tile_shift(p->hp);
+  return SHO_OK;
+}
+
+sho_status sho_plan_tune_expand(sho_plan_t p, const void *c, void *psi, int32_t reps,
+                                void *stream, sho_tune_expand_result *result) {
+  sho_status st = check_project(p, psi, c, -1);
+  if (st != SHO_OK) return st;
+  if (reps < 1 || reps > 1000) return fail(SHO_E_INVALID, "reps outside 1..1000");
+  if (p->hp.flags & (SHO_FLAG_STORED | SHO_FLAG_PER_ATOM | SHO_FLAG_DETERMINISTIC))
+    return fail(SHO_E_INVALID, "stored, per-atom and deterministic plans have fixed forms");
+  if ((st = ensure_u2(p)) != SHO_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  struct Cand {
+    int32_t mode, tbs, R, X;
+  };
+  std::vector<Cand> cands;
+  int nb_shift = 3;
+  while ((1 << nb_shift) < p->hp.nbands && nb_shift < 6) ++nb_shift;
+  const int32_t nfp = sho::table_nfp(p->hp.nu_max);
+  for (int32_t tbs = 3; tbs <= nb_shift; ++tbs) {
+    const int32_t keep = p->hp.expand_tbe_shift;
+    p->hp.expand_tbe_shift = tbs;
+    int32_t R = 0, X = 0;
+    sho::default_block_shape(p->hp, &R, &X);
+    for (const auto &rx : {std::make_pair(R, X), std::make_pair(std::max(1, R / 2), X),
+                           std::make_pair(R, std::max(1, X / 2)),
+                           std::make_pair(std::min(256 / nfp, 2 * R), std::max(1, X / 2))})
+      if (sho::block_shape_ok(p->hp, rx.first, rx.second))
+        cands.push_back({sho::kExpandBlocks, tbs, rx.first, rx.second});
+    p->hp.expand_tbe_shift = keep;
+  }
+  if (!p->fp32 && !p->bloch) cands.push_back({sho::kExpandRows, -1, 0, 0});
+  hipEvent_t ea = nullptr, eb = nullptr;
+  hipError_t e = hipEventCreate(&ea);
+  if (e == hipSuccess) e = hipEventCreate(&eb);
+  auto time_current = [&](double *ms) -> hipError_t {
+    hipError_t e1 = run_expand_own(p, c, psi, s, false);  // warm-up
+    if (e1 == hipSuccess) e1 = hipEventRecord(ea, s);
+    for (int r = 0; r < reps && e1 == hipSuccess; ++r) e1 = run_expand_own(p, c, psi, s, false);
+    if (e1 == hipSuccess) e1 = hipEventRecord(eb, s);
+    if (e1 == hipSuccess) e1 = hipEventSynchronize(eb);
+    float t = 0.f;
+    if (e1 == hipSuccess) e1 = hipEventElapsedTime(&t, ea, eb);
+    *ms = (double)t / reps;
+    return e1;
+  };
+  const Cand before{p->hp.expand_mode, p->hp.expand_tbe_shift, p->hp.blk_rows, p->hp.blk_x};
+  double ms_before = 0.0;
+  if (e == hipSuccess) e = time_current(&ms_before);
+  double best = ms_before;
+  Cand pick = before;
+  int32_t tried = 1;
+  auto apply = [&](const Cand &cd) -> hipError_t {
+    hipError_t e1 = hipStreamSynchronize(s);
+    if (e1 != hipSuccess) return e1;
+    p->hp.expand_mode = cd.mode;
+    p->hp.expand_tbe_shift = cd.tbs;
+    if (cd.mode == sho::kExpandBlocks) {
+      sho::build_blocks(&p->hp, cd.R, cd.X);
+      e1 = upload_blocks(p);
+    }
+    return e1;
+  };
+  for (const Cand &cd : cands) {
+    if (e != hipSuccess) break;
+    if ((e = apply(cd)) != hipSuccess) break;
+    double ms = 0.0;
+    if ((e = time_current(&ms)) != hipSuccess) break;
+    ++tried;
+    if (ms < best) {
+      best = ms;
+      pick = cd;
+    }
+  }
+  if (ea) (void)hipEventDestroy(ea);
+  if (eb) (void)hipEventDestroy(eb);
+  if (e != hipSuccess) return hip_fail(e, "tuning");
+  if ((e = apply(pick)) != hipSuccess) return hip_fail(e, "expansion form upload");
+  p->sched_version++;
+  if (result) {
+    result->mode = pick.mode;
+    result->band_tile = 1 << sho::plan_expand_shift(p->hp);
+    result->block_rows = p->hp.blk_rows;
+    result->block_x = p->hp.blk_x;
+    result->ms = best;
+    result->ms_before = ms_before;
+    result->candidates = tried;
+    result->pad = 0;
+  }
+  return SHO_OK;
+}
+
 sho_status sho_plan_tune(sho_plan_t p, const void *psi, void *c, int32_t reps,
                          void *stream, sho_tune_result *result) {
   sho_status st = check_project(p, psi, c, -1);
@@ -1221,6 +1504,9 @@ sho_status sho_plan_tune(sho_plan_t p, const void *psi, void *c, int32_t reps,
   if (reps < 1 || reps > 1000) return fail(SHO_E_INVALID, "reps outside 1..1000");
   if (p->hp.flags & (SHO_FLAG_STORED | SHO_FLAG_PER_ATOM))
     return fail(SHO_E_INVALID, "stored and per-atom plans have a fixed schedule");
+  const bool blocks_ok =
+      !(p->hp.flags & SHO_FLAG_DETERMINISTIC) && !p->fp32 && !p->bloch;
+  if (blocks_ok && (st = ensure_u2(p)) != SHO_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   struct Cand {
     int32_t sched, tbs;
@@ -1235,6 +1521,7 @@ sho_status sho_plan_tune(sho_plan_t p, const void *psi, void *c, int32_t reps,
       for (int32_t tb = tb0; tb >= std::max(tb_min, tb0 - 1); --tb) cands.push_back({sc, tb, tp});
   }
   const Cand before{p->hp.sched, tb0, p->hp.target_points};
+  const int32_t form0 = p->hp.proj_form;
   hipEvent_t ea = nullptr, eb = nullptr;
   hipError_t e = hipEventCreate(&ea);
   if (e == hipSuccess) e = hipEventCreate(&eb);
@@ -1249,14 +1536,17 @@ sho_status sho_plan_tune(sho_plan_t p, const void *psi, void *c, int32_t reps,
     *ms = (double)t / reps;
     return e1;
   };
-  double best = 1e300, ms_before = 0.0;
-  Cand pick = before;
+  double ms_before = 0.0;
   if (e == hipSuccess) e = time_current(&ms_before);
-  best = ms_before;
+  // item form: schedules x item sizes x band tiles
+  p->hp.proj_form = sho::kProjectItems;
+  double best = form0 == sho::kProjectItems ? ms_before : 1e300;
+  Cand pick = before;
   int32_t tried = 1;
   for (const Cand &cd : cands) {
     if (e != hipSuccess) break;
-    if (cd.sched == before.sched && cd.tbs == before.tbs && cd.target == before.target)
+    if (form0 == sho::kProjectItems && cd.sched == before.sched && cd.tbs == before.tbs &&
+        cd.target == before.target)
       continue;
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) break;
@@ -1270,19 +1560,59 @@ sho_status sho_plan_tune(sho_plan_t p, const void *psi, void *c, int32_t reps,
       pick = cd;
     }
   }
+  // block form: band tile x block width (rows: as many as the tile holds)
+  struct BCand {
+    int32_t tbs, x;
+  };
+  BCand bpick{0, 0};
+  double bbest = 1e300;
+  if (blocks_ok) {
+    for (const BCand &bc : {BCand{4, 32}, BCand{3, 32}, BCand{5, 16}, BCand{4, 16}, BCand{3, 64}}) {
+      if (e != hipSuccess) break;
+      if ((1 << bc.tbs) > 2 * std::max<int32_t>(p->hp.nbands, 8)) continue;
+      e = hipStreamSynchronize(s);
+      if (e != hipSuccess) break;
+      const int64_t per_row = (int64_t)sho::pow2_ceil(bc.x) << bc.tbs;
+      sho::build_block_set(&p->hp, (int32_t)std::min<int64_t>(255, sho::kProjTileDoubles / per_row),
+                           bc.x, &p->hp.pblk);
+      p->hp.pblk_tb_shift = bc.tbs;
+      if ((e = upload_pblocks(p)) != hipSuccess) break;
+      p->hp.proj_form = sho::kProjectBlocks;
+      double ms = 0.0;
+      e = time_current(&ms);
+      p->hp.proj_form = sho::kProjectItems;
+      if (e != hipSuccess) break;
+      ++tried;
+      if (ms < bbest) {
+        bbest = ms;
+        bpick = bc;
+      }
+    }
+  }
   if (ea) (void)hipEventDestroy(ea);
   if (eb) (void)hipEventDestroy(eb);
   if (e != hipSuccess) return hip_fail(e, "tuning");
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "tuning");
   sho::build_work(&p->hp, pick.tbs, pick.target, pick.sched);
   if ((e = upload_schedule(p)) != hipSuccess) return hip_fail(e, "schedule upload");
+  const bool use_blocks = bbest < best;
+  if (use_blocks) {
+    const int64_t per_row = (int64_t)sho::pow2_ceil(bpick.x) << bpick.tbs;
+    sho::build_block_set(&p->hp, (int32_t)std::min<int64_t>(255, sho::kProjTileDoubles / per_row),
+                         bpick.x, &p->hp.pblk);
+    p->hp.pblk_tb_shift = bpick.tbs;
+    if ((e = upload_pblocks(p)) != hipSuccess) return hip_fail(e, "block upload");
+    p->hp.proj_form = sho::kProjectBlocks;
+  }
+  p->sched_version++;
   if (result) {
     result->schedule = pick.sched;
     result->band_tile = 1 << pick.tbs;
     result->target_points = pick.target;
-    result->ms = best;
+    result->ms = use_blocks ? bbest : best;
     result->ms_before = ms_before;
     result->candidates = tried;
+    result->project_form = use_blocks ? sho::kProjectBlocks : sho::kProjectItems;
   }
   return SHO_OK;
 }
@@ -1338,7 +1668,7 @@ sho_status sho_plan_apply(sho_plan_t p, const double *psi, const double *D, doub
   if (st != SHO_OK || p->hp.coeff_rows == 0) return st;
   if ((st = ensure_u2(p)) != SHO_OK) return st;
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e = run_project(p, psi, c, s, p->prof_on);
+  hipError_t e = run_project_own(p, psi, c, s, p->prof_on);
   if (e == hipSuccess) e = run_multiply(p, D, c, d, s);
   if (e == hipSuccess) e = run_expand_own(p, d, out, s, p->prof_on);
   if (e != hipSuccess) return hip_fail(e, "apply launch");

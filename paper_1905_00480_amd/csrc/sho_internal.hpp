@@ -150,6 +150,17 @@ constexpr int kBlockTileDoubles = 4096;  // LDS tile of a block workgroup
 // Rows handled by one expansion workgroup.
 constexpr int kRowsPerGroup = 1;
 
+// Blocks of R rows x X points of one plane with their entries (atom plane,
+// image) and run descriptors: the work of the block forms.
+struct BlockSet {
+  int32_t rows = 0, x = 0;
+  int64_t points = 0;                 // grid points inside the blocks
+  std::vector<BlockRec> blocks;       // XCD-interleaved by plane
+  std::vector<EntryRec> entries;
+  std::vector<uint32_t> run_desc;
+  std::vector<int32_t> run_desc_run;  // the run of every descriptor
+};
+
 // Host-side plan contents (built without any device call).
 // A chunk of one atom's stored points [k0, k1) (stored-projector kernels).
 struct StoredItem {
@@ -194,6 +205,8 @@ struct HostPlan {
   std::vector<int32_t> nu_atoms;       // atoms with a support, sorted by nu
   int64_t u2_doubles = 0;
   int32_t expand_mode = kExpandBlocks;
+  int32_t expand_tbe_shift = -1;        // block form: log2(bands per tile),
+                                        // -1: the default rule
   int32_t blk_rows = 0, blk_x = 0;      // block shape of the block form
   int64_t block_points = 0;             // grid points inside the blocks
   std::vector<BlockRec> blocks;         // XCD-interleaved by plane
@@ -201,6 +214,9 @@ struct HostPlan {
   std::vector<uint32_t> run_desc;
   std::vector<int32_t> run_desc_run;    // the run of every descriptor
   std::vector<int64_t> desc_pbase;      // stored plans: P double of block x 0
+  int32_t proj_form = 0;                // kProjectItems or kProjectBlocks
+  int32_t pblk_tb_shift = 0;            // log2(bands per lane slot), block form
+  BlockSet pblk;                        // the projection's block form
   std::vector<int64_t> run_poff;      // stored projectors: first double of
                                       // each run's [len][N_SHO] block
   std::vector<int64_t> atom_poff;     // [natoms+1] first double of each atom
@@ -298,6 +314,16 @@ void build_rows(HostPlan *P);
 // Blocks of R rows x X points for the block form of the expansion (needs
 // build_rows for run_atom).
 void build_blocks(HostPlan *P, int32_t R, int32_t X);
+void build_block_set(const HostPlan *P, int32_t R, int32_t X, BlockSet *out);
+
+// Projection forms: work items of atoms (the run bundles of an atom streamed
+// by one workgroup), or blocks of the grid (each block of psi read once,
+// every atom plane touching it adds its share of the plane sums).
+constexpr int32_t kProjectItems = 0;
+constexpr int32_t kProjectBlocks = 1;
+// LDS tile of a projection block (no write-back, so larger than the
+// expansion's).
+constexpr int kProjTileDoubles = 8192;
 
 // log2 of the bands per lane slot of the expansion's y/x passes: the row form
 // takes 32 or 64; the block form also 8 or 16, so that few bands still fill
@@ -308,6 +334,20 @@ inline int expand_tile_shift(int nbands, int mode, bool stored = false) {
   if (nbands > 32) return 6;
   if (mode == kExpandRows || nbands > 16) return 5;
   return nbands > 8 ? 4 : 3;
+}
+
+// log2 of the band tile of the expansion's block form for plan P: the
+// plan's setting (sho_plan_set_expand_tile) or the default rule.
+inline int block_tile_shift(const HostPlan &P) {
+  const bool stored = (P.flags & SHO_FLAG_STORED) != 0;
+  if (!stored && P.expand_tbe_shift >= 0) return P.expand_tbe_shift;
+  return expand_tile_shift(P.nbands, kExpandBlocks, stored);
+}
+
+// log2 of the band tile of the plan's current expansion form.
+inline int plan_expand_shift(const HostPlan &P) {
+  if (P.expand_mode == kExpandBlocks) return block_tile_shift(P);
+  return expand_tile_shift(P.nbands, P.expand_mode, (P.flags & SHO_FLAG_STORED) != 0);
 }
 
 // Values (bands, or band pairs of SHO_FLAG_FP32 plans, which accumulate
@@ -327,8 +367,7 @@ inline int32_t pow2_ceil(int32_t X) {
 // the row stride of the block kernel's tile, per band tile) and the x-table
 // staging of one wave (X rows of the widest table).
 inline bool block_shape_ok(const HostPlan &P, int32_t R, int32_t X) {
-  const int tbe = 1 << expand_tile_shift(P.nbands, kExpandBlocks,
-                                         (P.flags & SHO_FLAG_STORED) != 0);
+  const int tbe = 1 << block_tile_shift(P);
   return R >= 1 && X >= 1 && X <= 256 &&
          (int64_t)R * pow2_ceil(X) * tbe <= block_tile_values(P) &&
          X * table_nfp(P.nu_max) <= 256 && R * table_nfp(P.nu_max) <= 256;
@@ -345,8 +384,7 @@ inline bool owner_width_ok(int32_t X) { return X == 16 || X == 32; }
 // 16 for 64-band tiles), then as many rows as the tile holds and the y
 // staging allows.
 inline void default_block_shape(const HostPlan &P, int32_t *R, int32_t *X) {
-  const int tbe = 1 << expand_tile_shift(P.nbands, kExpandBlocks,
-                                         (P.flags & SHO_FLAG_STORED) != 0);
+  const int tbe = 1 << block_tile_shift(P);
   const int nfp = table_nfp(P.nu_max);
   *X = std::min(256 / nfp, tbe == 64 ? 16 : 32);
   *R = std::min(block_tile_values(P) / (*X * tbe), 256 / nfp);

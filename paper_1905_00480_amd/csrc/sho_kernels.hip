@@ -28,6 +28,7 @@
 
 #include <mutex>
 
+#include "sho_device.hpp"
 #include "sho_launch.hpp"
 
 namespace sho {
@@ -40,28 +41,6 @@ constexpr int kBatch = 8;  // loads in flight per lane and batch
 
 // waves per SIMD the register allocator must allow (4 keeps <= 128 VGPRs)
 constexpr int waves_per_eu(int nf) { return nf <= 6 ? 4 : 2; }
-
-// Read-only data that every lane of a wave reads at the same address goes
-// through the constant address space, i.e. scalar loads.
-template <typename T>
-using cptr = const __attribute__((address_space(4))) T *;
-
-template <typename T>
-__device__ inline cptr<T> as_const(const T *p) {
-  return (cptr<T>)p;
-}
-
-// Copies a record that all lanes read at the same address (scalar loads).
-template <typename T>
-__device__ inline T load_uniform(const T *p) {
-  static_assert(sizeof(T) % 4 == 0, "record size");
-  T out;
-  const cptr<uint32_t> src = (cptr<uint32_t>)p;
-  uint32_t *dst = reinterpret_cast<uint32_t *>(&out);
-#pragma unroll
-  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) dst[i] = src[i];
-  return out;
-}
 
 // dst[t] = value(t) for t < count, with U global loads in flight per thread
 // (all loads of a round are issued before the first LDS write waits).
@@ -146,9 +125,6 @@ __device__ inline Lanes lane_geometry(const KArgs &K, int tile) {
   return L;
 }
 
-__device__ inline int wave_id() {
-  return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-}
 
 // The run a lane streams in the current bundle.  Slots beyond the bundle's
 // run count mirror its last run (valid addresses) and contribute nothing.
@@ -158,23 +134,10 @@ struct RunState {
   int len;
   int jy;
   bool active;
-  double pc, ps;       // Bloch plans: cos, sin of k.T for the run's image T
 };
 
-// Phase angle k.T of a run of atom A: T = unwrapped minus memory position
-// of its points (a lattice translation), per axis (i - (i mod n)) h.
-__device__ inline double run_angle(const KArgs &K, const AtomRec &A, const LineRec &ln) {
-  const int ym = ln.row % K.ny, zm = ln.row / K.ny;
-  double th = K.k[0] * ((double)(A.ix0 + ln.jx0 - ln.x0m) * K.h);
-  th += K.k[1] * ((double)(A.iy0 + ln.jy - ym) * K.h);
-  th += K.k[2] * ((double)(A.iz0 + ln.jz - zm) * K.h);
-  return th;
-}
-
-template <bool CPLX = false>
 __device__ inline RunState run_state(const KArgs &K, const Lanes &L,
-                                     const double *psi, const BundleRec &bd,
-                                     const AtomRec *A = nullptr) {
+                                     const double *psi, const BundleRec &bd) {
   const int s = min(L.slot, bd.nruns - 1);
   const LineRec ln = K.lines[bd.run0 + s];
   RunState r;
@@ -183,7 +146,6 @@ __device__ inline RunState run_state(const KArgs &K, const Lanes &L,
   r.len = ln.len;
   r.jy = ln.jy;
   r.active = L.slot < bd.nruns;
-  if constexpr (CPLX) sincos(run_angle(K, *A, ln), &r.ps, &r.pc);
   return r;
 }
 
@@ -267,7 +229,7 @@ __device__ inline void project_bundles(const KArgs &K, const AtomRec &A,
   for (int q = 0; q < NP; ++q) T2[q] = 0.0;
   int cur_jz = -1;
   BundleRec bd = load_uniform(K.bundles + b0);
-  RunState rs = run_state<CPLX>(K, L, psi, bd, &A);
+  RunState rs = run_state(K, L, psi, bd);
   double v[kBatch];
   load_batch(K, rs, bd.jlo, v);
   for (int bi = b0; bi < b1; ++bi) {
@@ -286,7 +248,7 @@ __device__ inline void project_bundles(const KArgs &K, const AtomRec &A,
         load_batch(K, rs, jb + kBatch, w);
       } else if (bi + 1 < b1) {
         nbd = load_uniform(K.bundles + bi + 1);
-        nrs = run_state<CPLX>(K, L, psi, nbd, &A);
+        nrs = run_state(K, L, psi, nbd);
         load_batch(K, nrs, nbd.jlo, w);
       } else {
 #pragma unroll
@@ -308,10 +270,13 @@ __device__ inline void project_bundles(const KArgs &K, const AtomRec &A,
       for (int u = 0; u < kBatch; ++u) v[u] = w[u];
     }
     if constexpr (CPLX) {
-      // the run's image carries e^{+i k.T}
-      const double sg = (L.bl & 1) ? rs.ps : -rs.ps;
+      // the bundle's runs share one periodic image T, which carries e^{+i k.T}
+      // (cos, sin from the plan's table: scalar loads)
+      const cptr<double> ph = as_const(K.bundle_phase) + 2 * bi;
+      const double pc = ph[0], ps = ph[1];
+      const double sg = (L.bl & 1) ? ps : -ps;
 #pragma unroll
-      for (int n = 0; n < NF; ++n) T1[n] = rotate_pair(T1[n], rs.pc, sg);
+      for (int n = 0; n < NF; ++n) T1[n] = rotate_pair(T1[n], pc, sg);
     }
     // y pass with this lane's run
     const double *fy = ty + rs.jy * nfp;
@@ -697,7 +662,7 @@ constexpr int kBlkXStage = 256;  // doubles per wave: the x-table rows of a bloc
 constexpr int blk_group(int nu, int numax) { return (numax > 5 && nu <= 5) ? 4 : 2; }
 
 template <int NU, int NUMAX, bool CPLX>
-__device__ inline void add_entry(const EArgs &E, const EntryRec &en, const double *u2,
+__device__ inline void add_entry(const EArgs &E, const EntryRec &en, int ei, const double *u2,
                                  int nxl, double *tile, double *xstage, int TB, int slot,
                                  int bl, int bc) {
   constexpr int NF = NU + 1;
@@ -714,11 +679,9 @@ __device__ inline void add_entry(const EArgs &E, const EntryRec &en, const doubl
   for (int q = 0; q < NP; ++q) u2v[q] = ub[(int64_t)q * E.B];
   if constexpr (CPLX) {
     // the entry's image T receives e^{-i k.T} times the plane partials
-    double th = E.k[0] * ((double)(en.img[0] * E.nx) * E.h);
-    th += E.k[1] * ((double)(en.img[1] * E.ny) * E.h);
-    th += E.k[2] * ((double)(en.img[2] * E.nz) * E.h);
-    double sn, cs;
-    sincos(th, &sn, &cs);
+    // (cos, sin from the plan's table: scalar loads)
+    const cptr<double> ph = as_const(E.entry_phase) + 2 * ei;
+    const double cs = ph[0], sn = ph[1];
     const double sg = (bl & 1) ? -sn : sn;
 #pragma unroll
     for (int q = 0; q < NP; ++q) u2v[q] = rotate_pair(u2v[q], cs, sg);
@@ -839,7 +802,8 @@ __global__ __launch_bounds__(kBlkBlock) void k_expand_blocks(EArgs E,
 #define X(N)                                                                          \
   case N:                                                                             \
     if constexpr (N <= NUMAX)                                                         \
-      add_entry<N, NUMAX, CPLX>(E, en, u2, 1 << x2s, tile, xstage, TB, lslot, bl, bc); \
+      add_entry<N, NUMAX, CPLX>(E, en, bk.entry_begin + i, u2, 1 << x2s, tile, xstage, TB, \
+                                lslot, bl, bc);                                     \
     break;
       X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10)
 #undef X
@@ -864,6 +828,170 @@ __global__ __launch_bounds__(kBlkBlock) void k_expand_blocks(EArgs E,
       const int t = t0 + u * kBlkBlock + (int)threadIdx.x;
       int64_t g = 0;
       if (t < nval && slot(gb, t, g)) psi[g] = v[u];
+    }
+  }
+}
+
+// ------------------------------------------------ projection by blocks --
+
+// Block form of the projection, for plans whose supports overlap much: one
+// workgroup per (block of R rows x X points of one plane, band tile) reads
+// the block's values of psi into LDS once, and every entry (atom plane,
+// image) touching the block adds its share of the atom plane's sums,
+//   T2[nx][ny] = sum_{rows y} phi_ny(y) sum_x phi_nx(x) psi(x, y, z),
+// to the plane partials P2[jz][pair][band] (global atomics; the layout of
+// the expansion's plane partials).  k_zpass then takes the z pass,
+// c[n] = h^3 sum_jz phi_nz(z_jz) P2[jz][nx,ny].  Each value of psi is read
+// from memory once per band tile however many supports hold it; the price is
+// one atomic add per pair and band for every entry.
+// Lanes are (run slot, band) as in the expansion's block form; phi_x is
+// wave-uniform (scalar loads), phi_y per lane.
+template <int NU>
+__device__ inline void proj_entry(const EArgs &E, const EntryRec &en, double *p2,
+                                  const double *tile, int x2, int TB, int slot, int bl,
+                                  int bc, bool bok) {
+  constexpr int NF = NU + 1;
+  constexpr int NP = NF * (NF + 1) / 2;
+  const int nfp = en.nfp;
+  const int lane = threadIdx.x & 63;
+  const int slots = 64 / TB;
+  const uint32_t mydesc = lane < en.nruns ? as_const(E.run_desc)[en.run_begin + lane] : 0u;
+  const cptr<double> tx = as_const(E.tab) + en.tab_x;
+  double T2[NP];
+#pragma unroll
+  for (int q = 0; q < NP; ++q) T2[q] = 0.0;
+  for (int g0 = 0; g0 < en.nruns; g0 += slots) {
+    const int gend = min(g0 + slots, (int)en.nruns);
+    int lo = 255, hi = 0;  // wave-uniform x range of the group
+    for (int k = g0; k < gend; ++k) {
+      const uint32_t d = __builtin_amdgcn_readlane(mydesc, k);
+      lo = min(lo, (int)((d >> 8) & 0xff));
+      hi = max(hi, (int)((d >> 16) & 0xff));
+    }
+    const int i = g0 + slot;
+    const uint32_t d = __shfl(mydesc, min(i, gend - 1));
+    const int r = d & 0xff;
+    const int xa = i < gend ? (int)((d >> 8) & 0xff) : 0;
+    const int xb = i < gend ? (int)((d >> 16) & 0xff) : 0;
+    const double *trow = tile + ((r * x2) << __builtin_ctz(TB)) + bl;
+    double T1[NF];
+#pragma unroll
+    for (int n = 0; n < NF; ++n) T1[n] = 0.0;
+    for (int x = lo; x < hi; ++x) {
+      const double v = (x >= xa && x < xb) ? trow[x * TB] : 0.0;
+      const cptr<double> f = tx + x * nfp;
+#pragma unroll
+      for (int n = 0; n < NF; ++n) T1[n] = fma(f[n], v, T1[n]);
+    }
+    const double *fy = E.tab + en.tab_y + r * nfp;
+    int q = 0;
+#pragma unroll
+    for (int ny = 0; ny < NF; ++ny) {
+      const double fv = fy[ny];
+#pragma unroll
+      for (int nx = 0; nx < NF - ny; ++nx, ++q) T2[q] = fma(fv, T1[nx], T2[q]);
+    }
+  }
+  for (int sft = 32; sft >= TB; sft >>= 1) {
+#pragma unroll
+    for (int q = 0; q < NP; ++q) T2[q] += __shfl_xor(T2[q], sft);
+  }
+  if (slot == 0 && bok) {
+    double *dst = p2 + en.u2 + bc;
+#pragma unroll
+    for (int q = 0; q < NP; ++q) unsafeAtomicAdd(dst + (int64_t)q * E.B, T2[q]);
+  }
+}
+
+template <int NUMAX>
+__global__ __launch_bounds__(kBlkBlock) void k_project_blocks(EArgs E,
+                                                             const double *__restrict__ psi,
+                                                             double *p2) {
+  extern __shared__ double lds[];
+  const BlockRec bk = load_uniform(E.blocks + blockIdx.x);
+  if (bk.nentries < 0) return;
+  const int w = wave_id();
+  double *tile = lds;
+  const int TB = 1 << E.tbe_shift;
+  const int btile = blockIdx.y;
+  const int xe = min(bk.x0 + E.blk_x, E.nx);
+  const int nxl = xe - bk.x0;
+  const int nrow = min(bk.y0 + E.blk_rows, E.ny) - bk.y0;
+  const int x2s = E.blk_x <= 1 ? 0 : 32 - __clz(E.blk_x - 1);
+  const int rs = x2s + E.tbe_shift;
+  const int nval = nrow << rs;
+  const int64_t gbase = ((int64_t)(bk.z * E.ny + bk.y0) * E.nx + bk.x0) * E.B + btile * TB;
+  const int64_t grow = (int64_t)E.nx * E.B;
+  fill_lds<16>(tile, nval, [&](int t) {
+    const int r = t >> rs;
+    const int x = (t >> E.tbe_shift) & ((1 << x2s) - 1);
+    const int l = t & (TB - 1);
+    return (x < nxl && btile * TB + l < E.B)
+               ? psi[gbase + r * grow + (int64_t)__umul24(x, E.B) + l]
+               : 0.0;
+  });
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int lslot = lane >> E.tbe_shift;
+  const int bl = lane & (TB - 1);
+  const int b = btile * TB + bl;
+  const bool bok = b < E.B;
+  const int bc = bok ? b : E.B - 1;
+  for (int i = w; i < bk.nentries; i += kBlkWaves) {
+    const EntryRec en = load_uniform(E.entries + bk.entry_begin + i);
+    switch (en.nu) {
+#define X(N)                                                                      \
+  case N:                                                                         \
+    if constexpr (N <= NUMAX) proj_entry<N>(E, en, p2, tile, 1 << x2s, TB, lslot, bl, bc, bok); \
+    break;
+      SHO_NU_CASES(X)
+#undef X
+    }
+  }
+}
+
+// z pass of the block projection: c[n][b] = h^3 sum_jz phi_nz(z_jz) P2[jz][nx,ny][b]
+// for every atom of cut-off NU; thread = (pair, band), each plane partial
+// read once.
+template <int NU>
+__global__ __launch_bounds__(256) void k_zpass(EArgs E, const double *__restrict__ p2,
+                                               double *__restrict__ c, double h3) {
+  constexpr int NF = NU + 1;
+  constexpr int NP = NF * (NF + 1) / 2;
+  const int a = E.nu_atoms[E.nu_begin[NU] + blockIdx.x];
+  const AtomRec A = load_uniform(E.atoms + a);
+  const int b0 = blockIdx.y * kU2Tile;
+  const cptr<double> tz = as_const(E.tab) + A.tab_off + (int64_t)(A.mx + A.my) * A.tab_nfp;
+  const double *src = p2 + E.u2_off[a];
+  for (int t = threadIdx.x; t < NP * kU2Tile; t += blockDim.x) {
+    const int q = t / kU2Tile, bl = t % kU2Tile;
+    const int b = b0 + bl;
+    if (b >= E.B) continue;
+    // pair q -> (nx, ny), ny outer
+    int ny = 0, qq = q;
+    while (qq >= NF - ny) {
+      qq -= NF - ny;
+      ++ny;
+    }
+    const int nx = qq;
+    double acc[NF];
+#pragma unroll
+    for (int n = 0; n < NF; ++n) acc[n] = 0.0;
+    for (int jz = 0; jz < A.mz; ++jz) {
+      const double v = src[((int64_t)jz * NP + q) * E.B + b];
+      const cptr<double> fz = tz + jz * A.tab_nfp;
+#pragma unroll
+      for (int nz = 0; nz < NF; ++nz) acc[nz] = fma(fz[nz], v, acc[nz]);
+    }
+    // C index of (nx, ny, nz): nz-major, then ny, nx fastest
+#pragma unroll
+    for (int nz = 0; nz < NF; ++nz) {
+      if (nx + ny + nz <= NU) {
+        int base = 0;
+        for (int k = 0; k < nz; ++k) base += (NU - k + 1) * (NU - k + 2) / 2;
+        for (int j = 0; j < ny; ++j) base += NU - nz - j + 1;
+        c[(A.coeff_row + base + nx) * E.B + b] = h3 * acc[nz];
+      }
     }
   }
 }
@@ -1834,6 +1962,45 @@ hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s) {
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(k_fill, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
   return hipGetLastError();
+}
+
+hipError_t launch_project_blocks(const EArgs &E, const double *psi, double *p2,
+                                 hipStream_t s) {
+  if (E.nblocks <= 0) return hipSuccess;
+  if (E.bloch) return hipErrorInvalidValue;
+  const dim3 g((unsigned)E.nblocks, (unsigned)E.ntiles);
+  const size_t shm = kProjTileDoubles * sizeof(double);
+  switch (E.nu_max) {
+#define X(N)                                                                          \
+  case N:                                                                             \
+    hipLaunchKernelGGL((k_project_blocks<N>), g, dim3(kBlkBlock), shm, s, E, psi, p2); \
+    break;
+    SHO_NU_CASES(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_zpass(const EArgs &E, const double *p2, double *c, double h3,
+                        hipStream_t s) {
+  for (int nu = 0; nu <= SHO_NU_MAX; ++nu) {
+    const int cnt = E.nu_begin[nu + 1] - E.nu_begin[nu];
+    if (cnt <= 0) continue;
+    const dim3 g((unsigned)cnt, (unsigned)E.ntiles_u2);
+    switch (nu) {
+#define X(N)                                                                 \
+  case N:                                                                    \
+    hipLaunchKernelGGL(k_zpass<N>, g, dim3(256), 0, s, E, p2, c, h3);        \
+    break;
+      SHO_NU_CASES(X)
+#undef X
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // ------------------------------------------------- static expansion scratch --

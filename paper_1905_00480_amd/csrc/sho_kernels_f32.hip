@@ -20,6 +20,7 @@
 // that the FP64 kernels are compiled exactly as they are without them.
 #include <hip/hip_runtime.h>
 
+#include "sho_device.hpp"
 #include "sho_launch.hpp"
 
 namespace sho {
@@ -45,25 +46,6 @@ __device__ inline Pair fma2(float s, Pair v, Pair acc) {
 }
 
 __device__ inline Pair zero2() { return Pair{0.f, 0.f}; }
-
-template <typename T>
-using cptr = const __attribute__((address_space(4))) T *;
-
-template <typename T>
-__device__ inline cptr<T> as_const(const T *p) {
-  return (cptr<T>)p;
-}
-
-template <typename T>
-__device__ inline T load_uniform(const T *p) {
-  static_assert(sizeof(T) % 4 == 0, "record size");
-  T out;
-  const cptr<uint32_t> src = (cptr<uint32_t>)p;
-  uint32_t *dst = reinterpret_cast<uint32_t *>(&out);
-#pragma unroll
-  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) dst[i] = src[i];
-  return out;
-}
 
 // ---------------------------------------------------------------- tables --
 
@@ -97,9 +79,6 @@ __device__ inline Lanes lane_geometry(const KArgs &K, int tile) {
   return L;
 }
 
-__device__ inline int wave_id() {
-  return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-}
 
 struct RunState {
   const Pair *base;  // psi at the run's first point, this lane's pair
@@ -107,12 +86,10 @@ struct RunState {
   int len;
   int jy;
   bool active;
-  float pc, ps;      // Bloch plans: cos, sin of k.T for the run's image T
 };
 
-template <bool CPLX = false>
 __device__ inline RunState run_state(const KArgs &K, const Lanes &L, const Pair *psi,
-                                     const BundleRec &bd, const AtomRec *A = nullptr) {
+                                     const BundleRec &bd) {
   const int s = min(L.slot, bd.nruns - 1);
   const LineRec ln = K.lines[bd.run0 + s];
   RunState r;
@@ -121,18 +98,6 @@ __device__ inline RunState run_state(const KArgs &K, const Lanes &L, const Pair 
   r.len = ln.len;
   r.jy = ln.jy;
   r.active = L.slot < bd.nruns;
-  if constexpr (CPLX) {
-    // k.T, T = unwrapped minus memory position of the run's points; the
-    // angle and its sine and cosine in double, rounded once to float
-    const int ym = ln.row % K.ny, zm = ln.row / K.ny;
-    double th = K.k[0] * ((double)(A->ix0 + ln.jx0 - ln.x0m) * K.h);
-    th += K.k[1] * ((double)(A->iy0 + ln.jy - ym) * K.h);
-    th += K.k[2] * ((double)(A->iz0 + ln.jz - zm) * K.h);
-    double sn, cs;
-    sincos(th, &sn, &cs);
-    r.pc = (float)cs;
-    r.ps = (float)sn;
-  }
   return r;
 }
 
@@ -215,7 +180,7 @@ __device__ inline void project_bundles(const KArgs &K, const float *tab, const A
   for (int q = 0; q < NP; ++q) T2[q] = zero2();
   int cur_jz = -1;
   BundleRec bd = load_uniform(K.bundles + b0);
-  RunState rs = run_state<CPLX>(K, L, psi, bd, &A);
+  RunState rs = run_state(K, L, psi, bd);
   Pair v[kBatch];
   load_batch(K, rs, bd.jlo, v);
   for (int bi = b0; bi < b1; ++bi) {
@@ -234,7 +199,7 @@ __device__ inline void project_bundles(const KArgs &K, const float *tab, const A
         load_batch(K, rs, jb + kBatch, w);
       } else if (bi + 1 < b1) {
         nbd = load_uniform(K.bundles + bi + 1);
-        nrs = run_state<CPLX>(K, L, psi, nbd, &A);
+        nrs = run_state(K, L, psi, nbd);
         load_batch(K, nrs, nbd.jlo, w);
       } else {
 #pragma unroll
@@ -256,9 +221,12 @@ __device__ inline void project_bundles(const KArgs &K, const float *tab, const A
       for (int u = 0; u < kBatch; ++u) v[u] = w[u];
     }
     if constexpr (CPLX) {
-      // the run's image carries e^{+i k.T}
+      // the bundle's runs share one periodic image T, which carries e^{+i k.T}
+      // (cos, sin in double from the plan's table, rounded once to float)
+      const cptr<double> ph = as_const(K.bundle_phase) + 2 * bi;
+      const float pc = (float)ph[0], ps = (float)ph[1];
 #pragma unroll
-      for (int n = 0; n < NF; ++n) T1[n] = rotate(T1[n], rs.pc, rs.ps);
+      for (int n = 0; n < NF; ++n) T1[n] = rotate(T1[n], pc, ps);
     }
     const float *fy = ty + rs.jy * nfp;
     int q = 0;
@@ -414,7 +382,7 @@ constexpr int blk_group(int nu, int numax) { return (numax > 5 && nu <= 5) ? 4 :
 // Adds every run of one entry (one atom plane, one image) into the LDS tile
 // of the block ([row][x][2][TB] doubles).
 template <int NU, int NUMAX, bool CPLX = false>
-__device__ inline void add_entry(const EArgs &E, const float *tab, const EntryRec &en,
+__device__ inline void add_entry(const EArgs &E, const float *tab, const EntryRec &en, int ei,
                                  const Pair *u2, int nxl, double *tile, float *xstage,
                                  int TB, int slot, int bl, int bc) {
   constexpr int NF = NU + 1;
@@ -429,11 +397,8 @@ __device__ inline void add_entry(const EArgs &E, const float *tab, const EntryRe
   for (int q = 0; q < NP; ++q) u2v[q] = ub[(int64_t)q * E.B];
   if constexpr (CPLX) {
     // the entry's image T receives e^{-i k.T} times the plane partials
-    double th = E.k[0] * ((double)(en.img[0] * E.nx) * E.h);
-    th += E.k[1] * ((double)(en.img[1] * E.ny) * E.h);
-    th += E.k[2] * ((double)(en.img[2] * E.nz) * E.h);
-    double sn, cs;
-    sincos(th, &sn, &cs);
+    const cptr<double> ph = as_const(E.entry_phase) + 2 * ei;
+    const double cs = ph[0], sn = ph[1];
 #pragma unroll
     for (int q = 0; q < NP; ++q) u2v[q] = rotate(u2v[q], (float)cs, -(float)sn);
   }
@@ -566,7 +531,8 @@ __global__ __launch_bounds__(kBlkBlock) void k_expand_blocks(EArgs E,
 #define X(N)                                                                        \
   case N:                                                                           \
     if constexpr (N <= NUMAX)                                                       \
-      add_entry<N, NUMAX, CPLX>(E, tab, en, u2, 1 << x2s, tile, xstage, TB, lslot, bl, bc); \
+      add_entry<N, NUMAX, CPLX>(E, tab, en, bk.entry_begin + i, u2, 1 << x2s, tile, xstage, TB, \
+                                lslot, bl, bc);                                     \
     break;
       SHO_F32_NU_CASES(X)
 #undef X

@@ -30,12 +30,10 @@ struct KArgs {
   int32_t ntiles;            // band tiles per atom
   int32_t det;               // 1: deterministic sums (per-wave LDS tiles
                              // added in wave order; no atomics)
-  int32_t ny, nz;            // grid points along y, z
-  int32_t bloch;             // 1: complex bands (re, im) at wave vector k
+  int32_t bloch;             // 1: complex bands (re, im) at a wave vector k
   double h3;
   double alpha;              // expansion: psi += alpha * sum_n c P_n
-  double h;                  // grid spacing
-  double k[3];               // Bloch wave vector (Bohr^-1)
+  const double *bundle_phase;  // Bloch plans: (cos, sin) of k.T per bundle
 };
 
 // Argument block of the row-owner expansion.
@@ -68,11 +66,9 @@ struct EArgs {
   int32_t blk_x;        // X
   int32_t ny;
   int32_t ncol;         // stored plans: 0, or the radial projectors per atom
-  int32_t nz;
-  int32_t bloch;        // 1: complex bands (re, im) at wave vector k
+  int32_t bloch;        // 1: complex bands (re, im) at a wave vector k
   double alpha;         // psi += alpha * sum_n c P_n (applied to c in the z pass)
-  double h;             // grid spacing
-  double k[3];          // Bloch wave vector (Bohr^-1)
+  const double *entry_phase;  // Bloch plans: (cos, sin) of k.T per block entry
 };
 
 // Argument block of the stored-projector kernels.
@@ -124,6 +120,15 @@ hipError_t launch_rows(const EArgs &E, const double *u2, double *psi,
 // Block form of the second half (blocks of R rows x X points).
 hipError_t launch_blocks(const EArgs &E, const double *u2, double *psi,
                          hipStream_t s);
+// Block form of the projection: every block of psi read once, the atom
+// planes touching it add their plane sums into p2 (the plane-partial layout,
+// zeroed first: launch_fill); launch_zpass then writes c = h3 * z pass of p2.
+// E's block tables are the projection's (R x X blocks, band tile of
+// 1 << E.tbe_shift bands, at most kProjTileDoubles values per block).
+hipError_t launch_project_blocks(const EArgs &E, const double *psi, double *p2,
+                                 hipStream_t s);
+hipError_t launch_zpass(const EArgs &E, const double *p2, double *c, double h3,
+                        hipStream_t s);
 // Owner form of the second half: one wave per strip of 64/TB rows x X points
 // (X = E.blk_x, 16 or 32), values in registers, entries in plan order.
 hipError_t launch_owner(const EArgs &E, const double *u2, double *psi, hipStream_t s);

@@ -314,12 +314,34 @@ void build_work(HostPlan *P, int tb_shift, int64_t target_points, int32_t sched)
       const int32_t re = (pi + 1 < A.plane_begin + A.nplanes)
                              ? P->planes[pi + 1].line_begin
                              : A.line_begin + A.nlines;
-      std::stable_sort(P->lines.begin() + rb, P->lines.begin() + re,
-                       [](const LineRec &x, const LineRec &y) { return x.jx0 < y.jx0; });
-      for (int32_t r = rb; r < re; r += slots) {
+      // Bloch plans: runs of one periodic image together (a bundle carries
+      // one phase), then by first x index
+      const bool bloch = (P->flags & SHO_FLAG_BLOCH) != 0;
+      auto image = [&](const LineRec &L) {  // image counts along x and y
+        const int64_t mx = (int64_t)(A.ix0 + L.jx0 - L.x0m) / P->grid.n[0];
+        const int64_t my = (int64_t)(A.iy0 + L.jy - L.row % P->grid.n[1]) / P->grid.n[1];
+        return mx * 1024 + my;
+      };
+      if (bloch)
+        std::stable_sort(P->lines.begin() + rb, P->lines.begin() + re,
+                         [&](const LineRec &x, const LineRec &y) {
+                           const int64_t ix = image(x), iy = image(y);
+                           return ix != iy ? ix < iy : x.jx0 < y.jx0;
+                         });
+      else
+        std::stable_sort(P->lines.begin() + rb, P->lines.begin() + re,
+                         [](const LineRec &x, const LineRec &y) { return x.jx0 < y.jx0; });
+      for (int32_t r = rb, rn = rb; r < re; r = rn) {
+        rn = std::min(re, r + slots);
+        if (bloch)
+          for (int32_t k = r + 1; k < rn; ++k)
+            if (image(P->lines[k]) != image(P->lines[r])) {
+              rn = k;
+              break;
+            }
         BundleRec b;
         b.run0 = r;
-        b.nruns = (int16_t)std::min(slots, re - r);
+        b.nruns = (int16_t)(rn - r);
         b.jz = P->lines[r].jz;
         int lo = INT32_MAX, hi = INT32_MIN;
         for (int32_t k = r; k < r + b.nruns; ++k) {
@@ -569,11 +591,11 @@ void build_rows(HostPlan *P) {
       if (P->atoms[a].nu == nu && P->atoms[a].npoints > 0) P->nu_atoms.push_back(a);
 }
 
-void build_blocks(HostPlan *P, int32_t R, int32_t X) {
+void build_block_set(const HostPlan *P, int32_t R, int32_t X, BlockSet *out) {
   const int32_t nx = P->grid.n[0], ny = P->grid.n[1];
   const int64_t nyb = (ny + R - 1) / R, nxb = (nx + X - 1) / X;
-  P->blk_rows = R;
-  P->blk_x = X;
+  out->rows = R;
+  out->x = X;
   struct Item {
     int64_t block;
     int32_t atom, jz, jshift, yshift, row, run;
@@ -596,9 +618,9 @@ void build_blocks(HostPlan *P, int32_t R, int32_t X) {
     if (a.row != b.row) return a.row < b.row;
     return a.run < b.run;
   });
-  P->entries.clear();
-  P->run_desc.clear();
-  P->run_desc_run.clear();
+  out->entries.clear();
+  out->run_desc.clear();
+  out->run_desc_run.clear();
   std::vector<std::vector<BlockRec>> cls(8);
   for (size_t i = 0; i < items.size();) {
     const int64_t blk = items[i].block;
@@ -607,7 +629,7 @@ void build_blocks(HostPlan *P, int32_t R, int32_t X) {
     B.z = (int32_t)(yz / nyb);
     B.y0 = (int32_t)(yz % nyb) * R;
     B.x0 = (int32_t)cx * X;
-    B.entry_begin = (int32_t)P->entries.size();
+    B.entry_begin = (int32_t)out->entries.size();
     B.nentries = 0;
     B.pad = 0;
     while (i < items.size() && items[i].block == blk) {
@@ -626,7 +648,7 @@ void build_blocks(HostPlan *P, int32_t R, int32_t X) {
       E.x_hi = (int16_t)std::min(X, A.mx - jx0);
       E.y_lo = (int16_t)std::max(0, -jy0);
       E.y_hi = (int16_t)std::min(R, A.my - jy0);
-      E.run_begin = (int32_t)P->run_desc.size();
+      E.run_begin = (int32_t)out->run_desc.size();
       E.nruns = 0;
       // image counts (clamped; Bloch plans refuse supports beyond 127 images)
       {
@@ -647,36 +669,48 @@ void build_blocks(HostPlan *P, int32_t R, int32_t X) {
         const LineRec &L = P->lines[items[i].run];
         const int32_t xa = std::max((int32_t)L.x0m, B.x0) - B.x0;
         const int32_t xb = std::min((int32_t)L.x0m + L.len, B.x0 + X) - B.x0;
-        P->run_desc.push_back(pack_run(L.row % ny - B.y0, xa, xb));
-        P->run_desc_run.push_back(items[i].run);
+        out->run_desc.push_back(pack_run(L.row % ny - B.y0, xa, xb));
+        out->run_desc_run.push_back(items[i].run);
         E.nruns++;
         ++i;
       }
-      P->entries.push_back(E);
+      out->entries.push_back(E);
       B.nentries++;
     }
     cls[B.z % 8].push_back(B);
   }
   // blocks of planes z = k mod 8 go to workgroups g = k mod 8 (XCD k)
-  P->blocks.clear();
+  out->blocks.clear();
   std::vector<size_t> at(8, 0);
   const BlockRec pad{0, 0, 0, 0, -1, 0};
   for (bool any = true; any;) {
     any = false;
     for (int k = 0; k < 8; ++k) {
       if (at[k] < cls[k].size()) {
-        P->blocks.push_back(cls[k][at[k]++]);
+        out->blocks.push_back(cls[k][at[k]++]);
         any = true;
       } else {
-        P->blocks.push_back(pad);
+        out->blocks.push_back(pad);
       }
     }
   }
-  while (!P->blocks.empty() && P->blocks.back().nentries < 0) P->blocks.pop_back();
-  P->block_points = 0;
-  for (const BlockRec &B : P->blocks)
+  while (!out->blocks.empty() && out->blocks.back().nentries < 0) out->blocks.pop_back();
+  out->points = 0;
+  for (const BlockRec &B : out->blocks)
     if (B.nentries >= 0)
-      P->block_points += (int64_t)(std::min(B.y0 + R, ny) - B.y0) * (std::min(B.x0 + X, nx) - B.x0);
+      out->points += (int64_t)(std::min(B.y0 + R, ny) - B.y0) * (std::min(B.x0 + X, nx) - B.x0);
+}
+
+void build_blocks(HostPlan *P, int32_t R, int32_t X) {
+  BlockSet bs;
+  build_block_set(P, R, X, &bs);
+  P->blk_rows = bs.rows;
+  P->blk_x = bs.x;
+  P->block_points = bs.points;
+  P->blocks.swap(bs.blocks);
+  P->entries.swap(bs.entries);
+  P->run_desc.swap(bs.run_desc);
+  P->run_desc_run.swap(bs.run_desc_run);
 }
 
 void build_desc_pbase(HostPlan *P) {

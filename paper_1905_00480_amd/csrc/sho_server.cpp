@@ -9,11 +9,14 @@
 // last request is waited for, their device memory freed; inputs are never
 // modified on the device, so nothing is copied back).
 //
-// Requests of one system run in submission order on the stream the system
-// was given at admission (the least loaded one); systems overlap across
-// streams.  A poller thread timestamps every request when its completion
-// event has fired, without taking the admission lock, so that latencies are
-// not inflated by a concurrent admission.
+// Every request goes to the stream with the least outstanding work (the
+// estimated cost of its requests not yet completed: support points x bands
+// x a factor per job kind), so that small requests do not queue behind large
+// ones; a request placed on another stream than its system's previous one
+// first waits for that request (an event), so the requests of one system
+// still run in submission order.  A poller thread timestamps every request
+// when its completion event has fired, without taking the admission lock, so
+// that latencies are not inflated by a concurrent admission.
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
@@ -48,8 +51,9 @@ struct Sys {
   sho_plan_t plan = nullptr;
   double *d_psi = nullptr, *d_w = nullptr, *d_c = nullptr, *d_grad = nullptr,
          *d_out = nullptr;
-  int stream = 0;
-  hipEvent_t last = nullptr;  // after the latest request of this system
+  int stream = 0;             // stream of the latest request (or the upload)
+  double units = 0.0;         // support points x bands (cost of a request)
+  hipEvent_t last = nullptr;  // after the latest request (or upload) of this system
   uint64_t last_use = 0;
   std::atomic<int32_t> inflight{0};
   int64_t done_by_job[3] = {0, 0, 0};
@@ -60,6 +64,7 @@ struct Req {
   Sys *sysp = nullptr;
   int32_t sys = 0, job = 0;
   int32_t stream = 0;
+  double cost = 0.0;  // estimated work, counted on its stream until done
   sho_status status = SHO_OK;
   double t_submit = 0.0;
   std::atomic<double> t_done{-1.0};
@@ -73,7 +78,8 @@ struct sho_server_s {
   uint32_t flags = 0;
   bool dry = false;  // SHO_FLAG_HOST_ONLY: admission bookkeeping only
   std::vector<hipStream_t> streams;
-  std::vector<int32_t> stream_load;  // resident systems per stream
+  std::mutex wmu;                    // stream_work
+  std::vector<double> stream_work;   // outstanding estimated work per stream
   std::deque<std::unique_ptr<Sys>> systems;
   std::deque<std::unique_ptr<Req>> reqs;  // stable addresses
   int64_t resident_bytes = 0, peak_bytes = 0;
@@ -124,6 +130,10 @@ void poll_loop(sho_server_s *S) {
       r->ev = nullptr;
       if (q != hipSuccess) r->status = SHO_E_DEVICE;
       r->t_done.store(t);
+      {
+        std::lock_guard<std::mutex> wl(S->wmu);
+        S->stream_work[r->stream] -= r->cost;
+      }
       r->sysp->inflight--;
       S->completed++;
       r = nullptr;
@@ -145,7 +155,6 @@ void free_resident(sho_server_s *S, Sys &y) {
       if (q) (void)hipFree(q);
     if (y.plan) (void)sho_plan_destroy(y.plan);
     if (y.last) (void)hipEventDestroy(y.last);
-    S->stream_load[y.stream]--;
   }
   y.d_psi = y.d_w = y.d_c = y.d_grad = y.d_out = nullptr;
   y.plan = nullptr;
@@ -172,6 +181,15 @@ bool make_room(sho_server_s *S, int64_t need, int32_t keep) {
   return true;
 }
 
+// The stream with the least outstanding work.
+int least_loaded(sho_server_s *S) {
+  std::lock_guard<std::mutex> wl(S->wmu);
+  int best = 0;
+  for (size_t k = 1; k < S->stream_work.size(); ++k)
+    if (S->stream_work[k] < S->stream_work[best]) best = (int)k;
+  return best;
+}
+
 sho_status admit(sho_server_s *S, int32_t id) {
   Sys &y = *S->systems[id];
   if (!make_room(S, y.charge, id)) {
@@ -180,11 +198,8 @@ sho_status admit(sho_server_s *S, int32_t id) {
                                   " bytes of a budget of " + std::to_string(S->budget));
   }
   if (!S->dry) {
-    int best = 0;
-    for (size_t k = 1; k < S->streams.size(); ++k)
-      if (S->stream_load[k] < S->stream_load[best]) best = (int)k;
+    const int best = least_loaded(S);
     y.stream = best;
-    S->stream_load[best]++;
     hipStream_t st = S->streams[best];
     sho_status r = sho_plan_create(&y.grid, y.natoms, y.pos.data(), y.sigma.data(),
                                    y.numax.data(), nullptr, y.nbands, S->flags, &y.plan);
@@ -198,9 +213,13 @@ sho_status admit(sho_server_s *S, int32_t id) {
           (e = hipMalloc((void **)&y.d_grad, std::max(3 * y.natoms, 1) * sizeof(double))) ==
               hipSuccess &&
           (e = hipEventCreateWithFlags(&y.last, hipEventDisableTiming)) == hipSuccess &&
-          (e = hipMemcpyAsync(y.d_psi, y.h_psi, pb, hipMemcpyHostToDevice, st)) == hipSuccess)
-        e = hipMemcpyAsync(y.d_w, y.h_w, y.coeff_doubles * sizeof(double),
-                           hipMemcpyHostToDevice, st);
+          (e = hipMemcpyAsync(y.d_psi, y.h_psi, pb, hipMemcpyHostToDevice, st)) == hipSuccess &&
+          (e = hipMemcpyAsync(y.d_w, y.h_w, y.coeff_doubles * sizeof(double),
+                              hipMemcpyHostToDevice, st)) == hipSuccess)
+        e = hipEventRecord(y.last, st);  // requests on other streams wait for the upload
+      sho_plan_info info;
+      if (e == hipSuccess && sho_plan_get_info(y.plan, &info) == SHO_OK)
+        y.units = (double)info.support_points * y.nbands;
     }
     if (r != SHO_OK || e != hipSuccess) {
       const std::string why = r != SHO_OK ? std::string(sho_last_error()) : "";
@@ -217,6 +236,14 @@ sho_status admit(sho_server_s *S, int32_t id) {
   S->peak_bytes = std::max(S->peak_bytes, S->resident_bytes);
   S->admissions++;
   return SHO_OK;
+}
+
+// Relative cost of a job on a system of `units` support points x bands
+// (measured: an expansion and a derivative take about 1.4 and 1.3 times a
+// projection).
+double job_cost(double units, int32_t job) {
+  static const double factor[3] = {1.0, 1.4, 1.3};
+  return units * factor[job];
 }
 
 sho_status launch_job(sho_server_s *S, Sys &y, int32_t job) {
@@ -262,7 +289,7 @@ sho_status sho_server_create(int64_t budget_bytes, int32_t nstreams, uint32_t pl
       }
       S->streams.push_back(st);
     }
-    S->stream_load.assign(nstreams, 0);
+    S->stream_work.assign(nstreams, 0.0);
     S->poller = std::thread(poll_loop, S.get());
   }
   *out = S.release();
@@ -341,20 +368,41 @@ sho_status sho_server_submit(sho_server_t S, int32_t sys, int32_t job, int64_t *
   q->sysp = &y;
   q->job = job;
   q->t_submit = t_submit;
+  if (!S->dry) {
+    // least outstanding work; after the system's previous request if that
+    // ran (or its inputs were uploaded) on another stream
+    const int st_new = least_loaded(S);
+    if (st_new != y.stream) {
+      hipError_t e = hipStreamWaitEvent(S->streams[st_new], y.last, 0);
+      if (e != hipSuccess) return hip_fail(e, "stream ordering");
+      y.stream = st_new;
+    }
+    q->cost = job_cost(y.units, job);
+    std::lock_guard<std::mutex> wl(S->wmu);
+    S->stream_work[y.stream] += q->cost;
+  }
   q->stream = y.stream;
   if (S->dry) {
     q->t_done.store(t_submit);
     y.done_by_job[job]++;
     S->completed++;
   } else {
+    auto unclaim = [&]() {
+      std::lock_guard<std::mutex> wl(S->wmu);
+      S->stream_work[y.stream] -= q->cost;
+    };
     sho_status r = launch_job(S, y, job);
-    if (r != SHO_OK) return r;
+    if (r != SHO_OK) {
+      unclaim();
+      return r;
+    }
     hipStream_t st = S->streams[y.stream];
     hipError_t e = hipEventCreateWithFlags(&q->ev, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventRecord(q->ev, st);
     if (e == hipSuccess) e = hipEventRecord(y.last, st);
     if (e != hipSuccess) {
       if (q->ev) (void)hipEventDestroy(q->ev);
+      unclaim();
       return hip_fail(e, "completion event");
     }
     y.inflight++;

@@ -103,6 +103,10 @@ def run(server, sids, units, rate_hz=200.0, warmup=200, requests=2000, seed=4,
         jobs.append(job)
     lat = np.array(lat)
     span = max(done) - (base_srv + arrivals[warmup])
+    # where the tail comes from: requests to the three largest systems (by
+    # support points x bands) against the rest
+    big = set(np.argsort(units)[::-1][:3].tolist())
+    sel = np.array([int(which[i]) in big for i in range(warmup, count)])
     work = float(units[which[warmup:]].sum())
     st = server.stats()
     return {"requests": requests, "warmup": warmup, "rate_hz": rate_hz,
@@ -111,6 +115,11 @@ def run(server, sids, units, rate_hz=200.0, warmup=200, requests=2000, seed=4,
             "latency_ms_p50": 1e3 * float(np.percentile(lat, 50)),
             "latency_ms_p99": 1e3 * float(np.percentile(lat, 99)),
             "latency_ms_mean": 1e3 * float(lat.mean()),
+            "largest3_share_of_work": float(units[sorted(big)].sum() / units.sum()),
+            "latency_ms_p50_p99_largest3": [1e3 * float(np.percentile(lat[sel], q))
+                                            for q in (50, 99)] if sel.any() else None,
+            "latency_ms_p50_p99_others": [1e3 * float(np.percentile(lat[~sel], q))
+                                          for q in (50, 99)] if (~sel).any() else None,
             "jobs": {j: int(np.sum(np.array(jobs) == k))
                      for k, j in enumerate(("project", "expand", "force"))},
             "admissions": st["admissions"], "evictions": st["evictions"],
@@ -118,21 +127,27 @@ def run(server, sids, units, rate_hz=200.0, warmup=200, requests=2000, seed=4,
 
 
 def compare(budget_bytes=64 << 30, nstreams=4, rate_hz=200.0, warmup=200, requests=2000,
-            seed=4, nsystems=32, plain_requests=200, plain_warmup=20):
+            seed=4, nsystems=32, plain_requests=200, plain_warmup=20,
+            tight_budget_bytes=40 << 30, tight_requests=300, tight_warmup=30):
     """The batched server and the per-request reference on the same stream of
     requests over the same pool (the reference on its first plain_warmup +
     plain_requests requests only: it serves a few requests per second, so a
-    full stream would queue for many minutes)."""
+    full stream would queue for many minutes), and the batched server again
+    under a budget below the pool's resident size, so that systems are
+    evicted and admitted again during the stream."""
     pool = wl.serving_pool(seed=seed, nsystems=nsystems)
     units = units_of(pool)
     _log("pool of %d systems sized" % len(pool))
     res = {"pool": {"systems": len(pool),
                     "psi_GB": float(sum(np.prod(s.n) * s.nbands * 8 for s in pool)) / 1e9},
            "budget_GB": budget_bytes / 1e9}
-    for name, streams, flags, nw, nr in (
-            ("batched", nstreams, 0, warmup, requests),
-            ("per_request_plain", 1, bd.FLAG_PER_ATOM, plain_warmup, plain_requests)):
-        srv = bd.Server(budget_bytes, streams, flags)
+    for name, streams, flags, nw, nr, budget in (
+            ("batched", nstreams, 0, warmup, requests, budget_bytes),
+            ("batched_tight_budget", nstreams, 0, tight_warmup, tight_requests,
+             tight_budget_bytes),
+            ("per_request_plain", 1, bd.FLAG_PER_ATOM, plain_warmup, plain_requests,
+             budget_bytes)):
+        srv = bd.Server(budget, streams, flags)
         t0 = time.perf_counter()
         sids = register(srv, pool, seed)
         reg_s = time.perf_counter() - t0
@@ -142,6 +157,7 @@ def compare(budget_bytes=64 << 30, nstreams=4, rate_hz=200.0, warmup=200, reques
              % (name, nr, r["latency_ms_p50"], r["latency_ms_p99"], r["req_per_s"]))
         r["streams"] = streams
         r["register_s"] = reg_s
+        r["budget_GB"] = budget / 1e9
         srv.close()
         res[name] = r
     res["p99_ratio_plain_over_batched"] = (res["per_request_plain"]["latency_ms_p99"] /

@@ -199,3 +199,33 @@ def test_expansion_forms_wide_boxes():
         plan.expand(_dev(c), out)
         _check(_host(out), e_ref, e_abs, "wide boxes, form %s" % (form,))
         plan.close()
+
+
+@pytest.mark.parametrize("tile", [8, 16, 32])
+def test_expand_tile_matches_oracle(mixed, tile):
+    """The expansion's block form with narrower band tiles (more, larger
+    blocks), into zeros and accumulating."""
+    bd = _bd()
+    s, psi, cin, _, (e_ref, e_abs), _ = mixed
+    plan = bd.Plan.from_system(s)
+    plan.set_expand_tile(tile)
+    assert plan.expand_tile() == tile
+    d_acc = _dev(psi)
+    plan.expand(_dev(cin), d_acc)
+    _check(_host(d_acc), e_ref, e_abs, "expand, band tile %d" % tile)
+    plan.set_expand_tile(0)
+    plan.close()
+
+
+def test_expand_tuner_keeps_results(mixed):
+    bd = _bd()
+    s, psi, cin, _, (e_ref, e_abs), _ = mixed
+    plan = bd.Plan.from_system(s)
+    scratch = torch.zeros(s.psi_shape, dtype=torch.float64, device="cuda")
+    r = plan.tune_expand(_dev(cin), scratch, reps=2)
+    assert r["candidates"] >= 4 and 0 < r["ms"] <= r["ms_before"]
+    assert plan.expand_form()[0] == r["mode"]
+    d_acc = _dev(psi)
+    plan.expand(_dev(cin), d_acc)
+    _check(_host(d_acc), e_ref, e_abs, "expand after tuning %s" % (r,))
+    plan.close()
