@@ -628,7 +628,9 @@ def batching(bd, wl, args):
                     "expand_z_ms": prof["expand_z"][1],
                     "expand_xy_ms": prof["expand_xy"][1],
                     "project_per_atom_box_GB/s":
-                        (units * 8 + plan.coeff_doubles * 8) / (prof["project"][1] * 1e-3) / 1e9}
+                        (units * 8 + plan.coeff_doubles * 8) / (prof["project"][1] * 1e-3) / 1e9,
+                    "hbm_bytes_counters": {k: measured_traffic(k, "batching")
+                                           for k in ("project", "expand_z", "expand_xy")}}
     g = plan.graph(psi, c, out)
     ms, _ = _time_steps(g.launch, steps, 1)
     res["graph"] = {"ms_per_step": ms, "value": units / (ms * 1e-3)}
