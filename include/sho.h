@@ -273,6 +273,16 @@ sho_status sho_plan_set_kpoint(sho_plan_t plan, const double *k);
  * queued with the plan finishes.  NULL is accepted. */
 sho_status sho_plan_destroy(sho_plan_t plan);
 
+/* Free the plan's own device scratch (the expansion's plane partials, also
+ * the block projection's plane sums: sho_plan_info.expand_scratch_doubles
+ * doubles), keeping its tables; the next call that needs the scratch
+ * allocates it again.  For a plan kept while its system's buffers are
+ * released (a server evicting a system it expects back).  Waits for the
+ * device first (queued work finishes).  Graphs captured before are refused
+ * afterwards (they hold the old address).  No-op for plans that hold no
+ * scratch.  Errors: SHO_E_INVALID (NULL), SHO_E_DEVICE. */
+sho_status sho_plan_release_scratch(sho_plan_t plan);
+
 sho_status sho_plan_get_info(sho_plan_t plan, sho_plan_info *info);
 
 /* off[a] = first element of atom a's block in c / w, off[natoms] = total.
@@ -561,10 +571,18 @@ sho_status sho_graph_destroy(sho_graph_t graph);
  * all on the system's resident buffers.  A system is made resident (plan
  * tables + psi, out, w, c, grad in device memory: its charge) on its first
  * request; when the charges would exceed budget_bytes, least recently used
- * other systems are evicted first.  A system whose charge alone exceeds the
- * budget is refused with SHO_E_BUDGET.  Requests of one system run in
+ * other systems are evicted first.  An evicted system keeps its plan's
+ * tables on the device (charged, without the plan's scratch, until they are
+ * needed: then least recently used kept plans are freed too), so that its
+ * next admission only uploads its inputs.  A system whose charge alone
+ * exceeds the budget is refused with SHO_E_BUDGET.  Requests of one system run in
  * submission order on one of nstreams streams (1..16, default priority);
- * different systems overlap.  plan_flags go to every plan (0, or
+ * different systems overlap.  With two or more streams the first is kept
+ * for short requests: those whose estimated cost (support points x bands x
+ * a per-job factor) is at most both the median and half the mean of the
+ * latest 256 requests' costs.  They never queue behind a long request; the
+ * other requests go to the remaining stream with the least outstanding
+ * estimated work.  plan_flags go to every plan (0, or
  * SHO_FLAG_PER_ATOM for the per-request reference); SHO_FLAG_HOST_ONLY makes
  * a server that only does the admission bookkeeping (no device use; every
  * request completes at once).
@@ -595,6 +613,9 @@ typedef struct sho_server_stats {
   int64_t requests, completed;
   int64_t admissions, evictions, rejected;
   int32_t systems, resident_systems;
+  int64_t short_requests;       /* requests sent to the short-request stream */
+  int64_t plan_reuses;          /* admissions that found the plan kept */
+  int64_t plan_drops;           /* kept plans freed to make room */
 } sho_server_stats;
 
 sho_status sho_server_create(int64_t budget_bytes, int32_t nstreams,

@@ -69,6 +69,7 @@ EXPORTS = (
     "sho_graph_create", "sho_graph_launch", "sho_graph_destroy",
     "sho_server_create", "sho_server_add_system", "sho_server_submit",
     "sho_server_drain", "sho_server_request_info", "sho_server_read",
+    "sho_plan_release_scratch",
     "sho_server_get_stats", "sho_server_system_info", "sho_server_inputs",
     "sho_server_clock", "sho_server_destroy", "sho_server_prefetch",
     "sho_setup_unitary", "sho_setup_radial", "sho_setup_matrix", "sho_setup_quality",
@@ -119,7 +120,9 @@ class sho_server_stats(ctypes.Structure):
                 ("peak_resident_bytes", ctypes.c_int64), ("requests", ctypes.c_int64),
                 ("completed", ctypes.c_int64), ("admissions", ctypes.c_int64),
                 ("evictions", ctypes.c_int64), ("rejected", ctypes.c_int64),
-                ("systems", ctypes.c_int32), ("resident_systems", ctypes.c_int32)]
+                ("systems", ctypes.c_int32), ("resident_systems", ctypes.c_int32),
+                ("short_requests", ctypes.c_int64), ("plan_reuses", ctypes.c_int64),
+                ("plan_drops", ctypes.c_int64)]
 
 
 _lib = None
@@ -156,6 +159,7 @@ def load_library(path=None):
                                            ctypes.c_int32, ctypes.c_double, _dp, ctypes.c_int32,
                                            ctypes.c_uint32, ctypes.POINTER(ctypes.c_void_p)]
     lib.sho_plan_destroy.argtypes = [P]
+    lib.sho_plan_release_scratch.argtypes = [P]
     lib.sho_plan_get_info.argtypes = [P, ctypes.POINTER(sho_plan_info)]
     lib.sho_plan_coeff_offsets.argtypes = [P, _i64p]
     lib.sho_plan_support_counts.argtypes = [P, _i64p]
@@ -536,6 +540,10 @@ class Plan:
         _check(self._lib.sho_plan_profile_read(self._h, cnt.ctypes.data_as(_i64p),
                                                ms.ctypes.data_as(_dp)))
         return {k: (int(cnt[i]), float(ms[i])) for i, k in enumerate(KERNEL_KINDS)}
+
+    def release_scratch(self):
+        """Free the plan's device scratch (plane partials); kept tables."""
+        _check(self._lib.sho_plan_release_scratch(self._h))
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

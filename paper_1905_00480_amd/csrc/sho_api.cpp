@@ -103,6 +103,7 @@ struct sho_plan_s {
   hipEvent_t scratch_ev = nullptr;
   hipStream_t scratch_stream = nullptr;
   bool scratch_used = false;
+  int64_t scratch_gen = 0;  // bumped when the scratch is released
   int64_t device_bytes = 0;
   int64_t stored_bytes = 0;
 };
@@ -992,6 +993,24 @@ sho_status sho_plan_destroy(sho_plan_t p) {
   return SHO_OK;
 }
 
+sho_status sho_plan_release_scratch(sho_plan_t p) {
+  if (!p) return fail(SHO_E_INVALID, "NULL plan");
+  if (!p->d_u2) return SHO_OK;
+  // queued calls and graph launches may still read the scratch
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  if (cur != p->device) (void)hipSetDevice(p->device);
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipFree(p->d_u2);
+  if (cur != p->device) (void)hipSetDevice(cur);
+  p->d_u2 = nullptr;
+  p->device_bytes -= std::max<int64_t>(p->hp.u2_doubles, 1) * sizeof(double);
+  p->scratch_used = false;
+  p->scratch_gen++;
+  if (e != hipSuccess) return hip_fail(e, "hipFree");
+  return SHO_OK;
+}
+
 sho_status sho_plan_profile(sho_plan_t p, int32_t enable) {
   if (!p) return fail(SHO_E_INVALID, "NULL plan");
   if (p->hp.flags & SHO_FLAG_HOST_ONLY)
@@ -1680,6 +1699,7 @@ sho_status sho_plan_apply(sho_plan_t p, const double *psi, const double *D, doub
 struct sho_graph_s {
   sho_plan_t plan = nullptr;
   int64_t sched_version = 0;
+  int64_t scratch_gen = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -1695,6 +1715,7 @@ sho_status capture(sho_plan_t p, F &&f, sho_graph_t *g) {
   if (!G) return fail(SHO_E_NOMEM, "host allocation failed");
   G->plan = p;
   G->sched_version = p->sched_version;
+  G->scratch_gen = p->scratch_gen;
   hipStream_t cs = nullptr;
   hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
@@ -1759,6 +1780,8 @@ sho_status sho_graph_launch(sho_graph_t g, void *stream) {
   if (!g) return fail(SHO_E_INVALID, "NULL graph");
   if (g->plan->sched_version != g->sched_version)
     return fail(SHO_E_INVALID, "the plan's schedule changed after the graph was made");
+  if (g->plan->scratch_gen != g->scratch_gen)
+    return fail(SHO_E_INVALID, "the plan's scratch was released after the graph was made");
   hipError_t e = hipGraphLaunch(g->exec, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "graph launch");
   return SHO_OK;

@@ -44,10 +44,13 @@ struct Sys {
   std::vector<double> pos, sigma;
   std::vector<int32_t> numax;
   int64_t psi_doubles = 0, coeff_doubles = 0;
-  int64_t charge = 0;  // bytes charged against the budget while resident
+  int64_t charge = 0;        // bytes charged against the budget while resident
+  int64_t table_charge = 0;  // of which the plan's tables (kept while parked)
   double *h_psi = nullptr, *h_w = nullptr;  // pinned inputs
-  // resident state
+  // resident: plan, scratch and buffers on the device; parked: only the
+  // plan's tables (evicted, the host-side plan build is kept); else neither
   bool resident = false;
+  bool parked = false;
   sho_plan_t plan = nullptr;
   double *d_psi = nullptr, *d_w = nullptr, *d_c = nullptr, *d_grad = nullptr,
          *d_out = nullptr;
@@ -80,10 +83,16 @@ struct sho_server_s {
   std::vector<hipStream_t> streams;
   std::mutex wmu;                    // stream_work
   std::vector<double> stream_work;   // outstanding estimated work per stream
+  // estimated costs of the latest requests (ring), for the short-request rule
+  static constexpr int kRecent = 256;
+  double recent[kRecent] = {};
+  int64_t nrecent = 0;
+  int64_t express = 0;  // requests sent to the short-request stream
   std::deque<std::unique_ptr<Sys>> systems;
   std::deque<std::unique_ptr<Req>> reqs;  // stable addresses
   int64_t resident_bytes = 0, peak_bytes = 0;
   int64_t admissions = 0, evictions = 0, rejected = 0;
+  int64_t plan_reuses = 0, plan_drops = 0;
   uint64_t tick = 0;
   Clock::time_point t0 = Clock::now();
   std::mutex mu;  // systems, admission, submission
@@ -148,61 +157,121 @@ void poll_loop(sho_server_s *S) {
   }
 }
 
-void free_resident(sho_server_s *S, Sys &y) {
-  if (!S->dry) {
-    if (y.last) (void)hipEventSynchronize(y.last);
-    for (double *q : {y.d_psi, y.d_w, y.d_c, y.d_grad, y.d_out})
-      if (q) (void)hipFree(q);
-    if (y.plan) (void)sho_plan_destroy(y.plan);
-    if (y.last) (void)hipEventDestroy(y.last);
-  }
+// Frees a system's buffers (psi, out, w, c, grad) once its queued work is done.
+void free_buffers(Sys &y) {
+  if (y.last) (void)hipEventSynchronize(y.last);
+  for (double *q : {y.d_psi, y.d_w, y.d_c, y.d_grad, y.d_out})
+    if (q) (void)hipFree(q);
   y.d_psi = y.d_w = y.d_c = y.d_grad = y.d_out = nullptr;
-  y.plan = nullptr;
-  y.last = nullptr;
-  y.resident = false;
-  S->resident_bytes -= y.charge;
 }
 
-// Makes room for `need` bytes by evicting least recently used systems other
-// than `keep`.  Returns false if even an empty device would not do.
+void free_plan(Sys &y) {
+  if (y.plan) (void)sho_plan_destroy(y.plan);
+  if (y.last) (void)hipEventDestroy(y.last);
+  y.plan = nullptr;
+  y.last = nullptr;
+}
+
+// Resident -> parked: the buffers and the plan's scratch go, the plan's
+// tables stay (a later admission skips the host-side plan build).
+void park(sho_server_s *S, Sys &y) {
+  if (!S->dry) {
+    free_buffers(y);
+    if (y.plan) (void)sho_plan_release_scratch(y.plan);
+  }
+  y.resident = false;
+  y.parked = true;
+  S->resident_bytes -= y.charge - y.table_charge;
+}
+
+// Parked -> not on the device at all.
+void drop(sho_server_s *S, Sys &y) {
+  if (!S->dry) free_plan(y);
+  y.parked = false;
+  S->resident_bytes -= y.table_charge;
+  S->plan_drops++;
+}
+
+// Makes room for `need` more bytes: parks least recently used resident
+// systems other than `keep`, then, if that is not enough, drops least
+// recently used parked plans.  Returns false if even that would not do.
 bool make_room(sho_server_s *S, int64_t need, int32_t keep) {
   if (need > S->budget) return false;
-  while (S->resident_bytes + need > S->budget) {
+  auto lru = [&](bool resident) {
     Sys *victim = nullptr;
     for (size_t k = 0; k < S->systems.size(); ++k) {
       Sys &y = *S->systems[k];
-      if ((int32_t)k == keep || !y.resident) continue;
+      if ((int32_t)k == keep || (resident ? !y.resident : !y.parked)) continue;
       if (!victim || y.last_use < victim->last_use) victim = &y;
     }
-    if (!victim) return false;
-    free_resident(S, *victim);
+    return victim;
+  };
+  while (S->resident_bytes + need > S->budget) {
+    Sys *victim = lru(true);
+    if (!victim) break;
+    park(S, *victim);
     S->evictions++;
+  }
+  while (S->resident_bytes + need > S->budget) {
+    Sys *victim = lru(false);
+    if (!victim) return false;
+    drop(S, *victim);
   }
   return true;
 }
 
-// The stream with the least outstanding work.
-int least_loaded(sho_server_s *S) {
+// The stream with the least outstanding work among streams first..n-1.
+int least_loaded(sho_server_s *S, int first = 0) {
   std::lock_guard<std::mutex> wl(S->wmu);
-  int best = 0;
-  for (size_t k = 1; k < S->stream_work.size(); ++k)
-    if (S->stream_work[k] < S->stream_work[best]) best = (int)k;
+  const int n = (int)S->stream_work.size();
+  int best = std::min(first, n - 1);
+  for (int k = best + 1; k < n; ++k)
+    if (S->stream_work[k] < S->stream_work[best]) best = k;
   return best;
+}
+
+// Stream of a request of estimated cost `cost`.  With two or more streams
+// the first one is kept for short requests, so that they never queue behind
+// a long one: a request is short when its cost is at most both the median
+// and half the mean of the latest kRecent requests' costs (the current one
+// included; a pool of equal requests has none).  Every other request goes to
+// the remaining stream with the least outstanding work.
+int choose_stream(sho_server_s *S, double cost, bool *is_short) {
+  S->recent[S->nrecent % sho_server_s::kRecent] = cost;
+  S->nrecent++;
+  *is_short = false;
+  const int n = (int)S->stream_work.size();
+  if (n < 2) return 0;
+  const int m = (int)std::min<int64_t>(S->nrecent, sho_server_s::kRecent);
+  double v[sho_server_s::kRecent];
+  double sum = 0.0;
+  for (int k = 0; k < m; ++k) sum += (v[k] = S->recent[k]);
+  std::nth_element(v, v + m / 2, v + m);
+  if (cost <= v[m / 2] && cost <= 0.5 * sum / m) {
+    *is_short = true;
+    return 0;
+  }
+  return least_loaded(S, 1);
 }
 
 sho_status admit(sho_server_s *S, int32_t id) {
   Sys &y = *S->systems[id];
-  if (!make_room(S, y.charge, id)) {
+  const bool reuse = y.parked;  // the plan's tables are still on the device
+  const int64_t need = reuse ? y.charge - y.table_charge : y.charge;
+  if (y.charge > S->budget || !make_room(S, need, id)) {
     S->rejected++;
     return fail(SHO_E_BUDGET, "system needs " + std::to_string(y.charge) +
                                   " bytes of a budget of " + std::to_string(S->budget));
   }
   if (!S->dry) {
-    const int best = least_loaded(S);
+    // inputs are uploaded on a stream of the long requests
+    const int best = least_loaded(S, S->stream_work.size() > 1 ? 1 : 0);
     y.stream = best;
     hipStream_t st = S->streams[best];
-    sho_status r = sho_plan_create(&y.grid, y.natoms, y.pos.data(), y.sigma.data(),
-                                   y.numax.data(), nullptr, y.nbands, S->flags, &y.plan);
+    sho_status r = SHO_OK;
+    if (!reuse)
+      r = sho_plan_create(&y.grid, y.natoms, y.pos.data(), y.sigma.data(), y.numax.data(),
+                          nullptr, y.nbands, S->flags, &y.plan);
     hipError_t e = hipSuccess;
     const size_t pb = y.psi_doubles * sizeof(double), cb = std::max<int64_t>(y.coeff_doubles, 1) * 8;
     if (r == SHO_OK) {
@@ -212,27 +281,29 @@ sho_status admit(sho_server_s *S, int32_t id) {
           (e = hipMalloc((void **)&y.d_c, cb)) == hipSuccess &&
           (e = hipMalloc((void **)&y.d_grad, std::max(3 * y.natoms, 1) * sizeof(double))) ==
               hipSuccess &&
-          (e = hipEventCreateWithFlags(&y.last, hipEventDisableTiming)) == hipSuccess &&
+          (y.last || (e = hipEventCreateWithFlags(&y.last, hipEventDisableTiming)) == hipSuccess) &&
           (e = hipMemcpyAsync(y.d_psi, y.h_psi, pb, hipMemcpyHostToDevice, st)) == hipSuccess &&
           (e = hipMemcpyAsync(y.d_w, y.h_w, y.coeff_doubles * sizeof(double),
                               hipMemcpyHostToDevice, st)) == hipSuccess)
         e = hipEventRecord(y.last, st);  // requests on other streams wait for the upload
-      sho_plan_info info;
-      if (e == hipSuccess && sho_plan_get_info(y.plan, &info) == SHO_OK)
-        y.units = (double)info.support_points * y.nbands;
     }
     if (r != SHO_OK || e != hipSuccess) {
       const std::string why = r != SHO_OK ? std::string(sho_last_error()) : "";
-      y.resident = true;  // so that free_resident releases what exists
-      S->resident_bytes += y.charge;
-      free_resident(S, y);
+      free_buffers(y);
+      free_plan(y);
+      if (reuse) {
+        y.parked = false;
+        S->resident_bytes -= y.table_charge;
+      }
       if (r != SHO_OK) return fail(r, "admission: " + why);
       return e == hipErrorOutOfMemory ? fail(SHO_E_NOMEM, "admission: device allocation failed")
                                       : hip_fail(e, "admission");
     }
   }
+  if (reuse) S->plan_reuses++;
+  y.parked = false;
   y.resident = true;
-  S->resident_bytes += y.charge;
+  S->resident_bytes += need;
   S->peak_bytes = std::max(S->peak_bytes, S->resident_bytes);
   S->admissions++;
   return SHO_OK;
@@ -289,9 +360,9 @@ sho_status sho_server_create(int64_t budget_bytes, int32_t nstreams, uint32_t pl
       }
       S->streams.push_back(st);
     }
-    S->stream_work.assign(nstreams, 0.0);
     S->poller = std::thread(poll_loop, S.get());
   }
+  S->stream_work.assign(nstreams, 0.0);
   *out = S.release();
   return SHO_OK;
 }
@@ -324,6 +395,10 @@ sho_status sho_server_add_system(sho_server_t S, const sho_grid *grid, int32_t n
   auto pg = [](int64_t b) { return (b + 4095) / 4096 * 4096; };
   y->charge = pg(info.device_bytes) + 2 * pg(y->psi_doubles * 8) +
               2 * pg(std::max<int64_t>(y->coeff_doubles, 1) * 8) + pg(24 * std::max(natoms, 1));
+  // the plan's tables without its scratch (the plane partials)
+  y->table_charge =
+      pg(info.device_bytes - std::max<int64_t>(info.expand_scratch_doubles, 1) * 8);
+  y->units = (double)info.support_points * nbands;
   if (!S->dry) {
     hipError_t e = hipHostMalloc((void **)&y->h_psi, y->psi_doubles * sizeof(double));
     if (e == hipSuccess)
@@ -368,16 +443,19 @@ sho_status sho_server_submit(sho_server_t S, int32_t sys, int32_t job, int64_t *
   q->sysp = &y;
   q->job = job;
   q->t_submit = t_submit;
+  // short requests on their own stream, the others by least outstanding
+  // work; after the system's previous request if that ran (or its inputs
+  // were uploaded) on another stream
+  q->cost = job_cost(y.units, job);
+  bool is_short = false;
+  const int st_new = choose_stream(S, q->cost, &is_short);
+  if (is_short) S->express++;
   if (!S->dry) {
-    // least outstanding work; after the system's previous request if that
-    // ran (or its inputs were uploaded) on another stream
-    const int st_new = least_loaded(S);
     if (st_new != y.stream) {
       hipError_t e = hipStreamWaitEvent(S->streams[st_new], y.last, 0);
       if (e != hipSuccess) return hip_fail(e, "stream ordering");
       y.stream = st_new;
     }
-    q->cost = job_cost(y.units, job);
     std::lock_guard<std::mutex> wl(S->wmu);
     S->stream_work[y.stream] += q->cost;
   }
@@ -510,6 +588,9 @@ sho_status sho_server_get_stats(sho_server_t S, sho_server_stats *st) {
   for (const auto &y : S->systems) res += y->resident ? 1 : 0;
   st->systems = (int32_t)S->systems.size();
   st->resident_systems = res;
+  st->short_requests = S->express;
+  st->plan_reuses = S->plan_reuses;
+  st->plan_drops = S->plan_drops;
   return SHO_OK;
 }
 
@@ -550,7 +631,8 @@ sho_status sho_server_destroy(sho_server_t S) {
     if (S->poller.joinable()) S->poller.join();
   }
   for (auto &y : S->systems) {
-    if (y->resident) free_resident(S, *y);
+    if (y->resident) park(S, *y);
+    if (y->parked) drop(S, *y);
     if (y->h_psi) (void)hipHostFree(y->h_psi);
     if (y->h_w) (void)hipHostFree(y->h_w);
   }

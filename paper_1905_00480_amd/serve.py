@@ -62,8 +62,27 @@ def units_of(pool):
     return np.array(out, dtype=np.float64)
 
 
+def alone_ms(server, sids, which, reps=3):
+    """Latency (ms) of each job of the systems `which` on an otherwise idle
+    device, one request at a time: the least time a request to them can
+    take in the stream (median of reps)."""
+    out = {}
+    for k in which:
+        row = []
+        for job in (0, 1, 2):
+            t = []
+            for _ in range(reps):
+                rid = server.submit(sids[k], job)
+                server.drain()
+                _, _, t_sub, t_done = server.request_info(rid)
+                t.append(1e3 * (t_done - t_sub))
+            row.append(float(np.median(t)))
+        out[int(k)] = row
+    return out
+
+
 def run(server, sids, units, rate_hz=200.0, warmup=200, requests=2000, seed=4,
-        preload=True):
+        preload=True, alone_largest=False):
     """Submit a Poisson stream (warm-up requests first, not measured) and
     return throughput and latency percentiles of the measured requests.  With
     preload, every system that fits the budget is made resident first (as a
@@ -109,6 +128,7 @@ def run(server, sids, units, rate_hz=200.0, warmup=200, requests=2000, seed=4,
     sel = np.array([int(which[i]) in big for i in range(warmup, count)])
     work = float(units[which[warmup:]].sum())
     st = server.stats()
+    alone = alone_ms(server, sids, sorted(big)) if alone_largest else None
     return {"requests": requests, "warmup": warmup, "rate_hz": rate_hz,
             "span_s": span, "req_per_s": requests / span,
             "gridpoint*bands/s": work / span,
@@ -122,6 +142,8 @@ def run(server, sids, units, rate_hz=200.0, warmup=200, requests=2000, seed=4,
                                           for q in (50, 99)] if (~sel).any() else None,
             "jobs": {j: int(np.sum(np.array(jobs) == k))
                      for k, j in enumerate(("project", "expand", "force"))},
+            "short_requests": st["short_requests"],
+            "alone_ms_largest3": alone,
             "admissions": st["admissions"], "evictions": st["evictions"],
             "peak_resident_GB": st["peak_resident_bytes"] / 1e9}
 
@@ -152,7 +174,7 @@ def compare(budget_bytes=64 << 30, nstreams=4, rate_hz=200.0, warmup=200, reques
         sids = register(srv, pool, seed)
         reg_s = time.perf_counter() - t0
         _log("%s: registered in %.1f s" % (name, reg_s))
-        r = run(srv, sids, units, rate_hz, nw, nr, seed)
+        r = run(srv, sids, units, rate_hz, nw, nr, seed, alone_largest=(name == "batched"))
         _log("%s: %d requests, p50 %.2f ms, p99 %.2f ms, %.1f req/s"
              % (name, nr, r["latency_ms_p50"], r["latency_ms_p99"], r["req_per_s"]))
         r["streams"] = streams

@@ -99,13 +99,27 @@ def test_mix_equals_alone_and_oracle(reference):
     srv.close()
 
 
-def test_eviction_and_readmission(reference):
+def _tables(bd, s):
+    p = bd.Plan(s.n, s.h, s.periodic, s.pos, s.sigma, s.numax, s.nbands,
+                flags=bd.FLAG_HOST_ONLY)
+    b = p.info["device_bytes"] - max(p.info["expand_scratch_doubles"], 1) * 8
+    p.close()
+    return (b + 4095) // 4096 * 4096
+
+
+@pytest.mark.parametrize("keep_plans", [False, True])
+def test_eviction_and_readmission(reference, keep_plans):
+    """Evicted systems admitted again give the same results, whether their
+    plans had to be freed (budget of the two largest systems) or were kept
+    (room for every plan's tables besides)."""
     bd = _bd()
     pool, ref = reference
     probe = bd.Server(1 << 34, 1, bd.FLAG_HOST_ONLY)
     charges = [probe.system_info(probe.add(s))[0] for s in pool]
     probe.close()
     budget = sorted(charges)[-1] + sorted(charges)[-2]
+    if keep_plans:
+        budget += sum(_tables(bd, s) for s in pool)
     srv = bd.Server(budget, 2, 0)
     sids, _ = _register(bd, srv, pool)
     for rnd in range(3):
@@ -119,6 +133,8 @@ def test_eviction_and_readmission(reference):
     st = srv.stats()
     assert st["evictions"] > 0 and st["admissions"] > len(pool)
     assert st["peak_resident_bytes"] <= budget
+    if keep_plans:
+        assert st["plan_reuses"] > 0 and st["plan_drops"] == 0
     for j in JOBS:
         _check(srv.read(sids[last], j), ref[last][j], "after re-admission job %d" % j)
     srv.close()

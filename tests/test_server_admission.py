@@ -59,11 +59,88 @@ def test_lru_eviction_order_and_stats():
     st = srv.stats()
     assert st["admissions"] == 3 and st["evictions"] == 1 and st["rejected"] == 0
     assert st["requests"] == 4 and st["completed"] == 4
-    assert st["resident_bytes"] == charges[1] + charges[3] <= budget
+    # system 2 keeps its plan tables unless they had to go as well
+    kept = 0 if st["plan_drops"] else _table_charge(systems[2])
+    assert st["resident_bytes"] == charges[1] + charges[3] + kept <= budget
     assert st["peak_resident_bytes"] <= budget
     # a request to a resident system admits nothing
     srv.submit(sids[1], bd.JOB_FORCE)
     assert srv.stats()["admissions"] == 3
+    srv.close()
+
+
+def _table_charge(s):
+    """Bytes a parked system keeps charged: its plan's tables without the
+    scratch, rounded up to 4 KiB as the server does."""
+    p = bd.Plan(s.n, s.h, s.periodic, s.pos, s.sigma, s.numax, s.nbands,
+                flags=bd.FLAG_HOST_ONLY)
+    b = p.info["device_bytes"] - max(p.info["expand_scratch_doubles"], 1) * 8
+    p.close()
+    return (b + 4095) // 4096 * 4096
+
+
+def test_evicted_systems_keep_their_plans():
+    """Eviction parks a system (its buffers go, its plan's tables stay
+    charged); its next admission reuses the plan.  Parked plans are freed,
+    least recently used first, only when the room is needed."""
+    systems = _systems()
+    probe, sids = _server(1 << 40, systems)
+    charges = [probe.system_info(i)[0] for i in sids]
+    probe.close()
+    tables = [_table_charge(s) for s in systems]
+    assert all(0 < t < c for t, c in zip(tables, charges))
+    # room for systems 2 and 3 plus every plan's tables
+    budget = charges[2] + charges[3] + sum(tables)
+    srv, sids = _server(budget, systems)
+    srv.submit(sids[2], bd.JOB_PROJECT)
+    srv.submit(sids[3], bd.JOB_PROJECT)
+    srv.submit(sids[1], bd.JOB_EXPAND)            # parks 2
+    st = srv.stats()
+    assert [srv.system_info(i)[1] for i in sids] == [False, True, False, True]
+    assert st["evictions"] == 1 and st["plan_reuses"] == 0 and st["plan_drops"] == 0
+    assert st["resident_bytes"] == charges[1] + charges[3] + tables[2]
+    srv.submit(sids[2], bd.JOB_FORCE)             # parks 3, reuses 2's plan
+    st = srv.stats()
+    assert [srv.system_info(i)[1] for i in sids] == [False, True, True, False]
+    assert st["admissions"] == 4 and st["evictions"] == 2
+    assert st["plan_reuses"] == 1 and st["plan_drops"] == 0
+    assert st["resident_bytes"] == charges[1] + charges[2] + tables[3]
+    srv.close()
+    # a budget of exactly the largest charge: the parked tables must go too
+    srv, sids = _server(charges[3], systems)
+    srv.submit(sids[0], bd.JOB_PROJECT)
+    srv.submit(sids[3], bd.JOB_PROJECT)
+    st = srv.stats()
+    assert [srv.system_info(i)[1] for i in sids] == [False, False, False, True]
+    assert st["evictions"] == 1 and st["plan_drops"] == 1
+    assert st["resident_bytes"] == charges[3]
+    srv.submit(sids[0], bd.JOB_PROJECT)           # a new plan: nothing was kept
+    assert srv.stats()["plan_reuses"] == 0
+    srv.close()
+
+
+def test_short_request_rule():
+    """With several streams, requests whose estimated cost is at most the
+    median and half the mean of the recent requests' costs count as short;
+    with one stream, or a pool of equal requests, none does."""
+    bd.load_library()
+    small = wl.small_periodic(seed=40, natoms=1, nbands=2)
+    big = wl.small_periodic(seed=41, natoms=8, nbands=64)
+    for nstreams, expect_short in ((1, False), (4, True)):
+        srv = bd.Server(1 << 40, nstreams, bd.FLAG_HOST_ONLY)
+        a, b = srv.add(small), srv.add(big)
+        for k in range(20):
+            srv.submit(b if k % 2 else a, bd.JOB_PROJECT)
+        n_short = srv.stats()["short_requests"]
+        # every request to the small system (but possibly the first, seen
+        # alone) and none to the big one
+        assert (9 <= n_short <= 10) if expect_short else n_short == 0
+        srv.close()
+    srv = bd.Server(1 << 40, 4, bd.FLAG_HOST_ONLY)
+    a = srv.add(small)
+    for _ in range(10):
+        srv.submit(a, bd.JOB_PROJECT)
+    assert srv.stats()["short_requests"] == 0
     srv.close()
 
 
