@@ -315,6 +315,7 @@ sho::KArgs make_args(const sho_plan_s *p, const Group &g) {
   K.stored = p->d_stored;
   K.run_poff = p->d_run_poff;
   K.nwork = g.count;
+  K.nlines = (int32_t)std::max<size_t>(p->hp.lines.size(), 1);
   K.nx = p->hp.grid.n[0];
   K.B = p->hp.nbands;
   K.tb_shift = p->hp.tb_shift;
@@ -718,7 +719,7 @@ sho_status finish_plan(sho_plan_s *p, uint32_t flags, int32_t nbands, bool f32,
   const size_t lds_div = f32 ? 2 : (flags & SHO_FLAG_DETERMINISTIC) ? sho::kWaves : 1;
   if (flags & SHO_FLAG_HOST_ONLY) {
     // geometry and sizes only; work split as for a 64 KiB workgroup LDS
-    const int tbs = sho::choose_tb_shift(nbands, p->hp.nu_max, (65536 - 1024) / lds_div);
+    const int tbs = sho::choose_tb_shift(nbands, p->hp.nu_max, (65536 - sho::kStaticLds) / lds_div);
     if (tbs < 0 || (p->bloch && !f32 && tbs < 1)) {
       delete p;
       return fail(SHO_E_BOX, "coefficient tile too large for the workgroup LDS");
@@ -741,7 +742,7 @@ sho_status finish_plan(sho_plan_s *p, uint32_t flags, int32_t nbands, bool f32,
     delete p;
     return hip_fail(e, "hipDeviceGetAttribute");
   }
-  p->lds_limit = (size_t)std::max(shm - 1024, 0) / lds_div;  // static LDS of the kernels
+  p->lds_limit = (size_t)std::max(shm - sho::kStaticLds, 0) / lds_div;  // static LDS of the kernels
   const int tbs = sho::choose_tb_shift(nbands, p->hp.nu_max, p->lds_limit);
   if (tbs < 0 || (p->bloch && !f32 && tbs < 1)) {
     delete p;
@@ -1252,7 +1253,7 @@ sho_status sho_plan_set_schedule(sho_plan_t p, int32_t schedule, int32_t band_ti
   if (p->bloch && !p->fp32 && tbs < 1)
     return fail(SHO_E_INVALID, "Bloch plans keep the real and imaginary lanes in one tile");
   const size_t limit = (p->hp.flags & SHO_FLAG_HOST_ONLY)
-                           ? (65536 - 1024) / (p->fp32 ? 2
+                           ? (65536 - sho::kStaticLds) / (p->fp32 ? 2
                                                : (p->hp.flags & SHO_FLAG_DETERMINISTIC) ? sho::kWaves
                                                                                         : 1)
                            : p->lds_limit;

@@ -81,6 +81,10 @@ static_assert(sizeof(BundleRec) == 16, "BundleRec layout");
 
 // Waves per workgroup of the streaming kernels.
 constexpr int kWaves = 8;
+// Bytes of LDS the kernels may declare statically (the streaming kernels'
+// staged line records and small reduction arrays); the coefficient tiles get
+// the rest of a workgroup's LDS.
+constexpr int kStaticLds = 1024 + kWaves * 64 * 16;
 
 // One workgroup's share of an atom: a contiguous range of its bundles, cut
 // into kWaves cost-balanced wave ranges.  `split` is set when the atom is

@@ -38,6 +38,9 @@ constexpr int kBlock = 64 * kWaves;
 #define SHO_NU_CASES(X) \
   X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10)
 constexpr int kBatch = 8;  // loads in flight per lane and batch
+constexpr int kLineStage = 64;  // line records per wave held in LDS
+static_assert(kWaves * kLineStage * sizeof(LineRec) + 1024 <= kStaticLds,
+              "static LDS of the streaming kernels");
 
 // waves per SIMD the register allocator must allow (4 keeps <= 128 VGPRs)
 constexpr int waves_per_eu(int nf) { return nf <= 6 ? 4 : 2; }
@@ -149,6 +152,41 @@ __device__ inline RunState run_state(const KArgs &K, const Lanes &L,
   return r;
 }
 
+// The runs of a wave's bundles are consecutive line records.  The wave
+// copies kLineStage of them at a time into its LDS stage (one 16-byte load
+// per lane), so that moving to the next bundle reads its runs from LDS: a
+// global load there would make the wave wait for every load in flight
+// before it, the streamed psi of the current bundle included.
+__device__ inline void stage_lines(const KArgs &K, int base, LineRec *st) {
+  const int lane = threadIdx.x & 63;
+  const int i = min(base + lane, K.nlines - 1);
+  reinterpret_cast<int4 *>(st)[lane] = reinterpret_cast<const int4 *>(K.lines)[i];
+  __builtin_amdgcn_wave_barrier();
+}
+
+// The stage, one per wave of a workgroup (a single variable, so that a kernel
+// whose branches instantiate several cut-offs still allocates it once).
+__shared__ LineRec g_line_stage[kWaves][kLineStage];
+
+// run_state with the line records of [base, base + kLineStage) staged in st;
+// restages first if bd's runs reach past them.
+__device__ inline RunState run_state_staged(const KArgs &K, const Lanes &L, const double *psi,
+                                            const BundleRec &bd, LineRec *st, int &base) {
+  if (bd.run0 + bd.nruns > base + kLineStage) {
+    base = bd.run0;
+    stage_lines(K, base, st);
+  }
+  const int s = min(L.slot, bd.nruns - 1);
+  const LineRec ln = st[bd.run0 + s - base];
+  RunState r;
+  r.base = psi + ((int64_t)ln.row * K.nx + ln.x0m) * K.B + L.bc;
+  r.jx0 = ln.jx0;
+  r.len = ln.len;
+  r.jy = ln.jy;
+  r.active = L.slot < bd.nruns;
+  return r;
+}
+
 // Complex bands: lanes hold the real (even band) and imaginary (odd band)
 // part of one band, in neighbouring lanes.  v <- e^{+-i th} v for the pair:
 // sgn_s = -s on real lanes and +s on imaginary lanes multiplies by e^{+i th};
@@ -224,73 +262,97 @@ __device__ inline void project_bundles(const KArgs &K, const AtomRec &A,
   const double *ty = K.tab + A.tab_off + (int64_t)A.mx * nfp;
   const cptr<double> tz = tx + (int64_t)(A.mx + A.my) * nfp;
 
-  double T2[NP];
+  double T1[NF], T2[NP];
+#pragma unroll
+  for (int n = 0; n < NF; ++n) T1[n] = 0.0;
 #pragma unroll
   for (int q = 0; q < NP; ++q) T2[q] = 0.0;
-  int cur_jz = -1;
-  BundleRec bd = load_uniform(K.bundles + b0);
-  RunState rs = run_state(K, L, psi, bd);
-  double v[kBatch];
-  load_batch(K, rs, bd.jlo, v);
-  for (int bi = b0; bi < b1; ++bi) {
-    if (bd.jz != cur_jz) {
-      if (cur_jz >= 0) flush_plane<NU, DET>(tz + cur_jz * nfp, T2, cacc, L);
-      cur_jz = bd.jz;
-    }
-    double T1[NF];
-#pragma unroll
-    for (int n = 0; n < NF; ++n) T1[n] = 0.0;
+  LineRec *st = g_line_stage[wave_id()];
+  int bi = b0;
+  BundleRec bd = load_uniform(K.bundles + bi);
+  int sbase = bd.run0;
+  stage_lines(K, sbase, st);
+  RunState rs = run_state_staged(K, L, psi, bd, st, sbase);
+  int jb = bd.jlo;
+  // One batch: request the next batch (of this bundle or the next one) into
+  // nxt, contract cur, and at the bundle's end take the y pass and, at the
+  // plane's end, the z pass.  Returns false after the last batch.  The loop
+  // below alternates the two buffers instead of copying nxt into cur (a copy
+  // would wait for the loads just issued), and runs both steps of a round
+  // unconditionally, the second idle (live false: loads of valid addresses,
+  // zero weights) once the first was the last: an exit between the two
+  // would let the compiler's waits count the first step's loads as in
+  // flight at the top of the loop.
+  auto step = [&](double (&cur)[kBatch], double (&nxt)[kBatch], bool live) -> bool {
     BundleRec nbd = bd;
     RunState nrs = rs;
-    for (int jb = bd.jlo; jb <= bd.jhi; jb += kBatch) {
-      double w[kBatch];
-      if (jb + kBatch <= bd.jhi) {
-        load_batch(K, rs, jb + kBatch, w);
-      } else if (bi + 1 < b1) {
-        nbd = load_uniform(K.bundles + bi + 1);
-        nrs = run_state(K, L, psi, nbd);
-        load_batch(K, nrs, nbd.jlo, w);
-      } else {
+    int njb = jb + kBatch;
+    const bool end = live && njb > bd.jhi;  // last batch of the bundle
+    const bool more = live && (njb <= bd.jhi || bi + 1 < b1);
+    // the y table row of this lane's run, requested before the next batch so
+    // that waiting for it leaves that batch in flight
+    double fy[NF];
+    if (end) {
+      const double *ry = ty + rs.jy * nfp;
 #pragma unroll
-        for (int u = 0; u < kBatch; ++u) w[u] = 0.0;
+      for (int n = 0; n < NF; ++n) fy[n] = ry[n];
+    }
+    if (end && more) {
+      nbd = load_uniform(K.bundles + bi + 1);
+      nrs = run_state_staged(K, L, psi, nbd, st, sbase);
+      njb = nbd.jlo;
+    }
+    // issued also after the last batch (valid addresses of the last run,
+    // unused): a load on one path only makes the waits of the other path
+    // count it as still in flight
+    load_batch(K, nrs, njb, nxt);
+    // every loaded value is consumed (zero weight past the bundle's end), so
+    // that no load is left pending into registers that are loaded again
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int jx = jb + u;
+      const int k = jx - rs.jx0;
+      const bool ok = live && jx <= bd.jhi && rs.active && k >= 0 && k < rs.len;
+      const double xv = ok ? cur[u] : 0.0;
+      const cptr<double> f = tx + min(jx, (int)bd.jhi) * nfp;
+#pragma unroll
+      for (int n = 0; n < NF; ++n) T1[n] = fma(f[n], xv, T1[n]);
+    }
+    if (end) {
+      if constexpr (CPLX) {
+        // the bundle's runs share one periodic image T, which carries
+        // e^{+i k.T} (cos, sin from the plan's table: scalar loads)
+        const cptr<double> ph = as_const(K.bundle_phase) + 2 * bi;
+        const double pc = ph[0], ps = ph[1];
+        const double sg = (L.bl & 1) ? ps : -ps;
+#pragma unroll
+        for (int n = 0; n < NF; ++n) T1[n] = rotate_pair(T1[n], pc, sg);
+      }
+      // y pass with this lane's run
+      int q = 0;
+#pragma unroll
+      for (int ny = 0; ny < NF; ++ny) {
+        const double fv = fy[ny];
+#pragma unroll
+        for (int nx = 0; nx < NF - ny; ++nx, ++q) T2[q] = fma(fv, T1[nx], T2[q]);
       }
 #pragma unroll
-      for (int u = 0; u < kBatch; ++u) {
-        const int jx = jb + u;
-        if (jx <= bd.jhi) {
-          const int k = jx - rs.jx0;
-          const bool ok = rs.active && k >= 0 && k < rs.len;
-          const double xv = ok ? v[u] : 0.0;
-          const cptr<double> f = tx + jx * nfp;
-#pragma unroll
-          for (int n = 0; n < NF; ++n) T1[n] = fma(f[n], xv, T1[n]);
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < kBatch; ++u) v[u] = w[u];
-    }
-    if constexpr (CPLX) {
-      // the bundle's runs share one periodic image T, which carries e^{+i k.T}
-      // (cos, sin from the plan's table: scalar loads)
-      const cptr<double> ph = as_const(K.bundle_phase) + 2 * bi;
-      const double pc = ph[0], ps = ph[1];
-      const double sg = (L.bl & 1) ? ps : -ps;
-#pragma unroll
-      for (int n = 0; n < NF; ++n) T1[n] = rotate_pair(T1[n], pc, sg);
-    }
-    // y pass with this lane's run
-    const double *fy = ty + rs.jy * nfp;
-    int q = 0;
-#pragma unroll
-    for (int ny = 0; ny < NF; ++ny) {
-      const double fv = fy[ny];
-#pragma unroll
-      for (int nx = 0; nx < NF - ny; ++nx, ++q) T2[q] = fma(fv, T1[nx], T2[q]);
+      for (int n = 0; n < NF; ++n) T1[n] = 0.0;
+      if (!more || nbd.jz != bd.jz) flush_plane<NU, DET>(tz + bd.jz * nfp, T2, cacc, L);
+      ++bi;
     }
     bd = nbd;
     rs = nrs;
-  }
-  flush_plane<NU, DET>(tz + cur_jz * nfp, T2, cacc, L);
+    jb = njb;
+    return more;
+  };
+  double v[kBatch], w[kBatch];
+  load_batch(K, rs, jb, v);
+  bool more = true;
+  do {
+    more = step(v, w, true);
+    more = step(w, v, more);
+  } while (more);
 }
 
 // One work item of the projection: zero the LDS tile, stream the item's

@@ -101,6 +101,38 @@ __device__ inline RunState run_state(const KArgs &K, const Lanes &L, const Pair 
   return r;
 }
 
+// Line records staged per wave in LDS (see the FP64 unit): moving to the
+// next bundle reads its runs there instead of waiting for a global load
+// issued behind the streamed psi.
+constexpr int kLineStage = 64;
+static_assert(kWaves * kLineStage * sizeof(LineRec) + 1024 <= kStaticLds,
+              "static LDS of the streaming kernels");
+__shared__ LineRec g_line_stage[kWaves][kLineStage];
+
+__device__ inline void stage_lines(const KArgs &K, int base, LineRec *st) {
+  const int lane = threadIdx.x & 63;
+  const int i = min(base + lane, K.nlines - 1);
+  reinterpret_cast<int4 *>(st)[lane] = reinterpret_cast<const int4 *>(K.lines)[i];
+  __builtin_amdgcn_wave_barrier();
+}
+
+__device__ inline RunState run_state_staged(const KArgs &K, const Lanes &L, const Pair *psi,
+                                            const BundleRec &bd, LineRec *st, int &base) {
+  if (bd.run0 + bd.nruns > base + kLineStage) {
+    base = bd.run0;
+    stage_lines(K, base, st);
+  }
+  const int s = min(L.slot, bd.nruns - 1);
+  const LineRec ln = st[bd.run0 + s - base];
+  RunState r;
+  r.base = psi + ((int64_t)ln.row * K.nx + ln.x0m) * K.B + L.bc;
+  r.jx0 = ln.jx0;
+  r.len = ln.len;
+  r.jy = ln.jy;
+  r.active = L.slot < bd.nruns;
+  return r;
+}
+
 // A complex band as one pair (a = real, b = imaginary part): v e^{i th} for
 // sn = sin th, or v e^{-i th} for sn = -sin th.
 __device__ inline Pair rotate(Pair v, float cs, float sn) {
@@ -175,71 +207,84 @@ __device__ inline void project_bundles(const KArgs &K, const float *tab, const A
   const float *ty = tab + A.tab_off + (int64_t)A.mx * nfp;
   const cptr<float> tz = tx + (int64_t)(A.mx + A.my) * nfp;
 
-  Pair T2[NP];
+  Pair T1[NF], T2[NP];
+#pragma unroll
+  for (int n = 0; n < NF; ++n) T1[n] = zero2();
 #pragma unroll
   for (int q = 0; q < NP; ++q) T2[q] = zero2();
-  int cur_jz = -1;
-  BundleRec bd = load_uniform(K.bundles + b0);
-  RunState rs = run_state(K, L, psi, bd);
-  Pair v[kBatch];
-  load_batch(K, rs, bd.jlo, v);
-  for (int bi = b0; bi < b1; ++bi) {
-    if (bd.jz != cur_jz) {
-      if (cur_jz >= 0) flush_plane<NU>(tz + cur_jz * nfp, T2, cacc, L);
-      cur_jz = bd.jz;
-    }
-    Pair T1[NF];
-#pragma unroll
-    for (int n = 0; n < NF; ++n) T1[n] = zero2();
+  LineRec *st = g_line_stage[wave_id()];
+  int bi = b0;
+  BundleRec bd = load_uniform(K.bundles + bi);
+  int sbase = bd.run0;
+  stage_lines(K, sbase, st);
+  RunState rs = run_state_staged(K, L, psi, bd, st, sbase);
+  int jb = bd.jlo;
+  // One batch, as in the FP64 unit: request the next batch into nxt (also
+  // when idle, from valid addresses), contract cur (zero weights when idle
+  // or past the bundle), y pass at the bundle's end, z pass at the plane's
+  // end; the loop alternates the buffers and runs both steps of a round.
+  auto step = [&](Pair (&cur)[kBatch], Pair (&nxt)[kBatch], bool live) -> bool {
     BundleRec nbd = bd;
     RunState nrs = rs;
-    for (int jb = bd.jlo; jb <= bd.jhi; jb += kBatch) {
-      Pair w[kBatch];
-      if (jb + kBatch <= bd.jhi) {
-        load_batch(K, rs, jb + kBatch, w);
-      } else if (bi + 1 < b1) {
-        nbd = load_uniform(K.bundles + bi + 1);
-        nrs = run_state(K, L, psi, nbd);
-        load_batch(K, nrs, nbd.jlo, w);
-      } else {
+    int njb = jb + kBatch;
+    const bool end = live && njb > bd.jhi;
+    const bool more = live && (njb <= bd.jhi || bi + 1 < b1);
+    float fy[NF];
+    if (end) {
+      const float *ry = ty + rs.jy * nfp;
 #pragma unroll
-        for (int u = 0; u < kBatch; ++u) w[u] = zero2();
+      for (int n = 0; n < NF; ++n) fy[n] = ry[n];
+    }
+    if (end && more) {
+      nbd = load_uniform(K.bundles + bi + 1);
+      nrs = run_state_staged(K, L, psi, nbd, st, sbase);
+      njb = nbd.jlo;
+    }
+    load_batch(K, nrs, njb, nxt);
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int jx = jb + u;
+      const int k = jx - rs.jx0;
+      const bool ok = live && jx <= bd.jhi && rs.active && k >= 0 && k < rs.len;
+      const Pair xv = ok ? cur[u] : zero2();
+      const cptr<float> f = tx + min(jx, (int)bd.jhi) * nfp;
+#pragma unroll
+      for (int n = 0; n < NF; ++n) T1[n] = fma2(f[n], xv, T1[n]);
+    }
+    if (end) {
+      if constexpr (CPLX) {
+        // the bundle's runs share one periodic image T, which carries
+        // e^{+i k.T} (cos, sin in double from the plan's table, rounded once
+        // to float)
+        const cptr<double> ph = as_const(K.bundle_phase) + 2 * bi;
+        const float pc = (float)ph[0], ps = (float)ph[1];
+#pragma unroll
+        for (int n = 0; n < NF; ++n) T1[n] = rotate(T1[n], pc, ps);
+      }
+      int q = 0;
+#pragma unroll
+      for (int ny = 0; ny < NF; ++ny) {
+        const float fv = fy[ny];
+#pragma unroll
+        for (int nx = 0; nx < NF - ny; ++nx, ++q) T2[q] = fma2(fv, T1[nx], T2[q]);
       }
 #pragma unroll
-      for (int u = 0; u < kBatch; ++u) {
-        const int jx = jb + u;
-        if (jx <= bd.jhi) {
-          const int k = jx - rs.jx0;
-          const bool ok = rs.active && k >= 0 && k < rs.len;
-          const Pair xv = ok ? v[u] : zero2();
-          const cptr<float> f = tx + jx * nfp;
-#pragma unroll
-          for (int n = 0; n < NF; ++n) T1[n] = fma2(f[n], xv, T1[n]);
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < kBatch; ++u) v[u] = w[u];
-    }
-    if constexpr (CPLX) {
-      // the bundle's runs share one periodic image T, which carries e^{+i k.T}
-      // (cos, sin in double from the plan's table, rounded once to float)
-      const cptr<double> ph = as_const(K.bundle_phase) + 2 * bi;
-      const float pc = (float)ph[0], ps = (float)ph[1];
-#pragma unroll
-      for (int n = 0; n < NF; ++n) T1[n] = rotate(T1[n], pc, ps);
-    }
-    const float *fy = ty + rs.jy * nfp;
-    int q = 0;
-#pragma unroll
-    for (int ny = 0; ny < NF; ++ny) {
-      const float fv = fy[ny];
-#pragma unroll
-      for (int nx = 0; nx < NF - ny; ++nx, ++q) T2[q] = fma2(fv, T1[nx], T2[q]);
+      for (int n = 0; n < NF; ++n) T1[n] = zero2();
+      if (!more || nbd.jz != bd.jz) flush_plane<NU>(tz + bd.jz * nfp, T2, cacc, L);
+      ++bi;
     }
     bd = nbd;
     rs = nrs;
-  }
-  flush_plane<NU>(tz + cur_jz * nfp, T2, cacc, L);
+    jb = njb;
+    return more;
+  };
+  Pair v[kBatch], w[kBatch];
+  load_batch(K, rs, jb, v);
+  bool more = true;
+  do {
+    more = step(v, w, true);
+    more = step(w, v, more);
+  } while (more);
 }
 
 template <int NU, bool CPLX = false>

@@ -24,6 +24,7 @@ struct KArgs {
   const double *stored;      // stored projectors (SHO_FLAG_STORED plans)
   const int64_t *run_poff;   // per run: first double of its stored block
   int32_t nwork;
+  int32_t nlines;            // line records in the plan
   int32_t nx;                // grid points along x
   int32_t B;                 // bands: stride of one grid point
   int32_t tb_shift;          // log2(bands per lane slot)
