@@ -150,6 +150,11 @@ constexpr int32_t kExpandRows = 0;
 constexpr int32_t kExpandBlocks = 1;
 constexpr int32_t kExpandOwner = 2;  // one wave per strip, values in registers
 constexpr int kBlockTileDoubles = 4096;  // LDS tile of a block workgroup
+// Tile of the FP64 block expansion for plans up to cut-off numax: twice the
+// size from 8 on, where the kernel's registers allow two waves per SIMD (two
+// workgroups per CU) anyway, so that a block holds more of each atom plane
+// and the plane partials are loaded fewer times.
+constexpr int blk_tile_doubles(int numax) { return numax >= 8 ? 2 * kBlockTileDoubles : kBlockTileDoubles; }
 
 // Rows handled by one expansion workgroup.
 constexpr int kRowsPerGroup = 1;
@@ -357,7 +362,9 @@ inline int plan_expand_shift(const HostPlan &P) {
 // Values (bands, or band pairs of SHO_FLAG_FP32 plans, which accumulate
 // both bands of a pair in double) that one block's LDS tile holds.
 inline int32_t block_tile_values(const HostPlan &P) {
-  return (P.flags & SHO_FLAG_FP32) ? kBlockTileDoubles / 2 : kBlockTileDoubles;
+  if (P.flags & SHO_FLAG_FP32) return kBlockTileDoubles / 2;
+  if (P.flags & SHO_FLAG_STORED) return kBlockTileDoubles;
+  return blk_tile_doubles(P.nu_max);
 }
 
 // Smallest power of two >= X.

@@ -721,7 +721,9 @@ constexpr int kBlkXStage = 256;  // doubles per wave: the x-table rows of a bloc
 // Runs of one slot handled together: phi_x(x) is read once per x and applied
 // to all of them.  Four where the kernel's register budget is set by a larger
 // cut-off anyway, else two.
-constexpr int blk_group(int nu, int numax) { return (numax > 5 && nu <= 5) ? 4 : 2; }
+constexpr int blk_group(int nu, int numax) {
+  return ((numax > 5 && nu <= 5) || (numax >= 8 && nu <= 7) || (numax >= 9 && nu <= 8)) ? 4 : 2;
+}
 
 template <int NU, int NUMAX, bool CPLX>
 __device__ inline void add_entry(const EArgs &E, const EntryRec &en, int ei, const double *u2,
@@ -818,6 +820,7 @@ __global__ __launch_bounds__(kBlkBlock) void k_expand_blocks(EArgs E,
                                                             const double *__restrict__ u2,
                                                             double *psi) {
   extern __shared__ double lds[];
+  constexpr int kTile = blk_tile_doubles(NUMAX);
   const BlockRec bk = load_uniform(E.blocks + blockIdx.x);
   if (bk.nentries < 0) return;
   const int w = wave_id();
@@ -841,17 +844,41 @@ __global__ __launch_bounds__(kBlkBlock) void k_expand_blocks(EArgs E,
     g = base + r * grow + (int64_t)__umul24(x, E.B) + l;
     return x < nxl && btile * TB + l < E.B;
   };
-  fill_lds<kBlockTileDoubles / kBlkBlock>(tile, nval, [&](int t) {
-    int64_t g = 0;
-    return slot(gbase, t, g) ? psi[g] : 0.0;
-  });
+  // 16-byte chunks (two bands) when every band pair is whole: the tile is
+  // filled by direct loads into LDS (no registers, no LDS writes).  (A
+  // write-back in 16-byte chunks, ds_read_b128 + 16-byte stores, measured
+  // slower than the 8-byte one below.)
+  const bool wide = TB >= 2 && (E.B & 1) == 0;
+  if (wide) {
+    // chunk c of the tile is slot 2c; each wave moves 64 chunks (1 KiB) per
+    // load, lane i into the wave's LDS address + 16 i.  Slots that hold no
+    // value of the block (padding columns and bands, chunks past nval) are
+    // loaded from the block's first point: never added to by an entry that
+    // is written back.
+    const int nchunk = nval >> 1;
+    const int lane = threadIdx.x & 63;
+    for (int c0 = w * 64; c0 < nchunk; c0 += kBlkBlock) {
+      const int c = c0 + lane;
+      int64_t g = gbase;
+      int64_t gc = 0;
+      if (c < nchunk && slot(gbase, 2 * c, gc)) g = gc;
+      __builtin_amdgcn_global_load_lds(psi + g, (__attribute__((address_space(3))) void *)(tile + 2 * c0),
+                                       16, 0, 0);
+    }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  } else {
+    fill_lds<kTile / kBlkBlock>(tile, nval, [&](int t) {
+      int64_t g = 0;
+      return slot(gbase, t, g) ? psi[g] : 0.0;
+    });
+  }
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const int lslot = lane >> E.tbe_shift;
   const int bl = lane & (TB - 1);
   const int b = btile * TB + bl;
   const int bc = b < E.B ? b : E.B - 1;
-  double *xstage = lds + kBlockTileDoubles + w * kBlkXStage;
+  double *xstage = lds + kTile + w * kBlkXStage;
   // entries round robin over the waves; the next entry's record is requested
   // before the current one is processed
   EntryRec en;
@@ -877,7 +904,7 @@ __global__ __launch_bounds__(kBlkBlock) void k_expand_blocks(EArgs E,
   // instead of holding them in registers across the entries
   int64_t gb = gbase;
   asm volatile("" : "+s"(gb));
-  constexpr int kPer = kBlockTileDoubles / kBlkBlock;
+  constexpr int kPer = kTile / kBlkBlock;
   for (int t0 = 0; t0 < nval; t0 += kPer * kBlkBlock) {
     double v[kPer];
 #pragma unroll
@@ -1857,10 +1884,11 @@ hipError_t launch_blocks(const EArgs &E, const double *u2, double *psi,
                          hipStream_t s) {
   if (E.nblocks > 0) {
     const dim3 g((unsigned)E.nblocks, (unsigned)E.ntiles);
-    const size_t shm = (kBlockTileDoubles + kBlkWaves * kBlkXStage) * sizeof(double);
+    size_t shm = 0;
     switch (E.nu_max) {
 #define X(N)                                                                          \
   case N:                                                                             \
+    shm = (blk_tile_doubles(N) + kBlkWaves * kBlkXStage) * sizeof(double);           \
     if (E.bloch)                                                                      \
       hipLaunchKernelGGL((k_expand_blocks<N, true>), g, dim3(kBlkBlock), shm, s, E, u2, \
                          psi);                                                        \
