@@ -725,22 +725,50 @@ constexpr int blk_group(int nu, int numax) {
   return ((numax > 5 && nu <= 5) || (numax >= 8 && nu <= 7) || (numax >= 9 && nu <= 8)) ? 4 : 2;
 }
 
+// The lane's run descriptor of an entry (lane < nruns), requested one entry
+// ahead of its use.
+__device__ inline uint32_t entry_desc(const EArgs &E, const EntryRec &en) {
+  const int lane = threadIdx.x & 63;
+  return lane < en.nruns ? as_const(E.run_desc)[en.run_begin + lane] : 0u;
+}
+
+// The y-table row of run i of an entry (i clamped into the runs).
+__device__ inline const double *entry_fy(const EArgs &E, const EntryRec &en, uint32_t mydesc,
+                                         int i, int gend) {
+  const uint32_t d = __shfl(mydesc, min(i, gend - 1));
+  return E.tab + en.tab_y + (int)(d & 0xff) * en.nfp;
+}
+
 template <int NU, int NUMAX, bool CPLX>
-__device__ inline void add_entry(const EArgs &E, const EntryRec &en, int ei, const double *u2,
-                                 int nxl, double *tile, double *xstage, int TB, int slot,
-                                 int bl, int bc) {
+__device__ inline void add_entry(const EArgs &E, const EntryRec &en, uint32_t mydesc,
+                                 const EntryRec &nen, bool has_next, uint32_t &ndesc, int ei,
+                                 const double *u2, int nxl, double *tile, double *xstage,
+                                 int TB, int slot, int bl, int bc) {
   constexpr int NF = NU + 1;
   constexpr int NP = NF * (NF + 1) / 2;
   constexpr int G = blk_group(NU, NUMAX);
   const int nfp = en.nfp;
   const int lane = threadIdx.x & 63;
   const int slots = 64 / TB;
-  // one round of loads: plane partials, run descriptors, the x-table rows of
-  // the block's x range (staged in LDS; rows that do not exist stay unset)
+  // one round of loads: plane partials, the x-table rows of the block's x
+  // range (staged in LDS; rows that do not exist stay unset), the y-table
+  // rows of the first group's runs, then the next entry's run descriptors
   const double *ub = u2 + en.u2 + bc;
   double u2v[NP];
 #pragma unroll
   for (int q = 0; q < NP; ++q) u2v[q] = ub[(int64_t)q * E.B];
+  // (up to cut-off 5: above, the registers would cost occupancy)
+  constexpr bool kPreY = NUMAX <= 5;
+  double fy0[kPreY ? G : 1][NF];
+  if constexpr (kPreY) {
+    const int gend = min(G * slots, (int)en.nruns);
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+      const double *fy = entry_fy(E, en, mydesc, j * slots + slot, gend);
+#pragma unroll
+      for (int n = 0; n < NF; ++n) fy0[j][n] = fy[n];
+    }
+  }
   if constexpr (CPLX) {
     // the entry's image T receives e^{-i k.T} times the plane partials
     // (cos, sin from the plan's table: scalar loads)
@@ -750,7 +778,6 @@ __device__ inline void add_entry(const EArgs &E, const EntryRec &en, int ei, con
 #pragma unroll
     for (int q = 0; q < NP; ++q) u2v[q] = rotate_pair(u2v[q], cs, sg);
   }
-  const uint32_t mydesc = lane < en.nruns ? as_const(E.run_desc)[en.run_begin + lane] : 0u;
   double tx[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
@@ -758,6 +785,7 @@ __device__ inline void add_entry(const EArgs &E, const EntryRec &en, int ei, con
     const int pt = i / nfp;
     tx[k] = (pt >= en.x_lo && pt < en.x_hi) ? E.tab[en.tab_x + i] : 0.0;
   }
+  if (has_next) ndesc = entry_desc(E, nen);
 #pragma unroll
   for (int k = 0; k < 4; ++k) xstage[lane * 4 + k] = tx[k];
   for (int g0 = 0; g0 < en.nruns; g0 += G * slots) {
@@ -779,7 +807,16 @@ __device__ inline void add_entry(const EArgs &E, const EntryRec &en, int ei, con
       rr[j] = d & 0xff;
       xa[j] = i < gend ? (int)((d >> 8) & 0xff) : 0;
       xb[j] = i < gend ? (int)((d >> 16) & 0xff) : 0;
-      const double *fy = E.tab + en.tab_y + rr[j] * nfp;
+      // the first group's rows were requested with the plane partials
+      double fy[NF];
+      if (kPreY && g0 == 0) {
+#pragma unroll
+        for (int n = 0; n < NF; ++n) fy[n] = fy0[kPreY ? j : 0][n];
+      } else {
+        const double *ry = E.tab + en.tab_y + rr[j] * nfp;
+#pragma unroll
+        for (int n = 0; n < NF; ++n) fy[n] = ry[n];
+      }
 #pragma unroll
       for (int n = 0; n < NF; ++n) U1[j][n] = 0.0;
       int q = 0;
@@ -882,22 +919,28 @@ __global__ __launch_bounds__(kBlkBlock) void k_expand_blocks(EArgs E,
   // entries round robin over the waves; the next entry's record is requested
   // before the current one is processed
   EntryRec en;
-  if (w < bk.nentries) en = load_uniform(E.entries + bk.entry_begin + w);
+  uint32_t desc = 0u;
+  if (w < bk.nentries) {
+    en = load_uniform(E.entries + bk.entry_begin + w);
+    desc = entry_desc(E, en);
+  }
   for (int i = w; i < bk.nentries; i += kBlkWaves) {
     EntryRec nxt = en;
-    if (i + kBlkWaves < bk.nentries)
-      nxt = load_uniform(E.entries + bk.entry_begin + i + kBlkWaves);
+    const bool has_next = i + kBlkWaves < bk.nentries;
+    if (has_next) nxt = load_uniform(E.entries + bk.entry_begin + i + kBlkWaves);
+    uint32_t ndesc = 0u;
     switch (en.nu) {
 #define X(N)                                                                          \
   case N:                                                                             \
     if constexpr (N <= NUMAX)                                                         \
-      add_entry<N, NUMAX, CPLX>(E, en, bk.entry_begin + i, u2, 1 << x2s, tile, xstage, TB, \
-                                lslot, bl, bc);                                     \
+      add_entry<N, NUMAX, CPLX>(E, en, desc, nxt, has_next, ndesc, bk.entry_begin + i, u2, \
+                                1 << x2s, tile, xstage, TB, lslot, bl, bc);          \
     break;
       X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10)
 #undef X
     }
     en = nxt;
+    desc = ndesc;
   }
   __syncthreads();
   // the write-back forms its addresses again (the base is made opaque)
