@@ -459,21 +459,23 @@ __attribute__((amdgpu_waves_per_eu(waves_per_eu(NU + 1)))) void k_expand_atomic(
       const cptr<double> fz = tz + cur_jz * nfp;
 #pragma unroll
       for (int q = 0; q < NP; ++q) U2[q] = 0.0;
-      int idx = 0;
-#pragma unroll
+      // one layer nz per iteration (not unrolled: with every layer's LDS
+      // reads in flight at once the large cut-offs ran out of registers);
+      // layer nz holds the pairs nx + ny <= NU - nz, ny outer, nx fastest
+      int base = 0;
+#pragma unroll 1
       for (int nz = 0; nz < NF; ++nz) {
         const double fv = fz[nz];
+        const int lim = NU - nz;
         int q = 0;
 #pragma unroll
         for (int ny = 0; ny < NF; ++ny) {
+          const int row = base + ny * (lim + 1) - ny * (ny - 1) / 2;
 #pragma unroll
-          for (int nx = 0; nx < NF - ny; ++nx, ++q) {
-            if (nx + ny + nz <= NU) {
-              U2[q] = fma(fv, cin[idx * TB + L.bl], U2[q]);
-              ++idx;
-            }
-          }
+          for (int nx = 0; nx < NF - ny; ++nx, ++q)
+            if (nx + ny <= lim) U2[q] = fma(fv, cin[(row + nx) * TB + L.bl], U2[q]);
         }
+        base += (lim + 1) * (lim + 2) / 2;
       }
     }
     const RunState rs = run_state(K, L, psi, bd);
