@@ -481,6 +481,9 @@ def diff_step(bd, wl, args):
     c = torch.empty(plan.coeff_doubles, dtype=torch.float64, device="cuda")
     gpsi = torch.zeros_like(psi)
     grad = torch.empty((s.natoms, 3), dtype=torch.float64, device="cuda")
+    # plan set-up, untimed: the schedule tuner (its work items serve the
+    # projection and the derivative kernel)
+    tune = None if args.no_tune else plan.tune(psi, c, reps=3)
 
     def step():
         plan.project(psi, c)
@@ -500,6 +503,7 @@ def diff_step(bd, wl, args):
                         "16 FP64 bands; step = forward projection + backward (expansion "
                         "of h^3 dL/dc, derivative kernel at nu+1)",
             "ms_per_step": ms, "gridpoint*bands/s (forward units)": units / (ms * 1e-3),
+            "tune": tune,
             "kernel_ms": {k: round(v[1], 4) for k, v in prof.items() if v[0]}}
 
 
