@@ -1132,6 +1132,9 @@ sho_status sho_plan_project(sho_plan_t p, const double *psi, double *c,
                             void *stream) {
   sho_status st = check_project(p, psi, c);
   if (st != SHO_OK || p->hp.coeff_rows == 0) return st;
+  // the block form's plane sums live in the plan's scratch, which
+  // sho_plan_release_scratch may have freed
+  if (p->hp.proj_form == sho::kProjectBlocks && (st = ensure_u2(p)) != SHO_OK) return st;
   hipError_t e = run_project_own(p, psi, c, (hipStream_t)stream, p->prof_on);
   if (e != hipSuccess) return hip_fail(e, "project launch");
   return SHO_OK;

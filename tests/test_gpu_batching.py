@@ -119,6 +119,47 @@ def test_graph_replays_match_oracle(mixed):
     plan.close()
 
 
+def test_release_scratch(mixed):
+    """sho_plan_release_scratch: the plane partials are freed and allocated
+    again by the next expansion (results unchanged, twice), the block
+    projection's plane sums likewise, and a graph captured before is
+    refused instead of replaying on the freed address."""
+    bd = _bd()
+    s, psi, cin, (c_ref, c_abs), (e_ref, e_abs), _ = mixed
+    plan = bd.Plan.from_system(s)
+    d_psi = _dev(psi)
+    d_c = _dev(cin)
+    c = torch.empty(plan.coeff_doubles, dtype=torch.float64, device="cuda")
+    out = torch.empty_like(d_psi)
+    g = plan.graph(d_psi, c, out)  # allocates the scratch
+    scratch = plan.info["expand_scratch_doubles"] * 8
+    held = plan_info(plan)["device_bytes"]
+    plan.release_scratch()
+    assert plan_info(plan)["device_bytes"] == held - scratch
+    plan.release_scratch()  # nothing held: no-op
+    with pytest.raises(bd.ShoError):
+        g.launch()
+    for rep in range(2):
+        e = _dev(psi)
+        plan.expand(d_c, e)
+        _check(_host(e), e_ref, e_abs, "expand after release, %d" % rep)
+        assert plan_info(plan)["device_bytes"] == held
+        plan.release_scratch()
+    plan.set_project(bd.PROJECT_BLOCKS)
+    _check(_host(plan.project(d_psi, c)), c_ref, c_abs, "block projection after release")
+    plan.release_scratch()
+    _check(_host(plan.project(d_psi, c)), c_ref, c_abs, "block projection, released again")
+    g.close()
+    plan.close()
+
+
+def plan_info(plan):
+    from paper_1905_00480_amd import binding as bd
+    info = bd.sho_plan_info()
+    bd._check(plan._lib.sho_plan_get_info(plan._h, bd.ctypes.byref(info)))
+    return {k: getattr(info, k) for k, _ in bd.sho_plan_info._fields_}
+
+
 def test_tuner_keeps_results(mixed):
     bd = _bd()
     s, psi, cin, (c_ref, c_abs), _, _ = mixed
