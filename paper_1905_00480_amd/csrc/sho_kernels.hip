@@ -901,8 +901,11 @@ __global__ __launch_bounds__(kBlkBlock) void k_expand_blocks(EArgs E,
       int64_t g = gbase;
       int64_t gc = 0;
       if (c < nchunk && slot(gbase, 2 * c, gc)) g = gc;
+      // non-temporal (cache policy nt), like the write-back below: the
+      // block is read and written once, and should not evict from the
+      // memory-side cache the psi that the projection reads again
       __builtin_amdgcn_global_load_lds(psi + g, (__attribute__((address_space(3))) void *)(tile + 2 * c0),
-                                       16, 0, 0);
+                                       16, 0, 2);
     }
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   } else {
@@ -961,7 +964,7 @@ __global__ __launch_bounds__(kBlkBlock) void k_expand_blocks(EArgs E,
     for (int u = 0; u < kPer; ++u) {
       const int t = t0 + u * kBlkBlock + (int)threadIdx.x;
       int64_t g = 0;
-      if (t < nval && slot(gb, t, g)) psi[g] = v[u];
+      if (t < nval && slot(gb, t, g)) __builtin_nontemporal_store(v[u], psi + g);
     }
   }
 }

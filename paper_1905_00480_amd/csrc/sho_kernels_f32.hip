@@ -47,6 +47,18 @@ __device__ inline Pair fma2(float s, Pair v, Pair acc) {
 
 __device__ inline Pair zero2() { return Pair{0.f, 0.f}; }
 
+// Non-temporal load and store of a pair (the block expansion's read and
+// write of psi: once per block, not to evict what the projection reads).
+typedef float nt_float2 __attribute__((ext_vector_type(2)));
+__device__ inline Pair load_nt(const Pair *p) {
+  const nt_float2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_float2 *>(p));
+  return Pair{v.x, v.y};
+}
+__device__ inline void store_nt(Pair v, Pair *p) {
+  const nt_float2 w = {v.a, v.b};
+  __builtin_nontemporal_store(w, reinterpret_cast<nt_float2 *>(p));
+}
+
 // ---------------------------------------------------------------- tables --
 
 // The FP32 tables are the FP64 samples rounded once to nearest.
@@ -547,7 +559,7 @@ __global__ __launch_bounds__(kBlkBlock) void k_expand_blocks(EArgs E,
     for (int u = 0; u < kPer; ++u) {
       const int t = t0 + u * kBlkBlock + (int)threadIdx.x;
       int64_t g = 0;
-      v[u] = (t < nval && slot(gbase, t, g)) ? psi[g] : zero2();
+      v[u] = (t < nval && slot(gbase, t, g)) ? load_nt(psi + g) : zero2();
     }
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
@@ -600,7 +612,7 @@ __global__ __launch_bounds__(kBlkBlock) void k_expand_blocks(EArgs E,
     for (int u = 0; u < kPer; ++u) {
       const int t = t0 + u * kBlkBlock + (int)threadIdx.x;
       int64_t g = 0;
-      if (t < nval && slot(gb, t, g)) psi[g] = v[u];
+      if (t < nval && slot(gb, t, g)) store_nt(v[u], psi + g);
     }
   }
 }
