@@ -677,6 +677,35 @@ void build_block_set(const HostPlan *P, int32_t R, int32_t X, BlockSet *out) {
       out->entries.push_back(E);
       B.nentries++;
     }
+    // the block's waves take its entries round robin: costliest first, so
+    // that the waves finish closer together (cost: plane partial loads, y
+    // passes per run, x steps per point)
+    {
+      auto cost = [&](const EntryRec &E) {
+        const int64_t nf = E.nu + 1, np = nf * (nf + 1) / 2;
+        int64_t pts = 0;
+        for (int32_t k = E.run_begin; k < E.run_begin + E.nruns; ++k) {
+          const uint32_t d = out->run_desc[k];
+          pts += (int64_t)((d >> 16) & 0xff) - (int64_t)((d >> 8) & 0xff);
+        }
+        return np * (1 + E.nruns) + nf * pts;
+      };
+      std::stable_sort(out->entries.begin() + B.entry_begin, out->entries.end(),
+                       [&](const EntryRec &a, const EntryRec &b) { return cost(a) > cost(b); });
+      // then dealt to the 4 waves in snake order (round k goes 0..3 when k
+      // is even, 3..0 when odd), so that wave w's k-th entry sits at list
+      // position 4k + w
+      constexpr int32_t kWavesB = 4;  // waves of a block workgroup
+      const int32_t n = B.nentries;
+      std::vector<EntryRec> dealt(n);
+      for (int32_t i = 0; i < n; ++i) {
+        const int32_t k = i / kWavesB, r = i % kWavesB;
+        const int32_t w = (k % 2 == 0) ? r : kWavesB - 1 - r;
+        const int32_t pos = k * kWavesB + w;
+        dealt[pos < n ? pos : i] = out->entries[B.entry_begin + i];
+      }
+      std::copy(dealt.begin(), dealt.end(), out->entries.begin() + B.entry_begin);
+    }
     cls[B.z % 8].push_back(B);
   }
   // blocks of planes z = k mod 8 go to workgroups g = k mod 8 (XCD k)
