@@ -352,7 +352,8 @@ void build_work(HostPlan *P, int tb_shift, int64_t target_points, int32_t sched)
         b.jhi = (int16_t)hi;
         b.pad = 0;
         P->bundles.push_back(b);
-        cost.push_back(hi - lo + 1 + 2);  // x steps plus per-bundle overhead
+        // x steps, in whole batches of 8 loads, plus per-bundle overhead
+        cost.push_back((hi - lo + 8) / 8 * 8 + 2);
       }
     }
   }
