@@ -754,6 +754,11 @@ def main():
     xflops = 2 * 6 * S * B * 2  # x passes of projection and expansion, nu = 5
     floor_ms = max(3 * union_bytes / (HBM_PEAK_GBS * 1e9), xflops / 78.6e12) * 1e3
     protocol = _paper_protocol(step)
+    # the same step replayed as one captured graph (sho_graph_create), for
+    # comparison: the headline stays the plain calls
+    g = plan.graph(psi, c, out)
+    ms_graph, _ = _time_steps(g.launch, args.steps, args.warmup)
+    g.close()
 
     rec = {
         "metric": "projected gridpoint*bands/s",
@@ -792,6 +797,7 @@ def main():
         "wall_s_incl_warmup": wall,
         "step_ms_p10_p50_p90": [float(np.percentile(per_step, q)) for q in (10, 50, 90)],
         "paper_protocol": protocol,
+        "graph_ms_per_step": ms_graph,
     }
     _log("scale workload: %.3f ms per step" % ms_per_step)
     rec["apply"] = apply_step(bd, wl, plan, s, psi, args)
