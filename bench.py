@@ -670,8 +670,8 @@ def main():
         print(json.dumps(rec["kinds"], indent=1))
         return
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (--gpus 1); the path "
-              "shards over bands or z-slabs as described in DESIGN.md", file=sys.stderr)
+        print("bench.py: the benchmark runs on one GPU only (--gpus 1); sharding the "
+              "path over bands or z-slabs is not implemented", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_1905_00480_amd import binding as bd
