@@ -136,7 +136,8 @@ struct RunState {
   int jx0;             // table index of the first point
   int len;
   int jy;
-  bool active;
+  int active;  // int, not bool: a struct without padding bytes stays in
+               // registers when the loop carries it
 };
 
 __device__ inline RunState run_state(const KArgs &K, const Lanes &L,
