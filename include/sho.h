@@ -217,7 +217,9 @@ const char *sho_last_error(void);
  * must not be called from two host threads at once.
  *   rbox   optional host [natoms] support radii (NULL: default rule)
  *   flags  SHO_FLAG_* bits
- * Errors: SHO_E_INVALID, SHO_E_NU_RANGE, SHO_E_UNDERSAMPLED, SHO_E_BOX,
+ * Errors: SHO_E_INVALID (also when n[0] * nbands reaches 2^31 or nbands
+ * 2^24, counting band pairs for SHO_FLAG_FP32: the kernels address a grid
+ * line in 32-bit integers), SHO_E_NU_RANGE, SHO_E_UNDERSAMPLED, SHO_E_BOX,
  * SHO_E_NOMEM, SHO_E_DEVICE.  *out is NULL on failure.
  */
 sho_status sho_plan_create(const sho_grid *grid, int32_t natoms,

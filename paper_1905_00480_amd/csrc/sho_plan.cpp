@@ -65,6 +65,13 @@ sho_status build_host_plan(const sho_grid *grid, int32_t natoms,
     *msg = "grid too large";
     return SHO_E_INVALID;
   }
+  // the kernels address a point within a grid line as x * nbands in 32-bit
+  // integer (24-bit multiplies)
+  if (nbands >= (1 << 24) || (int64_t)grid->n[0] * nbands > std::numeric_limits<int32_t>::max()) {
+    *msg = "grid line too long for the band count (n[0] * nbands must stay below 2^31, "
+           "nbands below 2^24)";
+    return SHO_E_INVALID;
+  }
   const uint32_t known =
       SHO_FLAG_STORED | SHO_FLAG_ALLOW_UNDERSAMPLED | SHO_FLAG_HOST_ONLY | SHO_FLAG_PER_ATOM |
       SHO_FLAG_FP32 | SHO_FLAG_DETERMINISTIC | SHO_FLAG_BLOCH;

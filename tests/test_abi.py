@@ -78,6 +78,9 @@ def test_argument_errors():
                                           [[200.0, 0.8, 0.8]], [0.6], [3], 1,
                                           rbox=[120.0], flags=bd.FLAG_HOST_ONLY))
     _expect(bd.SHO_E_INVALID, lambda: mk(rbox=[1.0, -1.0]))
+    # the kernels address a grid line (n[0] * nbands values) in 32-bit integers
+    _expect(bd.SHO_E_INVALID, lambda: mk(n=(1 << 16, 4, 4), nbands=1 << 15))
+    _expect(bd.SHO_E_INVALID, lambda: mk(nbands=1 << 24))
     # deterministic sums are FP64, on-the-fly, batched only
     for other in (bd.FLAG_STORED, bd.FLAG_PER_ATOM, bd.FLAG_FP32):
         _expect(bd.SHO_E_INVALID,
