@@ -64,6 +64,8 @@ def parse():
                     help="batching workload: skip timing the per-atom launch reference")
     ap.add_argument("--no-bloch", action="store_true",
                     help="skip the complex Bloch-band scale step")
+    ap.add_argument("--no-det", action="store_true",
+                    help="skip the SHO_FLAG_DETERMINISTIC scale step")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the plan's default schedule (no autotuning)")
     ap.add_argument("--serve-requests", type=int, default=2000)
@@ -441,6 +443,46 @@ def bloch_step(bd, wl, args, ms_fp64):
             if prj_ms > 0 else None}
 
 
+def deterministic_step(bd, wl, args, ms_default):
+    """The scale workload with SHO_FLAG_DETERMINISTIC (every sum in an order
+    fixed by the plan: per-wave coefficient tiles added in wave order, one
+    work item per atom, the owner form of the expansion); step = projection
+    + expansion, FP64, default schedule.  Also checks that two steps on the
+    same inputs give identical bits."""
+    import torch
+    s = wl.scale()
+    psi = torch.from_numpy(wl.psi_for(s)).cuda()
+    plan = bd.Plan.from_system(s, flags=bd.FLAG_DETERMINISTIC)
+    c = torch.empty(plan.coeff_doubles, dtype=torch.float64, device="cuda")
+    out = torch.zeros_like(psi)
+
+    def step():
+        plan.project(psi, c)
+        plan.expand(c, out)
+
+    ms, _ = _time_steps(step, args.steps, args.warmup)
+    plan.profile(True)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    prof = plan.profile_read()
+    plan.profile(False)
+    out.zero_()
+    step()
+    c1, o1 = c.clone(), out.clone()
+    out.zero_()
+    step()
+    torch.cuda.synchronize()
+    same = bool(torch.equal(c1.view(torch.int64), c.view(torch.int64)) and
+                torch.equal(o1.view(torch.int64), out.view(torch.int64)))
+    plan.close()
+    return {"workload": "scale: periodic 128^3, h=0.2 Bohr, 512 atoms, sigma=0.6, nu_max=5, "
+                        "32 FP64 bands, SHO_FLAG_DETERMINISTIC; step = projection + expansion",
+            "ms_per_step": ms, "ms_vs_default": ms / ms_default,
+            "kernel_ms": {k: round(v[1], 4) for k, v in prof.items() if v[0]},
+            "bitwise_repeat": same}
+
+
 def setup_step(bd):
     """Host-side set-up of the basis (once per SCF cycle, sec. 3.5): the
     atomic matrix of 18 synthetic radial projectors (two each for s, p, d) in
@@ -806,6 +848,9 @@ def main():
     if not args.no_fp32:
         rec["fp32"] = fp32_step(bd, wl, args, ms_per_step)
         _log("fp32 scale step: %.3f ms" % rec["fp32"]["ms_per_step"])
+    if not args.no_det:
+        rec["deterministic"] = deterministic_step(bd, wl, args, ms_per_step)
+        _log("deterministic scale step: %.3f ms" % rec["deterministic"]["ms_per_step"])
     if not args.no_bloch:
         rec["bloch"] = bloch_step(bd, wl, args, ms_per_step)
         _log("bloch scale step: %.3f ms" % rec["bloch"]["ms_per_step"])
