@@ -42,8 +42,11 @@ constexpr int kLineStage = 64;  // line records per wave held in LDS
 static_assert(kWaves * kLineStage * sizeof(LineRec) + 1024 <= kStaticLds,
               "static LDS of the streaming kernels");
 
-// waves per SIMD the register allocator must allow (4 keeps <= 128 VGPRs)
-constexpr int waves_per_eu(int nf) { return nf <= 6 ? 4 : 2; }
+// waves per SIMD the register allocator must allow (4 keeps <= 128 VGPRs).
+// Deterministic plans keep eight coefficient tiles in LDS (one per wave), so
+// few of their workgroups fit on a CU (one at nu = 5 and 32-band tiles); they
+// may use the registers of two waves per SIMD instead of spilling to fit four.
+constexpr int waves_per_eu(int nf, bool det = false) { return nf <= 6 && !det ? 4 : 2; }
 
 // dst[t] = value(t) for t < count, with U global loads in flight per thread
 // (all loads of a round are issued before the first LDS write waits).
@@ -392,7 +395,7 @@ __device__ inline void project_item(const KArgs &K, cptr<WorkRec> W, const AtomR
 
 template <int NU, bool DET>
 __global__ __launch_bounds__(kBlock)
-__attribute__((amdgpu_waves_per_eu(waves_per_eu(NU + 1)))) void k_project(
+__attribute__((amdgpu_waves_per_eu(waves_per_eu(NU + 1, DET)))) void k_project(
     KArgs K, const double *__restrict__ psi, double *__restrict__ c) {
   extern __shared__ double cacc[];
   const cptr<WorkRec> W = as_const(K.work) + blockIdx.x;
@@ -406,7 +409,7 @@ __attribute__((amdgpu_waves_per_eu(waves_per_eu(NU + 1)))) void k_project(
 // single launch serves plans whose cut-offs differ.
 template <int NUMAX, bool DET, bool CPLX = false>
 __global__ __launch_bounds__(kBlock)
-__attribute__((amdgpu_waves_per_eu(waves_per_eu(NUMAX + 1)))) void k_project_any(
+__attribute__((amdgpu_waves_per_eu(waves_per_eu(NUMAX + 1, DET)))) void k_project_any(
     KArgs K, const double *__restrict__ psi, double *__restrict__ c) {
   extern __shared__ double cacc[];
   const cptr<WorkRec> W = as_const(K.work) + blockIdx.x;
@@ -1687,7 +1690,7 @@ __device__ inline void coeff_decode(int n, int nu, int &nx, int &ny, int &nz) {
 // grad must be zero before the launch (work items and band tiles add).
 template <int NU1, bool DET>
 __global__ __launch_bounds__(kBlock)
-__attribute__((amdgpu_waves_per_eu(waves_per_eu(NU1 + 1)))) void k_force(
+__attribute__((amdgpu_waves_per_eu(waves_per_eu(NU1 + 1, DET)))) void k_force(
     KArgs K, const double *__restrict__ psi, const double *__restrict__ w,
     double *grad, double *gpart) {
   constexpr int NF = NU1 + 1;
