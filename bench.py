@@ -66,6 +66,9 @@ def parse():
                     help="skip the complex Bloch-band scale step")
     ap.add_argument("--no-det", action="store_true",
                     help="skip the SHO_FLAG_DETERMINISTIC scale step")
+    ap.add_argument("--by-cutoff", action="store_true",
+                    help="only time the batching workload's projection on atom subsets "
+                         "by cut-off, print one JSON line and exit")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the plan's default schedule (no autotuning)")
     ap.add_argument("--serve-requests", type=int, default=2000)
@@ -483,6 +486,44 @@ def deterministic_step(bd, wl, args, ms_default):
             "bitwise_repeat": same}
 
 
+def by_cutoff(bd, wl, reps=10):
+    """The batching workload's projection on subsets of its atoms by cut-off
+    (each subset a plan of its own over the same psi, default schedule,
+    64-band tiles): mean ms per launch over `reps` launches and the per-atom
+    box bytes per second.  Shows which cut-offs stream below the rest."""
+    import torch
+    s = wl.batching()
+    psi = torch.from_numpy(wl.psi_for(s)).cuda()
+    nus = np.asarray(s.numax)
+    rows = []
+    subsets = [("3-9", None), ("3-6", (3, 6)), ("7-9", (7, 9))] + \
+        [(str(n), (n, n)) for n in range(3, 10)]
+    for name, rng in subsets:
+        sub = s if rng is None else s.subset(np.nonzero((nus >= rng[0]) & (nus <= rng[1]))[0])
+        plan = bd.Plan.from_system(sub)
+        sched = plan.schedule()
+        plan.set_schedule(sched[0], 64, sched[2])
+        c = torch.empty(plan.coeff_doubles, dtype=torch.float64, device="cuda")
+        for _ in range(3):
+            plan.project(psi, c)
+        torch.cuda.synchronize()
+        plan.profile(True)
+        for _ in range(reps):
+            plan.project(psi, c)
+        torch.cuda.synchronize()
+        ms = plan.profile_read()["project"][1]
+        plan.profile(False)
+        gbytes = plan.support_points * s.nbands * 8 / 1e9
+        rows.append({"nu": name, "atoms": int(sub.natoms), "schedule": list(plan.schedule()),
+                     "support_points": int(plan.support_points), "project_ms": round(ms, 4),
+                     "per_atom_box_TB/s": round(gbytes / ms, 3)})
+        _log("cut-offs %s: %.3f ms" % (name, ms))
+        plan.close()
+        del c
+    return {"workload": "batching: periodic 160^3, h=0.18 Bohr, 2048 atoms, nu_max 3..9, "
+                        "64 FP64 bands; projection of atom subsets by cut-off", "rows": rows}
+
+
 def setup_step(bd):
     """Host-side set-up of the basis (once per SCF cycle, sec. 3.5): the
     atomic matrix of 18 synthetic radial projectors (two each for s, p, d) in
@@ -723,6 +764,9 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     bd.load_library()
+    if args.by_cutoff:
+        print(json.dumps(by_cutoff(bd, wl)))
+        return
     dev = torch.device("cuda:0")
     s = wl.scale()
     psi_h = wl.psi_for(s)
